@@ -1,0 +1,89 @@
+"""Oracle: solve drivers around the cycle.
+
+Test infrastructure only (see the package header).
+
+* `stationary_solve` -- repeated pipelined cycles (the paper's iteration:
+  one traversal per cycle) until the finest h-norm residual has dropped by
+  rtol relative to the start, then a flush;
+* `bicgstab`         -- BiCGStab with the additive cycle from a zero start as
+  right preconditioner (the paper uses its solver as a preconditioner,
+  Sections 2 and 4); an addition beyond the paper, needed because the
+  stationary cycle diverges on indefinite 3D problems;
+* `dense_solve`      -- LU on the dense interior matrix (tiny grids only), the
+  fixed point both drivers must reach.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .cycle import Params, Pipelined, zero_start_cycle
+from .discretisation import dense_H, interior_mask, zero_boundary
+
+
+def stationary_solve(p: Params, b: np.ndarray, rtol: float, maxit: int, u0=None):
+    """Returns (u, cycles, history of h-norm residuals, converged?)."""
+    pipe = Pipelined(p, b, u0)
+    hist = []
+    converged = False
+    for _ in range(maxit):
+        rh, _ = pipe.cycle()
+        hist.append(rh)
+        if rh <= rtol * hist[0]:
+            converged = True
+            break
+        if not np.isfinite(rh) or rh > 1e8 * hist[0]:
+            break
+    u = pipe.flush()
+    return u, len(hist), hist, converged
+
+
+def bicgstab(p: Params, b: np.ndarray, rtol: float, maxit: int, x0=None, precondition=True):
+    """Right-preconditioned BiCGStab on interior vertices (van der Vorst 1992).
+    Inner products are conjugating (np.vdot).  Returns (x, iterations,
+    relative-residual history, converged?)."""
+    L = p.level_max
+    A = lambda v: p.H(v, L)
+    M = (lambda v: zero_start_cycle(p, v)) if precondition else (lambda v: v)
+    b = zero_boundary(b)
+    x = np.zeros_like(b) if x0 is None else zero_boundary(x0)
+    r = zero_boundary(b - A(x))
+    bnorm = np.linalg.norm(b)
+    rh = r.copy()
+    rho = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    pv = np.zeros_like(b)
+    hist = [np.linalg.norm(r) / bnorm]
+    for it in range(1, maxit + 1):
+        rho_new = np.vdot(rh, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        pv = r + beta * (pv - omega * v)
+        y = M(pv)
+        v = A(y)
+        alpha = rho_new / np.vdot(rh, v)
+        s = r - alpha * v
+        if np.linalg.norm(s) / bnorm <= rtol:
+            x = x + alpha * y
+            hist.append(np.linalg.norm(s) / bnorm)
+            return x, it, hist, True
+        z = M(s)
+        t = A(z)
+        omega = np.vdot(t, s) / np.vdot(t, t)
+        x = x + alpha * y + omega * z
+        r = s - omega * t
+        rho = rho_new
+        hist.append(np.linalg.norm(r) / bnorm)
+        if hist[-1] <= rtol:
+            return x, it, hist, True
+    return x, maxit, hist, False
+
+
+def dense_solve(p: Params, b: np.ndarray) -> np.ndarray:
+    """u with H u = b on interior vertices, zero boundary (np.linalg.solve)."""
+    L = p.level_max
+    n = p.n(L)
+    A = dense_H(n, p.dim, L, p.theta, p.phi_at(L), p.conjugate)
+    m = interior_mask(n, p.dim)
+    u = np.zeros((n,) * p.dim, dtype=np.complex128)
+    u[m] = np.linalg.solve(A, np.asarray(b)[m])
+    return u

@@ -1,0 +1,197 @@
+"""Pins of the oracle's cycles.
+
+* single-level cycle on a sine mode  <- damped Jacobi amplification 1 - w lambda / D
+* multilevel cycle                   <- dense additive operator
+      B = sum_l P^(L-l) Lop_l w_l D_l^-1 R^(L-l)   (constant phi), built from
+      explicit Kronecker-product transfer matrices, not from the oracle's P/R
+* the paper's theorem: Algorithm 1 with (omega_S, omega_cg) equals the FAS
+  cycle with omega_l = omega_S omega_cg^succ
+* bottom-up FAS (appendix) == semantic == pipelined single sweep + flush,
+  for add / hb / BPX, constant and varying phi
+* Lemma 1: injection invariant whenever a residual is evaluated
+* sf stays zero for hb and BPX (Section 5.2)
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.cycle import Params, omega_levels
+from oracle.discretisation import interior_mask
+
+from test_oracle_discretisation import sine_mode, symbol
+
+
+def rand_c(shape, rng):
+    return O.zero_boundary(rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+
+def test_single_level_jacobi_amplification():
+    dim, level, theta, phi, omega = 2, 3, 0.4, 80 * (1 + 0.5j), 0.7
+    N = 3 ** level
+    p = Params(dim=dim, level_max=level, level_min=level, theta=theta, phi=phi, omega=omega)
+    D = O.diag_H(N + 1, dim, level, theta, phi)[1, 1]
+    for ks in ([1, 1], [3, 7], [26, 13]):
+        s = sine_mode(dim, level, ks)
+        pipe = O.Pipelined(p, np.zeros_like(s), s)
+        pipe.cycle()
+        got = pipe.flush()
+        lam = symbol(dim, level, theta, phi, ks)
+        np.testing.assert_allclose(got, (1 - omega * lam / D) * s, atol=1e-13)
+
+
+def dense_transfer(level):
+    """Dense 1D interpolation from level-1 to level by its definition (hat
+    function values at the fine vertices), Kronecker-extended later."""
+    nf, nc = 3 ** level + 1, 3 ** (level - 1) + 1
+    xf = np.arange(nf) / 3 ** level
+    xc = np.arange(nc) / 3 ** (level - 1)
+    hc = 1.0 / 3 ** (level - 1)
+    return np.maximum(0.0, 1.0 - np.abs(xf[:, None] - xc[None, :]) / hc)
+
+
+def kron_pow(m, dim):
+    out = np.ones((1, 1))
+    for _ in range(dim):
+        out = np.kron(out, m)
+    return out
+
+
+@pytest.mark.parametrize("dim,L", [(2, 3), (3, 2)])
+@pytest.mark.parametrize("variant", ["add", "hb", "bpx"])
+@pytest.mark.parametrize("scheme", ["const", "exp"])
+def test_cycle_equals_dense_additive_operator(dim, L, variant, scheme, rng):
+    theta, phi = np.pi / 6, 200.0
+    p = Params(dim=dim, level_max=L, level_min=1, theta=theta, phi=phi, variant=variant,
+               omega_scheme=scheme, omega=0.6)
+    n = {l: 3 ** l + 1 for l in p.levels}
+    Pm = {l: kron_pow(dense_transfer(l), dim) for l in p.levels if l > 1}
+    bnd = {l: (~interior_mask(n[l], dim)).ravel() for l in p.levels}
+    cp = {l: np.zeros(n[l] ** dim, bool) for l in p.levels}
+    Im = {}
+    for l in p.levels:
+        if l > 1:
+            cp[l] = np.zeros((n[l],) * dim, bool)
+            cp[l][(slice(None, None, 3),) * dim] = True
+            cp[l] = cp[l].ravel()
+            Im[l] = np.eye(n[l] ** dim)[cp[l]]          # injection rows
+    om = omega_levels(p, 1)
+    Nf = n[L] ** dim
+    B = np.zeros((Nf, Nf), dtype=np.complex128)
+    for l in p.levels:
+        # R^(L-l): restriction to level l (boundary rows zeroed after each step)
+        Rl = np.eye(Nf)
+        Pl = np.eye(n[l] ** dim)
+        for k in range(L, l, -1):
+            Rk = Pm[k].T.copy()
+            Rk[bnd[k - 1]] = 0
+            Rl = Rk @ Rl
+        for k in range(l + 1, L + 1):
+            Pl = Pm[k] @ Pl
+        D = O.diag_H(n[l], dim, l, theta, phi).ravel()
+        S = np.diag(np.where(bnd[l], 0, om[l] / D))
+        if l > 1 and variant == "hb":
+            S = np.diag(np.where(cp[l], 0, 1.0)) @ S
+        if l > 1 and variant == "bpx":
+            S = (np.eye(n[l] ** dim) - Pm[l] @ Im[l]) @ S
+        B += Pl @ S @ Rl
+    u = rand_c((n[L],) * dim, rng)
+    b = rand_c((n[L],) * dim, rng)
+    r = (b - O.apply_H(u, L, theta, phi)).ravel()
+    ref = u.ravel() + B @ r
+    got, _, _ = O.semantic_cycle(p, u, b)
+    np.testing.assert_allclose(got.ravel(), ref, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dim,L", [(2, 3), (3, 2)])
+def test_theorem_additive_damping(dim, L, rng):
+    """Algorithm 1 with omega_S and omega_cg equals the FAS cycle whose level
+    omega is omega_S omega_cg^succ; exponential damping is omega_cg = omega_S."""
+    theta, phi, wS = 0.5, 150 * (1 + 0.5j), 0.55
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi, variant="add", omega_scheme="exp",
+               omega=wS)
+    n = 3 ** L + 1
+    u, b = rand_c((n,) * dim, rng), rand_c((n,) * dim, rng)
+    ref = O.textbook_additive(p, u, b, omega_S=wS, omega_cg=wS)
+    got, _, _ = O.semantic_cycle(p, u, b)
+    np.testing.assert_allclose(got, ref, atol=1e-13 * np.abs(ref).max())
+
+
+PHI_CASES = ["const", "varying"]
+
+
+def make_params(dim, L, variant, phi_case, rng, scheme="const"):
+    n = 3 ** L + 1
+    pn = None
+    if phi_case == "varying":
+        pn = (80 + 60 * rng.standard_normal((n,) * dim)) * (1 + 0.3j)
+    return Params(dim=dim, level_max=L, level_min=1, theta=0.3, phi=90 * (1 + 0.5j),
+                  phi_nodal=pn, variant=variant, omega=0.6, omega_scheme=scheme)
+
+
+@pytest.mark.parametrize("dim,L", [(2, 3), (3, 2)])
+@pytest.mark.parametrize("variant", ["add", "hb", "bpx"])
+@pytest.mark.parametrize("phi_case", PHI_CASES)
+def test_pipelined_bottom_up_semantic_agree(dim, L, variant, phi_case, rng):
+    p = make_params(dim, L, variant, phi_case, rng, scheme="transition")
+    n = 3 ** L + 1
+    u0, b = rand_c((n,) * dim, rng), rand_c((n,) * dim, rng)
+    pipe = O.Pipelined(p, b, u0)
+    u = u0
+    for it in range(1, 5):
+        rh, rmax = pipe.cycle()
+        ref_r = b - p.H(u, L)
+        assert abs(rh - O.norm_h(ref_r, L)) <= 1e-13 * rh
+        nxt, rh2, _ = O.semantic_cycle(p, u, b, it)
+        bu = O.bottom_up_fas(p, u, b, it)
+        np.testing.assert_allclose(bu, nxt, atol=1e-13 * np.abs(nxt).max())
+        u = nxt
+    got = pipe.flush()
+    np.testing.assert_allclose(got, u, atol=1e-13 * np.abs(u).max())
+
+
+def test_textbook_equals_semantic_for_add(rng):
+    p = make_params(2, 3, "add", "const", rng)
+    n = 28
+    u, b = rand_c((n, n), rng), rand_c((n, n), rng)
+    got, _, _ = O.semantic_cycle(p, u, b)
+    ref = O.textbook_additive(p, u, b)
+    np.testing.assert_allclose(got, ref, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("variant", ["add", "hb", "bpx"])
+@pytest.mark.parametrize("phi_case", PHI_CASES)
+def test_lemma1_injection_invariant_and_sf(variant, phi_case, rng):
+    dim, L = 3, 3
+    p = make_params(dim, L, variant, phi_case, rng)
+    n = 3 ** L + 1
+    pipe = O.Pipelined(p, rand_c((n,) * dim, rng), rand_c((n,) * dim, rng))
+    for _ in range(3):
+        pipe.iteration += 1
+        om = omega_levels(p, pipe.iteration)
+        for lev in p.levels:
+            pipe.pre(lev)
+        for lev in range(L, p.level_min, -1):
+            scale = np.abs(pipe.u[lev]).max()
+            assert np.abs(pipe.u[lev - 1] - O.inject(pipe.u[lev])).max() <= 1e-13 * scale
+        for lev in reversed(list(p.levels)):
+            pipe.post(lev, om[lev])
+        if variant in ("hb", "bpx"):
+            for lev in p.levels:
+                assert not pipe.sf[lev].any()
+
+
+def test_omega_table():
+    p = Params(dim=2, level_max=4, level_min=1, omega=0.5, omega_scheme="exp")
+    assert omega_levels(p) == {4: 0.5, 3: 0.25, 2: 0.125, 1: 0.0625}
+    p.omega_scheme = "jacobi"
+    assert omega_levels(p) == {4: 0.5, 3: 0, 2: 0, 1: 0}
+    p.omega_scheme = "lgrid"
+    p.omega_L = 1
+    assert omega_levels(p) == {4: 0.5, 3: 0.5, 2: 0, 1: 0}
+    p.omega_scheme = "transition"
+    assert omega_levels(p, 1) == {4: 1, 3: 1, 2: 1, 1: 1}
+    w = omega_levels(p, 2)
+    assert abs(w[3] - 0.5 ** 1.0) < 1e-15 and abs(w[1] - 0.5 ** 2.0) < 1e-15

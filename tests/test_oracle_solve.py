@@ -1,0 +1,58 @@
+"""Pins of the oracle's solve drivers and of the discretisation's accuracy.
+
+* fixed point   <- LU solve of the dense interior matrix
+* Poisson MMS   <- analytic prod sin(pi x) solution of the paper's Poisson load
+                   (phi = 0, theta = 0): second-order convergence, error / 9 per level
+* Helmholtz MMS <- the same with chi = (d pi^2 - phi) prod sin(pi x)
+* stationary Poisson cycle converges (Section 6.1: mesh-independent-ish rates)
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.cycle import Params
+from paper_1508_03954_amd.inputs import sine_load, sine_solution
+
+
+def rand_c(shape, rng):
+    return O.zero_boundary(rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+
+@pytest.mark.parametrize("dim,L", [(2, 3), (3, 2)])
+@pytest.mark.parametrize("variant", ["add", "bpx"])
+def test_bicgstab_reaches_dense_solution(dim, L, variant, rng):
+    p = Params(dim=dim, level_max=L, theta=np.pi / 6, phi=400.0, variant=variant, omega=0.6)
+    n = 3 ** L + 1
+    b = rand_c((n,) * dim, rng)
+    ref = O.dense_solve(p, b)
+    x, its, hist, ok = O.bicgstab(p, b, 1e-12, 200)
+    assert ok
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_stationary_poisson_converges():
+    L, dim = 4, 2
+    p = Params(dim=dim, level_max=L, theta=0.0, phi=0.0, variant="add", omega=0.6,
+               omega_scheme="exp")
+    b = O.lumped_rhs(sine_load(L, dim), L, 0.0)
+    u, its, hist, ok = O.stationary_solve(p, b, 1e-8, 400)
+    assert ok
+    ref = O.dense_solve(p, b)
+    assert np.linalg.norm(u - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("dim,levels", [(2, (3, 4, 5)), (3, (2, 3))])
+@pytest.mark.parametrize("phi", [0.0, 20.0])
+def test_manufactured_solution_second_order(dim, levels, phi):
+    errs = []
+    for L in levels:
+        p = Params(dim=dim, level_max=L, theta=0.0, phi=phi, variant="bpx", omega=0.6)
+        chi = sine_load(L, dim) * (1.0 - phi / (dim * np.pi ** 2))
+        b = O.lumped_rhs(chi, L, 0.0)
+        u, its, hist, ok = O.bicgstab(p, b, 1e-13, 300)
+        assert ok
+        errs.append(np.abs(u - sine_solution(L, dim)).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    for r in ratios:
+        assert 7.0 < r < 11.0, (errs, ratios)
