@@ -1,0 +1,186 @@
+/*
+ * mg.h -- C ABI of the MI355X complex additive multilevel Helmholtz library.
+ *
+ * The library solves the channel Helmholtz equation of the paper's Section 2,
+ *     -Lap u - phi u = chi   on (0,1)^d, d in {2,3}, zero Dirichlet boundary,
+ * discretised with d-linear finite elements on the regular levels of a
+ * 3-partitioned spacetree (Sections 3 and 4), with the complex grid rotation
+ * h -> h exp(i theta) (CSG) and complex phi (CSL shift) of Section 2.  One
+ * cycle is the single-sweep pipelined additive FAS of Section 5 (Algorithms
+ * tdAdd and tdBPX, with the hierarchical-basis mask of eq. hb-omega): damped
+ * Jacobi on every level, factor-3 d-linear prolongation P, R = P^T, and
+ * injection I.
+ *
+ * Conventions for every entry point
+ *   - Vectors are caller-owned DEVICE buffers of complex128 (mg_c128, the
+ *     layout of torch.complex128), contiguous C order of shape (n,)*d with
+ *     n = 3^level_max + 1 and x fastest; boundary vertices are included.
+ *     Input boundary entries are ignored; output boundary entries are zero.
+ *     Buffers are borrowed for the duration of the call and never retained.
+ *   - All device work is enqueued on the stream given to mg_setup.  Calls
+ *     that return host scalars synchronise that stream.
+ *   - int-returning calls return MG_OK or a negative MG_E* code;
+ *     mg_last_error() returns a thread-local message for the last failure.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef MG_H
+#define MG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_OK          0
+#define MG_EINVAL     (-1)   /* bad argument or size                         */
+#define MG_ENOMEM     (-2)   /* device allocation failed                     */
+#define MG_EDEVICE    (-3)   /* a HIP runtime call or kernel launch failed   */
+#define MG_ENOTCONV   (-4)   /* maxit reached; outputs hold the last iterate */
+#define MG_EDIVERGED  (-5)   /* non-finite residual or ||r|| > 1e8 ||r0||    */
+
+typedef struct { double re, im; } mg_c128;
+typedef struct mg_ctx mg_ctx;   /* opaque; owns all level buffers */
+
+/* Solver variants (Section 5.2): plain additive MG, hierarchical basis
+ * (c-point omega masked, eq. hb-omega), BPX (Algorithm tdBPX). */
+enum { MG_ADD = 0, MG_HB = 1, MG_BPX = 2 };
+
+/* Relaxation schemes omega_l (table of Section 5.1), succ = l_max - l:
+ * CONST omega; JACOBI omega on l_max only; LGRID omega where succ <= omega_L;
+ * EXP omega^(succ+1); TRANSITION omega^((1-1/n)(succ+1)), n = cycle counter. */
+enum { MG_OMEGA_CONST = 0, MG_OMEGA_JACOBI = 1, MG_OMEGA_LGRID = 2,
+       MG_OMEGA_EXP = 3, MG_OMEGA_TRANSITION = 4 };
+
+/* Arithmetic of the cycle: complex128 throughout, or complex64 level
+ * corrections inside an FP64 residual-refinement loop (mg_solve only; the
+ * operator application mg_apply is always FP64). */
+enum { MG_FP64 = 0, MG_FP32_REFINE = 1 };
+
+/* Solve drivers: repeated cycles, or BiCGStab preconditioned by one cycle
+ * from a zero start. */
+enum { MG_STATIONARY = 0, MG_BICGSTAB = 1 };
+
+/* How the coarse FAS right-hand side b_(l-1) is formed.
+ * FAS:      b_(l-1) = R (b_l - H_l uhat_l), uhat = u - P u_(l-1)  (eq. HTMG);
+ * GALERKIN: b_(l-1) = R r_l + H_(l-1) u_(l-1) (the paper's Lemma 2), valid
+ *           when R H_l P = H_(l-1): constant phi and uniform rotation.  The
+ *           coarse b slot then holds R r_l and the coarse residual is read
+ *           from it directly;
+ * AUTO:     GALERKIN for constant phi, FAS otherwise. */
+enum { MG_RESTRICT_AUTO = 0, MG_RESTRICT_FAS = 1, MG_RESTRICT_GALERKIN = 2 };
+
+/* Finest-level sweep implementation: AUTO picks FUSED when supported (constant
+ * phi, GALERKIN form), GENERIC runs the level operations as separate passes. */
+enum { MG_SWEEP_AUTO = 0, MG_SWEEP_GENERIC = 1, MG_SWEEP_FUSED = 2 };
+
+/* Level fields for mg_get_level. */
+enum { MG_FIELD_U = 0, MG_FIELD_B = 1, MG_FIELD_SC = 2, MG_FIELD_SF = 3, MG_FIELD_SI = 4 };
+
+typedef struct {
+  int dim;                   /* 2 or 3                                             */
+  int level_min, level_max;  /* 1 <= level_min <= level_max; 3^level cells/axis    */
+  double theta;              /* CSG rotation: cell side h -> h exp(i theta)        */
+  mg_c128 phi;               /* constant phi of  -Lap u - phi u = chi              */
+  const mg_c128* phi_field;  /* optional DEVICE nodal phi on the finest level      */
+                             /* (NULL: constant).  Read during mg_setup only;      */
+                             /* coarse levels sample it at their vertices.         */
+  int variant;               /* MG_ADD | MG_HB | MG_BPX                            */
+  int omega_scheme;          /* MG_OMEGA_*                                         */
+  mg_c128 omega;             /* omega_S                                            */
+  int omega_L;               /* grid bound of MG_OMEGA_LGRID                       */
+  int precision;             /* MG_FP64 | MG_FP32_REFINE                           */
+  int conjugate;             /* 1: operator is H^H = conj(H) (adjoint solves)      */
+  int restrict_form;         /* MG_RESTRICT_*                                      */
+  int sweep;                 /* MG_SWEEP_*                                         */
+} mg_params;
+
+/* Fills *p with: dim 3, levels 1..3, theta 0, phi 0, constant, BPX, CONST,
+ * omega 0.6, omega_L 1, FP64, no conjugation, AUTO forms. */
+void mg_params_default(mg_params* p);
+
+/* Builds a context: allocates every level's fields (u, b, sc, sf, si; the
+ * finest level keeps the folded iterate u + sc in two ping-pong buffers),
+ * derives per-level operator data (Section 4: rediscretisation on each level;
+ * for a phi field, nodal phi by injection, cell averages and the accumulated
+ * diagonal), zeroes the state.  hip_stream: a hipStream_t or NULL (default
+ * stream).  Returns MG_EINVAL for bad params, MG_ENOMEM/MG_EDEVICE on device
+ * failures; *out is NULL on failure. */
+int mg_setup(const mg_params* p, void* hip_stream, mg_ctx** out);
+
+/* Frees everything the context owns.  NULL is accepted. */
+void mg_destroy(mg_ctx* ctx);
+
+/* Thread-local text of the last error ("" if none). */
+const char* mg_last_error(void);
+
+/* Number of vertices per axis on `level` (3^level + 1), or MG_EINVAL. */
+int mg_level_size(const mg_ctx* ctx, int level);
+
+/* y = H_(level_max) x on interior vertices, y = 0 on the boundary (Section 4 /
+ * Appendix B: element-wise matrix-free operator, FP64). x and y must not
+ * alias. */
+int mg_apply(mg_ctx* ctx, const mg_c128* x, mg_c128* y);
+
+/* Lumped discrete load: b = eta_L^d chi at interior vertices, 0 on the
+ * boundary, eta_L = 3^-L exp(i theta) (the weight of the discretised
+ * right-hand side, Section 4).  chi and b may alias. */
+int mg_rhs_from_nodal(mg_ctx* ctx, const mg_c128* chi, mg_c128* b);
+
+/* Sets the finest right-hand side and resets the pipeline helpers
+ * (sc = sf = si = 0) and the cycle counter; a pending update is discarded
+ * (call mg_flush first to keep it). */
+int mg_set_rhs(mg_ctx* ctx, const mg_c128* b);
+
+/* Sets the finest iterate, injects it into every coarser level (the FAS
+ * constraint u_(l-1) = I u_l of Section 4) and resets the helpers and the
+ * cycle counter. */
+int mg_set_solution(mg_ctx* ctx, const mg_c128* u);
+
+/* Runs ncycles pipelined cycles (one traversal each).  Cycle k reports the
+ * residual of the iterate it started from (the half-iteration shift of
+ * Section 5): res_h[k] = |b - H u|_h, |x|_h^2 = sum |h|^d |x_i|^2 over interior
+ * vertices (Section 6), res_max[k] the max norm.  res_h / res_max may be
+ * NULL; when given they are host arrays of ncycles doubles and the call
+ * synchronises. */
+int mg_cycle(mg_ctx* ctx, int ncycles, double* res_h, double* res_max);
+
+/* Applies the pending update (pre-phase only), clears the helpers and, if
+ * u_out != NULL, copies the finest iterate into it. */
+int mg_flush(mg_ctx* ctx, mg_c128* u_out);
+
+/* Copies one level field into a device buffer of (3^level+1)^d complex128.
+ * Finest level: MG_FIELD_U returns the folded iterate u + sc (the finest
+ * smoothing update is applied eagerly, only the coarse correction is
+ * pending); MG_FIELD_SC/SF/SI return zeros.  Coarse levels with the GALERKIN
+ * form: MG_FIELD_B returns the restricted residual R r_(l+1) (= b_l - H_l u_l). */
+int mg_get_level(mg_ctx* ctx, int level, int field, mg_c128* out);
+
+/* z = B v: one additive cycle from a zero start with right-hand side v
+ * (restriction chain, damped Jacobi scaling per level, prolongation chain of
+ * the variant's corrections; no operator application survives u = 0). */
+int mg_precondition(mg_ctx* ctx, const mg_c128* v, mg_c128* z);
+
+/* Solves H u = b to relative residual rtol (|b - H u| / |b|, Euclidean over
+ * interior vertices).  u holds the initial guess on entry and the result on
+ * exit.  driver: MG_STATIONARY (cycles, then flush) or MG_BICGSTAB.  With
+ * MG_FP32_REFINE the inner corrections run in complex64 inside an FP64
+ * residual-refinement loop.  iters_out / relres_out may be NULL.  Returns
+ * MG_ENOTCONV or MG_EDIVERGED (u valid) when the target is missed.  Resets
+ * the cycle state. */
+int mg_solve(mg_ctx* ctx, const mg_c128* b, mg_c128* u, double rtol, int maxit,
+             int driver, int* iters_out, double* relres_out);
+
+/* res_h = |b - H u|_h (FP64). */
+int mg_residual_norm(mg_ctx* ctx, const mg_c128* u, const mg_c128* b, double* res_h);
+
+/* Gradient of J = sum_S |u|^2 with respect to a nodal potential V entering
+ * phi = phi0 - V (cell-averaged mass weight):
+ *   dJdV_j = -2 Re sum_{cells c containing j} 2^-d eta^d lam_c^H M u_c,
+ * u the forward solution, lam = H^-H (1_S u) the adjoint solution (both
+ * device complex128, zero boundary), dJdV a device array of n^d doubles
+ * (every vertex, boundary included). */
+int mg_grad_potential(mg_ctx* ctx, const mg_c128* u, const mg_c128* lam, double* dJdV);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H */

@@ -1,0 +1,146 @@
+// Internal declarations shared by the kernel and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mg {
+
+// Interleaved complex number; 16 B (double) or 8 B (float), naturally aligned
+// so that one vertex is one vector load.
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ inline cpx<T> mk(T a, T b) {
+  cpx<T> r;
+  r.re = a;
+  r.im = b;
+  return r;
+}
+
+// Per-level operator data, passed by value to kernels.
+//   H = alpha * S_K - etad * phi * S_M (constant phi: coef[] by neighbour class),
+//   or, for a nodal phi, stiffness alpha * S_K plus the cell-averaged mass.
+template <class T>
+struct OpData {
+  int n;                  // vertices per axis
+  cpx<T> coef[4];         // constant phi: stencil weight by number of nonzero offsets
+  cpx<T> alpha;           // eta^(d-2)
+  cpx<T> etad;            // eta^d
+  cpx<T> invD;            // constant phi: 1 / diag
+  const cpx<T>* phibar;   // nodal phi: per-cell averages ((n-1)^d), else nullptr
+  const cpx<T>* invDv;    // nodal phi: per-vertex 1 / diag (n^d), else nullptr
+};
+
+// Number of blocks of every kernel that writes reduction partials; the second
+// stage sums them in a fixed order, so reductions are deterministic.
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+// Launch wrappers (kernels live in mg_kernels.hip).  dim in {2,3}.
+template <class T>
+hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y, hipStream_t s);
+
+template <class T>
+hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
+                      const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s);
+
+template <class T>
+hipError_t launch_fine_pre(int dim, int n, const cpx<T>* w, cpx<T>* u, const cpx<T>* scc,
+                           const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s);
+
+template <class T>
+hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>* uhat, hipStream_t s);
+
+// r = b - H x; when partials != nullptr also writes per-block (sum |r|^2, max |r|).
+template <class T>
+hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
+                        double* partials, hipStream_t s);
+
+// s = omega r / D; sc = s or masked; finest: u += sc in place (sc_out == nullptr),
+// coarse: sc_out = sc.  Injection: sfc = sf + sc at c-points (if sfc), sic = s (if sic).
+template <class T>
+hipError_t launch_update(int dim, const OpData<T>& op, const cpx<T>* r, cpx<T> omega, int mask_c,
+                         cpx<T>* u_inplace, cpx<T>* sc_out, const cpx<T>* sf, cpx<T>* sfc, cpx<T>* sic,
+                         hipStream_t s);
+
+template <class T>
+hipError_t launch_restrict(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s);
+
+template <class T>
+hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s);
+
+// Zero-start cycle pieces: z_l = Lop(omega D^-1 rho_l) + P z_(l-1).
+template <class T>
+hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int variant,
+                          int is_lmin, const cpx<T>* zc, cpx<T>* z, hipStream_t s);
+
+template <class T>
+hipError_t launch_cellavg(int dim, int n, const cpx<T>* phi, cpx<T>* phibar, int conj, hipStream_t s);
+
+template <class T>
+hipError_t launch_invdiag(int dim, const OpData<T>& op, cpx<T>* invDv, hipStream_t s);
+
+template <class T>
+hipError_t launch_zero_boundary_copy(int dim, int n, const cpx<T>* in, cpx<T>* out, cpx<T> scale,
+                                     hipStream_t s);
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s);
+
+template <class S, class D>
+hipError_t launch_convert(size_t count, const cpx<S>* in, cpx<D>* out, double scale, hipStream_t s);
+
+// Vector ops for the Krylov driver (interior-only vectors: boundary entries 0).
+template <class T>
+hipError_t launch_dot(size_t count, const cpx<T>* a, const cpx<T>* b, double* partials, hipStream_t s);
+template <class T>
+hipError_t launch_norm2(size_t count, const cpx<T>* a, double* partials, hipStream_t s);
+// y = a*x + b*y  (complex scalars given in double)
+template <class T>
+hipError_t launch_axpby(size_t count, cpx<double> a, const cpx<T>* x, cpx<double> b, cpx<T>* y,
+                        hipStream_t s);
+// p = r + beta (p - w v)
+template <class T>
+hipError_t launch_bicg_p(size_t count, const cpx<T>* r, const cpx<T>* v, cpx<double> beta,
+                         cpx<double> w, cpx<T>* p, hipStream_t s);
+// x += a y + w z ; r = s - w t
+template <class T>
+hipError_t launch_bicg_xr(size_t count, cpx<T>* x, const cpx<T>* y, const cpx<T>* z, cpx<double> a,
+                          cpx<double> w, cpx<T>* r, const cpx<T>* sv, const cpx<T>* t, hipStream_t s);
+
+// Residual-refinement helpers: out64 += scale * in32 (in place FP64 accumulate).
+hipError_t launch_accum32(size_t count, const cpx<float>* e, double scale, cpx<double>* u, hipStream_t s);
+
+hipError_t launch_grad_potential(int dim, int n, cpx<double> etad, const cpx<double>* u,
+                                 const cpx<double>* lam, double* g, hipStream_t s);
+
+// Second reduction stage over `count` block partials [count][2], summed in
+// block order: out[0] = sum, out[1] = max (sum_max) or sum of the second
+// component (sum2).
+hipError_t launch_finish_sum_max(const double* partials, int count, double* out, hipStream_t s);
+hipError_t launch_finish_sum2(const double* partials, int count, double* out, hipStream_t s);
+
+// Fused finest-level sweep (GALERKIN form, constant phi); see mg_fused.hip.
+template <class T>
+struct FusedArgs {
+  int n, nc;
+  const cpx<T>* w;      // folded iterate in
+  cpx<T>* wout;         // folded iterate out
+  const cpx<T>* b;      // finest rhs
+  const cpx<T>* scc;    // coarse sc (after its pre-phase)
+  const cpx<T>* sic;    // coarse si (BPX) or nullptr
+  cpx<T>* rhoc;         // coarse b slot <- R r
+  cpx<T>* sfc;          // coarse sf <- I sc (ADD) or nullptr
+  cpx<T>* sic_out;      // coarse si <- I s (BPX) or nullptr
+  cpx<T> coef[4];
+  cpx<T> ws;            // omega * (1 / D)
+  double* partials;     // per-block (sum |r|^2, max |r|) or nullptr
+  int variant;          // 0 add, 1 hb, 2 bpx
+};
+template <class T>
+hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);
+int fused_partials_blocks(int dim, int n);
+
+}  // namespace mg

@@ -1,0 +1,836 @@
+// Generic level passes of the additive multilevel cycle: one thread per vertex,
+// neighbours gathered through the cache hierarchy.  They cover every case
+// (constant or nodal phi, FAS or Galerkin coarse right-hand sides, all levels);
+// the finest level of the constant-phi case has a fused single-pass kernel in
+// mg_fused.hip.
+//
+// Level l: n = 3^l + 1 vertices per axis, C order with x fastest.  Fields are
+// zero on boundary vertices; kernels keep them so.
+#include "mg_internal.h"
+
+namespace mg {
+
+template <class T>
+__device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class T>
+__device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class T>
+__device__ inline cpx<T> operator*(T s, cpx<T> a) { return mk(s * a.re, s * a.im); }
+template <class T>
+__device__ inline cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class T>
+__device__ inline cpx<T> cconjmul(cpx<T> a, cpx<T> b) {  // conj(a) * b
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <class T>
+__device__ inline cpx<T> czero() { return mk(T(0), T(0)); }
+
+template <int D>
+__device__ inline void unravel(long long i, int n, int j[3]) {
+  j[0] = (int)(i % n);
+  i /= n;
+  if (D == 3) {
+    j[1] = (int)(i % n);
+    j[2] = (int)(i / n);
+  } else {
+    j[1] = (int)i;
+    j[2] = 0;
+  }
+}
+
+template <int D>
+__device__ inline long long ravel(const int j[3], int n) {
+  return D == 3 ? ((long long)j[2] * n + j[1]) * n + j[0] : (long long)j[1] * n + j[0];
+}
+
+template <int D>
+__device__ inline bool is_interior(const int j[3], int n) {
+  for (int a = 0; a < D; ++a)
+    if (j[a] <= 0 || j[a] >= n - 1) return false;
+  return true;
+}
+
+template <int D>
+__device__ inline bool is_cpoint(const int j[3]) {
+  for (int a = 0; a < D; ++a)
+    if (j[a] % 3 != 0) return false;
+  return true;
+}
+
+template <int D>
+__device__ inline long long total(int n) {
+  return D == 3 ? (long long)n * n * n : (long long)n * n;
+}
+
+// (P v)_j: d-linear interpolation from the coarse level (nc per axis).  Per axis
+// a fine index j = 3m + q takes m with weight 1 (q = 0), or m and m+1 with
+// weights (2/3, 1/3) (q = 1) and (1/3, 2/3) (q = 2).
+template <class T, int D>
+__device__ cpx<T> prolong_at(const cpx<T>* __restrict__ vc, int nc, const int j[3]) {
+  const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
+  int m[3] = {0, 0, 0};
+  T w0[3] = {1, 1, 1}, w1[3] = {0, 0, 0};
+  bool two[3] = {false, false, false};
+  for (int a = 0; a < D; ++a) {
+    const int q = j[a] % 3;
+    m[a] = j[a] / 3;
+    if (q == 1) {
+      w0[a] = two3; w1[a] = third; two[a] = true;
+    } else if (q == 2) {
+      w0[a] = third; w1[a] = two3; two[a] = true;
+    }
+  }
+  cpx<T> acc = czero<T>();
+  for (int c = 0; c < (1 << D); ++c) {
+    T w = T(1);
+    int k[3] = {0, 0, 0};
+    bool use = true;
+    for (int a = 0; a < D; ++a) {
+      const int bit = (c >> a) & 1;
+      if (bit && !two[a]) { use = false; break; }
+      w *= bit ? w1[a] : w0[a];
+      k[a] = m[a] + bit;
+    }
+    if (use) acc = acc + w * vc[ravel<D>(k, nc)];
+  }
+  return acc;
+}
+
+// Constant-phi operator row at an interior vertex: the assembled 3^d stencil of
+// the d-linear element matrices has one weight per number of nonzero offsets
+// (centre, face, edge, corner).  Boundary neighbours count as zero.
+template <class T, int D>
+__device__ cpx<T> stencil_const(const cpx<T>* __restrict__ x, int n, const int j[3], const OpData<T>& op) {
+  cpx<T> s[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
+  const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
+  for (int oz = zlo; oz <= zhi; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
+        if (!is_interior<D>(k, n)) continue;
+        const int cls = (ox != 0) + (oy != 0) + (oz != 0);
+        s[cls] = s[cls] + x[ravel<D>(k, n)];
+      }
+  cpx<T> r = czero<T>();
+  for (int c = 0; c <= D; ++c) r = r + cmul(op.coef[c], s[c]);
+  return r;
+}
+
+// Stiffness-only stencil weights S_K by class (real), used with a nodal phi.
+template <class T, int D>
+__device__ inline T stiff_weight(int cls) {
+  if (D == 3) {
+    const T w[4] = {T(8.0 / 3.0), T(0), T(-1.0 / 6.0), T(-1.0 / 12.0)};
+    return w[cls];
+  } else {
+    const T w[3] = {T(8.0 / 3.0), T(-1.0 / 3.0), T(-1.0 / 3.0)};
+    return w[cls];
+  }
+}
+
+// Nodal-phi operator row: alpha * (S_K x)_j - etad * sum_{c contains j} phibar_c (M x_c)_loc(j),
+// with M_kk' = 3^-d 2^-(number of axes where k and k' differ).
+template <class T, int D>
+__device__ cpx<T> stencil_var(const cpx<T>* __restrict__ x, int n, const int j[3], const OpData<T>& op) {
+  cpx<T> st = czero<T>();
+  const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
+  for (int oz = zlo; oz <= zhi; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
+        if (!is_interior<D>(k, n)) continue;
+        const int cls = (ox != 0) + (oy != 0) + (oz != 0);
+        st = st + stiff_weight<T, D>(cls) * x[ravel<D>(k, n)];
+      }
+  const T m0 = D == 3 ? T(1.0 / 27.0) : T(1.0 / 9.0);
+  cpx<T> ms = czero<T>();
+  const int nc = n - 1;
+  for (int c = 0; c < (1 << D); ++c) {
+    int loc[3] = {0, 0, 0}, cell[3] = {0, 0, 0};
+    bool ok = true;
+    for (int a = 0; a < D; ++a) {
+      loc[a] = (c >> a) & 1;          // position of j inside the cell
+      cell[a] = j[a] - loc[a];
+      if (cell[a] < 0 || cell[a] >= nc) ok = false;
+    }
+    if (!ok) continue;
+    cpx<T> acc = czero<T>();
+    for (int kk = 0; kk < (1 << D); ++kk) {
+      int v[3] = {0, 0, 0};
+      T w = m0;
+      for (int a = 0; a < D; ++a) {
+        const int b = (kk >> a) & 1;
+        v[a] = cell[a] + b;
+        if (b != loc[a]) w *= T(0.5);
+      }
+      if (!is_interior<D>(v, n)) continue;
+      acc = acc + w * x[ravel<D>(v, n)];
+    }
+    ms = ms + cmul(op.phibar[ravel<D>(cell, nc)], acc);
+  }
+  return cmul(op.alpha, st) - cmul(op.etad, ms);
+}
+
+template <class T, int D>
+__device__ inline cpx<T> apply_row(const cpx<T>* x, int n, const int j[3], const OpData<T>& op) {
+  return op.phibar ? stencil_var<T, D>(x, n, j, op) : stencil_const<T, D>(x, n, j, op);
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of (sum, max) into partials[blockIdx.x][2].
+__device__ inline void block_sum_max(double s, double m, double* partials) {
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_down(s, off, 64);
+    m = fmax(m, __shfl_down(m, off, 64));
+  }
+  __shared__ double ss[16], sm[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { ss[wid] = s; sm[wid] = m; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) { a += ss[w]; b = fmax(b, sm[w]); }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__device__ inline void block_sum2(double s0, double s1, double* partials) {
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+  }
+  __shared__ double a0[16], a1[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { a0[wid] = s0; a1[wid] = s1; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0, y = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) { x += a0[w]; y += a1[w]; }
+    partials[2 * blockIdx.x] = x;
+    partials[2 * blockIdx.x + 1] = y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <class T, int D>
+__global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
+  const long long N = total<D>(op.n);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, op.n, j);
+    y[i] = is_interior<D>(j, op.n) ? apply_row<T, D>(x, op.n, j, op) : czero<T>();
+  }
+}
+
+// Coarse-level pre-phase (descent of tdAdd / tdBPX):
+//   sc += P sc_c ;  BPX: sc -= P si_c off c-points ;  u += sc + sf.
+template <class T, int D>
+__global__ void k_pre(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf,
+                      const cpx<T>* __restrict__ scc, const cpx<T>* __restrict__ sic, int has_coarse, int bpx) {
+  const long long N = total<D>(n);
+  const int nc = (n - 1) / 3 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    if (!is_interior<D>(j, n)) continue;
+    cpx<T> s = sc[i];
+    if (has_coarse) {
+      s = s + prolong_at<T, D>(scc, nc, j);
+      if (bpx && !is_cpoint<D>(j)) s = s - prolong_at<T, D>(sic, nc, j);
+      sc[i] = s;
+    }
+    u[i] = u[i] + s + sf[i];
+  }
+}
+
+// Finest-level pre-phase on the folded iterate w = u + sc:
+//   u = w + P sc_c (- P si_c off c-points for BPX), written to a second buffer.
+template <class T, int D>
+__global__ void k_fine_pre(int n, const cpx<T>* __restrict__ w, cpx<T>* __restrict__ u,
+                           const cpx<T>* __restrict__ scc, const cpx<T>* __restrict__ sic, int has_coarse,
+                           int bpx) {
+  const long long N = total<D>(n);
+  const int nc = (n - 1) / 3 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    if (!is_interior<D>(j, n)) { u[i] = czero<T>(); continue; }
+    cpx<T> v = w[i];
+    if (has_coarse) {
+      v = v + prolong_at<T, D>(scc, nc, j);
+      if (bpx && !is_cpoint<D>(j)) v = v - prolong_at<T, D>(sic, nc, j);
+    }
+    u[i] = v;
+  }
+}
+
+// Hierarchical surplus uhat = u - P u_c (eq. HTMG).
+template <class T, int D>
+__global__ void k_uhat(int n, const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ uc, cpx<T>* __restrict__ uh) {
+  const long long N = total<D>(n);
+  const int nc = (n - 1) / 3 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    uh[i] = is_interior<D>(j, n) ? u[i] - prolong_at<T, D>(uc, nc, j) : czero<T>();
+  }
+}
+
+// r = b - H x (interior), optional norm partials.
+template <class T, int D>
+__global__ void k_resid(OpData<T> op, const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ x,
+                        cpx<T>* __restrict__ r, double* partials) {
+  const long long N = total<D>(op.n);
+  double s2 = 0, mx = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, op.n, j);
+    cpx<T> v = czero<T>();
+    if (is_interior<D>(j, op.n)) {
+      v = b[i] - apply_row<T, D>(x, op.n, j, op);
+      const double a2 = (double)v.re * v.re + (double)v.im * v.im;
+      s2 += a2;
+      mx = fmax(mx, a2);
+    }
+    r[i] = v;
+  }
+  if (partials) block_sum_max(s2, sqrt(mx), partials);
+}
+
+// Post-phase pointwise part: s = omega r / D, sc = s (0 at c-points if mask_c),
+// finest: u += sc in place; coarse: sc_out = sc.  Injection to the coarser level
+// at c-points: sf_c = sf + sc, si_c = s.
+template <class T, int D>
+__global__ void k_update(OpData<T> op, const cpx<T>* __restrict__ r, cpx<T> omega, int mask_c,
+                         cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc_out, const cpx<T>* __restrict__ sf,
+                         cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
+  const int n = op.n;
+  const long long N = total<D>(n);
+  const int nc = (n - 1) / 3 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    const bool in = is_interior<D>(j, n);
+    cpx<T> s = czero<T>();
+    if (in) {
+      const cpx<T> id = op.invDv ? op.invDv[i] : op.invD;
+      s = cmul(omega, cmul(id, r[i]));
+    }
+    const bool cp = is_cpoint<D>(j);
+    const cpx<T> scv = (mask_c && cp) ? czero<T>() : s;
+    if (u) {
+      if (in) u[i] = u[i] + scv;
+    }
+    if (sc_out) sc_out[i] = scv;
+    if (cp && (sfc || sic)) {
+      int m[3] = {j[0] / 3, j[1] / 3, j[2] / 3};
+      const long long ic = ravel<D>(m, nc);
+      if (sfc) sfc[ic] = (sf ? sf[i] : czero<T>()) + scv;
+      if (sic) sic[ic] = s;
+    }
+  }
+}
+
+// R v = P^T v: per axis weights 1 - |o|/3 for fine offsets o in [-2, 2] around 3m;
+// zero on the coarse boundary.
+template <class T, int D>
+__global__ void k_restrict(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
+  const long long N = total<D>(nc);
+  const int nf = 3 * (nc - 1) + 1;
+  const T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int m[3];
+    unravel<D>(i, nc, m);
+    if (!is_interior<D>(m, nc)) { vc[i] = czero<T>(); continue; }
+    cpx<T> acc = czero<T>();
+    const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+      cpx<T> accy = czero<T>();
+      for (int oy = -2; oy <= 2; ++oy) {
+        cpx<T> accx = czero<T>();
+        for (int ox = -2; ox <= 2; ++ox) {
+          int j[3] = {3 * m[0] + ox, 3 * m[1] + oy, 3 * m[2] + oz};
+          accx = accx + w[ox + 2] * vf[ravel<D>(j, nf)];
+        }
+        accy = accy + w[oy + 2] * accx;
+      }
+      acc = acc + (D == 3 ? w[oz + 2] : T(1)) * accy;
+    }
+    vc[i] = acc;
+  }
+}
+
+template <class T, int D>
+__global__ void k_inject(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
+  const long long N = total<D>(nc);
+  const int nf = 3 * (nc - 1) + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int m[3];
+    unravel<D>(i, nc, m);
+    int j[3] = {3 * m[0], 3 * m[1], 3 * m[2]};
+    vc[i] = vf[ravel<D>(j, nf)];
+  }
+}
+
+// Zero-start cycle, upward part on one level:
+//   s = omega rho / D;  z = Lop(s) + P z_c, Lop = id (add), c-point mask (hb),
+//   s - P I s (BPX); on the coarsest level z = s.
+template <class T, int D>
+__global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int variant, int is_lmin,
+                          const cpx<T>* __restrict__ zc, cpx<T>* __restrict__ z) {
+  const int n = op.n;
+  const long long N = total<D>(n);
+  const int nc = (n - 1) / 3 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    if (!is_interior<D>(j, n)) { z[i] = czero<T>(); continue; }
+    const cpx<T> id = op.invDv ? op.invDv[i] : op.invD;
+    cpx<T> s = cmul(omega, cmul(id, rho[i]));
+    if (!is_lmin) {
+      if (variant == 1 && is_cpoint<D>(j)) s = czero<T>();
+      if (variant == 2) {
+        // (P I s)_j: interpolate the c-point values of s around j.
+        const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
+        int m[3] = {0, 0, 0};
+        T w0[3] = {1, 1, 1}, w1[3] = {0, 0, 0};
+        bool two[3] = {false, false, false};
+        for (int a = 0; a < D; ++a) {
+          const int q = j[a] % 3;
+          m[a] = j[a] / 3;
+          if (q == 1) { w0[a] = two3; w1[a] = third; two[a] = true; }
+          else if (q == 2) { w0[a] = third; w1[a] = two3; two[a] = true; }
+        }
+        cpx<T> pis = czero<T>();
+        for (int c = 0; c < (1 << D); ++c) {
+          T w = T(1);
+          int k[3] = {0, 0, 0};
+          bool use = true;
+          for (int a = 0; a < D; ++a) {
+            const int bit = (c >> a) & 1;
+            if (bit && !two[a]) { use = false; break; }
+            w *= bit ? w1[a] : w0[a];
+            k[a] = 3 * (m[a] + bit);
+          }
+          if (!use || !is_interior<D>(k, n)) continue;
+          const long long ik = ravel<D>(k, n);
+          const cpx<T> idk = op.invDv ? op.invDv[ik] : op.invD;
+          pis = pis + w * cmul(omega, cmul(idk, rho[ik]));
+        }
+        s = s - pis;
+      }
+      s = s + prolong_at<T, D>(zc, nc, j);
+    }
+    z[i] = s;
+  }
+}
+
+template <class T, int D>
+__global__ void k_cellavg(int n, const cpx<T>* __restrict__ phi, cpx<T>* __restrict__ phibar, int conj) {
+  const int nc = n - 1;
+  const long long N = total<D>(nc);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int c[3];
+    unravel<D>(i, nc, c);
+    cpx<T> acc = czero<T>();
+    for (int k = 0; k < (1 << D); ++k) {
+      int v[3] = {c[0] + (k & 1), c[1] + ((k >> 1) & 1), c[2] + ((k >> 2) & 1)};
+      acc = acc + phi[ravel<D>(v, n)];
+    }
+    acc = T(1.0 / (1 << D)) * acc;
+    if (conj) acc.im = -acc.im;
+    phibar[i] = acc;
+  }
+}
+
+// 1 / D_j with D_j = alpha 2d (2/3)^(d-1) - etad 3^-d sum_{c contains j} phibar_c.
+template <class T, int D>
+__global__ void k_invdiag(OpData<T> op, cpx<T>* __restrict__ invDv) {
+  const int n = op.n, nc = n - 1;
+  const long long N = total<D>(n);
+  const T kd = D == 3 ? T(6.0 * 4.0 / 9.0) : T(4.0 * 2.0 / 3.0);
+  const T m0 = D == 3 ? T(1.0 / 27.0) : T(1.0 / 9.0);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    if (!is_interior<D>(j, n)) { invDv[i] = mk(T(1), T(0)); continue; }
+    cpx<T> ps = czero<T>();
+    for (int k = 0; k < (1 << D); ++k) {
+      int c[3] = {j[0] - (k & 1), j[1] - ((k >> 1) & 1), j[2] - ((k >> 2) & 1)};
+      ps = ps + op.phibar[ravel<D>(c, nc)];
+    }
+    const cpx<T> d = kd * op.alpha - cmul(op.etad, m0 * ps);
+    // 1/d computed in double for both precisions
+    const double dr = d.re, di = d.im, den = dr * dr + di * di;
+    invDv[i] = mk(T(dr / den), T(-di / den));
+  }
+}
+
+template <class T, int D>
+__global__ void k_zero_boundary_copy(int n, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, cpx<T> scale) {
+  const long long N = total<D>(n);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    out[i] = is_interior<D>(j, n) ? cmul(scale, in[i]) : czero<T>();
+  }
+}
+
+__global__ void k_fill(unsigned int* p, size_t words) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+template <class S, class Dt>
+__global__ void k_convert(size_t count, const cpx<S>* __restrict__ in, cpx<Dt>* __restrict__ out, double scale) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<S> v = in[i];
+    out[i] = mk(Dt((double)v.re * scale), Dt((double)v.im * scale));
+  }
+}
+
+template <class T>
+__global__ void k_dot(size_t count, const cpx<T>* __restrict__ a, const cpx<T>* __restrict__ b, double* partials) {
+  double sr = 0, si = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> x = a[i], y = b[i];
+    sr += (double)x.re * y.re + (double)x.im * y.im;
+    si += (double)x.re * y.im - (double)x.im * y.re;
+  }
+  block_sum2(sr, si, partials);
+}
+
+template <class T>
+__global__ void k_norm2(size_t count, const cpx<T>* __restrict__ a, double* partials) {
+  double s = 0, m = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> x = a[i];
+    const double v = (double)x.re * x.re + (double)x.im * x.im;
+    s += v;
+    m = fmax(m, v);
+  }
+  block_sum_max(s, sqrt(m), partials);
+}
+
+template <class T>
+__global__ void k_axpby(size_t count, cpx<double> a, const cpx<T>* __restrict__ x, cpx<double> b, cpx<T>* __restrict__ y) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> xv = x[i], yv = y[i];
+    const double re = a.re * xv.re - a.im * xv.im + b.re * yv.re - b.im * yv.im;
+    const double im = a.re * xv.im + a.im * xv.re + b.re * yv.im + b.im * yv.re;
+    y[i] = mk(T(re), T(im));
+  }
+}
+
+template <class T>
+__global__ void k_bicg_p(size_t count, const cpx<T>* __restrict__ r, const cpx<T>* __restrict__ v, cpx<double> beta,
+                         cpx<double> w, cpx<T>* __restrict__ p) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> pv = p[i], vv = v[i], rv = r[i];
+    const double tr = pv.re - (w.re * vv.re - w.im * vv.im);
+    const double ti = pv.im - (w.re * vv.im + w.im * vv.re);
+    p[i] = mk(T(rv.re + beta.re * tr - beta.im * ti), T(rv.im + beta.re * ti + beta.im * tr));
+  }
+}
+
+template <class T>
+__global__ void k_bicg_xr(size_t count, cpx<T>* __restrict__ x, const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ z,
+                          cpx<double> a, cpx<double> w, cpx<T>* __restrict__ r, const cpx<T>* __restrict__ sv,
+                          const cpx<T>* __restrict__ t) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> xv = x[i], yv = y[i], zv = z[i], s = sv[i], tv = t[i];
+    x[i] = mk(T(xv.re + a.re * yv.re - a.im * yv.im + w.re * zv.re - w.im * zv.im),
+              T(xv.im + a.re * yv.im + a.im * yv.re + w.re * zv.im + w.im * zv.re));
+    r[i] = mk(T(s.re - (w.re * tv.re - w.im * tv.im)), T(s.im - (w.re * tv.im + w.im * tv.re)));
+  }
+}
+
+__global__ void k_accum32(size_t count, const cpx<float>* __restrict__ e, double scale, cpx<double>* __restrict__ u) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<float> ev = e[i];
+    const cpx<double> uv = u[i];
+    u[i] = mk(uv.re + scale * (double)ev.re, uv.im + scale * (double)ev.im);
+  }
+}
+
+// dJ/dV_j = -2 Re sum_{c contains j} 2^-d eta^d lam_c^H M u_c.
+template <int D>
+__global__ void k_grad_potential(int n, cpx<double> etad, const cpx<double>* __restrict__ u,
+                                 const cpx<double>* __restrict__ lam, double* __restrict__ g) {
+  const long long N = total<D>(n);
+  const int nc = n - 1;
+  const double m0 = D == 3 ? 1.0 / 27.0 : 1.0 / 9.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    unravel<D>(i, n, j);
+    double acc = 0;
+    for (int c = 0; c < (1 << D); ++c) {
+      int cell[3] = {0, 0, 0};
+      bool ok = true;
+      for (int a = 0; a < D; ++a) {
+        cell[a] = j[a] - ((c >> a) & 1);
+        if (cell[a] < 0 || cell[a] >= nc) ok = false;
+      }
+      if (!ok) continue;
+      // lam_c^H M u_c
+      cpx<double> cv = mk(0.0, 0.0);
+      for (int k = 0; k < (1 << D); ++k) {
+        int vk[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) vk[a] = cell[a] + ((k >> a) & 1);
+        const cpx<double> lk = lam[ravel<D>(vk, n)];
+        cpx<double> mu = mk(0.0, 0.0);
+        for (int kk = 0; kk < (1 << D); ++kk) {
+          int vv[3] = {0, 0, 0};
+          double w = m0;
+          for (int a = 0; a < D; ++a) {
+            const int b = (kk >> a) & 1;
+            vv[a] = cell[a] + b;
+            if (b != ((k >> a) & 1)) w *= 0.5;
+          }
+          mu = mu + w * u[ravel<D>(vv, n)];
+        }
+        cv = cv + cconjmul(lk, mu);
+      }
+      acc += cmul(etad, cv).re;
+    }
+    g[i] = -2.0 * acc / (1 << D);
+  }
+}
+
+__global__ void k_finish_sum_max(const double* __restrict__ partials, int count, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0, m = 0;
+    for (int i = 0; i < count; ++i) {
+      s += partials[2 * i];
+      m = fmax(m, partials[2 * i + 1]);
+    }
+    out[0] = s;
+    out[1] = m;
+  }
+}
+
+__global__ void k_finish_sum2(const double* __restrict__ partials, int count, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0, t = 0;
+    for (int i = 0; i < count; ++i) {
+      s += partials[2 * i];
+      t += partials[2 * i + 1];
+    }
+    out[0] = s;
+    out[1] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers.
+static inline int grid_for(long long N, int threads = 256) {
+  long long g = (N + threads - 1) / threads;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+#define MG_DISPATCH(dim, KERNEL, GRID, ...)                                         \
+  do {                                                                              \
+    if ((dim) == 3) hipLaunchKernelGGL((KERNEL<T, 3>), GRID, 256, 0, s, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KERNEL<T, 2>), GRID, 256, 0, s, __VA_ARGS__);            \
+  } while (0)
+
+static inline long long pow_n(int n, int dim) { return dim == 3 ? (long long)n * n * n : (long long)n * n; }
+
+template <class T>
+hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y, hipStream_t s) {
+  MG_DISPATCH(dim, k_apply, dim3(grid_for(pow_n(op.n, dim))), op, x, y);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
+                      const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s) {
+  MG_DISPATCH(dim, k_pre, dim3(grid_for(pow_n(n, dim))), n, u, sc, sf, scc, sic, has_coarse, bpx);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fine_pre(int dim, int n, const cpx<T>* w, cpx<T>* u, const cpx<T>* scc, const cpx<T>* sic,
+                           int has_coarse, int bpx, hipStream_t s) {
+  MG_DISPATCH(dim, k_fine_pre, dim3(grid_for(pow_n(n, dim))), n, w, u, scc, sic, has_coarse, bpx);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>* uh, hipStream_t s) {
+  MG_DISPATCH(dim, k_uhat, dim3(grid_for(pow_n(n, dim))), n, u, uc, uh);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
+                        double* partials, hipStream_t s) {
+  const int g = partials ? kRedBlocks : grid_for(pow_n(op.n, dim));
+  MG_DISPATCH(dim, k_resid, dim3(g), op, b, x, r, partials);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_update(int dim, const OpData<T>& op, const cpx<T>* r, cpx<T> omega, int mask_c, cpx<T>* u,
+                         cpx<T>* sc_out, const cpx<T>* sf, cpx<T>* sfc, cpx<T>* sic, hipStream_t s) {
+  MG_DISPATCH(dim, k_update, dim3(grid_for(pow_n(op.n, dim))), op, r, omega, mask_c, u, sc_out, sf, sfc, sic);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_restrict(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s) {
+  MG_DISPATCH(dim, k_restrict, dim3(grid_for(pow_n(nc, dim))), nc, vf, vc);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s) {
+  MG_DISPATCH(dim, k_inject, dim3(grid_for(pow_n(nc, dim))), nc, vf, vc);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int variant, int is_lmin,
+                          const cpx<T>* zc, cpx<T>* z, hipStream_t s) {
+  MG_DISPATCH(dim, k_prec_up, dim3(grid_for(pow_n(op.n, dim))), op, rho, omega, variant, is_lmin, zc, z);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_cellavg(int dim, int n, const cpx<T>* phi, cpx<T>* phibar, int conj, hipStream_t s) {
+  MG_DISPATCH(dim, k_cellavg, dim3(grid_for(pow_n(n - 1, dim))), n, phi, phibar, conj);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_invdiag(int dim, const OpData<T>& op, cpx<T>* invDv, hipStream_t s) {
+  MG_DISPATCH(dim, k_invdiag, dim3(grid_for(pow_n(op.n, dim))), op, invDv);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_zero_boundary_copy(int dim, int n, const cpx<T>* in, cpx<T>* out, cpx<T> scale, hipStream_t s) {
+  MG_DISPATCH(dim, k_zero_boundary_copy, dim3(grid_for(pow_n(n, dim))), n, in, out, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for((long long)words)), 256, 0, s, (unsigned int*)p, words);
+  return hipGetLastError();
+}
+
+template <class S, class Dt>
+hipError_t launch_convert(size_t count, const cpx<S>* in, cpx<Dt>* out, double scale, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<S, Dt>), dim3(grid_for((long long)count)), 256, 0, s, count, in, out, scale);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_dot(size_t count, const cpx<T>* a, const cpx<T>* b, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), kRedThreads, 0, s, count, a, b, partials);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_norm2(size_t count, const cpx<T>* a, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2<T>, dim3(kRedBlocks), kRedThreads, 0, s, count, a, partials);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_axpby(size_t count, cpx<double> a, const cpx<T>* x, cpx<double> b, cpx<T>* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for((long long)count)), 256, 0, s, count, a, x, b, y);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bicg_p(size_t count, const cpx<T>* r, const cpx<T>* v, cpx<double> beta, cpx<double> w,
+                         cpx<T>* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_p<T>, dim3(grid_for((long long)count)), 256, 0, s, count, r, v, beta, w, p);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bicg_xr(size_t count, cpx<T>* x, const cpx<T>* y, const cpx<T>* z, cpx<double> a, cpx<double> w,
+                          cpx<T>* r, const cpx<T>* sv, const cpx<T>* t, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_xr<T>, dim3(grid_for((long long)count)), 256, 0, s, count, x, y, z, a, w, r, sv, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum32(size_t count, const cpx<float>* e, double scale, cpx<double>* u, hipStream_t s) {
+  hipLaunchKernelGGL(k_accum32, dim3(grid_for((long long)count)), 256, 0, s, count, e, scale, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_potential(int dim, int n, cpx<double> etad, const cpx<double>* u, const cpx<double>* lam,
+                                 double* g, hipStream_t s) {
+  const int grid = grid_for(pow_n(n, dim));
+  if (dim == 3) hipLaunchKernelGGL(k_grad_potential<3>, dim3(grid), 256, 0, s, n, etad, u, lam, g);
+  else hipLaunchKernelGGL(k_grad_potential<2>, dim3(grid), 256, 0, s, n, etad, u, lam, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_sum_max(const double* partials, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_sum_max, dim3(1), 64, 0, s, partials, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_sum2(const double* partials, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_sum2, dim3(1), 64, 0, s, partials, count, out);
+  return hipGetLastError();
+}
+
+#define MG_INSTANTIATE(T)                                                                                        \
+  template hipError_t launch_apply<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>*, hipStream_t);              \
+  template hipError_t launch_pre<T>(int, int, cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*, int, \
+                                    int, hipStream_t);                                                          \
+  template hipError_t launch_fine_pre<T>(int, int, const cpx<T>*, cpx<T>*, const cpx<T>*, const cpx<T>*, int, int, \
+                                         hipStream_t);                                                          \
+  template hipError_t launch_uhat<T>(int, int, const cpx<T>*, const cpx<T>*, cpx<T>*, hipStream_t);             \
+  template hipError_t launch_resid<T>(int, const OpData<T>&, const cpx<T>*, const cpx<T>*, cpx<T>*, double*,     \
+                                      hipStream_t);                                                             \
+  template hipError_t launch_update<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, cpx<T>*, cpx<T>*,      \
+                                       const cpx<T>*, cpx<T>*, cpx<T>*, hipStream_t);                            \
+  template hipError_t launch_restrict<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                        \
+  template hipError_t launch_inject<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                          \
+  template hipError_t launch_prec_up<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, int, const cpx<T>*,   \
+                                        cpx<T>*, hipStream_t);                                                  \
+  template hipError_t launch_cellavg<T>(int, int, const cpx<T>*, cpx<T>*, int, hipStream_t);                    \
+  template hipError_t launch_invdiag<T>(int, const OpData<T>&, cpx<T>*, hipStream_t);                           \
+  template hipError_t launch_zero_boundary_copy<T>(int, int, const cpx<T>*, cpx<T>*, cpx<T>, hipStream_t);      \
+  template hipError_t launch_dot<T>(size_t, const cpx<T>*, const cpx<T>*, double*, hipStream_t);                \
+  template hipError_t launch_norm2<T>(size_t, const cpx<T>*, double*, hipStream_t);                             \
+  template hipError_t launch_axpby<T>(size_t, cpx<double>, const cpx<T>*, cpx<double>, cpx<T>*, hipStream_t);   \
+  template hipError_t launch_bicg_p<T>(size_t, const cpx<T>*, const cpx<T>*, cpx<double>, cpx<double>, cpx<T>*, \
+                                       hipStream_t);                                                            \
+  template hipError_t launch_bicg_xr<T>(size_t, cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<double>, cpx<double>, \
+                                        cpx<T>*, const cpx<T>*, const cpx<T>*, hipStream_t);
+
+MG_INSTANTIATE(double)
+MG_INSTANTIATE(float)
+template hipError_t launch_convert<double, float>(size_t, const cpx<double>*, cpx<float>*, double, hipStream_t);
+template hipError_t launch_convert<float, double>(size_t, const cpx<float>*, cpx<double>*, double, hipStream_t);
+template hipError_t launch_convert<double, double>(size_t, const cpx<double>*, cpx<double>*, double, hipStream_t);
+
+}  // namespace mg

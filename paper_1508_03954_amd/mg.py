@@ -1,0 +1,235 @@
+"""Python binding of the C ABI in include/mg.h (ctypes; argument marshalling only).
+
+Every numerical step runs in the HIP library libmg.so next to this file.  If
+the library is missing the binding raises: there is no CPU fallback.  torch
+supplies device memory (complex128 CUDA tensors) and the stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmg.so")
+
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ENOTCONV, MG_EDIVERGED = 0, -1, -2, -3, -4, -5
+VARIANTS = {"add": 0, "hb": 1, "bpx": 2}
+OMEGA_SCHEMES = {"const": 0, "jacobi": 1, "lgrid": 2, "exp": 3, "transition": 4}
+PRECISIONS = {"fp64": 0, "fp32_refine": 1}
+DRIVERS = {"stationary": 0, "bicgstab": 1}
+RESTRICT_FORMS = {"auto": 0, "fas": 1, "galerkin": 2}
+SWEEPS = {"auto": 0, "generic": 1, "fused": 2}
+FIELDS = {"u": 0, "b": 1, "sc": 2, "sf": 3, "si": 4}
+
+EXPORTED = [
+    "mg_params_default", "mg_setup", "mg_destroy", "mg_last_error", "mg_level_size", "mg_apply",
+    "mg_rhs_from_nodal", "mg_set_rhs", "mg_set_solution", "mg_cycle", "mg_flush", "mg_get_level",
+    "mg_precondition", "mg_solve", "mg_residual_norm", "mg_grad_potential",
+]
+
+
+class MGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mg error {code}: {msg}")
+        self.code = code
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("level_min", ctypes.c_int), ("level_max", ctypes.c_int),
+        ("theta", ctypes.c_double), ("phi", c128), ("phi_field", ctypes.c_void_p),
+        ("variant", ctypes.c_int), ("omega_scheme", ctypes.c_int), ("omega", c128),
+        ("omega_L", ctypes.c_int), ("precision", ctypes.c_int), ("conjugate", ctypes.c_int),
+        ("restrict_form", ctypes.c_int), ("sweep", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run `python -m paper_1508_03954_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    lib.mg_params_default.argtypes = [ctypes.POINTER(Params)]
+    lib.mg_params_default.restype = None
+    lib.mg_setup.argtypes = [ctypes.POINTER(Params), P, ctypes.POINTER(P)]
+    lib.mg_destroy.argtypes = [P]
+    lib.mg_destroy.restype = None
+    lib.mg_last_error.restype = ctypes.c_char_p
+    lib.mg_level_size.argtypes = [P, I]
+    lib.mg_apply.argtypes = [P, P, P]
+    lib.mg_rhs_from_nodal.argtypes = [P, P, P]
+    lib.mg_set_rhs.argtypes = [P, P]
+    lib.mg_set_solution.argtypes = [P, P]
+    lib.mg_cycle.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.mg_flush.argtypes = [P, P]
+    lib.mg_get_level.argtypes = [P, I, I, P]
+    lib.mg_precondition.argtypes = [P, P, P]
+    lib.mg_solve.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.mg_residual_norm.argtypes = [P, P, P, ctypes.POINTER(D)]
+    lib.mg_grad_potential.argtypes = [P, P, P, P]
+    for name in EXPORTED:
+        if name not in ("mg_params_default", "mg_destroy", "mg_last_error"):
+            getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow=()) -> int:
+    if rc != MG_OK and rc not in allow:
+        raise MGError(rc, load_library().mg_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class Solver:
+    """One complex additive multilevel hierarchy on the unit hypercube."""
+
+    def __init__(self, dim: int, level_max: int, level_min: int = 1, theta: float = 0.0,
+                 phi: complex = 0.0, phi_field=None, variant: str = "bpx", omega_scheme: str = "const",
+                 omega: complex = 0.6, omega_L: int = 1, precision: str = "fp64", conjugate: bool = False,
+                 restrict_form: str = "auto", sweep: str = "auto", stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        p = Params()
+        lib.mg_params_default(ctypes.byref(p))
+        p.dim, p.level_min, p.level_max = dim, level_min, level_max
+        p.theta = theta
+        p.phi = c128(complex(phi).real, complex(phi).imag)
+        self._phi_keep = None
+        if phi_field is not None:
+            phi_field = phi_field.to(device="cuda", dtype=torch.complex128).contiguous()
+            self._phi_keep = phi_field
+            p.phi_field = _ptr(phi_field)
+        p.variant = VARIANTS[variant]
+        p.omega_scheme = OMEGA_SCHEMES[omega_scheme]
+        p.omega = c128(complex(omega).real, complex(omega).imag)
+        p.omega_L = omega_L
+        p.precision = PRECISIONS[precision]
+        p.conjugate = 1 if conjugate else 0
+        p.restrict_form = RESTRICT_FORMS[restrict_form]
+        p.sweep = SWEEPS[sweep]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        ctx = ctypes.c_void_p()
+        _check(lib.mg_setup(ctypes.byref(p), self.stream.cuda_stream, ctypes.byref(ctx)))
+        self._ctx = ctx
+        self._lib = lib
+        self.dim, self.level_min, self.level_max = dim, level_min, level_max
+        self.n = 3 ** level_max + 1
+        self.shape = (self.n,) * dim
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.mg_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, shape=None, dtype=None):
+        t = self._torch
+        return t.zeros(shape or self.shape, dtype=dtype or t.complex128, device="cuda")
+
+    def _as_dev(self, x):
+        t = self._torch
+        if not isinstance(x, t.Tensor):
+            x = t.from_numpy(np.ascontiguousarray(x))
+        x = x.to(device="cuda", dtype=t.complex128).contiguous()
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"expected shape {self.shape}, got {tuple(x.shape)}")
+        return x
+
+    def level_size(self, level: int) -> int:
+        return _check(self._lib.mg_level_size(self._ctx, level), allow=range(1, 1 << 30))
+
+    def apply(self, x, out=None):
+        x = self._as_dev(x)
+        y = self._new() if out is None else out
+        _check(self._lib.mg_apply(self._ctx, _ptr(x), _ptr(y)))
+        return y
+
+    def rhs_from_nodal(self, chi):
+        chi = self._as_dev(chi)
+        b = self._new()
+        _check(self._lib.mg_rhs_from_nodal(self._ctx, _ptr(chi), _ptr(b)))
+        return b
+
+    def set_rhs(self, b):
+        b = self._as_dev(b)
+        _check(self._lib.mg_set_rhs(self._ctx, _ptr(b)))
+
+    def set_solution(self, u):
+        u = self._as_dev(u)
+        _check(self._lib.mg_set_solution(self._ctx, _ptr(u)))
+
+    def cycle(self, ncycles: int = 1, norms: bool = True):
+        if not norms:
+            _check(self._lib.mg_cycle(self._ctx, ncycles, None, None))
+            return None
+        rh = (ctypes.c_double * ncycles)()
+        rm = (ctypes.c_double * ncycles)()
+        _check(self._lib.mg_cycle(self._ctx, ncycles, rh, rm))
+        return np.array(rh[:]), np.array(rm[:])
+
+    def flush(self):
+        u = self._new()
+        _check(self._lib.mg_flush(self._ctx, _ptr(u)))
+        return u
+
+    def get_level(self, level: int, field: str):
+        n = 3 ** level + 1
+        out = self._new((n,) * self.dim)
+        _check(self._lib.mg_get_level(self._ctx, level, FIELDS[field], _ptr(out)))
+        return out
+
+    def precondition(self, v):
+        v = self._as_dev(v)
+        z = self._new()
+        _check(self._lib.mg_precondition(self._ctx, _ptr(v), _ptr(z)))
+        return z
+
+    def solve(self, b, u0=None, rtol: float = 1e-10, maxit: int = 500, driver: str = "bicgstab"):
+        """Returns (u, iterations, relative residual, status code)."""
+        b = self._as_dev(b)
+        u = self._new() if u0 is None else self._as_dev(u0).clone()
+        its = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        rc = self._lib.mg_solve(self._ctx, _ptr(b), _ptr(u), rtol, maxit, DRIVERS[driver],
+                                ctypes.byref(its), ctypes.byref(rel))
+        _check(rc, allow=(MG_ENOTCONV, MG_EDIVERGED))
+        return u, its.value, rel.value, rc
+
+    def residual_norm(self, u, b) -> float:
+        u, b = self._as_dev(u), self._as_dev(b)
+        out = ctypes.c_double(0.0)
+        _check(self._lib.mg_residual_norm(self._ctx, _ptr(u), _ptr(b), ctypes.byref(out)))
+        return out.value
+
+    def grad_potential(self, u, lam):
+        u, lam = self._as_dev(u), self._as_dev(lam)
+        g = self._new(dtype=self._torch.float64)
+        _check(self._lib.mg_grad_potential(self._ctx, _ptr(u), _ptr(lam), _ptr(g)))
+        return g

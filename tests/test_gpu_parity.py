@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Every comparison is element by element on seeded inputs; the FP64 bar is
+relative 2-norm error <= 1e-12 (the summation order differs between the two
+sides, nothing else).  Sizes span several thread blocks and the fused sweep's
+tiles with ragged tails.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.cycle import Params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_03954_amd import mg
+    mg.load_library()
+
+
+def mgmod():
+    from paper_1508_03954_amd import mg
+    return mg
+
+
+def to_np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(got, ref):
+    den = np.linalg.norm(ref)
+    return np.linalg.norm(got - ref) / (den if den > 0 else 1.0)
+
+
+def rand_c(shape, seed, zero_bnd=True):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    return O.zero_boundary(v) if zero_bnd else v
+
+
+def nodal_phi(dim, L, seed):
+    rng = np.random.default_rng(seed)
+    n = 3 ** L + 1
+    return (120 + 80 * rng.standard_normal((n,) * dim)) * (1 + 0.3j)
+
+
+APPLY_CASES = [(2, 3), (2, 5), (3, 2), (3, 3), (3, 4)]
+
+
+@pytest.mark.parametrize("dim,L", APPLY_CASES)
+@pytest.mark.parametrize("phi_case", ["const", "varying"])
+@pytest.mark.parametrize("conj", [False, True])
+def test_apply_matches_oracle(dim, L, phi_case, conj):
+    print(f"\n[case] apply dim={dim} L={L} phi={phi_case} conj={conj}", flush=True)
+    mg = mgmod()
+    theta, phi = 0.37, 150 * (1 + 0.4j)
+    pn = nodal_phi(dim, L, 11) if phi_case == "varying" else None
+    s = mg.Solver(dim, L, theta=theta, phi=phi, conjugate=conj,
+                  phi_field=None if pn is None else torch.from_numpy(pn))
+    x = rand_c((3 ** L + 1,) * dim, 5, zero_bnd=False)       # boundary entries must be ignored
+    y = to_np(s.apply(x))
+    ref = O.apply_H(x, L, theta, phi if pn is None else pn, conjugate=conj)
+    assert relerr(y, ref) <= TOL
+
+
+def test_rhs_from_nodal():
+    mg = mgmod()
+    dim, L, theta = 3, 3, math.pi / 6
+    s = mg.Solver(dim, L, theta=theta, phi=400.0)
+    chi = rand_c((3 ** L + 1,) * dim, 3, zero_bnd=False)
+    b = to_np(s.rhs_from_nodal(chi))
+    assert relerr(b, O.lumped_rhs(chi, L, theta)) <= 1e-15
+
+
+def level_ref(pipe, p, lev, field, galerkin):
+    """Oracle counterpart of a GPU level field.  The finest level stores the
+    folded iterate u + sc; with the Galerkin form a coarse b slot holds the
+    restricted residual b_l - H_l u_l."""
+    L = p.level_max
+    if lev == L:
+        if field == "u":
+            return pipe.u[L] + pipe.sc[L]
+        if field == "b":
+            return pipe.b[L]
+        return np.zeros_like(pipe.u[L])
+    if field == "b" and galerkin:
+        return O.zero_boundary(pipe.b[lev] - p.H(pipe.u[lev], lev))
+    return getattr(pipe, field)[lev]
+
+
+CYCLE_CASES = [
+    # dim, L, lmin, variant, restrict, sweep, phi_case, scheme
+    (2, 4, 1, "add", "galerkin", "generic", "const", "const"),
+    (2, 4, 1, "hb", "galerkin", "generic", "const", "exp"),
+    (2, 4, 1, "bpx", "galerkin", "generic", "const", "const"),
+    (2, 4, 2, "bpx", "fas", "generic", "const", "transition"),
+    (2, 4, 1, "add", "fas", "generic", "varying", "const"),
+    (2, 4, 1, "bpx", "fas", "generic", "varying", "exp"),
+    (3, 3, 1, "add", "galerkin", "generic", "const", "const"),
+    (3, 3, 1, "hb", "fas", "generic", "const", "const"),
+    (3, 3, 1, "bpx", "galerkin", "generic", "const", "const"),
+    (3, 3, 1, "bpx", "fas", "generic", "varying", "const"),
+    (3, 3, 3, "bpx", "galerkin", "generic", "const", "const"),
+    # fused finest sweep: grids of several tiles with ragged tails in every axis
+    (2, 4, 1, "add", "galerkin", "fused", "const", "const"),
+    (2, 5, 1, "hb", "galerkin", "fused", "const", "exp"),
+    (2, 5, 2, "bpx", "galerkin", "fused", "const", "const"),
+    (3, 3, 1, "add", "galerkin", "fused", "const", "const"),
+    (3, 3, 1, "hb", "galerkin", "fused", "const", "transition"),
+    (3, 3, 2, "bpx", "galerkin", "fused", "const", "const"),
+    (3, 4, 1, "bpx", "galerkin", "fused", "const", "const"),
+    (3, 4, 1, "add", "galerkin", "fused", "const", "exp"),
+    (3, 2, 1, "bpx", "galerkin", "fused", "const", "const"),
+]
+
+
+def run_cycle_parity(dim, L, lmin, variant, restrict, sweep, phi_case, scheme, ncycles=3, tol=TOL):
+    mg = mgmod()
+    theta, phi = 0.4, 90 * (1 + 0.5j)
+    n = 3 ** L + 1
+    pn = nodal_phi(dim, L, 7) if phi_case == "varying" else None
+    p = Params(dim=dim, level_max=L, level_min=lmin, theta=theta, phi=phi, phi_nodal=pn,
+               variant=variant, omega_scheme=scheme, omega=0.6)
+    b = rand_c((n,) * dim, 1)
+    u0 = rand_c((n,) * dim, 2)
+    s = mg.Solver(dim, L, level_min=lmin, theta=theta, phi=phi, variant=variant, omega_scheme=scheme,
+                  omega=0.6, restrict_form=restrict, sweep=sweep,
+                  phi_field=None if pn is None else torch.from_numpy(pn))
+    s.set_rhs(b)
+    s.set_solution(u0)
+    pipe = O.Pipelined(p, b, u0)
+    galerkin = restrict == "galerkin"
+    for k in range(ncycles):
+        rh_ref, rm_ref = pipe.cycle()
+        rh, rm = s.cycle(1)
+        assert abs(rh[0] - rh_ref) <= tol * rh_ref, (k, rh[0], rh_ref)
+        assert abs(rm[0] - rm_ref) <= tol * rm_ref
+        for lev in range(lmin, L + 1):
+            for field in ("u", "b", "sc", "sf", "si"):
+                got = to_np(s.get_level(lev, field))
+                ref = level_ref(pipe, p, lev, field, galerkin)
+                if not np.any(ref):
+                    assert not np.any(got), (k, lev, field)
+                    continue
+                scale = np.linalg.norm(ref)
+                if field == "b" and galerkin and lev < L:
+                    # restricted residual of a FAS state: compare at the scale of b_l
+                    scale = max(scale, np.linalg.norm(pipe.b[lev]))
+                err = np.linalg.norm(got - ref) / scale
+                assert err <= tol, (k, lev, field, err)
+    u_ref = pipe.flush()
+    u = to_np(s.flush())
+    assert relerr(u, u_ref) <= tol
+
+
+@pytest.mark.parametrize("case", CYCLE_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_cycle_state_matches_pipelined_oracle(case):
+    print(f"\n[case] cycle {case}", flush=True)
+    run_cycle_parity(*case)
+
+
+@pytest.mark.parametrize("dim,L,variant", [(2, 4, "bpx"), (3, 3, "hb"), (3, 3, "add")])
+@pytest.mark.parametrize("phi_case", ["const", "varying"])
+def test_precondition_matches_zero_start_cycle(dim, L, variant, phi_case):
+    print(f"\n[case] precondition dim={dim} L={L} {variant} {phi_case}", flush=True)
+    mg = mgmod()
+    theta, phi = 0.3, 200.0
+    pn = nodal_phi(dim, L, 3) if phi_case == "varying" else None
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi, phi_nodal=pn, variant=variant,
+               omega_scheme="exp", omega=0.7)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant=variant, omega_scheme="exp", omega=0.7,
+                  phi_field=None if pn is None else torch.from_numpy(pn))
+    v = rand_c((3 ** L + 1,) * dim, 9, zero_bnd=False)
+    z = to_np(s.precondition(v))
+    ref = O.zero_start_cycle(p, O.zero_boundary(v))
+    assert relerr(z, ref) <= TOL
+
+
+@pytest.mark.parametrize("dim,L", [(2, 3), (3, 2)])
+def test_bicgstab_reaches_dense_solution(dim, L):
+    mg = mgmod()
+    theta, phi = math.pi / 6, 400.0
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi, variant="bpx")
+    b = rand_c((3 ** L + 1,) * dim, 4)
+    ref = O.dense_solve(p, b)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant="bpx")
+    u, its, rel, rc = s.solve(b, rtol=1e-12, maxit=300, driver="bicgstab")
+    assert rc == 0 and rel <= 1e-12
+    assert relerr(to_np(u), ref) <= 1e-9
+
+
+def test_stationary_solve_poisson():
+    mg = mgmod()
+    from paper_1508_03954_amd.inputs import sine_load
+    dim, L = 2, 4
+    p = Params(dim=dim, level_max=L, theta=0.0, phi=0.0, variant="add", omega_scheme="exp", omega=0.6)
+    b = O.lumped_rhs(sine_load(L, dim), L, 0.0)
+    s = mg.Solver(dim, L, theta=0.0, phi=0.0, variant="add", omega_scheme="exp", omega=0.6)
+    u, its, rel, rc = s.solve(b, rtol=1e-8, maxit=400, driver="stationary")
+    assert rc == 0 and rel <= 1e-8
+    ref, its_ref, _, ok = O.stationary_solve(p, b, 1e-8, 400)
+    assert ok and abs(its - its_ref) <= 4
+    assert relerr(to_np(u), O.dense_solve(p, b)) <= 1e-6
+
+
+@pytest.mark.parametrize("dim,L", [(2, 4), (3, 3)])
+def test_fp32_refinement_reaches_fp64_accuracy(dim, L):
+    mg = mgmod()
+    theta, phi = 0.0, 100 * (1 + 0.5j)
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi, variant="bpx")
+    b = rand_c((3 ** L + 1,) * dim, 6)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant="bpx", precision="fp32_refine")
+    u, its, rel, rc = s.solve(b, rtol=1e-10, maxit=2000, driver="bicgstab")
+    assert rc == 0 and rel <= 1e-10
+    ref, _, _, ok = O.bicgstab(p, b, 1e-13, 400)
+    assert ok
+    err = relerr(to_np(u), ref)
+    print(f"\n[fp32-refine] dim={dim} L={L} inner iterations={its} relres={rel:.2e} error vs FP64={err:.2e}")
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("dim,L", [(2, 4), (3, 3)])
+def test_fp32_refinement_with_stationary_cycles(dim, L):
+    """Inner complex64 solves by pipelined cycles (fused sweep in FP32)."""
+    mg = mgmod()
+    p = Params(dim=dim, level_max=L, theta=0.0, phi=-30.0, variant="bpx", omega_scheme="const", omega=0.6)
+    b = rand_c((3 ** L + 1,) * dim, 8)
+    s = mg.Solver(dim, L, theta=0.0, phi=-30.0, variant="bpx", omega=0.6, precision="fp32_refine")
+    u, its, rel, rc = s.solve(b, rtol=1e-10, maxit=3000, driver="stationary")
+    assert rc == 0 and rel <= 1e-10, (rc, rel, its)
+    ref, _, _, ok = O.bicgstab(p, b, 1e-13, 400)
+    err = relerr(to_np(u), ref)
+    print(f"\n[fp32-refine stationary] dim={dim} L={L} cycles={its} relres={rel:.2e} error vs FP64={err:.2e}")
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("dim,L", [(2, 4), (3, 3)])
+def test_grad_potential_matches_oracle(dim, L):
+    mg = mgmod()
+    theta = 0.2
+    s = mg.Solver(dim, L, theta=theta, phi=50.0)
+    u = rand_c((3 ** L + 1,) * dim, 21)
+    lam = rand_c((3 ** L + 1,) * dim, 22)
+    g = to_np(s.grad_potential(u, lam))
+    ref = O.potential_gradient(u, lam, L, theta)
+    assert relerr(g, ref) <= TOL
+
+
+def test_invalid_arguments_raise():
+    mg = mgmod()
+    with pytest.raises(mg.MGError):
+        mg.Solver(3, 2, sweep="fused", phi_field=torch.zeros((10, 10, 10), dtype=torch.complex128))
+    s = mg.Solver(2, 2)
+    with pytest.raises(ValueError):
+        s.apply(np.zeros((5, 5), dtype=np.complex128))
