@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the complex additive multilevel cycle on one MI355X.
+
+Workload (default): d = 3, levels 1..5 (243^3 finest cells, 244^3 complex128
+vertices), -Lap u - k^2 u with k = 20 on the complex grid h exp(i pi/6), load =
+four Gaussians plus 1e-3 complex noise, BPX, omega 0.6 on every level.  One
+step = one pipelined additive cycle over the whole hierarchy (coarse descent,
+fused finest sweep, coarse backtracking, residual norm).  Inputs are resident
+in HBM before timing starts.
+
+Printed JSON line (last line of stdout): vertex-updates/s per cycle (interior
+vertices of all levels per cycle time), the finest sweep's achieved HBM
+bandwidth against the 8 TB/s peak, the FP64 CPU oracle's rate on a bounded
+sample, the hierarchical-basis variant's rate, and time to relative residual
+1e-10 with the BiCGStab driver.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def updates_per_cycle(dim, L, lmin=1):
+    return sum((3 ** l - 1) ** dim for l in range(lmin, L + 1))
+
+
+def fused_bytes(dim, L, variant, word=16):
+    """Algorithmic HBM bytes of one finest sweep: read w, b and write w' per
+    finest vertex; per coarse vertex read sc (and si for BPX), write R r (and
+    I s into sf for add / si for BPX)."""
+    NL = (3 ** L + 1) ** dim
+    Nc = (3 ** (L - 1) + 1) ** dim
+    coarse_words = {"add": 3, "hb": 2, "bpx": 4}[variant]
+    return word * (3 * NL + coarse_words * Nc)
+
+
+def traffic_from_profiles(kernel_src):
+    """HBM traffic of the finest sweep from the committed rocprofv3 counter
+    summary, scaled by the copy-kernel calibration; None when absent or when
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "fused3_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("kernel_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_cycles(s, steps, warmup, torch):
+    s.cycle(warmup, norms=False)
+    torch.cuda.synchronize()
+    s.time_sweeps(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(s.stream)
+    s.cycle(steps, norms=False)
+    stop.record(s.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    sweep_ms, cnt = s.sweep_time()
+    s.time_sweeps(False)
+    return ms / steps, sweep_ms / max(cnt, 1), cnt
+
+
+def cpu_baseline(prob, variant, cycles):
+    """The FP64 oracle as it stands on the host (numpy, one BLAS thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    from oracle.cycle import Params
+    L, dim = prob.level_max, prob.dim
+    p = Params(dim=dim, level_max=L, theta=prob.theta, phi=prob.phi, variant=variant, omega=0.6)
+    b = O.lumped_rhs(prob.chi, L, prob.theta)
+    with threadpool_limits(1):
+        pipe = O.Pipelined(p, b)
+        t0 = time.perf_counter()
+        for _ in range(cycles):
+            pipe.cycle()
+        dt = (time.perf_counter() - t0) / cycles
+    return {
+        "value": updates_per_cycle(dim, L) / dt,
+        "unit": "vertex-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{cycles} pipelined FP64 oracle cycle(s) of the same {dim}D L={L} {variant} workload "
+                  f"(full size; setup excluded), numpy with one BLAS thread; {dt:.2f} s per cycle",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--level", type=int, default=5)
+    ap.add_argument("--variant", default="bpx", choices=["add", "hb", "bpx"])
+    ap.add_argument("--sweep", default="auto", choices=["auto", "generic", "fused"])
+    ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the hb-variant and time-to-residual runs")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=None, help="fixed tile variant of the fused sweep (no autotune)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy three times (calibrates hardware byte counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only: the workload is a single-GPU "
+                                   "kernel; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_3d_csg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    mg.load_library()
+    L, dim = args.level, 3
+    prob = config_3d_csg(level_max=L, variant=args.variant)
+    chi = torch.from_numpy(prob.chi).cuda()
+
+    def make(variant):
+        s = mg.Solver(dim, L, theta=prob.theta, phi=prob.phi, variant=variant, omega=0.6, sweep=args.sweep)
+        b = s.rhs_from_nodal(chi)
+        s.set_rhs(b)
+        s.set_solution(torch.zeros_like(b))
+        return s, b
+
+    s, b = make(args.variant)
+    log(f"[bench] {prob.name}: {dim}D L={L} ({3 ** L + 1}^3 vertices), steps={args.steps} warmup={args.warmup}")
+    tune = None
+    if args.tile is not None:
+        s.set_tile(args.tile)
+        tune = {"tile": args.tile, "fixed": True}
+    elif args.sweep != "generic" and not args.no_autotune:
+        best, best_us, times = s.autotune(reps=5)
+        tune = {"tile": best, "us_per_tile": [round(t, 1) for t in times]}
+        log(f"[bench] autotune: tile {best} ({best_us:.1f} us); all: {', '.join(f'{t:.1f}' for t in times)}")
+    ms_step, sweep_ms, nsw = time_cycles(s, args.steps, args.warmup, torch)
+    ups = updates_per_cycle(dim, L)
+    value = ups / (ms_step * 1e-3)
+    fb = fused_bytes(dim, L, args.variant)
+    achieved = fb / (sweep_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_1508_03954_amd", "csrc", "mg_fused.hip"))
+    log(f"[bench] cycle {ms_step * 1e3:.1f} us, finest sweep {sweep_ms * 1e3:.1f} us ({nsw} timed), "
+        f"{achieved:.0f} GB/s algorithmic")
+    # residual history sanity (the stationary cycle on this indefinite problem may grow)
+    s.set_rhs(b)
+    s.set_solution(torch.zeros_like(b))
+    rh, _ = s.cycle(3)
+    log(f"[bench] residual h-norms of the first cycles: {', '.join(f'{v:.3e}' for v in rh)}")
+
+    out = {
+        "metric": "vertex-updates/s per additive cycle",
+        "value": value,
+        "unit": "vertex-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{prob.name}: d=3, levels 1..{L} ({3 ** L + 1}^3 complex128 vertices), k=20, "
+                        f"theta=pi/6, 4 Gaussians + 1e-3 noise, {args.variant}, omega=0.6 on every level",
+            "vertex_updates_per_cycle": ups,
+            "parallelism": "single GPU",
+            "sweep": "fused" if args.sweep != "generic" else "generic",
+            "autotune": tune,
+        },
+        "roofline": {
+            "kernel": "k_fused3 (finest-level fused sweep)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": fb,
+            "avg_launch_us": sweep_ms * 1e3,
+            "launches_timed": nsw,
+            "cycle_effective_GBs": None,
+        },
+    }
+
+    if not args.no_extras:
+        other = "hb" if args.variant != "hb" else "bpx"
+        s2, b2 = make(other)
+        if args.sweep != "generic" and not args.no_autotune and args.tile is None:
+            s2.autotune(reps=5)
+        ms2, sw2, _ = time_cycles(s2, args.steps, args.warmup, torch)
+        out["extra_variant"] = {"variant": other, "value": ups / (ms2 * 1e-3), "ms_per_step": ms2,
+                                "sweep_us": sw2 * 1e3,
+                                "sweep_GBs": fused_bytes(dim, L, other) / (sw2 * 1e-3) / 1e9}
+        del s2
+        # time to relative residual 1e-10: BiCGStab preconditioned by one zero-start cycle
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, its, rel, rc = s.solve(b, rtol=1e-10, maxit=2000, driver="bicgstab")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        true_rel = s.residual_norm(u, b) / s.residual_norm(torch.zeros_like(b), b)
+        out["time_to_1e-10"] = {"driver": "bicgstab (preconditioner: one zero-start additive cycle)",
+                                "seconds": t1 - t0, "iterations": its, "relres": rel,
+                                "true_relres": true_rel, "status": rc}
+        log(f"[bench] BiCGStab to 1e-10: {t1 - t0:.3f} s, {its} iterations, relres {true_rel:.2e}")
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline: FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(prob, args.variant, args.cpu_cycles)
+        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} vertex-updates/s")
+
+    if args.copy_probe:
+        src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 16
+        del src, dst
+
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,31 @@ int mg_residual_norm(mg_ctx* ctx, const mg_c128* u, const mg_c128* b, double* re
  * (every vertex, boundary included). */
 int mg_grad_potential(mg_ctx* ctx, const mg_c128* u, const mg_c128* lam, double* dJdV);
 
+/* Tile variants of the fused finest-level sweep (block shape and z extent).
+ * mg_tiles reports the current tile and the number of variants; mg_set_tile
+ * selects one (MG_EINVAL when out of range or when the context has no fused
+ * sweep). */
+int mg_tiles(const mg_ctx* ctx, int* current, int* count);
+int mg_set_tile(mg_ctx* ctx, int tile);
+
+/* Autotuner of the fused sweep: launches every tile variant `reps` times on the
+ * context's current data, writing into scratch buffers (the cycle state is not
+ * modified), times the launches with HIP events and selects the fastest.
+ * best_tile / best_us (average microseconds per launch) may be NULL;
+ * times_us, when not NULL, receives one average per variant (mg_tiles count).
+ * Synchronises. */
+int mg_autotune(mg_ctx* ctx, int reps, int* best_tile, double* best_us, double* times_us);
+
+/* Measurement hook for the finest-level sweep (the kernel that moves most of
+ * a cycle's bytes).  enable != 0: every following finest sweep launched by
+ * mg_cycle is bracketed by a HIP event pair recorded on the context stream;
+ * enable == 0 stops recording.  Enabling clears earlier records. */
+int mg_time_sweeps(mg_ctx* ctx, int enable);
+
+/* Synchronises and returns the summed event time (milliseconds) and the number
+ * of finest sweeps recorded since mg_time_sweeps(ctx, 1). */
+int mg_sweep_time(mg_ctx* ctx, double* total_ms, int* count);
+
 #ifdef __cplusplus
 }
 #endif

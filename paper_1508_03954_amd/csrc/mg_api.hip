@@ -124,6 +124,8 @@ struct Engine {
   std::vector<Level<T>> lv;
   cpx<T>* w[2] = {nullptr, nullptr};
   int cur = 0;
+  cpx<T>* si_alt = nullptr;    // second si buffer of level L-1 (fused BPX sweep reads old, writes new)
+  cpx<T>* tune_c = nullptr;    // coarse scratch for the autotuner
   cpx<T>*tA = nullptr, *tR = nullptr, *tRh = nullptr;
   double* partials = nullptr;  // 2 * max(kRedBlocks, fused blocks)
   double* red = nullptr;       // 2 doubles
@@ -133,9 +135,25 @@ struct Engine {
   int fused_blocks = 0;
   std::vector<cpx<T>*> kv;     // Krylov vectors
   std::vector<void*> owned;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs around finest sweeps
+  size_t ev_used = 0;
 
   ~Engine() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (void* p : owned) (void)hipFree(p);
+  }
+
+  int mark(bool start) {
+    if (!timing) return MG_OK;
+    if (ev_used == ev.size()) {
+      hipEvent_t e;
+      MG_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    MG_HIP(hipEventRecord(ev[ev_used++], s));
+    (void)start;
+    return MG_OK;
   }
 
   int alloc(void** p, size_t bytes) {
@@ -179,7 +197,7 @@ struct Engine {
       galerkin = true;
     }
     if (op_only) lmin = L;
-    const bool fused_ok = fused_partials_blocks(dim, (int)ipow(3, L) + 1) > 0;
+    const bool fused_ok = fused_partials_blocks(dim, (int)ipow(3, L) + 1, 0) > 0;
     fused = galerkin && !varying && L > lmin && p.sweep != MG_SWEEP_GENERIC && fused_ok && !op_only;
     if (p.sweep == MG_SWEEP_FUSED && !fused)
       return fail(MG_EINVAL, "FUSED sweep needs constant phi, GALERKIN form, level_max > level_min "
@@ -226,11 +244,30 @@ struct Engine {
         v.op.invDv = v.invDv;
       }
     }
-    fused_blocks = fused ? fused_partials_blocks(dim, lv[L].n) : 0;
-    MG_TRY(alloc_c(&partials, 2 * (size_t)std::max(kRedBlocks, fused_blocks)));
+    if (fused && variant == MG_BPX) MG_TRY(alloc_c(&si_alt, lv[L - 1].N));
+    int max_blocks = kRedBlocks;
+    if (fused) {
+      for (int t = 0; t < fused_tile_count(dim); ++t)
+        max_blocks = std::max(max_blocks, fused_partials_blocks(dim, lv[L].n, t));
+      set_tile(default_tile());
+    }
+    MG_TRY(alloc_c(&partials, 2 * (size_t)max_blocks));
     MG_TRY(alloc_c(&red, 4));
     MG_TRY(ensure_hist(64));
     return MG_OK;
+  }
+
+  int tile = 0;
+
+  // Default tile: small tiles while the coarse grid is small (more blocks),
+  // otherwise the tallest tile with the short z chunk.
+  int default_tile() const {
+    if (dim == 2) return lv[L].n <= 250 ? 1 : 0;
+    return lv[L].n <= 82 ? 1 : 0;
+  }
+  void set_tile(int t) {
+    tile = t;
+    fused_blocks = fused_partials_blocks(dim, lv[L].n, t);
   }
 
   int ensure_hist(int cap) {
@@ -263,6 +300,7 @@ struct Engine {
       MG_HIP(launch_fill(lv[l].sf, lv[l].N * sizeof(cpx<T>), s));
       MG_HIP(launch_fill(lv[l].si, lv[l].N * sizeof(cpx<T>), s));
     }
+    if (si_alt) MG_HIP(launch_fill(si_alt, lv[L - 1].N * sizeof(cpx<T>), s));
     iter = 0;
     return MG_OK;
   }
@@ -302,26 +340,11 @@ struct Engine {
     const complex<double> wL = omega_level(scheme, omega, omega_L, 0, iter);
     const int mask = (hc && variant != MG_ADD) ? 1 : 0;
     int nparts = kRedBlocks;
+    MG_TRY(mark(true));
     if (fused) {
-      FusedArgs<T> a;
-      a.n = f.n;
-      a.nc = c->n;
-      a.w = w[cur];
-      a.wout = w[1 - cur];
-      a.b = f.b;
-      a.scc = c->sc;
-      a.sic = variant == MG_BPX ? c->si : nullptr;
-      a.rhoc = c->b;
-      a.sfc = variant == MG_ADD ? c->sf : nullptr;
-      a.sic_out = variant == MG_BPX ? c->si : nullptr;
-      for (int q = 0; q < 4; ++q) a.coef[q] = f.op.coef[q];
-      {
-        const complex<double> id(f.op.invD.re, f.op.invD.im);
-        a.ws = to_c<T>(wL * id);
-      }
-      a.partials = partials;
-      a.variant = variant;
+      FusedArgs<T> a = fused_args(w[1 - cur], c->b, c->sf, si_alt, wL.real(), wL.imag());
       MG_HIP(launch_fused<T>(dim, a, s));
+      if (variant == MG_BPX) std::swap(c->si, si_alt);
       nparts = fused_blocks;
     } else {
       MG_TRY(ensure_scratch());
@@ -329,13 +352,14 @@ struct Engine {
       MG_HIP(launch_fine_pre<T>(dim, f.n, w[cur], U, hc ? c->sc : nullptr, hc ? c->si : nullptr, hc ? 1 : 0,
                                 variant == MG_BPX ? 1 : 0, s));
       if (!galerkin && hc) MG_HIP(launch_uhat<T>(dim, f.n, U, c->u, tA, s));
-      MG_HIP(launch_resid<T>(dim, f.op, f.b, U, tR, partials, s));
-      if (!galerkin && hc) MG_HIP(launch_resid<T>(dim, f.op, f.b, tA, tRh, nullptr, s));
+      MG_HIP(launch_resid<T>(dim, f.op, f.b, U, tR, partials, &nparts, s));
+      if (!galerkin && hc) MG_HIP(launch_resid<T>(dim, f.op, f.b, tA, tRh, nullptr, nullptr, s));
       MG_HIP(launch_update<T>(dim, f.op, tR, to_c<T>(wL), mask, U, nullptr, nullptr,
                               (hc && variant == MG_ADD) ? c->sf : nullptr, (hc && variant == MG_BPX) ? c->si : nullptr,
                               s));
       if (hc) MG_HIP(launch_restrict<T>(dim, c->n, galerkin ? tR : tRh, c->b, s));
     }
+    MG_TRY(mark(false));
     cur = 1 - cur;
     MG_HIP(launch_finish_sum_max(partials, nparts, hist + 2 * k, s));
     // Backtracking (post-phase) on the coarse levels L-1 .. l_min.
@@ -345,13 +369,18 @@ struct Engine {
       Level<T>* cc = hcc ? &lv[l - 1] : nullptr;
       const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, iter);
       const cpx<T>* r;
+      if (galerkin && hcc) {
+        MG_HIP(launch_post_galerkin<T>(dim, v.op, v.b, to_c<T>(wl), variant != MG_ADD ? 1 : 0, v.sc, v.sf, cc->b,
+                                       variant == MG_ADD ? cc->sf : nullptr, variant == MG_BPX ? cc->si : nullptr, s));
+        continue;
+      }
       if (galerkin) {
         r = v.b;
       } else {
         MG_TRY(ensure_scratch());
         if (hcc) MG_HIP(launch_uhat<T>(dim, v.n, v.u, cc->u, tA, s));
-        MG_HIP(launch_resid<T>(dim, v.op, v.b, v.u, tR, nullptr, s));
-        if (hcc) MG_HIP(launch_resid<T>(dim, v.op, v.b, tA, tRh, nullptr, s));
+        MG_HIP(launch_resid<T>(dim, v.op, v.b, v.u, tR, nullptr, nullptr, s));
+        if (hcc) MG_HIP(launch_resid<T>(dim, v.op, v.b, tA, tRh, nullptr, nullptr, s));
         r = tR;
       }
       MG_HIP(launch_update<T>(dim, v.op, r, to_c<T>(wl), (hcc && variant != MG_ADD) ? 1 : 0, nullptr, v.sc, v.sf,
@@ -359,6 +388,67 @@ struct Engine {
                               (hcc && variant == MG_BPX) ? cc->si : nullptr, s));
       if (hcc) MG_HIP(launch_restrict<T>(dim, cc->n, galerkin ? v.b : tRh, cc->b, s));
     }
+    return MG_OK;
+  }
+
+  FusedArgs<T> fused_args(cpx<T>* wout, cpx<T>* rhoc, cpx<T>* sfc, cpx<T>* sic_out, double wL_re, double wL_im) {
+    Level<T>& f = lv[L];
+    Level<T>* c = &lv[L - 1];
+    FusedArgs<T> a;
+    a.n = f.n;
+    a.nc = c->n;
+    a.w = w[cur];
+    a.wout = wout;
+    a.b = f.b;
+    a.scc = c->sc;
+    a.sic = variant == MG_BPX ? c->si : nullptr;
+    a.rhoc = rhoc;
+    a.sfc = variant == MG_ADD ? sfc : nullptr;
+    a.sic_out = variant == MG_BPX ? sic_out : nullptr;
+    for (int q = 0; q < 4; ++q) a.coef[q] = f.op.coef[q];
+    a.ws = to_c<T>(complex<double>(wL_re, wL_im) * complex<double>(f.op.invD.re, f.op.invD.im));
+    a.partials = partials;
+    a.variant = variant;
+    a.tile = tile;
+    return a;
+  }
+
+  // Times every tile variant of the fused sweep on scratch outputs; keeps the best.
+  int autotune(int reps, int* best_tile, double* best_us, double* times) {
+    if (!fused) return fail(MG_EINVAL, "the context has no fused sweep");
+    MG_TRY(ensure_scratch());
+    if (!tune_c) {
+      MG_TRY(alloc_c(&tune_c, lv[L - 1].N));
+    }
+    Level<T>* c = &lv[L - 1];
+    const int saved = tile;
+    hipEvent_t e0, e1;
+    MG_HIP(hipEventCreate(&e0));
+    MG_HIP(hipEventCreate(&e1));
+    int best = saved;
+    double best_t = 1e300;
+    for (int t = 0; t < fused_tile_count(dim); ++t) {
+      set_tile(t);
+      FusedArgs<T> a = fused_args(tA, c->pr, tune_c, c->pz, omega.real(), omega.imag());
+      MG_HIP(launch_fused<T>(dim, a, s));  // warm-up
+      MG_HIP(hipEventRecord(e0, s));
+      for (int k = 0; k < reps; ++k) MG_HIP(launch_fused<T>(dim, a, s));
+      MG_HIP(hipEventRecord(e1, s));
+      MG_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / std::max(reps, 1);
+      if (times) times[t] = us;
+      if (us < best_t) {
+        best_t = us;
+        best = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_tile(best);
+    if (best_tile) *best_tile = best;
+    if (best_us) *best_us = best_t;
     return MG_OK;
   }
 
@@ -466,7 +556,7 @@ struct Engine {
       if (relres) *relres = 0.0;
       return MG_OK;
     }
-    MG_HIP(launch_resid<T>(dim, op, b, x, r, nullptr, s));
+    MG_HIP(launch_resid<T>(dim, op, b, x, r, nullptr, nullptr, s));
     MG_HIP(hipMemcpyAsync(rh, r, N * sizeof(cpx<T>), hipMemcpyDeviceToDevice, s));
     MG_HIP(launch_fill(p, N * sizeof(cpx<T>), s));
     MG_HIP(launch_fill(v, N * sizeof(cpx<T>), s));
@@ -526,8 +616,9 @@ struct Engine {
   // Residual h-norm of (u, b) on the finest level: ||b - H u||_h.
   int resid_norm(const cpx<T>* u, const cpx<T>* b, double* res_h, double* res_max) {
     MG_TRY(ensure_scratch());
-    MG_HIP(launch_resid<T>(dim, lv[L].op, b, u, tA, partials, s));
-    MG_HIP(launch_finish_sum_max(partials, kRedBlocks, red, s));
+    int np = 0;
+    MG_HIP(launch_resid<T>(dim, lv[L].op, b, u, tA, partials, &np, s));
+    MG_HIP(launch_finish_sum_max(partials, np, red, s));
     double h[2];
     MG_HIP(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
     MG_HIP(hipStreamSynchronize(s));
@@ -610,13 +701,27 @@ static int check_params(const mg_params* p) {
   if (!p) return fail(MG_EINVAL, "params is NULL");
   if (p->dim != 2 && p->dim != 3) return fail(MG_EINVAL, "dim must be 2 or 3");
   if (p->level_min < 1 || p->level_max < p->level_min) return fail(MG_EINVAL, "need 1 <= level_min <= level_max");
-  const int maxL = p->dim == 3 ? 7 : 12;
-  if (p->level_max > maxL) return fail(MG_EINVAL, "level_max too large for 32-bit vertex counts per axis");
+  const int maxL = p->dim == 3 ? 6 : 9;   // every vertex index fits 32 bits
+  if (p->level_max > maxL) return fail(MG_EINVAL, "level_max too large (3D: <= 6, 2D: <= 9)");
   if (p->variant < MG_ADD || p->variant > MG_BPX) return fail(MG_EINVAL, "bad variant");
   if (p->omega_scheme < MG_OMEGA_CONST || p->omega_scheme > MG_OMEGA_TRANSITION) return fail(MG_EINVAL, "bad omega scheme");
   if (p->precision != MG_FP64 && p->precision != MG_FP32_REFINE) return fail(MG_EINVAL, "bad precision");
   if (p->restrict_form < MG_RESTRICT_AUTO || p->restrict_form > MG_RESTRICT_GALERKIN) return fail(MG_EINVAL, "bad restrict_form");
   if (p->sweep < MG_SWEEP_AUTO || p->sweep > MG_SWEEP_FUSED) return fail(MG_EINVAL, "bad sweep");
+  return MG_OK;
+}
+
+template <class T>
+static int sweep_time(Engine<T>& E, double* total_ms, int* count) {
+  MG_HIP(hipStreamSynchronize(E.s));
+  double tot = 0;
+  for (size_t i = 0; i + 1 < E.ev_used; i += 2) {
+    float ms = 0;
+    MG_HIP(hipEventElapsedTime(&ms, E.ev[i], E.ev[i + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (count) *count = (int)(E.ev_used / 2);
   return MG_OK;
 }
 
@@ -827,7 +932,7 @@ static int refine_solve(mg_ctx* c, const cpx<double>* b, cpx<double>* u, double 
   int total_inner = 0, status = MG_ENOTCONV;
   double rel = 1.0, rel0 = -1.0;
   for (int outer = 0; outer < 100; ++outer) {
-    MG_HIP(launch_resid<double>(dim, c->op64, E.tRh, u, r, nullptr, c->s));
+    MG_HIP(launch_resid<double>(dim, c->op64, E.tRh, u, r, nullptr, nullptr, c->s));
     double rn;
     MG_TRY(E.norm2(r, &rn));
     rel = rn / bn;
@@ -875,6 +980,48 @@ int mg_solve(mg_ctx* c, const mg_c128* b, mg_c128* u, double rtol, int maxit, in
   Engine<double>& E = *c->e64;
   if (driver == MG_BICGSTAB) return E.bicgstab((const cpx<double>*)b, (cpx<double>*)u, rtol, maxit, iters_out, relres_out);
   return E.stationary((const cpx<double>*)b, (cpx<double>*)u, rtol, maxit, iters_out, relres_out);
+}
+
+int mg_tiles(const mg_ctx* c, int* current, int* count) {
+  if (!c) return fail(MG_EINVAL, "NULL ctx");
+  const bool f = c->p.precision == MG_FP64 ? c->e64->fused : c->e32->fused;
+  if (current) *current = f ? (c->p.precision == MG_FP64 ? c->e64->tile : c->e32->tile) : -1;
+  if (count) *count = f ? fused_tile_count(c->p.dim) : 0;
+  return MG_OK;
+}
+
+int mg_set_tile(mg_ctx* c, int tile) {
+  if (!c) return fail(MG_EINVAL, "NULL ctx");
+  const bool f = c->p.precision == MG_FP64 ? c->e64->fused : c->e32->fused;
+  if (!f) return fail(MG_EINVAL, "the context has no fused sweep");
+  if (tile < 0 || tile >= fused_tile_count(c->p.dim)) return fail(MG_EINVAL, "tile out of range");
+  if (c->p.precision == MG_FP64) c->e64->set_tile(tile);
+  else c->e32->set_tile(tile);
+  return MG_OK;
+}
+
+int mg_autotune(mg_ctx* c, int reps, int* best_tile, double* best_us, double* times_us) {
+  if (!c || reps < 1) return fail(MG_EINVAL, "bad argument");
+  if (c->p.precision == MG_FP64) return c->e64->autotune(reps, best_tile, best_us, times_us);
+  return c->e32->autotune(reps, best_tile, best_us, times_us);
+}
+
+int mg_time_sweeps(mg_ctx* c, int enable) {
+  if (!c) return fail(MG_EINVAL, "NULL ctx");
+  if (c->p.precision == MG_FP64) {
+    c->e64->timing = enable != 0;
+    if (enable) c->e64->ev_used = 0;
+  } else {
+    c->e32->timing = enable != 0;
+    if (enable) c->e32->ev_used = 0;
+  }
+  return MG_OK;
+}
+
+int mg_sweep_time(mg_ctx* c, double* total_ms, int* count) {
+  if (!c) return fail(MG_EINVAL, "NULL ctx");
+  if (c->p.precision == MG_FP64) return sweep_time(*c->e64, total_ms, count);
+  return sweep_time(*c->e32, total_ms, count);
 }
 
 int mg_grad_potential(mg_ctx* c, const mg_c128* u, const mg_c128* lam, double* dJdV) {

@@ -54,10 +54,18 @@ hipError_t launch_fine_pre(int dim, int n, const cpx<T>* w, cpx<T>* u, const cpx
 template <class T>
 hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>* uhat, hipStream_t s);
 
-// r = b - H x; when partials != nullptr also writes per-block (sum |r|^2, max |r|).
+// r = b - H x; when partials != nullptr also writes per-block (sum |r|^2, max |r|)
+// and stores the number of blocks (<= kRedBlocks) in *nparts.
 template <class T>
 hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
-                        double* partials, hipStream_t s);
+                        double* partials, int* nparts, hipStream_t s);
+
+// Coarse post-phase of level l in the Galerkin form (op of level l): restriction
+// rho_c = R rho into the coarser b slot plus the pointwise update of level l.
+template <class T>
+hipError_t launch_post_galerkin(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int mask_c,
+                                cpx<T>* sc, const cpx<T>* sf, cpx<T>* rhoc, cpx<T>* sfc, cpx<T>* sic,
+                                hipStream_t s);
 
 // s = omega r / D; sc = s or masked; finest: u += sc in place (sc_out == nullptr),
 // coarse: sc_out = sc.  Injection: sfc = sf + sc at c-points (if sfc), sic = s (if sic).
@@ -138,9 +146,11 @@ struct FusedArgs {
   cpx<T> ws;            // omega * (1 / D)
   double* partials;     // per-block (sum |r|^2, max |r|) or nullptr
   int variant;          // 0 add, 1 hb, 2 bpx
+  int tile;             // tile variant, 0 .. fused_tile_count(dim) - 1
 };
 template <class T>
 hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);
-int fused_partials_blocks(int dim, int n);
+int fused_tile_count(int dim);
+int fused_partials_blocks(int dim, int n, int tile);  // -1 if unsupported
 
 }  // namespace mg

@@ -6,6 +6,8 @@
 //
 // Level l: n = 3^l + 1 vertices per axis, C order with x fastest.  Fields are
 // zero on boundary vertices; kernels keep them so.
+#include <algorithm>
+
 #include "mg_internal.h"
 
 namespace mg {
@@ -27,15 +29,20 @@ __device__ inline cpx<T> cconjmul(cpx<T> a, cpx<T> b) {  // conj(a) * b
 template <class T>
 __device__ inline cpx<T> czero() { return mk(T(0), T(0)); }
 
+// Level sizes are capped so that every vertex index fits 32 bits (the host
+// checks level_max), which keeps the index arithmetic in 32-bit integers.
 template <int D>
-__device__ inline void unravel(long long i, int n, int j[3]) {
-  j[0] = (int)(i % n);
-  i /= n;
+__device__ inline void unravel(long long ii, int n, int j[3]) {
+  unsigned i = (unsigned)ii;
+  const unsigned un = (unsigned)n;
+  const unsigned t = i / un;
+  j[0] = (int)(i - t * un);
   if (D == 3) {
-    j[1] = (int)(i % n);
-    j[2] = (int)(i / n);
+    const unsigned z = t / un;
+    j[1] = (int)(t - z * un);
+    j[2] = (int)z;
   } else {
-    j[1] = (int)i;
+    j[1] = (int)t;
     j[2] = 0;
   }
 }
@@ -64,6 +71,32 @@ __device__ inline long long total(int n) {
   return D == 3 ? (long long)n * n * n : (long long)n * n;
 }
 
+// Row-based traversal of a level: a wavefront covers 64 consecutive x of one
+// row (y, z); the row index is uniform across the wave, blocks of 4 waves walk
+// the rows grid-stride.  No per-vertex integer division.
+#define MG_ROWS(D, n)                                                                       \
+  const int lane_ = threadIdx.x & 63;                                                        \
+  const int x_ = blockIdx.x * 64 + lane_;                                                    \
+  const int nrows_ = (D == 3) ? (n) * (n) : (n);                                             \
+  for (int row_ = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); \
+       row_ < nrows_; row_ += gridDim.y * 4)
+
+// Inside MG_ROWS: vertex multi-index j and linear index i; false when x is past the row.
+template <int D>
+__device__ inline bool row_vertex(int row, int x, int n, int j[3], long long& i) {
+  if (x >= n) return false;
+  j[0] = x;
+  if (D == 3) {
+    j[2] = row / n;
+    j[1] = row - j[2] * n;
+  } else {
+    j[1] = row;
+    j[2] = 0;
+  }
+  i = (long long)row * n + x;
+  return true;
+}
+
 // (P v)_j: d-linear interpolation from the coarse level (nc per axis).  Per axis
 // a fine index j = 3m + q takes m with weight 1 (q = 0), or m and m+1 with
 // weights (2/3, 1/3) (q = 1) and (1/3, 2/3) (q = 2).
@@ -83,15 +116,17 @@ __device__ cpx<T> prolong_at(const cpx<T>* __restrict__ vc, int nc, const int j[
     }
   }
   cpx<T> acc = czero<T>();
+#pragma unroll
   for (int c = 0; c < (1 << D); ++c) {
     T w = T(1);
     int k[3] = {0, 0, 0};
     bool use = true;
+#pragma unroll
     for (int a = 0; a < D; ++a) {
       const int bit = (c >> a) & 1;
-      if (bit && !two[a]) { use = false; break; }
+      use = use && (!bit || two[a]);
       w *= bit ? w1[a] : w0[a];
-      k[a] = m[a] + bit;
+      k[a] = m[a] + (two[a] ? bit : 0);
     }
     if (use) acc = acc + w * vc[ravel<D>(k, nc)];
   }
@@ -193,8 +228,9 @@ __device__ inline void block_sum_max(double s, double m, double* partials) {
     double a = 0, b = 0;
     const int nw = (blockDim.x + 63) >> 6;
     for (int w = 0; w < nw; ++w) { a += ss[w]; b = fmax(b, sm[w]); }
-    partials[2 * blockIdx.x] = a;
-    partials[2 * blockIdx.x + 1] = b;
+    const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+    partials[2 * bid] = a;
+    partials[2 * bid + 1] = b;
   }
 }
 
@@ -219,11 +255,10 @@ __device__ inline void block_sum2(double s0, double s1, double* partials) {
 // ---------------------------------------------------------------------------
 template <class T, int D>
 __global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
-  const long long N = total<D>(op.n);
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, op.n) {
     int j[3];
-    unravel<D>(i, op.n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, op.n, j, i)) continue;
     y[i] = is_interior<D>(j, op.n) ? apply_row<T, D>(x, op.n, j, op) : czero<T>();
   }
 }
@@ -233,12 +268,11 @@ __global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __re
 template <class T, int D>
 __global__ void k_pre(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf,
                       const cpx<T>* __restrict__ scc, const cpx<T>* __restrict__ sic, int has_coarse, int bpx) {
-  const long long N = total<D>(n);
   const int nc = (n - 1) / 3 + 1;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     if (!is_interior<D>(j, n)) continue;
     cpx<T> s = sc[i];
     if (has_coarse) {
@@ -256,12 +290,11 @@ template <class T, int D>
 __global__ void k_fine_pre(int n, const cpx<T>* __restrict__ w, cpx<T>* __restrict__ u,
                            const cpx<T>* __restrict__ scc, const cpx<T>* __restrict__ sic, int has_coarse,
                            int bpx) {
-  const long long N = total<D>(n);
   const int nc = (n - 1) / 3 + 1;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     if (!is_interior<D>(j, n)) { u[i] = czero<T>(); continue; }
     cpx<T> v = w[i];
     if (has_coarse) {
@@ -275,12 +308,11 @@ __global__ void k_fine_pre(int n, const cpx<T>* __restrict__ w, cpx<T>* __restri
 // Hierarchical surplus uhat = u - P u_c (eq. HTMG).
 template <class T, int D>
 __global__ void k_uhat(int n, const cpx<T>* __restrict__ u, const cpx<T>* __restrict__ uc, cpx<T>* __restrict__ uh) {
-  const long long N = total<D>(n);
   const int nc = (n - 1) / 3 + 1;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     uh[i] = is_interior<D>(j, n) ? u[i] - prolong_at<T, D>(uc, nc, j) : czero<T>();
   }
 }
@@ -289,12 +321,11 @@ __global__ void k_uhat(int n, const cpx<T>* __restrict__ u, const cpx<T>* __rest
 template <class T, int D>
 __global__ void k_resid(OpData<T> op, const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ x,
                         cpx<T>* __restrict__ r, double* partials) {
-  const long long N = total<D>(op.n);
   double s2 = 0, mx = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, op.n) {
     int j[3];
-    unravel<D>(i, op.n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, op.n, j, i)) continue;
     cpx<T> v = czero<T>();
     if (is_interior<D>(j, op.n)) {
       v = b[i] - apply_row<T, D>(x, op.n, j, op);
@@ -315,12 +346,11 @@ __global__ void k_update(OpData<T> op, const cpx<T>* __restrict__ r, cpx<T> omeg
                          cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc_out, const cpx<T>* __restrict__ sf,
                          cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
   const int n = op.n;
-  const long long N = total<D>(n);
   const int nc = (n - 1) / 3 + 1;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     const bool in = is_interior<D>(j, n);
     cpx<T> s = czero<T>();
     if (in) {
@@ -342,17 +372,67 @@ __global__ void k_update(OpData<T> op, const cpx<T>* __restrict__ r, cpx<T> omeg
   }
 }
 
+// Coarse post-phase with the Galerkin form, one launch per level l > l_min.  A
+// thread owns coarse vertex m of level l-1 and the fine vertices 3m + q,
+// q in {0,1,2}^d, of level l.  It walks the restriction support 3m + o,
+// o in [-2, 2]^d, once: every value enters rho_c(m) = (R rho)(m), and on its
+// owned vertices it also forms s = omega rho / D, sc = s (0 on c-points when
+// masked) and the injections sf_c = sf + sc (add), si_c = s (BPX) at 3m.
+template <class T, int D>
+__global__ void k_post_galerkin(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c,
+                                cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf, cpx<T>* __restrict__ rhoc,
+                                cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
+  const int n = op.n, nc = (n - 1) / 3 + 1;
+  const T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
+  MG_ROWS(D, nc) {
+    int m[3];
+    long long ic;
+    if (!row_vertex<D>(row_, x_, nc, m, ic)) continue;
+    const bool cin = is_interior<D>(m, nc);
+    cpx<T> acc = czero<T>();
+    const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
+    for (int oz = zlo; oz <= zhi; ++oz) {
+      for (int oy = -2; oy <= 2; ++oy) {
+#pragma unroll
+        for (int ox = -2; ox <= 2; ++ox) {
+          int j[3] = {3 * m[0] + ox, 3 * m[1] + oy, 3 * m[2] + oz};
+          const bool owned = ox >= 0 && oy >= 0 && oz >= 0;
+          bool inside = true;
+#pragma unroll
+          for (int a = 0; a < D; ++a) inside = inside && j[a] >= 0 && j[a] < n;
+          if (!inside || !(cin || owned)) continue;
+          const long long i = ravel<D>(j, n);
+          const cpx<T> v = rho[i];
+          acc = acc + (w[ox + 2] * w[oy + 2] * (D == 3 ? w[oz + 2] : T(1))) * v;
+          if (owned) {
+            const bool in = is_interior<D>(j, n);
+            cpx<T> sv = czero<T>();
+            if (in) sv = cmul(omega, cmul(op.invDv ? op.invDv[i] : op.invD, v));
+            const bool cp = ox == 0 && oy == 0 && oz == 0;
+            const cpx<T> scm = (mask_c && cp) ? czero<T>() : sv;
+            sc[i] = scm;
+            if (cp) {
+              if (sfc) sfc[ic] = sf[i] + scm;
+              if (sic) sic[ic] = sv;
+            }
+          }
+        }
+      }
+    }
+    rhoc[ic] = cin ? acc : czero<T>();
+  }
+}
+
 // R v = P^T v: per axis weights 1 - |o|/3 for fine offsets o in [-2, 2] around 3m;
 // zero on the coarse boundary.
 template <class T, int D>
 __global__ void k_restrict(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
-  const long long N = total<D>(nc);
   const int nf = 3 * (nc - 1) + 1;
   const T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, nc) {
     int m[3];
-    unravel<D>(i, nc, m);
+    long long i;
+    if (!row_vertex<D>(row_, x_, nc, m, i)) continue;
     if (!is_interior<D>(m, nc)) { vc[i] = czero<T>(); continue; }
     cpx<T> acc = czero<T>();
     const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
@@ -374,12 +454,11 @@ __global__ void k_restrict(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __rest
 
 template <class T, int D>
 __global__ void k_inject(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
-  const long long N = total<D>(nc);
   const int nf = 3 * (nc - 1) + 1;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, nc) {
     int m[3];
-    unravel<D>(i, nc, m);
+    long long i;
+    if (!row_vertex<D>(row_, x_, nc, m, i)) continue;
     int j[3] = {3 * m[0], 3 * m[1], 3 * m[2]};
     vc[i] = vf[ravel<D>(j, nf)];
   }
@@ -392,12 +471,11 @@ template <class T, int D>
 __global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int variant, int is_lmin,
                           const cpx<T>* __restrict__ zc, cpx<T>* __restrict__ z) {
   const int n = op.n;
-  const long long N = total<D>(n);
   const int nc = (n - 1) / 3 + 1;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     if (!is_interior<D>(j, n)) { z[i] = czero<T>(); continue; }
     const cpx<T> id = op.invDv ? op.invDv[i] : op.invD;
     cpx<T> s = cmul(omega, cmul(id, rho[i]));
@@ -462,13 +540,12 @@ __global__ void k_cellavg(int n, const cpx<T>* __restrict__ phi, cpx<T>* __restr
 template <class T, int D>
 __global__ void k_invdiag(OpData<T> op, cpx<T>* __restrict__ invDv) {
   const int n = op.n, nc = n - 1;
-  const long long N = total<D>(n);
   const T kd = D == 3 ? T(6.0 * 4.0 / 9.0) : T(4.0 * 2.0 / 3.0);
   const T m0 = D == 3 ? T(1.0 / 27.0) : T(1.0 / 9.0);
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     if (!is_interior<D>(j, n)) { invDv[i] = mk(T(1), T(0)); continue; }
     cpx<T> ps = czero<T>();
     for (int k = 0; k < (1 << D); ++k) {
@@ -484,11 +561,10 @@ __global__ void k_invdiag(OpData<T> op, cpx<T>* __restrict__ invDv) {
 
 template <class T, int D>
 __global__ void k_zero_boundary_copy(int n, const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, cpx<T> scale) {
-  const long long N = total<D>(n);
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  MG_ROWS(D, n) {
     int j[3];
-    unravel<D>(i, n, j);
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     out[i] = is_interior<D>(j, n) ? cmul(scale, in[i]) : czero<T>();
   }
 }
@@ -615,27 +691,31 @@ __global__ void k_grad_potential(int n, cpx<double> etad, const cpx<double>* __r
   }
 }
 
-__global__ void k_finish_sum_max(const double* __restrict__ partials, int count, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0, m = 0;
-    for (int i = 0; i < count; ++i) {
-      s += partials[2 * i];
-      m = fmax(m, partials[2 * i + 1]);
-    }
-    out[0] = s;
-    out[1] = m;
+// Second reduction stage, one block of 256 threads: thread t folds partials
+// t, t+256, ... in order, then a fixed tree; the result does not depend on
+// timing, so repeated runs agree bitwise.
+template <bool MAX2>
+__global__ void k_finish(const double* __restrict__ partials, int count, double* out) {
+  __shared__ double s0[256], s1[256];
+  const int t = threadIdx.x;
+  double a = 0, b = 0;
+  for (int i = t; i < count; i += 256) {
+    a += partials[2 * i];
+    b = MAX2 ? fmax(b, partials[2 * i + 1]) : b + partials[2 * i + 1];
   }
-}
-
-__global__ void k_finish_sum2(const double* __restrict__ partials, int count, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0, t = 0;
-    for (int i = 0; i < count; ++i) {
-      s += partials[2 * i];
-      t += partials[2 * i + 1];
+  s0[t] = a;
+  s1[t] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      s0[t] += s0[t + w];
+      s1[t] = MAX2 ? fmax(s1[t], s1[t + w]) : s1[t] + s1[t + w];
     }
-    out[0] = s;
-    out[1] = t;
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
   }
 }
 
@@ -656,63 +736,85 @@ static inline int grid_for(long long N, int threads = 256) {
 
 static inline long long pow_n(int n, int dim) { return dim == 3 ? (long long)n * n * n : (long long)n * n; }
 
+// Grid of the row-based kernels: x blocks of 64 columns, 4 rows per block,
+// at most max_rows_blocks row blocks (grid-stride beyond).
+static inline dim3 row_grid(int n, int dim, int max_row_blocks = 65535) {
+  const long long rows = dim == 3 ? (long long)n * n : n;
+  long long gy = (rows + 3) / 4;
+  if (gy > max_row_blocks) gy = max_row_blocks;
+  return dim3((n + 63) / 64, (unsigned)gy, 1);
+}
+
 template <class T>
 hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y, hipStream_t s) {
-  MG_DISPATCH(dim, k_apply, dim3(grid_for(pow_n(op.n, dim))), op, x, y);
+  MG_DISPATCH(dim, k_apply, row_grid(op.n, dim), op, x, y);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
                       const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s) {
-  MG_DISPATCH(dim, k_pre, dim3(grid_for(pow_n(n, dim))), n, u, sc, sf, scc, sic, has_coarse, bpx);
+  MG_DISPATCH(dim, k_pre, row_grid(n, dim), n, u, sc, sf, scc, sic, has_coarse, bpx);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_fine_pre(int dim, int n, const cpx<T>* w, cpx<T>* u, const cpx<T>* scc, const cpx<T>* sic,
                            int has_coarse, int bpx, hipStream_t s) {
-  MG_DISPATCH(dim, k_fine_pre, dim3(grid_for(pow_n(n, dim))), n, w, u, scc, sic, has_coarse, bpx);
+  MG_DISPATCH(dim, k_fine_pre, row_grid(n, dim), n, w, u, scc, sic, has_coarse, bpx);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>* uh, hipStream_t s) {
-  MG_DISPATCH(dim, k_uhat, dim3(grid_for(pow_n(n, dim))), n, u, uc, uh);
+  MG_DISPATCH(dim, k_uhat, row_grid(n, dim), n, u, uc, uh);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
-                        double* partials, hipStream_t s) {
-  const int g = partials ? kRedBlocks : grid_for(pow_n(op.n, dim));
-  MG_DISPATCH(dim, k_resid, dim3(g), op, b, x, r, partials);
+                        double* partials, int* nparts, hipStream_t s) {
+  dim3 g = row_grid(op.n, dim);
+  if (partials) {
+    const int gx = (int)g.x;
+    g.y = std::max(1, std::min((int)g.y, kRedBlocks / gx));
+    if (nparts) *nparts = gx * (int)g.y;
+  }
+  MG_DISPATCH(dim, k_resid, g, op, b, x, r, partials);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_post_galerkin(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int mask_c,
+                                cpx<T>* sc, const cpx<T>* sf, cpx<T>* rhoc, cpx<T>* sfc, cpx<T>* sic, hipStream_t s) {
+  const int nc = (op.n - 1) / 3 + 1;
+  MG_DISPATCH(dim, k_post_galerkin, row_grid(nc, dim), op, rho, omega, mask_c, sc, sf, rhoc, sfc, sic);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_update(int dim, const OpData<T>& op, const cpx<T>* r, cpx<T> omega, int mask_c, cpx<T>* u,
                          cpx<T>* sc_out, const cpx<T>* sf, cpx<T>* sfc, cpx<T>* sic, hipStream_t s) {
-  MG_DISPATCH(dim, k_update, dim3(grid_for(pow_n(op.n, dim))), op, r, omega, mask_c, u, sc_out, sf, sfc, sic);
+  MG_DISPATCH(dim, k_update, row_grid(op.n, dim), op, r, omega, mask_c, u, sc_out, sf, sfc, sic);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_restrict(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s) {
-  MG_DISPATCH(dim, k_restrict, dim3(grid_for(pow_n(nc, dim))), nc, vf, vc);
+  MG_DISPATCH(dim, k_restrict, row_grid(nc, dim), nc, vf, vc);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s) {
-  MG_DISPATCH(dim, k_inject, dim3(grid_for(pow_n(nc, dim))), nc, vf, vc);
+  MG_DISPATCH(dim, k_inject, row_grid(nc, dim), nc, vf, vc);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int variant, int is_lmin,
                           const cpx<T>* zc, cpx<T>* z, hipStream_t s) {
-  MG_DISPATCH(dim, k_prec_up, dim3(grid_for(pow_n(op.n, dim))), op, rho, omega, variant, is_lmin, zc, z);
+  MG_DISPATCH(dim, k_prec_up, row_grid(op.n, dim), op, rho, omega, variant, is_lmin, zc, z);
   return hipGetLastError();
 }
 
@@ -724,13 +826,13 @@ hipError_t launch_cellavg(int dim, int n, const cpx<T>* phi, cpx<T>* phibar, int
 
 template <class T>
 hipError_t launch_invdiag(int dim, const OpData<T>& op, cpx<T>* invDv, hipStream_t s) {
-  MG_DISPATCH(dim, k_invdiag, dim3(grid_for(pow_n(op.n, dim))), op, invDv);
+  MG_DISPATCH(dim, k_invdiag, row_grid(op.n, dim), op, invDv);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_zero_boundary_copy(int dim, int n, const cpx<T>* in, cpx<T>* out, cpx<T> scale, hipStream_t s) {
-  MG_DISPATCH(dim, k_zero_boundary_copy, dim3(grid_for(pow_n(n, dim))), n, in, out, scale);
+  MG_DISPATCH(dim, k_zero_boundary_copy, row_grid(n, dim), n, in, out, scale);
   return hipGetLastError();
 }
 
@@ -792,12 +894,12 @@ hipError_t launch_grad_potential(int dim, int n, cpx<double> etad, const cpx<dou
 }
 
 hipError_t launch_finish_sum_max(const double* partials, int count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_sum_max, dim3(1), 64, 0, s, partials, count, out);
+  hipLaunchKernelGGL(k_finish<true>, dim3(1), 256, 0, s, partials, count, out);
   return hipGetLastError();
 }
 
 hipError_t launch_finish_sum2(const double* partials, int count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finish_sum2, dim3(1), 64, 0, s, partials, count, out);
+  hipLaunchKernelGGL(k_finish<false>, dim3(1), 256, 0, s, partials, count, out);
   return hipGetLastError();
 }
 
@@ -809,7 +911,9 @@ hipError_t launch_finish_sum2(const double* partials, int count, double* out, hi
                                          hipStream_t);                                                          \
   template hipError_t launch_uhat<T>(int, int, const cpx<T>*, const cpx<T>*, cpx<T>*, hipStream_t);             \
   template hipError_t launch_resid<T>(int, const OpData<T>&, const cpx<T>*, const cpx<T>*, cpx<T>*, double*,     \
-                                      hipStream_t);                                                             \
+                                      int*, hipStream_t);                                                       \
+  template hipError_t launch_post_galerkin<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, cpx<T>*,        \
+                                              const cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, hipStream_t);            \
   template hipError_t launch_update<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, cpx<T>*, cpx<T>*,      \
                                        const cpx<T>*, cpx<T>*, cpx<T>*, hipStream_t);                            \
   template hipError_t launch_restrict<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                        \

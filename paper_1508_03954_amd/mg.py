@@ -28,7 +28,8 @@ FIELDS = {"u": 0, "b": 1, "sc": 2, "sf": 3, "si": 4}
 EXPORTED = [
     "mg_params_default", "mg_setup", "mg_destroy", "mg_last_error", "mg_level_size", "mg_apply",
     "mg_rhs_from_nodal", "mg_set_rhs", "mg_set_solution", "mg_cycle", "mg_flush", "mg_get_level",
-    "mg_precondition", "mg_solve", "mg_residual_norm", "mg_grad_potential",
+    "mg_precondition", "mg_solve", "mg_residual_norm", "mg_grad_potential", "mg_time_sweeps",
+    "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune",
 ]
 
 
@@ -84,6 +85,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_solve.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.mg_residual_norm.argtypes = [P, P, P, ctypes.POINTER(D)]
     lib.mg_grad_potential.argtypes = [P, P, P, P]
+    lib.mg_time_sweeps.argtypes = [P, I]
+    lib.mg_tiles.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
+    lib.mg_set_tile.argtypes = [P, I]
+    lib.mg_autotune.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.mg_sweep_time.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I)]
     for name in EXPORTED:
         if name not in ("mg_params_default", "mg_destroy", "mg_last_error"):
             getattr(lib, name).restype = I
@@ -227,6 +233,33 @@ class Solver:
         out = ctypes.c_double(0.0)
         _check(self._lib.mg_residual_norm(self._ctx, _ptr(u), _ptr(b), ctypes.byref(out)))
         return out.value
+
+    def tiles(self):
+        """(current tile, number of tile variants) of the fused sweep; (-1, 0) without one."""
+        cur, cnt = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.mg_tiles(self._ctx, ctypes.byref(cur), ctypes.byref(cnt)))
+        return cur.value, cnt.value
+
+    def set_tile(self, tile: int):
+        _check(self._lib.mg_set_tile(self._ctx, tile))
+
+    def autotune(self, reps: int = 5):
+        """Times every fused tile variant (state untouched); returns (best tile, best us, all us)."""
+        _, cnt = self.tiles()
+        best, us = ctypes.c_int(0), ctypes.c_double(0.0)
+        times = (ctypes.c_double * max(cnt, 1))()
+        _check(self._lib.mg_autotune(self._ctx, reps, ctypes.byref(best), ctypes.byref(us), times))
+        return best.value, us.value, list(times[:cnt])
+
+    def time_sweeps(self, enable: bool = True):
+        _check(self._lib.mg_time_sweeps(self._ctx, 1 if enable else 0))
+
+    def sweep_time(self):
+        """(summed milliseconds, count) of the finest sweeps timed so far."""
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int(0)
+        _check(self._lib.mg_sweep_time(self._ctx, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def grad_potential(self, u, lam):
         u, lam = self._as_dev(u), self._as_dev(lam)

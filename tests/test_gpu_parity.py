@@ -125,7 +125,7 @@ CYCLE_CASES = [
 ]
 
 
-def run_cycle_parity(dim, L, lmin, variant, restrict, sweep, phi_case, scheme, ncycles=3, tol=TOL):
+def run_cycle_parity(dim, L, lmin, variant, restrict, sweep, phi_case, scheme, ncycles=3, tol=TOL, tile=None):
     mg = mgmod()
     theta, phi = 0.4, 90 * (1 + 0.5j)
     n = 3 ** L + 1
@@ -137,6 +137,8 @@ def run_cycle_parity(dim, L, lmin, variant, restrict, sweep, phi_case, scheme, n
     s = mg.Solver(dim, L, level_min=lmin, theta=theta, phi=phi, variant=variant, omega_scheme=scheme,
                   omega=0.6, restrict_form=restrict, sweep=sweep,
                   phi_field=None if pn is None else torch.from_numpy(pn))
+    if tile is not None:
+        s.set_tile(tile)
     s.set_rhs(b)
     s.set_solution(u0)
     pipe = O.Pipelined(p, b, u0)
@@ -168,6 +170,33 @@ def run_cycle_parity(dim, L, lmin, variant, restrict, sweep, phi_case, scheme, n
 def test_cycle_state_matches_pipelined_oracle(case):
     print(f"\n[case] cycle {case}", flush=True)
     run_cycle_parity(*case)
+
+
+@pytest.mark.parametrize("dim,L,ntiles", [(3, 4, 7), (2, 5, 4)])
+@pytest.mark.parametrize("variant", ["add", "bpx"])
+def test_every_fused_tile_matches_oracle(dim, L, ntiles, variant):
+    """Each tile variant of the fused sweep (the autotuner may choose any)."""
+    for tile in range(ntiles):
+        print(f"\n[case] fused tile {tile} dim={dim} L={L} {variant}", flush=True)
+        run_cycle_parity(dim, L, 1, variant, "galerkin", "fused", "const", "const", ncycles=2, tile=tile)
+
+
+def test_autotune_keeps_state():
+    mg = mgmod()
+    dim, L = 3, 4
+    s = mg.Solver(dim, L, theta=0.3, phi=200.0, variant="bpx", sweep="fused")
+    b = rand_c((3 ** L + 1,) * dim, 1)
+    s.set_rhs(b)
+    s.set_solution(rand_c((3 ** L + 1,) * dim, 2))
+    s.cycle(2)
+    before = {f: to_np(s.get_level(L - 1, f)) for f in ("u", "b", "sc", "si")}
+    before["w"] = to_np(s.get_level(L, "u"))
+    best, us, times = s.autotune(reps=2)
+    assert s.tiles()[0] == best and len(times) == s.tiles()[1] and min(times) == us
+    after = {f: to_np(s.get_level(L - 1, f)) for f in ("u", "b", "sc", "si")}
+    after["w"] = to_np(s.get_level(L, "u"))
+    for k in before:
+        np.testing.assert_array_equal(before[k], after[k])
 
 
 @pytest.mark.parametrize("dim,L,variant", [(2, 4, "bpx"), (3, 3, "hb"), (3, 3, "add")])
