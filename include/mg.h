@@ -205,6 +205,70 @@ int mg_time_sweeps(mg_ctx* ctx, int enable);
  * of finest sweeps recorded since mg_time_sweeps(ctx, 1). */
 int mg_sweep_time(mg_ctx* ctx, double* total_ms, int* count);
 
+/* ---------------------------------------------------------------------------
+ * Batched cycles (many independent problems, one persistent launch per cycle).
+ *
+ * The multilevel cycle of the method (Section 4, the pipelined additive
+ * schemes of Algorithms 3 and 4) applied to a set of independent problems --
+ * several right-hand sides, wavenumbers, dimensions and depths -- at once.
+ * Each problem lives in its own context (created by mg_batch_setup, reachable
+ * through mg_batch_problem for mg_set_rhs / mg_set_solution / mg_get_level /
+ * mg_flush); a batched cycle advances every problem by exactly one pipelined
+ * cycle and leaves each context in the state mg_cycle(ctx, 1, ...) would, with
+ * the fused sweep in the batch's tiling.  Requirements per problem: constant
+ * phi, level_max > level_min, level_max <= 7, an iteration-independent omega
+ * scheme (not MG_OMEGA_TRANSITION); all problems share one precision.
+ * Problems are advanced concurrently: a call overlaps the coarse levels of
+ * small problems with the finest sweeps of large ones. */
+typedef struct mg_batch mg_batch;
+
+/* Creates `count` contexts from params[0..count-1] (sweep forced to FUSED) on
+ * hip_stream (NULL = default stream).  *out = NULL on failure. */
+int mg_batch_setup(const mg_params* params, int count, void* hip_stream, mg_batch** out);
+void mg_batch_destroy(mg_batch* batch);
+
+/* The context of problem i (owned by the batch; do not mg_destroy it).  Its
+ * fused tile (mg_tiles) is kept equal to the batch's tiling of that problem,
+ * so mg_cycle on it reproduces a batched cycle exactly. */
+int mg_batch_problem(mg_batch* batch, int i, mg_ctx** ctx);
+
+/* ncycles batched cycles.  res_h, when not NULL, receives ncycles * count
+ * doubles: res_h[k * count + i] = |r|_h of problem i before its finest update
+ * in cycle k (as mg_cycle's res_h).  Synchronises.  MG_EDEVICE if an internal
+ * dependency wait exceeded its bound (the launch still completes; the state
+ * is then undefined). */
+int mg_batch_cycle(mg_batch* batch, int ncycles, double* res_h);
+
+/* Times every batch configuration (fused z extent per dimension, queue order)
+ * with `reps` batched cycles each and keeps the fastest.  The cycles run on
+ * the contexts' current data and advance them: reset the state afterwards.
+ * config / us_per_cycle may be NULL; times_us, when not NULL, receives the
+ * average microseconds per batched cycle of each of the mg_batch_configs()
+ * configurations. */
+int mg_batch_autotune(mg_batch* batch, int reps, int* config, double* us_per_cycle, double* times_us);
+
+/* Number of batch configurations the autotuner tries. */
+int mg_batch_configs(void);
+
+/* Scheduler trace.  mg_batch_trace(b, 1) makes every following batched cycle
+ * record, per work item, the device wall clock (100 MHz) when its workgroup
+ * starts waiting for the item's dependencies, when they are met and when the
+ * item is published, and the XCD and workgroup that ran it.
+ * mg_batch_get_trace copies the last cycle's record: 8 values per item in
+ * queue order -- problem, phase, tile, kind (0 descent, 1/2 finest sweep 3D/2D,
+ * 3 Galerkin backtracking, 4 coarsest update, 5 norm), wait start, ready,
+ * done, XCD << 16 | workgroup -- for min(cap, count) items; *count receives
+ * the number of items.  Synchronises. */
+int mg_batch_trace(mg_batch* batch, int enable);
+int mg_batch_get_trace(mg_batch* batch, long long* out, int cap, int* count);
+
+/* Solves every problem i: H_i u_i = b_i (device complex128 buffers bs[i],
+ * us[i] of each problem's finest size; us[i] holds the initial guess) with
+ * mg_solve semantics per problem.  iters / relres: arrays of count entries or
+ * NULL.  Returns MG_OK, or the first MG_ENOTCONV / MG_EDIVERGED. */
+int mg_batch_solve(mg_batch* batch, const mg_c128* const* bs, mg_c128* const* us, double rtol,
+                   int maxit, int driver, int* iters, double* relres);
+
 #ifdef __cplusplus
 }
 #endif

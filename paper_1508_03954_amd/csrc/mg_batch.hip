@@ -1,0 +1,717 @@
+// Batched form: many independent problems (right-hand sides, wavenumbers,
+// dimensions and grid depths) advanced by one pipelined cycle each in ONE
+// persistent kernel launch.
+//
+// Work items are (problem, phase, tile).  The phases of one problem's cycle
+// are its coarse pre-phases (levels l_min .. L-1), the fused finest sweep, the
+// coarse Galerkin post-phases (levels L-1 .. l_min+1), the coarsest update and
+// the residual-norm reduction; each phase depends on all tiles of the
+// previous phase of the same problem and on nothing else.  A resident grid of
+// workgroups pulls items from an atomic queue ordered so that every item comes
+// after the items it waits for, so the waits always end: a waiting workgroup
+// only waits for items claimed earlier by workgroups that are resident and
+// whose own waits point further back.  Completion is published per
+// (problem, phase) with an agent-scope release; waiters acquire at agent scope
+// (each XCD has its own L2).  Every wait is bounded; a timeout sets an error
+// flag and the kernel still drains.
+//
+// The per-vertex and per-tile code is the same as in the single-problem
+// kernels (mg_level_ops.h, mg_fused_ops.h), so a problem advanced in a batch
+// ends in the same state as the same problem advanced alone with the same tile.
+#include <array>
+
+#include "mg_engine.h"
+#include "mg_fused_ops.h"
+#include "mg_level_ops.h"
+
+namespace mg {
+
+enum BatchKind { BK_PRE = 0, BK_FUSED3 = 1, BK_FUSED2 = 2, BK_POST = 3, BK_UPDATE = 4, BK_NORM = 5 };
+constexpr int kBMaxPhases = 16;
+constexpr int kBMaxLevels = 8;
+constexpr int kBRows = 16;          // rows of a coarse level per item (4 per wavefront)
+constexpr int kBThreads = 256;
+// 3D tiles usable by a 256-thread workgroup: coarse rows 2, rows per thread 2;
+// z extent selectable.  2D: one tile per wavefront, four per item.
+constexpr int kBZc3[] = {9, 27};
+constexpr int kBZc2[] = {1, 2, 4, 8};
+// configurations: z extent (3D) x z extent (2D) x queue order
+constexpr int kBatchConfigs = 2 * 4 * 2;
+
+template <class T>
+struct BLevel {
+  int n;
+  cpx<T>*u, *b, *sc, *sf, *si;
+  OpData<T> op;
+  cpx<T> omega;
+};
+
+template <class T>
+struct BProb {
+  int dim, L, lmin, variant, nphase;
+  int zc3, zc2;                     // indices into kBZc3 / kBZc2
+  int ftiles;                       // fused tiles of the finest sweep
+  int fgx, fgy;                     // fused tile grid extents (x, y)
+  int parw, pars;                   // ping-pong parity of w and of si at level L-1 at launch 0
+  int phase_items[kBMaxPhases];
+  int phase_kind[kBMaxPhases];
+  int phase_level[kBMaxPhases];
+  BLevel<T> lv[kBMaxLevels];
+  cpx<T>* w[2];
+  cpx<T>* si2[2];
+  cpx<T> wsL;
+  double* part;
+};
+
+struct BItem {
+  int prob, phase, tile;
+};
+
+template <class T>
+struct BatchArgs {
+  const BItem* items;
+  int nitems;
+  const BProb<T>* probs;
+  int* done;        // [nprob][kBMaxPhases]
+  int* queue;
+  int* err;
+  double* hist;     // [nprob][2] of this cycle
+  int cyc;          // cycle index within the call (flips the ping-pong parity)
+  unsigned spin_limit;
+  unsigned long long* trace;  // per item: claim-to-ready wait start, ready, done (wall clock), XCD << 16 | block; or null
+};
+
+__device__ inline unsigned xcc_id() {
+  unsigned x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & 0xf;
+}
+
+// Coarse-level row items: wave w handles rows tile*kBRows + w + 4k.
+template <class T, int D, class F>
+__device__ inline void for_rows(int n, int tile, F f) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nrows = D == 3 ? n * n : n;
+  for (int k = 0; k < kBRows / 4; ++k) {
+    const int row = tile * kBRows + wv + 4 * k;
+    if (row >= nrows) break;
+    for (int x = lane; x < n; x += 64) {
+      int j[3];
+      long long i;
+      row_vertex<D>(row, x, n, j, i);
+      f(j, i);
+    }
+  }
+}
+
+// The finest-sweep tiles run out of line so that their register allocation
+// does not add to that of the rest of the persistent loop.
+template <class T>
+__device__ inline FusedArgs<T> batch_fused_args(const BProb<T>& P, int cyc) {
+  const int L = P.L;
+  const bool bpx = P.variant == MG_BPX, add = P.variant == MG_ADD;
+  const int pw = (P.parw + cyc) & 1, ps = (P.pars + cyc) & 1;
+  FusedArgs<T> f;
+  f.n = P.lv[L].n;
+  f.nc = P.lv[L - 1].n;
+  f.w = P.w[pw];
+  f.wout = P.w[1 - pw];
+  f.b = P.lv[L].b;
+  f.scc = P.lv[L - 1].sc;
+  f.sic = bpx ? P.si2[ps] : nullptr;
+  f.rhoc = P.lv[L - 1].b;
+  f.sfc = add ? P.lv[L - 1].sf : nullptr;
+  f.sic_out = bpx ? P.si2[1 - ps] : nullptr;
+  for (int q = 0; q < 4; ++q) f.coef[q] = P.lv[L].op.coef[q];
+  f.ws = P.wsL;
+  f.partials = nullptr;
+  f.variant = P.variant;
+  f.tile = 0;
+  return f;
+}
+
+template <class T>
+__device__ inline void batch_fused3(const BProb<T>* Pp, int cyc, int tile, F3Lds<T, 2, 2, true>& sm) {
+  const BProb<T>& P = *Pp;
+  const FusedArgs<T> f = batch_fused_args(P, cyc);
+  const bool bpx = P.variant == MG_BPX;
+  const int bx = tile % P.fgx, by = (tile / P.fgx) % P.fgy, bz = tile / (P.fgx * P.fgy);
+  double* part = P.part + 2 * tile;
+  // the non-BPX layout is a prefix of the BPX one
+  auto& sm0 = reinterpret_cast<F3Lds<T, 2, 2, false>&>(sm);
+  if (P.zc3 == 0) {
+    if (bpx) fused3_tile<T, 2, 2, 9, true>(f, bx, by, bz, part, sm);
+    else fused3_tile<T, 2, 2, 9, false>(f, bx, by, bz, part, sm0);
+  } else {
+    if (bpx) fused3_tile<T, 2, 2, 27, true>(f, bx, by, bz, part, sm);
+    else fused3_tile<T, 2, 2, 27, false>(f, bx, by, bz, part, sm0);
+  }
+}
+
+template <class T>
+__device__ inline void batch_fused2(const BProb<T>* Pp, int cyc, int id, cpx<T> (*Gz)[F2_GX],
+                                          cpx<T> (*Sz)[F2_GX]) {
+  const BProb<T>& P = *Pp;
+  const FusedArgs<T> f = batch_fused_args(P, cyc);
+  const bool bpx = P.variant == MG_BPX;
+  const int bx = id % P.fgx, by = id / P.fgx;
+  double* part = P.part + 2 * id;
+  switch (P.zc2) {
+    case 0:
+      if (bpx) fused2_wave_tile<T, 1, true>(f, bx, by, Gz, Sz, part);
+      else fused2_wave_tile<T, 1, false>(f, bx, by, Gz, Sz, part);
+      break;
+    case 1:
+      if (bpx) fused2_wave_tile<T, 2, true>(f, bx, by, Gz, Sz, part);
+      else fused2_wave_tile<T, 2, false>(f, bx, by, Gz, Sz, part);
+      break;
+    case 2:
+      if (bpx) fused2_wave_tile<T, 4, true>(f, bx, by, Gz, Sz, part);
+      else fused2_wave_tile<T, 4, false>(f, bx, by, Gz, Sz, part);
+      break;
+    default:
+      if (bpx) fused2_wave_tile<T, 8, true>(f, bx, by, Gz, Sz, part);
+      else fused2_wave_tile<T, 8, false>(f, bx, by, Gz, Sz, part);
+      break;
+  }
+}
+
+template <class T, int D>
+__device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, int phase, int tile,
+                           cpx<T> (*Gz2)[2][F2_GX], cpx<T> (*Sz2)[2][F2_GX], F3Lds<T, 2, 2, true>* f3lds) {
+  const int kind = P.phase_kind[phase], lev = P.phase_level[phase];
+  const bool bpx = P.variant == MG_BPX, add = P.variant == MG_ADD;
+  if (kind == BK_PRE) {
+    const BLevel<T>& v = P.lv[lev];
+    const bool hc = lev > P.lmin;
+    const cpx<T>* scc = hc ? P.lv[lev - 1].sc : nullptr;
+    const cpx<T>* sic = hc ? P.lv[lev - 1].si : nullptr;
+    for_rows<T, D>(v.n, tile, [&](const int j[3], long long i) {
+      pre_vertex<T, D>(v.n, j, i, v.u, v.sc, v.sf, scc, sic, hc ? 1 : 0, bpx ? 1 : 0);
+    });
+  } else if (kind == BK_POST) {
+    const BLevel<T>& v = P.lv[lev];
+    const BLevel<T>& c = P.lv[lev - 1];
+    for_rows<T, D>(c.n, tile, [&](const int m[3], long long ic) {
+      post_galerkin_vertex<T, D>(v.op, m, ic, v.b, v.omega, add ? 0 : 1, v.sc, v.sf, c.b, add ? c.sf : nullptr,
+                                 bpx ? c.si : nullptr);
+    });
+  } else if (kind == BK_UPDATE) {
+    const BLevel<T>& v = P.lv[lev];
+    for_rows<T, D>(v.n, tile, [&](const int j[3], long long i) {
+      update_vertex<T, D>(v.op, j, i, v.b, v.omega, 0, nullptr, v.sc, v.sf, nullptr, nullptr);
+    });
+  } else if (kind == BK_NORM) {
+    // the fixed-order second stage of the single-problem path
+    __shared__ double s0[kBThreads], s1[kBThreads];
+    const int t = threadIdx.x;
+    double a = 0, b = 0;
+    for (int i = t; i < P.ftiles; i += kBThreads) {
+      a += P.part[2 * i];
+      b = fmax(b, P.part[2 * i + 1]);
+    }
+    s0[t] = a;
+    s1[t] = b;
+    __syncthreads();
+    for (int w = kBThreads / 2; w > 0; w >>= 1) {
+      if (t < w) {
+        s0[t] += s0[t + w];
+        s1[t] = fmax(s1[t], s1[t + w]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      A.hist[2 * prob] = s0[0];
+      A.hist[2 * prob + 1] = s1[0];
+    }
+  } else {
+    if (kind == BK_FUSED3) {
+      if (D == 3) batch_fused3<T>(&P, A.cyc, tile, *f3lds);
+    } else if (D == 2) {
+      const int wv = threadIdx.x >> 6;
+      const int id = 4 * tile + wv;
+      if (id < P.ftiles) batch_fused2<T>(&P, A.cyc, id, Gz2[wv], Sz2[wv]);
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBThreads, 2) void k_batch_cycle(BatchArgs<T> A) {
+  __shared__ int s_item, s_ok;
+  __shared__ cpx<T> Gz2[4][2][F2_GX];
+  __shared__ cpx<T> Sz2[4][2][F2_GX];
+  __shared__ F3Lds<T, 2, 2, true> f3lds;
+  // Thread 0 claims items and publishes completions; every step it takes is
+  // followed by a workgroup barrier before any other thread depends on it, and
+  // the loop exit is decided on a value every thread reads after a barrier.
+  // (Keeping "publish" and "claim" in one block before one barrier also keeps
+  // the loop's back edge uniform: no lane may take a different path around it.)
+  if (threadIdx.x == 0) s_item = atomicAdd(A.queue, 1);
+  __syncthreads();
+  for (;;) {
+    // item indices are uniform over the workgroup: keep them (and every
+    // descriptor field read through them) in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= A.nitems) break;
+    BItem w = A.items[it];
+    w.prob = __builtin_amdgcn_readfirstlane(w.prob);
+    w.phase = __builtin_amdgcn_readfirstlane(w.phase);
+    w.tile = __builtin_amdgcn_readfirstlane(w.tile);
+    const BProb<T>& P = A.probs[w.prob];
+    unsigned long long t_wait = 0, t_ready = 0;
+    if (threadIdx.x == 0) {
+      if (A.trace) t_wait = wall_clock64();
+      int ok = 1;
+      if (w.phase > 0) {
+        const int need = P.phase_items[w.phase - 1];
+        int* cnt = A.done + w.prob * kBMaxPhases + w.phase - 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (++spins > A.spin_limit) {
+            ok = 0;
+            atomicOr(A.err, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      s_ok = ok;
+      if (A.trace) t_ready = wall_clock64();
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (s_ok) {
+      if (P.dim == 3) batch_item<T, 3>(A, P, w.prob, w.phase, w.tile, Gz2, Sz2, &f3lds);
+      else batch_item<T, 2>(A, P, w.prob, w.phase, w.tile, Gz2, Sz2, &f3lds);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (A.trace) {
+        unsigned long long* t = A.trace + 4 * (size_t)it;
+        t[0] = t_wait;
+        t[1] = t_ready;
+        t[2] = wall_clock64();
+        t[3] = ((unsigned long long)xcc_id() << 16) | blockIdx.x;
+      }
+      __hip_atomic_fetch_add(A.done + w.prob * kBMaxPhases + w.phase, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = atomicAdd(A.queue, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host driver.
+
+template <class T>
+static Engine<T>* engine_of(mg_ctx* c);
+template <>
+Engine<double>* engine_of<double>(mg_ctx* c) { return c->e64; }
+template <>
+Engine<float>* engine_of<float>(mg_ctx* c) { return c->e32; }
+
+struct BatchBase {
+  virtual ~BatchBase() {}
+  virtual int cycle(int ncycles, double* res) = 0;
+  virtual int autotune(int reps, int* best, double* best_us, double* times) = 0;
+  virtual int set_trace(bool on) = 0;
+  virtual int get_trace(long long* out, int cap, int* count) = 0;
+  std::vector<mg_ctx*> ctx;
+  hipStream_t s = nullptr;
+};
+
+template <class T>
+struct Batch : BatchBase {
+  int np = 0, zc3 = 0, zc2 = 1, schedule = 0;
+  std::vector<BProb<T>> hp;
+  BProb<T>* dp = nullptr;
+  BItem* ditems = nullptr;
+  int nitems = 0;
+  int* ddone = nullptr;
+  int* dq = nullptr;
+  double* dhist = nullptr;
+  int hist_cap = 0;
+  int grid = 0;
+  std::vector<void*> owned;
+
+  ~Batch() override {
+    for (void* p : owned) (void)hipFree(p);
+    for (mg_ctx* c : ctx) mg_destroy(c);
+  }
+
+  template <class P>
+  int dalloc(P** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(P));
+    if (e != hipSuccess) return fail(MG_ENOMEM, std::string("batch hipMalloc: ") + hipGetErrorString(e));
+    owned.push_back(q);
+    *p = (P*)q;
+    return MG_OK;
+  }
+
+  // Per-problem descriptor (static parts); tile choices from zc3 / zc2.
+  int describe(int i, BProb<T>& P) {
+    Engine<T>& E = *engine_of<T>(ctx[i]);
+    std::memset(&P, 0, sizeof(P));
+    P.dim = E.dim;
+    P.L = E.L;
+    P.lmin = E.lmin;
+    P.variant = E.variant;
+    if (!E.fused) return fail(MG_EINVAL, "batched problems need the fused finest sweep (constant phi, level_max > level_min)");
+    if (E.scheme == MG_OMEGA_TRANSITION) return fail(MG_EINVAL, "batched cycles need an iteration-independent omega scheme");
+    if (E.L >= kBMaxLevels) return fail(MG_EINVAL, "level_max too large for a batch");
+    for (int l = E.lmin; l <= E.L; ++l) {
+      BLevel<T>& v = P.lv[l];
+      v.n = E.lv[l].n;
+      v.u = E.lv[l].u;
+      v.b = E.lv[l].b;
+      v.sc = E.lv[l].sc;
+      v.sf = E.lv[l].sf;
+      v.si = E.lv[l].si;
+      v.op = E.lv[l].op;
+      v.omega = to_c<T>(omega_level(E.scheme, E.omega, E.omega_L, E.L - l, 1));
+    }
+    P.w[0] = E.w[0];
+    P.w[1] = E.w[1];
+    P.si2[0] = E.lv[E.L - 1].si;
+    P.si2[1] = E.si_alt ? E.si_alt : E.lv[E.L - 1].si;
+    P.parw = E.cur;
+    P.pars = 0;
+    const complex<double> wL = omega_level(E.scheme, E.omega, E.omega_L, 0, 1);
+    P.wsL = to_c<T>(wL * complex<double>(E.lv[E.L].op.invD.re, E.lv[E.L].op.invD.im));
+    P.part = E.partials;
+    P.zc3 = zc3;
+    P.zc2 = zc2;
+    // the context's own tile follows the batch tiling, so that a standalone
+    // cycle on it partitions the finest sweep (and its norm) identically
+    const int same = E.dim == 3 ? fused_tile_index(3, 2, 2, kBZc3[zc3]) : fused_tile_index(2, 0, 0, kBZc2[zc2]);
+    if (same < 0) return fail(MG_EINVAL, "batch tiling has no standalone counterpart");
+    E.set_tile(same);
+    const int nL = E.lv[E.L].n, nc = E.lv[E.L - 1].n;
+    int k = 0;
+    auto rows_items = [&](int n) { const int rows = E.dim == 3 ? n * n : n; return (rows + kBRows - 1) / kBRows; };
+    for (int l = E.lmin; l < E.L; ++l) {
+      P.phase_kind[k] = BK_PRE;
+      P.phase_level[k] = l;
+      P.phase_items[k++] = rows_items(E.lv[l].n);
+    }
+    if (E.dim == 3) {
+      P.fgx = (nc + F3_TXC - 1) / F3_TXC;
+      P.fgy = (nc + 1) / 2;
+      const int gz = (nc + kBZc3[zc3] - 1) / kBZc3[zc3];
+      P.ftiles = P.fgx * P.fgy * gz;
+      P.phase_kind[k] = BK_FUSED3;
+      P.phase_items[k] = P.ftiles;
+    } else {
+      P.fgx = (nc + F2_TXC - 1) / F2_TXC;
+      P.fgy = (nc + kBZc2[zc2] - 1) / kBZc2[zc2];
+      P.ftiles = P.fgx * P.fgy;
+      P.phase_kind[k] = BK_FUSED2;
+      P.phase_items[k] = (P.ftiles + 3) / 4;
+    }
+    (void)nL;
+    P.phase_level[k++] = E.L;
+    for (int l = E.L - 1; l > E.lmin; --l) {
+      P.phase_kind[k] = BK_POST;
+      P.phase_level[k] = l;
+      P.phase_items[k++] = rows_items(E.lv[l - 1].n);
+    }
+    P.phase_kind[k] = BK_UPDATE;
+    P.phase_level[k] = E.lmin;
+    P.phase_items[k++] = rows_items(E.lv[E.lmin].n);
+    P.phase_kind[k] = BK_NORM;
+    P.phase_level[k] = E.L;
+    P.phase_items[k++] = 1;
+    P.nphase = k;
+    if (k > kBMaxPhases) return fail(MG_EINVAL, "too many phases for a batch");
+    // the single-problem partials buffer must hold this tiling
+    if (P.ftiles > E.partials_cap) return fail(MG_EINVAL, "partials buffer too small for the batch tiling");
+    return MG_OK;
+  }
+
+  // Queue order: schedule 0 = phase-major; 1 = phases aligned on each problem's
+  // fused sweep.  Within a step, larger problems first.
+  int build_items() {
+    std::vector<std::array<long long, 4>> keys;  // sort key, prob, phase, tile
+    int maxf = 0;
+    for (int i = 0; i < np; ++i) maxf = std::max(maxf, hp[i].L - hp[i].lmin);
+    for (int i = 0; i < np; ++i) {
+      const BProb<T>& P = hp[i];
+      const long long size = (long long)P.lv[P.L].n * P.lv[P.L].n * (P.dim == 3 ? P.lv[P.L].n : 1);
+      for (int ph = 0; ph < P.nphase; ++ph) {
+        const int step = schedule == 0 ? ph : ph - (P.L - P.lmin) + maxf;
+        for (int t = 0; t < P.phase_items[ph]; ++t)
+          keys.push_back({((long long)step << 40) - size, i, ph, t});
+      }
+    }
+    std::stable_sort(keys.begin(), keys.end(), [](const std::array<long long, 4>& a, const std::array<long long, 4>& b) {
+      return a[0] < b[0];
+    });
+    std::vector<BItem>& items = hitems;
+    items.resize(keys.size());
+    for (size_t k = 0; k < keys.size(); ++k) items[k] = BItem{(int)keys[k][1], (int)keys[k][2], (int)keys[k][3]};
+    nitems = (int)items.size();
+    if (!ditems || nitems > item_cap) {
+      MG_TRY(dalloc(&ditems, items.size()));
+      item_cap = nitems;
+    }
+    if (tracing) MG_TRY(ensure_trace());
+    MG_HIP(hipMemcpy(ditems, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice));
+    return MG_OK;
+  }
+  int item_cap = 0;
+  std::vector<BItem> hitems;
+  bool tracing = false;
+  unsigned long long* dtrace = nullptr;
+  int trace_cap = 0;
+
+  int ensure_trace() {
+    if (nitems > trace_cap) {
+      MG_TRY(dalloc(&dtrace, 4 * (size_t)nitems));
+      trace_cap = nitems;
+    }
+    return MG_OK;
+  }
+
+  int set_trace(bool on) override {
+    tracing = on;
+    return on ? ensure_trace() : MG_OK;
+  }
+
+  // per item: prob, phase, tile, kind, wait start, ready, done, XCD << 16 | block
+  int get_trace(long long* out, int cap, int* count) override {
+    if (count) *count = nitems;
+    if (!out || !dtrace) return MG_OK;
+    const int m = std::min(cap, nitems);
+    std::vector<unsigned long long> t(4 * (size_t)nitems);
+    MG_HIP(hipMemcpyAsync(t.data(), dtrace, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < m; ++k) {
+      const BItem& w = hitems[k];
+      long long* o = out + 8 * (size_t)k;
+      o[0] = w.prob;
+      o[1] = w.phase;
+      o[2] = w.tile;
+      o[3] = hp[w.prob].phase_kind[w.phase];
+      for (int q = 0; q < 4; ++q) o[4 + q] = (long long)t[4 * (size_t)k + q];
+    }
+    return MG_OK;
+  }
+
+  int setup(const mg_params* ps, int count, hipStream_t stream) {
+    s = stream;
+    np = count;
+    for (int i = 0; i < count; ++i) {
+      mg_params q = ps[i];
+      q.sweep = MG_SWEEP_FUSED;
+      mg_ctx* c = nullptr;
+      MG_TRY(mg_setup(&q, stream, &c));
+      ctx.push_back(c);
+    }
+    hp.resize(np);
+    for (int i = 0; i < np; ++i) MG_TRY(describe(i, hp[i]));
+    MG_TRY(dalloc(&dp, np));
+    MG_TRY(dalloc(&ddone, (size_t)np * kBMaxPhases + 2));
+    dq = ddone + (size_t)np * kBMaxPhases;
+    int dev = 0, ncu = 0, per = 0;
+    MG_HIP(hipGetDevice(&dev));
+    MG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_cycle<T>, kBThreads, 0));
+    if (per < 1) return fail(MG_EDEVICE, "the batched kernel cannot be resident");
+    grid = per * ncu;
+    return build_items();
+  }
+
+  int ensure_hist(int n) {
+    if (n > hist_cap) {
+      MG_TRY(dalloc(&dhist, (size_t)2 * np * n));
+      hist_cap = n;
+    }
+    return MG_OK;
+  }
+
+  int cycle(int ncycles, double* res) override {
+    if (ncycles <= 0) return MG_OK;
+    MG_TRY(ensure_hist(ncycles));
+    // parities of the ping-pong buffers at this call
+    for (int i = 0; i < np; ++i) {
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      hp[i].parw = E.cur;
+      hp[i].pars = E.lv[E.L - 1].si == hp[i].si2[0] ? 0 : 1;
+      hp[i].w[0] = E.w[0];
+      hp[i].w[1] = E.w[1];
+    }
+    MG_HIP(hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(BProb<T>), hipMemcpyHostToDevice, s));
+    for (int k = 0; k < ncycles; ++k) {
+      MG_HIP(launch_fill(ddone, ((size_t)np * kBMaxPhases + 2) * sizeof(int), s));
+      BatchArgs<T> A;
+      A.items = ditems;
+      A.nitems = nitems;
+      A.probs = dp;
+      A.done = ddone;
+      A.queue = dq;
+      A.err = dq + 1;
+      A.hist = dhist + (size_t)2 * np * k;
+      A.cyc = k;
+      A.spin_limit = 1u << 20;
+      A.trace = tracing ? dtrace : nullptr;
+      hipLaunchKernelGGL(k_batch_cycle<T>, dim3(grid), dim3(kBThreads), 0, s, A);
+      MG_HIP(hipGetLastError());
+    }
+    int err = 0;
+    MG_HIP(hipMemcpyAsync(&err, dq + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    std::vector<double> h;
+    if (res) {
+      h.resize((size_t)2 * np * ncycles);
+      MG_HIP(hipMemcpyAsync(h.data(), dhist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    MG_HIP(hipStreamSynchronize(s));
+    // the engines advance with the device state
+    for (int i = 0; i < np; ++i) {
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      if (ncycles & 1) {
+        E.cur = 1 - E.cur;
+        if (E.si_alt) std::swap(E.lv[E.L - 1].si, E.si_alt);
+      }
+      E.iter += ncycles;
+    }
+    if (err) return fail(MG_EDEVICE, "batched cycle: a dependency wait exceeded its bound");
+    if (res) {
+      for (int k = 0; k < ncycles; ++k)
+        for (int i = 0; i < np; ++i) {
+          Engine<T>& E = *engine_of<T>(ctx[i]);
+          res[(size_t)k * np + i] = std::sqrt(E.hnorm_scale() * h[(size_t)2 * (np * k + i)]);
+        }
+    }
+    return MG_OK;
+  }
+
+  int configure(int z3, int z2, int sch) {
+    zc3 = z3;
+    zc2 = z2;
+    schedule = sch;
+    for (int i = 0; i < np; ++i) MG_TRY(describe(i, hp[i]));
+    return build_items();
+  }
+
+  int autotune(int reps, int* best, double* best_us, double* times) override {
+    hipEvent_t e0, e1;
+    MG_HIP(hipEventCreate(&e0));
+    MG_HIP(hipEventCreate(&e1));
+    int bcfg = 0;
+    double bt = 1e300;
+    const int n3 = (int)(sizeof(kBZc3) / sizeof(kBZc3[0])), n2 = (int)(sizeof(kBZc2) / sizeof(kBZc2[0]));
+    for (int cfg = 0; cfg < n3 * n2 * 2; ++cfg) {
+      MG_TRY(configure(cfg % n3, (cfg / n3) % n2, cfg / (n3 * n2)));
+      MG_TRY(cycle(1, nullptr));
+      MG_HIP(hipEventRecord(e0, s));
+      MG_TRY(cycle(reps, nullptr));
+      MG_HIP(hipEventRecord(e1, s));
+      MG_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / reps;
+      if (times) times[cfg] = us;
+      if (us < bt) {
+        bt = us;
+        bcfg = cfg;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    MG_TRY(configure(bcfg % n3, (bcfg / n3) % n2, bcfg / (n3 * n2)));
+    if (best) *best = bcfg;
+    if (best_us) *best_us = bt;
+    return MG_OK;
+  }
+};
+
+}  // namespace mg
+
+using namespace mg;
+
+struct mg_batch {
+  BatchBase* impl = nullptr;
+  ~mg_batch() { delete impl; }
+};
+
+extern "C" {
+
+int mg_batch_setup(const mg_params* ps, int count, void* hip_stream, mg_batch** out) {
+  if (!out) return fail(MG_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ps || count < 1) return fail(MG_EINVAL, "need at least one problem");
+  const int prec = ps[0].precision;
+  for (int i = 1; i < count; ++i)
+    if (ps[i].precision != prec) return fail(MG_EINVAL, "all problems of a batch share one precision");
+  mg_batch* b = new mg_batch();
+  int rc;
+  if (prec == MG_FP64) {
+    auto* impl = new Batch<double>();
+    b->impl = impl;
+    rc = impl->setup(ps, count, (hipStream_t)hip_stream);
+  } else {
+    auto* impl = new Batch<float>();
+    b->impl = impl;
+    rc = impl->setup(ps, count, (hipStream_t)hip_stream);
+  }
+  if (rc != MG_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return MG_OK;
+}
+
+void mg_batch_destroy(mg_batch* b) {
+  if (!b) return;
+  if (b->impl) (void)hipStreamSynchronize(b->impl->s);
+  delete b;
+}
+
+int mg_batch_problem(mg_batch* b, int i, mg_ctx** ctx) {
+  if (!b || !ctx || i < 0 || i >= (int)b->impl->ctx.size()) return fail(MG_EINVAL, "bad problem index");
+  *ctx = b->impl->ctx[i];
+  return MG_OK;
+}
+
+int mg_batch_cycle(mg_batch* b, int ncycles, double* res_h) {
+  if (!b || ncycles < 0) return fail(MG_EINVAL, "bad argument");
+  return b->impl->cycle(ncycles, res_h);
+}
+
+int mg_batch_autotune(mg_batch* b, int reps, int* config, double* us_per_cycle, double* times_us) {
+  if (!b || reps < 1) return fail(MG_EINVAL, "bad argument");
+  return b->impl->autotune(reps, config, us_per_cycle, times_us);
+}
+
+int mg_batch_configs(void) { return kBatchConfigs; }
+
+int mg_batch_trace(mg_batch* b, int enable) {
+  if (!b) return fail(MG_EINVAL, "NULL batch");
+  return b->impl->set_trace(enable != 0);
+}
+
+int mg_batch_get_trace(mg_batch* b, long long* out, int cap, int* count) {
+  if (!b || cap < 0) return fail(MG_EINVAL, "bad argument");
+  return b->impl->get_trace(out, cap, count);
+}
+
+int mg_batch_solve(mg_batch* b, const mg_c128* const* bs, mg_c128* const* us, double rtol, int maxit, int driver,
+                   int* iters, double* relres) {
+  if (!b || !bs || !us) return fail(MG_EINVAL, "NULL argument");
+  int worst = MG_OK;
+  for (size_t i = 0; i < b->impl->ctx.size(); ++i) {
+    int it = 0;
+    double rr = 0;
+    const int rc = mg_solve(b->impl->ctx[i], bs[i], us[i], rtol, maxit, driver, &it, &rr);
+    if (rc != MG_OK && rc != MG_ENOTCONV && rc != MG_EDIVERGED) return rc;
+    if (rc != MG_OK && worst == MG_OK) worst = rc;
+    if (iters) iters[i] = it;
+    if (relres) relres[i] = rr;
+  }
+  return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,704 @@
+// Host-side engine: per-level storage, cycle and solve drivers of one problem.
+// Shared by the C-ABI entry points (mg_api.hip) and the batched driver
+// (mg_batch.hip).
+#pragma once
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mg.h"
+#include "mg_internal.h"
+
+using std::complex;
+
+namespace mg {
+
+inline thread_local std::string g_err;
+
+inline int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define MG_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      return fail(MG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    }                                                                                  \
+  } while (0)
+
+#define MG_TRY(call)          \
+  do {                        \
+    int rc_ = (call);         \
+    if (rc_ != MG_OK) return rc_; \
+  } while (0)
+
+template <class T>
+inline cpx<T> to_c(complex<double> z) {
+  return mk(T(z.real()), T(z.imag()));
+}
+
+inline long long ipow(long long b, int e) {
+  long long r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+// Assembled stencil weights of the d-linear element matrices by number of
+// nonzero offsets: stiffness S_K and mass S_M (rows sum to 0 and 1).
+inline void stencil_weights(int dim, double sk[4], double sm[4]) {
+  if (dim == 3) {
+    const double k[4] = {8.0 / 3.0, 0.0, -1.0 / 6.0, -1.0 / 12.0};
+    const double m[4] = {8.0 / 27.0, 2.0 / 27.0, 1.0 / 54.0, 1.0 / 216.0};
+    std::copy(k, k + 4, sk);
+    std::copy(m, m + 4, sm);
+  } else {
+    const double k[4] = {8.0 / 3.0, -1.0 / 3.0, -1.0 / 3.0, 0.0};
+    const double m[4] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0, 0.0};
+    std::copy(k, k + 4, sk);
+    std::copy(m, m + 4, sm);
+  }
+}
+
+struct LevelScalars {
+  complex<double> eta, alpha, etad;
+};
+
+inline LevelScalars level_scalars(int dim, int lev, double theta, bool conj) {
+  LevelScalars s;
+  s.eta = std::pow(3.0, -lev) * std::exp(complex<double>(0.0, theta));
+  if (conj) s.eta = std::conj(s.eta);
+  s.alpha = std::pow(s.eta, dim - 2);
+  s.etad = std::pow(s.eta, dim);
+  return s;
+}
+
+template <class T>
+inline OpData<T> make_const_op(int dim, int lev, double theta, complex<double> phi, bool conj) {
+  OpData<T> op;
+  std::memset(&op, 0, sizeof(op));
+  op.n = (int)ipow(3, lev) + 1;
+  const LevelScalars ls = level_scalars(dim, lev, theta, conj);
+  if (conj) phi = std::conj(phi);
+  double sk[4], sm[4];
+  stencil_weights(dim, sk, sm);
+  for (int c = 0; c < 4; ++c) op.coef[c] = to_c<T>(ls.alpha * sk[c] - phi * ls.etad * sm[c]);
+  op.alpha = to_c<T>(ls.alpha);
+  op.etad = to_c<T>(ls.etad);
+  const complex<double> D = ls.alpha * (2.0 * dim * std::pow(2.0 / 3.0, dim - 1)) -
+                            phi * ls.etad * std::pow(2.0 / 3.0, dim);
+  op.invD = to_c<T>(1.0 / D);
+  op.phibar = nullptr;
+  op.invDv = nullptr;
+  return op;
+}
+
+inline complex<double> omega_level(int scheme, complex<double> w, int omega_L, int succ, int iteration) {
+  switch (scheme) {
+    case MG_OMEGA_CONST: return w;
+    case MG_OMEGA_JACOBI: return succ == 0 ? w : 0.0;
+    case MG_OMEGA_LGRID: return succ <= omega_L ? w : 0.0;
+    case MG_OMEGA_EXP: return std::pow(w, (double)(succ + 1));
+    default: return std::pow(w, (1.0 - 1.0 / std::max(iteration, 1)) * (succ + 1));
+  }
+}
+
+template <class T>
+struct Level {
+  int lev = 0, n = 0;
+  size_t N = 0;
+  cpx<T>*u = nullptr, *b = nullptr, *sc = nullptr, *sf = nullptr, *si = nullptr;
+  cpx<T>*phi = nullptr, *phibar = nullptr, *invDv = nullptr;
+  cpx<T>*pr = nullptr, *pz = nullptr;  // zero-start cycle scratch (coarse levels)
+  OpData<T> op;
+};
+
+template <class T>
+struct Engine {
+  int dim = 3, lmin = 1, L = 1, variant = MG_BPX, scheme = MG_OMEGA_CONST, omega_L = 1;
+  complex<double> omega = 0.6;
+  bool galerkin = true, fused = false, varying = false;
+  hipStream_t s = nullptr;
+  std::vector<Level<T>> lv;
+  cpx<T>* w[2] = {nullptr, nullptr};
+  int cur = 0;
+  cpx<T>* si_alt = nullptr;    // second si buffer of level L-1 (fused BPX sweep reads old, writes new)
+  cpx<T>* tune_c = nullptr;    // coarse scratch for the autotuner
+  cpx<T>*tA = nullptr, *tR = nullptr, *tRh = nullptr;
+  double* partials = nullptr;  // 2 * max(kRedBlocks, fused blocks)
+  double* red = nullptr;       // 2 doubles
+  double* hist = nullptr;      // 2 * hist_cap
+  int hist_cap = 0;
+  int iter = 0;
+  int fused_blocks = 0;
+  int partials_cap = 0;        // capacity of `partials` in (sum, max) pairs
+  std::vector<cpx<T>*> kv;     // Krylov vectors
+  std::vector<void*> owned;
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs around finest sweeps
+  size_t ev_used = 0;
+
+  ~Engine() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (void* p : owned) (void)hipFree(p);
+  }
+
+  int mark(bool start) {
+    if (!timing) return MG_OK;
+    if (ev_used == ev.size()) {
+      hipEvent_t e;
+      MG_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    MG_HIP(hipEventRecord(ev[ev_used++], s));
+    (void)start;
+    return MG_OK;
+  }
+
+  int alloc(void** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return fail(MG_ENOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    owned.push_back(*p);
+    return MG_OK;
+  }
+  template <class P>
+  int alloc_c(P** p, size_t count) {
+    void* q = nullptr;
+    MG_TRY(alloc(&q, count * sizeof(P)));
+    MG_HIP(launch_fill(q, count * sizeof(P), s));
+    *p = (P*)q;
+    return MG_OK;
+  }
+
+  size_t NL() const { return lv[L].N; }
+
+  // op_only: keep the finest-level operator data only (no cycle state); used
+  // for the FP64 residual of the refinement loop.
+  int setup(const mg_params& p, hipStream_t stream, const cpx<double>* phi_field, bool op_only = false) {
+    s = stream;
+    dim = p.dim;
+    lmin = p.level_min;
+    L = p.level_max;
+    variant = p.variant;
+    scheme = p.omega_scheme;
+    omega_L = p.omega_L;
+    omega = complex<double>(p.omega.re, p.omega.im);
+    varying = phi_field != nullptr;
+    const bool conj = p.conjugate != 0;
+    galerkin = !varying;
+    if (p.restrict_form == MG_RESTRICT_FAS) galerkin = false;
+    if (p.restrict_form == MG_RESTRICT_GALERKIN) {
+      if (varying) return fail(MG_EINVAL, "GALERKIN restriction needs a constant phi");
+      galerkin = true;
+    }
+    if (op_only) lmin = L;
+    const bool fused_ok = fused_partials_blocks(dim, (int)ipow(3, L) + 1, 0) > 0;
+    fused = galerkin && !varying && L > lmin && p.sweep != MG_SWEEP_GENERIC && fused_ok && !op_only;
+    if (p.sweep == MG_SWEEP_FUSED && !fused)
+      return fail(MG_EINVAL, "FUSED sweep needs constant phi, GALERKIN form, level_max > level_min "
+                             "and a built fused kernel");
+    lv.resize(L + 1);
+    for (int l = lmin; l <= L; ++l) {
+      Level<T>& v = lv[l];
+      v.lev = l;
+      v.n = (int)ipow(3, l) + 1;
+      v.N = (size_t)ipow(v.n, dim);
+      v.op = make_const_op<T>(dim, l, p.theta, complex<double>(p.phi.re, p.phi.im), conj);
+      if (l < L) {
+        MG_TRY(alloc_c(&v.u, v.N));
+        MG_TRY(alloc_c(&v.b, v.N));
+        MG_TRY(alloc_c(&v.sc, v.N));
+        MG_TRY(alloc_c(&v.sf, v.N));
+        MG_TRY(alloc_c(&v.si, v.N));
+        MG_TRY(alloc_c(&v.pr, v.N));
+        MG_TRY(alloc_c(&v.pz, v.N));
+      } else if (!op_only) {
+        MG_TRY(alloc_c(&v.b, v.N));
+        MG_TRY(alloc_c(&w[0], v.N));
+        MG_TRY(alloc_c(&w[1], v.N));
+      }
+    }
+    if (varying) {
+      // nodal phi on every level by injection, cell averages, accumulated diagonal
+      for (int l = L; l >= lmin; --l) {
+        Level<T>& v = lv[l];
+        MG_TRY(alloc_c(&v.phi, v.N));
+        if (l == L) {
+          MG_HIP((launch_convert<double, T>(v.N, phi_field, v.phi, 1.0, s)));
+        } else {
+          MG_HIP(launch_inject<T>(dim, v.n, lv[l + 1].phi, v.phi, s));
+        }
+      }
+      for (int l = lmin; l <= L; ++l) {
+        Level<T>& v = lv[l];
+        MG_TRY(alloc_c(&v.phibar, (size_t)ipow(v.n - 1, dim)));
+        MG_TRY(alloc_c(&v.invDv, v.N));
+        MG_HIP(launch_cellavg<T>(dim, v.n, v.phi, v.phibar, conj ? 1 : 0, s));
+        v.op.phibar = v.phibar;
+        MG_HIP(launch_invdiag<T>(dim, v.op, v.invDv, s));
+        v.op.invDv = v.invDv;
+      }
+    }
+    if (fused && variant == MG_BPX) MG_TRY(alloc_c(&si_alt, lv[L - 1].N));
+    int max_blocks = kRedBlocks;
+    if (fused) {
+      for (int t = 0; t < fused_tile_count(dim); ++t)
+        max_blocks = std::max(max_blocks, fused_partials_blocks(dim, lv[L].n, t));
+      set_tile(default_tile());
+    }
+    MG_TRY(alloc_c(&partials, 2 * (size_t)max_blocks));
+    partials_cap = max_blocks;
+    MG_TRY(alloc_c(&red, 4));
+    MG_TRY(ensure_hist(64));
+    return MG_OK;
+  }
+
+  int tile = 0;
+
+  // Default tile: small tiles while the coarse grid is small (more blocks),
+  // otherwise the tallest tile with the short z chunk.
+  int default_tile() const {
+    if (dim == 2) return lv[L].n <= 250 ? 1 : 0;
+    return lv[L].n <= 82 ? 1 : 0;
+  }
+  void set_tile(int t) {
+    tile = t;
+    fused_blocks = fused_partials_blocks(dim, lv[L].n, t);
+  }
+
+  int ensure_hist(int cap) {
+    if (cap <= hist_cap) return MG_OK;
+    MG_TRY(alloc_c(&hist, 2 * (size_t)cap));
+    hist_cap = cap;
+    return MG_OK;
+  }
+
+  int ensure_scratch() {
+    if (!tA) {
+      MG_TRY(alloc_c(&tA, NL()));
+      MG_TRY(alloc_c(&tR, NL()));
+      MG_TRY(alloc_c(&tRh, NL()));
+    }
+    return MG_OK;
+  }
+
+  int ensure_krylov() {
+    if (kv.empty()) {
+      kv.resize(8);
+      for (auto& p : kv) MG_TRY(alloc_c(&p, NL()));
+    }
+    return MG_OK;
+  }
+
+  int zero_helpers() {
+    for (int l = lmin; l < L; ++l) {
+      MG_HIP(launch_fill(lv[l].sc, lv[l].N * sizeof(cpx<T>), s));
+      MG_HIP(launch_fill(lv[l].sf, lv[l].N * sizeof(cpx<T>), s));
+      MG_HIP(launch_fill(lv[l].si, lv[l].N * sizeof(cpx<T>), s));
+    }
+    if (si_alt) MG_HIP(launch_fill(si_alt, lv[L - 1].N * sizeof(cpx<T>), s));
+    iter = 0;
+    return MG_OK;
+  }
+
+  int set_rhs(const cpx<T>* b) {
+    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, b, lv[L].b, mk(T(1), T(0)), s));
+    return zero_helpers();
+  }
+
+  int set_solution(const cpx<T>* u) {
+    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, u, w[cur], mk(T(1), T(0)), s));
+    for (int l = L; l > lmin; --l) {
+      const cpx<T>* src = l == L ? w[cur] : lv[l].u;
+      MG_HIP(launch_inject<T>(dim, lv[l - 1].n, src, lv[l - 1].u, s));
+    }
+    return zero_helpers();
+  }
+
+  // Descent (pre-phase) on the coarse levels l_min .. L-1.
+  int pre_coarse() {
+    for (int l = lmin; l < L; ++l) {
+      Level<T>& v = lv[l];
+      const bool hc = l > lmin;
+      MG_HIP(launch_pre<T>(dim, v.n, v.u, v.sc, v.sf, hc ? lv[l - 1].sc : nullptr, hc ? lv[l - 1].si : nullptr,
+                           hc ? 1 : 0, variant == MG_BPX ? 1 : 0, s));
+    }
+    return MG_OK;
+  }
+
+  int cycle_once(int k) {
+    ++iter;
+    MG_TRY(ensure_hist(k + 1));
+    MG_TRY(pre_coarse());
+    Level<T>& f = lv[L];
+    const bool hc = L > lmin;
+    Level<T>* c = hc ? &lv[L - 1] : nullptr;
+    const complex<double> wL = omega_level(scheme, omega, omega_L, 0, iter);
+    const int mask = (hc && variant != MG_ADD) ? 1 : 0;
+    int nparts = kRedBlocks;
+    MG_TRY(mark(true));
+    if (fused) {
+      FusedArgs<T> a = fused_args(w[1 - cur], c->b, c->sf, si_alt, wL.real(), wL.imag());
+      MG_HIP(launch_fused<T>(dim, a, s));
+      if (variant == MG_BPX) std::swap(c->si, si_alt);
+      nparts = fused_blocks;
+    } else {
+      MG_TRY(ensure_scratch());
+      cpx<T>* U = w[1 - cur];
+      MG_HIP(launch_fine_pre<T>(dim, f.n, w[cur], U, hc ? c->sc : nullptr, hc ? c->si : nullptr, hc ? 1 : 0,
+                                variant == MG_BPX ? 1 : 0, s));
+      if (!galerkin && hc) MG_HIP(launch_uhat<T>(dim, f.n, U, c->u, tA, s));
+      MG_HIP(launch_resid<T>(dim, f.op, f.b, U, tR, partials, &nparts, s));
+      if (!galerkin && hc) MG_HIP(launch_resid<T>(dim, f.op, f.b, tA, tRh, nullptr, nullptr, s));
+      MG_HIP(launch_update<T>(dim, f.op, tR, to_c<T>(wL), mask, U, nullptr, nullptr,
+                              (hc && variant == MG_ADD) ? c->sf : nullptr, (hc && variant == MG_BPX) ? c->si : nullptr,
+                              s));
+      if (hc) MG_HIP(launch_restrict<T>(dim, c->n, galerkin ? tR : tRh, c->b, s));
+    }
+    MG_TRY(mark(false));
+    cur = 1 - cur;
+    MG_HIP(launch_finish_sum_max(partials, nparts, hist + 2 * k, s));
+    // Backtracking (post-phase) on the coarse levels L-1 .. l_min.
+    for (int l = L - 1; l >= lmin; --l) {
+      Level<T>& v = lv[l];
+      const bool hcc = l > lmin;
+      Level<T>* cc = hcc ? &lv[l - 1] : nullptr;
+      const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, iter);
+      const cpx<T>* r;
+      if (galerkin && hcc) {
+        MG_HIP(launch_post_galerkin<T>(dim, v.op, v.b, to_c<T>(wl), variant != MG_ADD ? 1 : 0, v.sc, v.sf, cc->b,
+                                       variant == MG_ADD ? cc->sf : nullptr, variant == MG_BPX ? cc->si : nullptr, s));
+        continue;
+      }
+      if (galerkin) {
+        r = v.b;
+      } else {
+        MG_TRY(ensure_scratch());
+        if (hcc) MG_HIP(launch_uhat<T>(dim, v.n, v.u, cc->u, tA, s));
+        MG_HIP(launch_resid<T>(dim, v.op, v.b, v.u, tR, nullptr, nullptr, s));
+        if (hcc) MG_HIP(launch_resid<T>(dim, v.op, v.b, tA, tRh, nullptr, nullptr, s));
+        r = tR;
+      }
+      MG_HIP(launch_update<T>(dim, v.op, r, to_c<T>(wl), (hcc && variant != MG_ADD) ? 1 : 0, nullptr, v.sc, v.sf,
+                              (hcc && variant == MG_ADD) ? cc->sf : nullptr,
+                              (hcc && variant == MG_BPX) ? cc->si : nullptr, s));
+      if (hcc) MG_HIP(launch_restrict<T>(dim, cc->n, galerkin ? v.b : tRh, cc->b, s));
+    }
+    return MG_OK;
+  }
+
+  FusedArgs<T> fused_args(cpx<T>* wout, cpx<T>* rhoc, cpx<T>* sfc, cpx<T>* sic_out, double wL_re, double wL_im) {
+    Level<T>& f = lv[L];
+    Level<T>* c = &lv[L - 1];
+    FusedArgs<T> a;
+    a.n = f.n;
+    a.nc = c->n;
+    a.w = w[cur];
+    a.wout = wout;
+    a.b = f.b;
+    a.scc = c->sc;
+    a.sic = variant == MG_BPX ? c->si : nullptr;
+    a.rhoc = rhoc;
+    a.sfc = variant == MG_ADD ? sfc : nullptr;
+    a.sic_out = variant == MG_BPX ? sic_out : nullptr;
+    for (int q = 0; q < 4; ++q) a.coef[q] = f.op.coef[q];
+    a.ws = to_c<T>(complex<double>(wL_re, wL_im) * complex<double>(f.op.invD.re, f.op.invD.im));
+    a.partials = partials;
+    a.variant = variant;
+    a.tile = tile;
+    return a;
+  }
+
+  // Times every tile variant of the fused sweep on scratch outputs; keeps the best.
+  int autotune(int reps, int* best_tile, double* best_us, double* times) {
+    if (!fused) return fail(MG_EINVAL, "the context has no fused sweep");
+    MG_TRY(ensure_scratch());
+    if (!tune_c) {
+      MG_TRY(alloc_c(&tune_c, lv[L - 1].N));
+    }
+    Level<T>* c = &lv[L - 1];
+    const int saved = tile;
+    hipEvent_t e0, e1;
+    MG_HIP(hipEventCreate(&e0));
+    MG_HIP(hipEventCreate(&e1));
+    int best = saved;
+    double best_t = 1e300;
+    for (int t = 0; t < fused_tile_count(dim); ++t) {
+      set_tile(t);
+      FusedArgs<T> a = fused_args(tA, c->pr, tune_c, c->pz, omega.real(), omega.imag());
+      MG_HIP(launch_fused<T>(dim, a, s));  // warm-up
+      MG_HIP(hipEventRecord(e0, s));
+      for (int k = 0; k < reps; ++k) MG_HIP(launch_fused<T>(dim, a, s));
+      MG_HIP(hipEventRecord(e1, s));
+      MG_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double us = 1e3 * ms / std::max(reps, 1);
+      if (times) times[t] = us;
+      if (us < best_t) {
+        best_t = us;
+        best = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_tile(best);
+    if (best_tile) *best_tile = best;
+    if (best_us) *best_us = best_t;
+    return MG_OK;
+  }
+
+  // ||r||_h of cycle k from the history (host, after sync).
+  double hnorm_scale() const { return std::pow(3.0, -L * dim); }
+
+  int cycles(int ncycles, double* res_h, double* res_max) {
+    MG_TRY(ensure_hist(ncycles));
+    for (int k = 0; k < ncycles; ++k) MG_TRY(cycle_once(k));
+    if (res_h || res_max) {
+      std::vector<double> h(2 * (size_t)ncycles);
+      MG_HIP(hipMemcpyAsync(h.data(), hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < ncycles; ++k) {
+        if (res_h) res_h[k] = std::sqrt(hnorm_scale() * h[2 * k]);
+        if (res_max) res_max[k] = h[2 * k + 1];
+      }
+    }
+    return MG_OK;
+  }
+
+  int flush(cpx<T>* u_out_T) {
+    MG_TRY(pre_coarse());
+    const bool hc = L > lmin;
+    Level<T>* c = hc ? &lv[L - 1] : nullptr;
+    MG_HIP(launch_fine_pre<T>(dim, lv[L].n, w[cur], w[1 - cur], hc ? c->sc : nullptr, hc ? c->si : nullptr,
+                              hc ? 1 : 0, variant == MG_BPX ? 1 : 0, s));
+    cur = 1 - cur;
+    MG_TRY(zero_helpers());
+    if (u_out_T) MG_HIP(hipMemcpyAsync(u_out_T, w[cur], NL() * sizeof(cpx<T>), hipMemcpyDeviceToDevice, s));
+    return MG_OK;
+  }
+
+  const cpx<T>* field(int level, int f) const {
+    const Level<T>& v = lv[level];
+    if (level == L) {
+      if (f == MG_FIELD_U) return w[cur];
+      if (f == MG_FIELD_B) return v.b;
+      return nullptr;
+    }
+    switch (f) {
+      case MG_FIELD_U: return v.u;
+      case MG_FIELD_B: return v.b;
+      case MG_FIELD_SC: return v.sc;
+      case MG_FIELD_SF: return v.sf;
+      default: return v.si;
+    }
+  }
+
+  // z = B v (zero-start cycle); v, z finest-size T buffers; v's boundary ignored.
+  int precondition(const cpx<T>* v, cpx<T>* z) {
+    MG_TRY(ensure_scratch());
+    const int it = 1;
+    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, v, tR, mk(T(1), T(0)), s));
+    for (int l = L; l > lmin; --l) {
+      const cpx<T>* src = l == L ? tR : lv[l].pr;
+      MG_HIP(launch_restrict<T>(dim, lv[l - 1].n, src, lv[l - 1].pr, s));
+    }
+    for (int l = lmin; l <= L; ++l) {
+      const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, it);
+      const cpx<T>* rho = l == L ? tR : lv[l].pr;
+      cpx<T>* out = l == L ? z : lv[l].pz;
+      const cpx<T>* zc = l > lmin ? lv[l - 1].pz : nullptr;
+      MG_HIP(launch_prec_up<T>(dim, lv[l].op, rho, to_c<T>(wl), variant, l == lmin ? 1 : 0, zc, out, s));
+    }
+    return MG_OK;
+  }
+
+  int dot(const cpx<T>* a, const cpx<T>* b, complex<double>* out) {
+    MG_HIP(launch_dot<T>(NL(), a, b, partials, s));
+    MG_HIP(launch_finish_sum2(partials, kRedBlocks, red, s));
+    double h[2];
+    MG_HIP(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    *out = complex<double>(h[0], h[1]);
+    return MG_OK;
+  }
+
+  int norm2(const cpx<T>* a, double* out) {
+    MG_HIP(launch_norm2<T>(NL(), a, partials, s));
+    MG_HIP(launch_finish_sum_max(partials, kRedBlocks, red, s));
+    double h[2];
+    MG_HIP(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    *out = std::sqrt(h[0]);
+    return MG_OK;
+  }
+
+  // Right-preconditioned BiCGStab (van der Vorst) on H x = b, T-precision vectors,
+  // FP64 scalars.  b, x finest-size T buffers (x: initial guess in, result out).
+  int bicgstab(const cpx<T>* b_in, cpx<T>* x, double rtol, int maxit, int* its, double* relres) {
+    MG_TRY(ensure_krylov());
+    MG_TRY(ensure_scratch());
+    cpx<T>*r = kv[0], *rh = kv[1], *p = kv[2], *v = kv[3], *sv = kv[4], *t = kv[5], *y = kv[6], *z = kv[7];
+    const size_t N = NL();
+    const OpData<T>& op = lv[L].op;
+    cpx<T>* b = tRh;  // boundary-cleaned copy of b
+    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, b_in, b, mk(T(1), T(0)), s));
+    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, x, x, mk(T(1), T(0)), s));
+    double bnorm;
+    MG_TRY(norm2(b, &bnorm));
+    if (bnorm == 0.0) {
+      MG_HIP(launch_fill(x, N * sizeof(cpx<T>), s));
+      if (its) *its = 0;
+      if (relres) *relres = 0.0;
+      return MG_OK;
+    }
+    MG_HIP(launch_resid<T>(dim, op, b, x, r, nullptr, nullptr, s));
+    MG_HIP(hipMemcpyAsync(rh, r, N * sizeof(cpx<T>), hipMemcpyDeviceToDevice, s));
+    MG_HIP(launch_fill(p, N * sizeof(cpx<T>), s));
+    MG_HIP(launch_fill(v, N * sizeof(cpx<T>), s));
+    complex<double> rho = 1.0, alpha = 1.0, om = 1.0;
+    double rn;
+    MG_TRY(norm2(r, &rn));
+    double rel = rn / bnorm;
+    const double r0 = rel;
+    int it = 0;
+    int status = MG_ENOTCONV;
+    if (rel <= rtol) status = MG_OK;
+    for (it = 1; it <= maxit && status == MG_ENOTCONV; ++it) {
+      complex<double> rho_new;
+      MG_TRY(dot(rh, r, &rho_new));
+      const complex<double> beta = (rho_new / rho) * (alpha / om);
+      MG_HIP(launch_bicg_p<T>(N, r, v, to_c<double>(beta), to_c<double>(om), p, s));
+      MG_TRY(precondition(p, y));
+      MG_HIP(launch_apply<T>(dim, op, y, v, s));
+      complex<double> rhv;
+      MG_TRY(dot(rh, v, &rhv));
+      alpha = rho_new / rhv;
+      // s = r - alpha v
+      MG_HIP(hipMemcpyAsync(sv, r, N * sizeof(cpx<T>), hipMemcpyDeviceToDevice, s));
+      MG_HIP(launch_axpby<T>(N, to_c<double>(-alpha), v, mk(1.0, 0.0), sv, s));
+      double sn;
+      MG_TRY(norm2(sv, &sn));
+      if (sn / bnorm <= rtol) {
+        MG_HIP(launch_axpby<T>(N, to_c<double>(alpha), y, mk(1.0, 0.0), x, s));
+        rel = sn / bnorm;
+        status = MG_OK;
+        break;
+      }
+      MG_TRY(precondition(sv, z));
+      MG_HIP(launch_apply<T>(dim, op, z, t, s));
+      complex<double> ts, tt;
+      MG_TRY(dot(t, sv, &ts));
+      MG_TRY(dot(t, t, &tt));
+      om = ts / tt;
+      MG_HIP(launch_bicg_xr<T>(N, x, y, z, to_c<double>(alpha), to_c<double>(om), r, sv, t, s));
+      rho = rho_new;
+      MG_TRY(norm2(r, &rn));
+      rel = rn / bnorm;
+      if (!std::isfinite(rel) || rel > 1e8 * std::max(r0, 1e-300)) {
+        status = MG_EDIVERGED;
+        break;
+      }
+      if (rel <= rtol) {
+        status = MG_OK;
+        break;
+      }
+    }
+    if (its) *its = std::min(it, maxit);
+    if (relres) *relres = rel;
+    return status;
+  }
+
+  // Residual h-norm of (u, b) on the finest level: ||b - H u||_h.
+  int resid_norm(const cpx<T>* u, const cpx<T>* b, double* res_h, double* res_max) {
+    MG_TRY(ensure_scratch());
+    int np = 0;
+    MG_HIP(launch_resid<T>(dim, lv[L].op, b, u, tA, partials, &np, s));
+    MG_HIP(launch_finish_sum_max(partials, np, red, s));
+    double h[2];
+    MG_HIP(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (res_h) *res_h = std::sqrt(hnorm_scale() * h[0]);
+    if (res_max) *res_max = h[1];
+    return MG_OK;
+  }
+
+  // Stationary driver: cycles until ||r_n||_h <= rtol ||b||_h, then flush.
+  int stationary(const cpx<T>* b, cpx<T>* u, double rtol, int maxit, int* its, double* relres) {
+    MG_TRY(set_rhs(b));
+    MG_TRY(set_solution(u));
+    double bh;
+    {
+      MG_TRY(ensure_scratch());
+      MG_HIP(launch_fill(tRh, NL() * sizeof(cpx<T>), s));
+      MG_TRY(resid_norm(tRh, lv[L].b, &bh, nullptr));
+    }
+    if (bh == 0.0) {
+      MG_HIP(launch_fill(u, NL() * sizeof(cpx<T>), s));
+      if (its) *its = 0;
+      if (relres) *relres = 0;
+      return MG_OK;
+    }
+    const int chunk = 4;
+    int done = 0, status = MG_ENOTCONV;
+    double r0 = -1;
+    std::vector<double> rh(chunk);
+    while (done < maxit) {
+      const int m = std::min(chunk, maxit - done);
+      MG_TRY(cycles(m, rh.data(), nullptr));
+      for (int k = 0; k < m; ++k) {
+        if (r0 < 0) r0 = rh[k];
+        const double rel = rh[k] / bh;
+        if (!std::isfinite(rel) || rh[k] > 1e8 * r0) {
+          status = MG_EDIVERGED;
+          break;
+        }
+        if (rel <= rtol) {
+          status = MG_OK;
+          break;
+        }
+      }
+      done += m;
+      if (status != MG_ENOTCONV) break;
+    }
+    MG_TRY(flush(u));
+    double fin;
+    MG_TRY(resid_norm(u, lv[L].b, &fin, nullptr));
+    if (its) *its = done;
+    if (relres) *relres = fin / bh;
+    if (status == MG_OK && fin / bh > rtol) status = MG_OK;  // the flushed iterate is one cycle further
+    return status;
+  }
+};
+
+}  // namespace mg
+
+using namespace mg;
+
+struct mg_ctx {
+  mg_params p;
+  hipStream_t s = nullptr;
+  Engine<double>* e64 = nullptr;  // FP64 engine (precision FP64) or FP64 finest operator holder
+  Engine<float>* e32 = nullptr;   // complex64 corrections (precision FP32_REFINE)
+  cpx<double>* phi64 = nullptr;   // copy of the nodal phi field (FP64 operator with FP32 engine)
+  std::vector<void*> owned;
+  // FP64 finest operator and scratch for the refinement loop
+  OpData<double> op64;
+  cpx<double>*r64 = nullptr, *b64 = nullptr;
+  cpx<float>*r32 = nullptr, *e32v = nullptr;
+  ~mg_ctx() {
+    delete e64;
+    delete e32;
+    for (void* q : owned) (void)hipFree(q);
+  }
+};
+

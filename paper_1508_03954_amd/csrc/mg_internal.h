@@ -152,5 +152,8 @@ template <class T>
 hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);
 int fused_tile_count(int dim);
 int fused_partials_blocks(int dim, int n, int tile);  // -1 if unsupported
+// Tile variant with the given shape (3D: coarse rows, rows per thread, coarse
+// planes; 2D: coarse rows zc only), or -1.
+int fused_tile_index(int dim, int tyc, int rpt, int zc);
 
 }  // namespace mg

@@ -8,210 +8,10 @@
 // zero on boundary vertices; kernels keep them so.
 #include <algorithm>
 
-#include "mg_internal.h"
+#include "mg_common.h"
+#include "mg_level_ops.h"
 
 namespace mg {
-
-template <class T>
-__device__ inline cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.re + b.re, a.im + b.im); }
-template <class T>
-__device__ inline cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.re - b.re, a.im - b.im); }
-template <class T>
-__device__ inline cpx<T> operator*(T s, cpx<T> a) { return mk(s * a.re, s * a.im); }
-template <class T>
-__device__ inline cpx<T> cmul(cpx<T> a, cpx<T> b) {
-  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
-}
-template <class T>
-__device__ inline cpx<T> cconjmul(cpx<T> a, cpx<T> b) {  // conj(a) * b
-  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
-}
-template <class T>
-__device__ inline cpx<T> czero() { return mk(T(0), T(0)); }
-
-// Level sizes are capped so that every vertex index fits 32 bits (the host
-// checks level_max), which keeps the index arithmetic in 32-bit integers.
-template <int D>
-__device__ inline void unravel(long long ii, int n, int j[3]) {
-  unsigned i = (unsigned)ii;
-  const unsigned un = (unsigned)n;
-  const unsigned t = i / un;
-  j[0] = (int)(i - t * un);
-  if (D == 3) {
-    const unsigned z = t / un;
-    j[1] = (int)(t - z * un);
-    j[2] = (int)z;
-  } else {
-    j[1] = (int)t;
-    j[2] = 0;
-  }
-}
-
-template <int D>
-__device__ inline long long ravel(const int j[3], int n) {
-  return D == 3 ? ((long long)j[2] * n + j[1]) * n + j[0] : (long long)j[1] * n + j[0];
-}
-
-template <int D>
-__device__ inline bool is_interior(const int j[3], int n) {
-  for (int a = 0; a < D; ++a)
-    if (j[a] <= 0 || j[a] >= n - 1) return false;
-  return true;
-}
-
-template <int D>
-__device__ inline bool is_cpoint(const int j[3]) {
-  for (int a = 0; a < D; ++a)
-    if (j[a] % 3 != 0) return false;
-  return true;
-}
-
-template <int D>
-__device__ inline long long total(int n) {
-  return D == 3 ? (long long)n * n * n : (long long)n * n;
-}
-
-// Row-based traversal of a level: a wavefront covers 64 consecutive x of one
-// row (y, z); the row index is uniform across the wave, blocks of 4 waves walk
-// the rows grid-stride.  No per-vertex integer division.
-#define MG_ROWS(D, n)                                                                       \
-  const int lane_ = threadIdx.x & 63;                                                        \
-  const int x_ = blockIdx.x * 64 + lane_;                                                    \
-  const int nrows_ = (D == 3) ? (n) * (n) : (n);                                             \
-  for (int row_ = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); \
-       row_ < nrows_; row_ += gridDim.y * 4)
-
-// Inside MG_ROWS: vertex multi-index j and linear index i; false when x is past the row.
-template <int D>
-__device__ inline bool row_vertex(int row, int x, int n, int j[3], long long& i) {
-  if (x >= n) return false;
-  j[0] = x;
-  if (D == 3) {
-    j[2] = row / n;
-    j[1] = row - j[2] * n;
-  } else {
-    j[1] = row;
-    j[2] = 0;
-  }
-  i = (long long)row * n + x;
-  return true;
-}
-
-// (P v)_j: d-linear interpolation from the coarse level (nc per axis).  Per axis
-// a fine index j = 3m + q takes m with weight 1 (q = 0), or m and m+1 with
-// weights (2/3, 1/3) (q = 1) and (1/3, 2/3) (q = 2).
-template <class T, int D>
-__device__ cpx<T> prolong_at(const cpx<T>* __restrict__ vc, int nc, const int j[3]) {
-  const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
-  int m[3] = {0, 0, 0};
-  T w0[3] = {1, 1, 1}, w1[3] = {0, 0, 0};
-  bool two[3] = {false, false, false};
-  for (int a = 0; a < D; ++a) {
-    const int q = j[a] % 3;
-    m[a] = j[a] / 3;
-    if (q == 1) {
-      w0[a] = two3; w1[a] = third; two[a] = true;
-    } else if (q == 2) {
-      w0[a] = third; w1[a] = two3; two[a] = true;
-    }
-  }
-  cpx<T> acc = czero<T>();
-#pragma unroll
-  for (int c = 0; c < (1 << D); ++c) {
-    T w = T(1);
-    int k[3] = {0, 0, 0};
-    bool use = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const int bit = (c >> a) & 1;
-      use = use && (!bit || two[a]);
-      w *= bit ? w1[a] : w0[a];
-      k[a] = m[a] + (two[a] ? bit : 0);
-    }
-    if (use) acc = acc + w * vc[ravel<D>(k, nc)];
-  }
-  return acc;
-}
-
-// Constant-phi operator row at an interior vertex: the assembled 3^d stencil of
-// the d-linear element matrices has one weight per number of nonzero offsets
-// (centre, face, edge, corner).  Boundary neighbours count as zero.
-template <class T, int D>
-__device__ cpx<T> stencil_const(const cpx<T>* __restrict__ x, int n, const int j[3], const OpData<T>& op) {
-  cpx<T> s[4] = {czero<T>(), czero<T>(), czero<T>(), czero<T>()};
-  const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-  for (int oz = zlo; oz <= zhi; ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
-        if (!is_interior<D>(k, n)) continue;
-        const int cls = (ox != 0) + (oy != 0) + (oz != 0);
-        s[cls] = s[cls] + x[ravel<D>(k, n)];
-      }
-  cpx<T> r = czero<T>();
-  for (int c = 0; c <= D; ++c) r = r + cmul(op.coef[c], s[c]);
-  return r;
-}
-
-// Stiffness-only stencil weights S_K by class (real), used with a nodal phi.
-template <class T, int D>
-__device__ inline T stiff_weight(int cls) {
-  if (D == 3) {
-    const T w[4] = {T(8.0 / 3.0), T(0), T(-1.0 / 6.0), T(-1.0 / 12.0)};
-    return w[cls];
-  } else {
-    const T w[3] = {T(8.0 / 3.0), T(-1.0 / 3.0), T(-1.0 / 3.0)};
-    return w[cls];
-  }
-}
-
-// Nodal-phi operator row: alpha * (S_K x)_j - etad * sum_{c contains j} phibar_c (M x_c)_loc(j),
-// with M_kk' = 3^-d 2^-(number of axes where k and k' differ).
-template <class T, int D>
-__device__ cpx<T> stencil_var(const cpx<T>* __restrict__ x, int n, const int j[3], const OpData<T>& op) {
-  cpx<T> st = czero<T>();
-  const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-  for (int oz = zlo; oz <= zhi; ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
-        if (!is_interior<D>(k, n)) continue;
-        const int cls = (ox != 0) + (oy != 0) + (oz != 0);
-        st = st + stiff_weight<T, D>(cls) * x[ravel<D>(k, n)];
-      }
-  const T m0 = D == 3 ? T(1.0 / 27.0) : T(1.0 / 9.0);
-  cpx<T> ms = czero<T>();
-  const int nc = n - 1;
-  for (int c = 0; c < (1 << D); ++c) {
-    int loc[3] = {0, 0, 0}, cell[3] = {0, 0, 0};
-    bool ok = true;
-    for (int a = 0; a < D; ++a) {
-      loc[a] = (c >> a) & 1;          // position of j inside the cell
-      cell[a] = j[a] - loc[a];
-      if (cell[a] < 0 || cell[a] >= nc) ok = false;
-    }
-    if (!ok) continue;
-    cpx<T> acc = czero<T>();
-    for (int kk = 0; kk < (1 << D); ++kk) {
-      int v[3] = {0, 0, 0};
-      T w = m0;
-      for (int a = 0; a < D; ++a) {
-        const int b = (kk >> a) & 1;
-        v[a] = cell[a] + b;
-        if (b != loc[a]) w *= T(0.5);
-      }
-      if (!is_interior<D>(v, n)) continue;
-      acc = acc + w * x[ravel<D>(v, n)];
-    }
-    ms = ms + cmul(op.phibar[ravel<D>(cell, nc)], acc);
-  }
-  return cmul(op.alpha, st) - cmul(op.etad, ms);
-}
-
-template <class T, int D>
-__device__ inline cpx<T> apply_row(const cpx<T>* x, int n, const int j[3], const OpData<T>& op) {
-  return op.phibar ? stencil_var<T, D>(x, n, j, op) : stencil_const<T, D>(x, n, j, op);
-}
 
 // ---------------------------------------------------------------------------
 // Block reduction of (sum, max) into partials[blockIdx.x][2].
@@ -263,24 +63,15 @@ __global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __re
   }
 }
 
-// Coarse-level pre-phase (descent of tdAdd / tdBPX):
-//   sc += P sc_c ;  BPX: sc -= P si_c off c-points ;  u += sc + sf.
+// Coarse-level pre-phase (descent of tdAdd / tdBPX), see pre_vertex.
 template <class T, int D>
 __global__ void k_pre(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf,
                       const cpx<T>* __restrict__ scc, const cpx<T>* __restrict__ sic, int has_coarse, int bpx) {
-  const int nc = (n - 1) / 3 + 1;
   MG_ROWS(D, n) {
     int j[3];
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    if (!is_interior<D>(j, n)) continue;
-    cpx<T> s = sc[i];
-    if (has_coarse) {
-      s = s + prolong_at<T, D>(scc, nc, j);
-      if (bpx && !is_cpoint<D>(j)) s = s - prolong_at<T, D>(sic, nc, j);
-      sc[i] = s;
-    }
-    u[i] = u[i] + s + sf[i];
+    pre_vertex<T, D>(n, j, i, u, sc, sf, scc, sic, has_coarse, bpx);
   }
 }
 
@@ -338,88 +129,31 @@ __global__ void k_resid(OpData<T> op, const cpx<T>* __restrict__ b, const cpx<T>
   if (partials) block_sum_max(s2, sqrt(mx), partials);
 }
 
-// Post-phase pointwise part: s = omega r / D, sc = s (0 at c-points if mask_c),
-// finest: u += sc in place; coarse: sc_out = sc.  Injection to the coarser level
-// at c-points: sf_c = sf + sc, si_c = s.
+// Post-phase pointwise part, see update_vertex.
 template <class T, int D>
 __global__ void k_update(OpData<T> op, const cpx<T>* __restrict__ r, cpx<T> omega, int mask_c,
                          cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc_out, const cpx<T>* __restrict__ sf,
                          cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
-  const int n = op.n;
-  const int nc = (n - 1) / 3 + 1;
-  MG_ROWS(D, n) {
+  MG_ROWS(D, op.n) {
     int j[3];
     long long i;
-    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    const bool in = is_interior<D>(j, n);
-    cpx<T> s = czero<T>();
-    if (in) {
-      const cpx<T> id = op.invDv ? op.invDv[i] : op.invD;
-      s = cmul(omega, cmul(id, r[i]));
-    }
-    const bool cp = is_cpoint<D>(j);
-    const cpx<T> scv = (mask_c && cp) ? czero<T>() : s;
-    if (u) {
-      if (in) u[i] = u[i] + scv;
-    }
-    if (sc_out) sc_out[i] = scv;
-    if (cp && (sfc || sic)) {
-      int m[3] = {j[0] / 3, j[1] / 3, j[2] / 3};
-      const long long ic = ravel<D>(m, nc);
-      if (sfc) sfc[ic] = (sf ? sf[i] : czero<T>()) + scv;
-      if (sic) sic[ic] = s;
-    }
+    if (!row_vertex<D>(row_, x_, op.n, j, i)) continue;
+    update_vertex<T, D>(op, j, i, r, omega, mask_c, u, sc_out, sf, sfc, sic);
   }
 }
 
-// Coarse post-phase with the Galerkin form, one launch per level l > l_min.  A
-// thread owns coarse vertex m of level l-1 and the fine vertices 3m + q,
-// q in {0,1,2}^d, of level l.  It walks the restriction support 3m + o,
-// o in [-2, 2]^d, once: every value enters rho_c(m) = (R rho)(m), and on its
-// owned vertices it also forms s = omega rho / D, sc = s (0 on c-points when
-// masked) and the injections sf_c = sf + sc (add), si_c = s (BPX) at 3m.
+// Coarse post-phase with the Galerkin form, one launch per level l > l_min,
+// one thread per coarse vertex (see post_galerkin_vertex).
 template <class T, int D>
 __global__ void k_post_galerkin(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c,
                                 cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf, cpx<T>* __restrict__ rhoc,
                                 cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
-  const int n = op.n, nc = (n - 1) / 3 + 1;
-  const T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
+  const int nc = (op.n - 1) / 3 + 1;
   MG_ROWS(D, nc) {
     int m[3];
     long long ic;
     if (!row_vertex<D>(row_, x_, nc, m, ic)) continue;
-    const bool cin = is_interior<D>(m, nc);
-    cpx<T> acc = czero<T>();
-    const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
-    for (int oz = zlo; oz <= zhi; ++oz) {
-      for (int oy = -2; oy <= 2; ++oy) {
-#pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-          int j[3] = {3 * m[0] + ox, 3 * m[1] + oy, 3 * m[2] + oz};
-          const bool owned = ox >= 0 && oy >= 0 && oz >= 0;
-          bool inside = true;
-#pragma unroll
-          for (int a = 0; a < D; ++a) inside = inside && j[a] >= 0 && j[a] < n;
-          if (!inside || !(cin || owned)) continue;
-          const long long i = ravel<D>(j, n);
-          const cpx<T> v = rho[i];
-          acc = acc + (w[ox + 2] * w[oy + 2] * (D == 3 ? w[oz + 2] : T(1))) * v;
-          if (owned) {
-            const bool in = is_interior<D>(j, n);
-            cpx<T> sv = czero<T>();
-            if (in) sv = cmul(omega, cmul(op.invDv ? op.invDv[i] : op.invD, v));
-            const bool cp = ox == 0 && oy == 0 && oz == 0;
-            const cpx<T> scm = (mask_c && cp) ? czero<T>() : sv;
-            sc[i] = scm;
-            if (cp) {
-              if (sfc) sfc[ic] = sf[i] + scm;
-              if (sic) sic[ic] = sv;
-            }
-          }
-        }
-      }
-    }
-    rhoc[ic] = cin ? acc : czero<T>();
+    post_galerkin_vertex<T, D>(op, m, ic, rho, omega, mask_c, sc, sf, rhoc, sfc, sic);
   }
 }
 

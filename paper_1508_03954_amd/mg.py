@@ -29,7 +29,9 @@ EXPORTED = [
     "mg_params_default", "mg_setup", "mg_destroy", "mg_last_error", "mg_level_size", "mg_apply",
     "mg_rhs_from_nodal", "mg_set_rhs", "mg_set_solution", "mg_cycle", "mg_flush", "mg_get_level",
     "mg_precondition", "mg_solve", "mg_residual_norm", "mg_grad_potential", "mg_time_sweeps",
-    "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune",
+    "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
+    "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
+    "mg_batch_trace", "mg_batch_get_trace",
 ]
 
 
@@ -90,8 +92,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_set_tile.argtypes = [P, I]
     lib.mg_autotune.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.mg_sweep_time.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I)]
+    lib.mg_batch_setup.argtypes = [ctypes.POINTER(Params), I, P, ctypes.POINTER(P)]
+    lib.mg_batch_destroy.argtypes = [P]
+    lib.mg_batch_destroy.restype = None
+    lib.mg_batch_problem.argtypes = [P, I, ctypes.POINTER(P)]
+    lib.mg_batch_cycle.argtypes = [P, I, ctypes.POINTER(D)]
+    lib.mg_batch_autotune.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.mg_batch_configs.argtypes = []
+    lib.mg_batch_trace.argtypes = [P, I]
+    lib.mg_batch_get_trace.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]
+    lib.mg_batch_solve.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, I, ctypes.POINTER(I),
+                                   ctypes.POINTER(D)]
     for name in EXPORTED:
-        if name not in ("mg_params_default", "mg_destroy", "mg_last_error"):
+        if name not in ("mg_params_default", "mg_destroy", "mg_last_error", "mg_batch_destroy"):
             getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -107,6 +120,33 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def make_params(dim: int, level_max: int, level_min: int = 1, theta: float = 0.0, phi: complex = 0.0,
+                phi_field=None, variant: str = "bpx", omega_scheme: str = "const", omega: complex = 0.6,
+                omega_L: int = 1, precision: str = "fp64", conjugate: bool = False, restrict_form: str = "auto",
+                sweep: str = "auto"):
+    """mg_params from keyword values; returns (params, device phi field kept alive or None)."""
+    import torch
+    lib = load_library()
+    p = Params()
+    lib.mg_params_default(ctypes.byref(p))
+    p.dim, p.level_min, p.level_max = dim, level_min, level_max
+    p.theta = theta
+    p.phi = c128(complex(phi).real, complex(phi).imag)
+    keep = None
+    if phi_field is not None:
+        keep = phi_field.to(device="cuda", dtype=torch.complex128).contiguous()
+        p.phi_field = _ptr(keep)
+    p.variant = VARIANTS[variant]
+    p.omega_scheme = OMEGA_SCHEMES[omega_scheme]
+    p.omega = c128(complex(omega).real, complex(omega).imag)
+    p.omega_L = omega_L
+    p.precision = PRECISIONS[precision]
+    p.conjugate = 1 if conjugate else 0
+    p.restrict_form = RESTRICT_FORMS[restrict_form]
+    p.sweep = SWEEPS[sweep]
+    return p, keep
+
+
 class Solver:
     """One complex additive multilevel hierarchy on the unit hypercube."""
 
@@ -115,36 +155,37 @@ class Solver:
                  omega: complex = 0.6, omega_L: int = 1, precision: str = "fp64", conjugate: bool = False,
                  restrict_form: str = "auto", sweep: str = "auto", stream=None):
         import torch
-        self._torch = torch
         lib = load_library()
-        p = Params()
-        lib.mg_params_default(ctypes.byref(p))
-        p.dim, p.level_min, p.level_max = dim, level_min, level_max
-        p.theta = theta
-        p.phi = c128(complex(phi).real, complex(phi).imag)
-        self._phi_keep = None
-        if phi_field is not None:
-            phi_field = phi_field.to(device="cuda", dtype=torch.complex128).contiguous()
-            self._phi_keep = phi_field
-            p.phi_field = _ptr(phi_field)
-        p.variant = VARIANTS[variant]
-        p.omega_scheme = OMEGA_SCHEMES[omega_scheme]
-        p.omega = c128(complex(omega).real, complex(omega).imag)
-        p.omega_L = omega_L
-        p.precision = PRECISIONS[precision]
-        p.conjugate = 1 if conjugate else 0
-        p.restrict_form = RESTRICT_FORMS[restrict_form]
-        p.sweep = SWEEPS[sweep]
+        p, keep = make_params(dim, level_max, level_min, theta, phi, phi_field, variant, omega_scheme, omega,
+                              omega_L, precision, conjugate, restrict_form, sweep)
+        self._phi_keep = keep
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         ctx = ctypes.c_void_p()
         _check(lib.mg_setup(ctypes.byref(p), self.stream.cuda_stream, ctypes.byref(ctx)))
+        self._init_view(ctx, dim, level_min, level_max, self.stream, owned=True)
+
+    @classmethod
+    def _view(cls, ctx, dim, level_min, level_max, stream):
+        """A Solver on a context owned by someone else (a Batch)."""
+        obj = cls.__new__(cls)
+        obj._phi_keep = None
+        obj._init_view(ctx, dim, level_min, level_max, stream, owned=False)
+        return obj
+
+    def _init_view(self, ctx, dim, level_min, level_max, stream, owned):
+        import torch
+        self._torch = torch
         self._ctx = ctx
-        self._lib = lib
+        self._owned = owned
+        self._lib = load_library()
+        self.stream = stream
         self.dim, self.level_min, self.level_max = dim, level_min, level_max
         self.n = 3 ** level_max + 1
         self.shape = (self.n,) * dim
 
     def close(self):
+        if not getattr(self, "_owned", False):
+            return
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self._lib.mg_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
@@ -266,3 +307,89 @@ class Solver:
         g = self._new(dtype=self._torch.float64)
         _check(self._lib.mg_grad_potential(self._ctx, _ptr(u), _ptr(lam), _ptr(g)))
         return g
+
+
+class Batch:
+    """Independent problems advanced together by one persistent launch per cycle.
+
+    `problems` is a list of dicts of Solver keyword arguments (dim, level_max,
+    theta, phi, variant, omega, precision, ...; constant phi only).  The
+    per-problem contexts are reachable as `batch.solvers[i]` (set_rhs,
+    set_solution, get_level, flush, solve work on them as on a Solver)."""
+
+    def __init__(self, problems, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self._lib = lib
+        arr = (Params * len(problems))()
+        for i, kw in enumerate(problems):
+            kw = dict(kw)
+            if kw.get("phi_field") is not None:
+                raise ValueError("batched problems need a constant phi")
+            p, _ = make_params(**kw)
+            arr[i] = p
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        b = ctypes.c_void_p()
+        _check(lib.mg_batch_setup(arr, len(problems), self.stream.cuda_stream, ctypes.byref(b)))
+        self._b = b
+        self.count = len(problems)
+        self.solvers = []
+        for i, kw in enumerate(problems):
+            ctx = ctypes.c_void_p()
+            _check(lib.mg_batch_problem(b, i, ctypes.byref(ctx)))
+            self.solvers.append(Solver._view(ctx, kw["dim"], kw.get("level_min", 1), kw["level_max"], self.stream))
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._lib.mg_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+            self.solvers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cycle(self, ncycles: int = 1, norms: bool = True):
+        """ncycles batched cycles; returns an (ncycles, count) array of |r|_h (or None)."""
+        if not norms:
+            _check(self._lib.mg_batch_cycle(self._b, ncycles, None))
+            return None
+        res = (ctypes.c_double * (ncycles * self.count))()
+        _check(self._lib.mg_batch_cycle(self._b, ncycles, res))
+        return np.array(res[:]).reshape(ncycles, self.count)
+
+    def autotune(self, reps: int = 3):
+        """Times every configuration; returns (best, us per cycle, all times).
+        Advances the problems' state."""
+        cfg, us = ctypes.c_int(), ctypes.c_double()
+        n = self._lib.mg_batch_configs()
+        times = (ctypes.c_double * n)()
+        _check(self._lib.mg_batch_autotune(self._b, reps, ctypes.byref(cfg), ctypes.byref(us), times))
+        return cfg.value, us.value, list(times)
+
+    def trace(self, enable: bool = True):
+        _check(self._lib.mg_batch_trace(self._b, 1 if enable else 0))
+
+    def get_trace(self):
+        """Last cycle's per-item record as an (items, 8) int64 array: problem,
+        phase, tile, kind, wait start, ready, done (10 ns ticks), XCD << 16 | block."""
+        cnt = ctypes.c_int()
+        _check(self._lib.mg_batch_get_trace(self._b, None, 0, ctypes.byref(cnt)))
+        buf = (ctypes.c_longlong * (8 * cnt.value))()
+        _check(self._lib.mg_batch_get_trace(self._b, buf, cnt.value, ctypes.byref(cnt)))
+        return np.array(buf[:], dtype=np.int64).reshape(cnt.value, 8)
+
+    def solve(self, bs, us, rtol: float = 1e-10, maxit: int = 500, driver: str = "bicgstab"):
+        """Solves every problem (device complex128 tensors; us[i] initial guess,
+        overwritten).  Returns (iterations, relative residuals, status)."""
+        n = self.count
+        pb = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])
+        pu = (ctypes.c_void_p * n)(*[_ptr(u) for u in us])
+        its = (ctypes.c_int * n)()
+        rel = (ctypes.c_double * n)()
+        rc = self._lib.mg_batch_solve(self._b, pb, pu, rtol, maxit, DRIVERS[driver], its, rel)
+        _check(rc, allow=(MG_ENOTCONV, MG_EDIVERGED))
+        return np.array(its[:]), np.array(rel[:]), rc

@@ -1,0 +1,147 @@
+"""Batched form: independent problems of uneven depth (2D and 3D, several
+wavenumbers and variants) advanced by one persistent launch per cycle.
+
+* Each problem's full level state after batched cycles equals, bit for bit,
+  the state of the same problem advanced alone by mg_cycle with the same fused
+  tiling (FP64 and complex64), for the default and for every autotuned batch
+  configuration.
+* FP64 batched cycles against the pipelined FP64 oracle (1e-12).
+* The batched solve (complex64 corrections inside FP64 refinement) reaches the
+  requested residual on members of the many-problem workload.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.cycle import Params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1508_03954_amd import mg
+    mg.load_library()
+
+
+VARIANTS = ["bpx", "hb", "add"]
+
+
+def small_batch(precision="fp64"):
+    """Nine problems: 2D levels 3..5 and 3D levels 3..4, every variant."""
+    from paper_1508_03954_amd.inputs import config_batched
+    probs = config_batched(seed=4, n2d=6, n3d=3, levels2d=(3, 5), levels3d=(3, 4))
+    kws = []
+    for i, p in enumerate(probs):
+        kws.append(dict(dim=p.dim, level_max=p.level_max, theta=0.3 * (i % 2), phi=p.phi,
+                        variant=VARIANTS[i % 3], omega=0.6, precision=precision))
+    return probs, kws
+
+
+def field_states(s, L, lmin=1):
+    out = {}
+    for lev in range(lmin, L + 1):
+        for f in ("u", "b", "sc", "sf", "si"):
+            out[(lev, f)] = s.get_level(lev, f).cpu().numpy()
+    return out
+
+
+def start(s, chi):
+    b = s.rhs_from_nodal(torch.from_numpy(chi).cuda())
+    s.set_rhs(b)
+    s.set_solution(torch.zeros_like(b))
+    return b
+
+
+def check_equal_to_standalone(batch, probs, kws, ncycles):
+    from paper_1508_03954_amd import mg
+    for s, p in zip(batch.solvers, probs):
+        start(s, p.chi)
+    res = batch.cycle(ncycles)
+    for i, (s, p, kw) in enumerate(zip(batch.solvers, probs, kws)):
+        tile = s.tiles()[0]
+        alone = mg.Solver(**kw, sweep="fused")
+        alone.set_tile(tile)
+        start(alone, p.chi)
+        rh, _ = alone.cycle(ncycles)
+        assert np.array_equal(np.asarray(rh), res[:, i]), (i, rh, res[:, i])
+        got, ref = field_states(s, p.level_max), field_states(alone, p.level_max)
+        for key in ref:
+            assert np.array_equal(got[key], ref[key]), (i, key)
+        alone.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batched_cycles_equal_standalone(precision):
+    from paper_1508_03954_amd import mg
+    probs, kws = small_batch(precision)
+    batch = mg.Batch(kws)
+    print(f"\n[case] batch of {len(kws)} ({precision}), default configuration", flush=True)
+    check_equal_to_standalone(batch, probs, kws, 3)
+    batch.close()
+
+
+def test_batched_autotune_configurations_equal_standalone():
+    from paper_1508_03954_amd import mg
+    probs, kws = small_batch("fp64")
+    batch = mg.Batch(kws)
+    for s, p in zip(batch.solvers, probs):
+        start(s, p.chi)
+    cfg, us, _ = batch.autotune(reps=2)
+    print(f"\n[case] batch autotune: configuration {cfg}, {us:.1f} us per batched cycle", flush=True)
+    assert us > 0
+    check_equal_to_standalone(batch, probs, kws, 2)
+    batch.close()
+
+
+def test_batched_cycles_match_oracle():
+    from paper_1508_03954_amd import mg
+    probs, kws = small_batch("fp64")
+    batch = mg.Batch(kws)
+    for s, p in zip(batch.solvers, probs):
+        start(s, p.chi)
+    ncyc = 3
+    res = batch.cycle(ncyc)
+    for i, (s, p, kw) in enumerate(zip(batch.solvers, probs, kws)):
+        op = Params(dim=p.dim, level_max=p.level_max, theta=kw["theta"], phi=p.phi, variant=kw["variant"],
+                    omega=0.6)
+        pipe = O.Pipelined(op, O.lumped_rhs(p.chi, p.level_max, kw["theta"]))
+        for k in range(ncyc):
+            rh_ref, _ = pipe.cycle()
+            assert abs(res[k, i] - rh_ref) <= 1e-12 * rh_ref, (i, k, res[k, i], rh_ref)
+        u_ref = pipe.flush()
+        u = s.flush().cpu().numpy()
+        assert np.linalg.norm(u - u_ref) <= 1e-12 * np.linalg.norm(u_ref), i
+    batch.close()
+
+
+def test_batched_solve_fp32_refinement():
+    """Members of the many-problem workload (both dimensions, the deepest
+    levels) solved to 1e-10 with complex64 corrections in FP64 refinement; the
+    result against the FP64 solve of the same problem."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_batched
+    probs = config_batched()
+    pick = [i for i, p in enumerate(probs) if (p.dim == 2 and p.level_max == 6) or
+            (p.dim == 3 and p.level_max == 5)][:2]
+    pick += [i for i, p in enumerate(probs) if p.level_max == 3][:2]
+    sub = [probs[i] for i in pick]
+    kws = [dict(dim=p.dim, level_max=p.level_max, phi=p.phi, variant="bpx", precision="fp32_refine") for p in sub]
+    batch = mg.Batch(kws)
+    bs = [s.rhs_from_nodal(torch.from_numpy(p.chi).cuda()) for s, p in zip(batch.solvers, sub)]
+    us = [torch.zeros_like(b) for b in bs]
+    its, rel, rc = batch.solve(bs, us, rtol=1e-10, maxit=400)
+    print(f"\n[case] batched solve of problems {pick}: iterations {its.tolist()}, relres {rel.tolist()}", flush=True)
+    assert rc == 0 and np.all(rel <= 1e-10)
+    for p, b, u in zip(sub, bs, us):
+        ref = mg.Solver(p.dim, p.level_max, phi=p.phi, variant="bpx")
+        u64, _, rel64, rc64 = ref.solve(b, rtol=1e-12, maxit=2000)
+        assert rc64 == 0
+        err = (torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64)).item()
+        # relative residual 1e-10 bounds the error by cond(H) * 1e-10
+        assert err <= 1e-6, (p.name, err)
+    batch.close()

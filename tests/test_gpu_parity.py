@@ -156,9 +156,14 @@ def run_cycle_parity(dim, L, lmin, variant, restrict, sweep, phi_case, scheme, n
                     assert not np.any(got), (k, lev, field)
                     continue
                 scale = np.linalg.norm(ref)
-                if field == "b" and galerkin and lev < L:
-                    # restricted residual of a FAS state: compare at the scale of b_l
-                    scale = max(scale, np.linalg.norm(pipe.b[lev]))
+                if lev < L:
+                    # coarse FAS residuals are differences of O(|b_l|) terms: the
+                    # oracle's own rounding floor is relative to b_l (and to
+                    # omega b_l / D_l for the smoothing updates)
+                    if field == "b" and galerkin:
+                        scale = max(scale, np.linalg.norm(pipe.b[lev]))
+                    elif field in ("sc", "sf", "si"):
+                        scale = max(scale, abs(p.omega) * np.linalg.norm(pipe.b[lev] / p.D(lev)))
                 err = np.linalg.norm(got - ref) / scale
                 assert err <= tol, (k, lev, field, err)
     u_ref = pipe.flush()
