@@ -49,16 +49,27 @@ def fused_bytes(dim, L, variant, word=16):
     return word * (3 * NL + coarse_words * Nc)
 
 
-def traffic_from_profiles(kernel_src):
+FUSED_SOURCES = ["mg_fused_ops.h", "mg_fused.hip", "mg_internal.h", "mg_common.h"]
+
+
+def fused_source_digest():
+    """sha256 over the sources the finest-sweep kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in FUSED_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1508_03954_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles(tile):
     """HBM traffic of the finest sweep from the committed rocprofv3 counter
-    summary, scaled by the copy-kernel calibration; None when absent or when
-    the kernel source changed since the counters were taken."""
+    summary, scaled by the copy-kernel calibration; None when absent, when the
+    kernel sources changed since the counters were taken or when the counters
+    were taken for another tile."""
     path = os.path.join(ROOT, "profiles", "fused3_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    if rec.get("kernel_sha256") != digest:
+    if rec.get("kernel_sha256") != fused_source_digest() or rec.get("tile") != tile:
         return None
     return rec.get("bytes_per_launch")
 
@@ -105,6 +116,95 @@ def cpu_baseline(prob, variant, cycles):
     }
 
 
+def batched_extra(torch):
+    """96 independent problems (64 2D with finest level 3..6, 32 3D with 3..5,
+    k in [5, 60], phi = k^2 (1 + 0.5i), complex64 corrections): one batched
+    persistent cycle vs the same cycles launched problem by problem."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_batched
+    probs = config_batched()
+    kws = [dict(dim=p.dim, level_max=p.level_max, phi=p.phi, variant="bpx", precision="fp32_refine") for p in probs]
+    b = mg.Batch(kws)
+    rhs = [s.rhs_from_nodal(torch.from_numpy(p.chi).cuda()) for s, p in zip(b.solvers, probs)]
+
+    def reset():
+        for s, r in zip(b.solvers, rhs):
+            s.set_rhs(r)
+            s.set_solution(torch.zeros_like(r))
+        torch.cuda.synchronize()
+
+    reset()
+    best, best_us, times = b.autotune(reps=3)
+    reset()
+    reps = 10
+    b.cycle(2, norms=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.cycle(reps, norms=False)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / reps
+    reset()
+    for s in b.solvers:
+        s.cycle(1, norms=False)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    for _ in range(reps):
+        for s in b.solvers:
+            s.cycle(1, norms=False)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) / reps
+    U = sum(updates_per_cycle(p.dim, p.level_max) for p in probs)
+    NL = sum((3 ** p.level_max + 1) ** p.dim for p in probs)
+    b.close()
+    log(f"[bench] batched: {t_batch * 1e3:.0f} us per cycle of all 96 problems vs {t_seq * 1e3:.0f} us "
+        f"problem by problem (configuration {best})")
+    return {"workload": "96 problems: 64 2D (finest level 3..6) + 32 3D (3..5), k~U[5,60], phi=k^2(1+0.5i), "
+                        "BPX, complex64 corrections, seeds [4, i]",
+            "finest_vertices": NL, "vertex_updates_per_cycle": U,
+            "batched_ms_per_cycle": t_batch, "sequential_ms_per_cycle": t_seq,
+            "batched_vertex_updates_per_s": U / (t_batch * 1e-3),
+            "sequential_vertex_updates_per_s": U / (t_seq * 1e-3),
+            "speedup": t_seq / t_batch, "autotune": {"config": best, "us_per_config": [round(t, 1) for t in times]}}
+
+
+def refine_extra(torch, level):
+    """3D k = 40, phi = k^2 (1 + 0.5i): BiCGStab to relative residual 1e-10 with
+    complex64 corrections inside FP64 residual refinement vs the plain
+    complex128 solve; the mixed result's deviation from the FP64 one."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_3d_large
+    prob = config_3d_large(level_max=level)
+    res = {"workload": f"{prob.name}: d=3, levels 1..{level} ({3 ** level + 1}^3 vertices), BPX, omega 0.6"}
+    chi = torch.from_numpy(prob.chi).cuda()
+    del prob
+    u64 = None
+    for prec in ("fp32_refine", "fp64"):
+        s = mg.Solver(3, level, phi=1600.0 * (1 + 0.5j), variant="bpx", precision=prec)
+        b = s.rhs_from_nodal(chi)
+        u = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, its, rel, rc = s.solve(b, u0=u, rtol=1e-10, maxit=3000, driver="bicgstab")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        true_rel = s.residual_norm(u, b) / s.residual_norm(torch.zeros_like(b), b)
+        res[prec] = {"seconds": dt, "iterations": its, "relres": rel, "true_relres": true_rel, "status": rc}
+        log(f"[bench] L={level} {prec}: {dt:.2f} s, {its} iterations, relres {true_rel:.2e}")
+        if prec == "fp32_refine":
+            u_mixed = u
+        else:
+            u64 = u
+        del s, b
+        torch.cuda.empty_cache()
+    res["mixed_vs_fp64_rel_error"] = (torch.linalg.vector_norm(u_mixed - u64) /
+                                      torch.linalg.vector_norm(u64)).item()
+    res["speedup"] = res["fp64"]["seconds"] / res["fp32_refine"]["seconds"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +218,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the hb-variant and time-to-residual runs")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile variant of the fused sweep (no autotune)")
+    ap.add_argument("--refine-level", type=int, default=0,
+                    help="also solve the 3D k=40 problem at this level with complex64 refinement vs FP64 (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy three times (calibrates hardware byte counters)")
     args = ap.parse_args()
@@ -162,7 +264,7 @@ def main():
     value = ups / (ms_step * 1e-3)
     fb = fused_bytes(dim, L, args.variant)
     achieved = fb / (sweep_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_1508_03954_amd", "csrc", "mg_fused.hip"))
+    traffic = traffic_from_profiles(s.tiles()[0])
     log(f"[bench] cycle {ms_step * 1e3:.1f} us, finest sweep {sweep_ms * 1e3:.1f} us ({nsw} timed), "
         f"{achieved:.0f} GB/s algorithmic")
     # residual history sanity (the stationary cycle on this indefinite problem may grow)
@@ -228,6 +330,11 @@ def main():
                                 "seconds": t1 - t0, "iterations": its, "relres": rel,
                                 "true_relres": true_rel, "status": rc}
         log(f"[bench] BiCGStab to 1e-10: {t1 - t0:.3f} s, {its} iterations, relres {true_rel:.2e}")
+
+    if not args.no_extras:
+        out["batched"] = batched_extra(torch)
+    if args.refine_level:
+        out["fp32_refinement"] = refine_extra(torch, args.refine_level)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: FP64 oracle on the host ...")

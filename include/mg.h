@@ -138,7 +138,7 @@ int mg_set_solution(mg_ctx* ctx, const mg_c128* u);
 /* Runs ncycles pipelined cycles (one traversal each).  Cycle k reports the
  * residual of the iterate it started from (the half-iteration shift of
  * Section 5): res_h[k] = |b - H u|_h, |x|_h^2 = sum |h|^d |x_i|^2 over interior
- * vertices (Section 6), res_max[k] the max norm.  res_h / res_max may be
+ * vertices (Section 7), res_max[k] the max norm.  res_h / res_max may be
  * NULL; when given they are host arrays of ncycles doubles and the call
  * synchronises. */
 int mg_cycle(mg_ctx* ctx, int ncycles, double* res_h, double* res_max);
@@ -208,8 +208,8 @@ int mg_sweep_time(mg_ctx* ctx, double* total_ms, int* count);
 /* ---------------------------------------------------------------------------
  * Batched cycles (many independent problems, one persistent launch per cycle).
  *
- * The multilevel cycle of the method (Section 4, the pipelined additive
- * schemes of Algorithms 3 and 4) applied to a set of independent problems --
+ * The multilevel cycle of the method (Section 5, the pipelined additive
+ * schemes tdAdd and tdBPX) applied to a set of independent problems --
  * several right-hand sides, wavenumbers, dimensions and depths -- at once.
  * Each problem lives in its own context (created by mg_batch_setup, reachable
  * through mg_batch_problem for mg_set_rhs / mg_set_solution / mg_get_level /

@@ -174,7 +174,7 @@ def dense_H(n: int, dim: int, level: int, theta: float, phi, conjugate: bool = F
 
 
 def norm_h(r: np.ndarray, level: int) -> float:
-    """|r|_h = (sum_i |h|^d |r_i|^2)^(1/2) over interior vertices (Section 6),
+    """|r|_h = (sum_i |h|^d |r_i|^2)^(1/2) over interior vertices (Section 7),
     |h| the real cell width of the level."""
     dim = r.ndim
     n = r.shape[0]

@@ -11,8 +11,8 @@ the paper's Section 3).  Arrays are C-ordered numpy arrays of shape (n_l,)*d;
 the last axis is x (fastest).  Vertex j sits at the real position j * 3^-l.
 
 The right-hand sides follow the paper's benchmark families: Gaussian loads
-(the application problem of Section 6.4 uses a Gaussian chi) and the
-manufactured product-of-sines load of the Poisson study (Section 6.1).
+(the application problem of Section 7.4 uses a Gaussian chi) and the
+manufactured product-of-sines load of the Poisson study (Section 7.1).
 """
 
 from __future__ import annotations

@@ -186,7 +186,7 @@ def test_norms():
 
 def test_paper_regular_grid_vertex_count():
     """The regular h = 1/81 grid of the p = 2 application study has 6,400
-    (interior) vertices (Section 6.4); fixture under tests/golden."""
+    (interior) vertices (Section 7.4); fixture under tests/golden."""
     path = os.path.join(os.path.dirname(__file__), "golden", "paper_counts.txt")
     rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
     for dim, level, count in ((int(a), int(b), int(c)) for a, b, c in rows):

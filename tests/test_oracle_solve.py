@@ -4,7 +4,7 @@
 * Poisson MMS   <- analytic prod sin(pi x) solution of the paper's Poisson load
                    (phi = 0, theta = 0): second-order convergence, error / 9 per level
 * Helmholtz MMS <- the same with chi = (d pi^2 - phi) prod sin(pi x)
-* stationary Poisson cycle converges (Section 6.1: mesh-independent-ish rates)
+* stationary Poisson cycle converges (Section 7.1: mesh-independent-ish rates)
 """
 
 import numpy as np
