@@ -127,6 +127,7 @@ __device__ inline FusedArgs<T> batch_fused_args(const BProb<T>& P, int cyc) {
   f.partials = nullptr;
   f.variant = P.variant;
   f.tile = 0;
+  f.order = 0;
   return f;
 }
 
@@ -139,12 +140,15 @@ __device__ inline void batch_fused3(const BProb<T>* Pp, int cyc, int tile, F3Lds
   double* part = P.part + 2 * tile;
   // the non-BPX layout is a prefix of the BPX one
   auto& sm0 = reinterpret_cast<F3Lds<T, 2, 2, false>&>(sm);
+  const bool add = P.variant == MG_ADD;
   if (P.zc3 == 0) {
-    if (bpx) fused3_tile<T, 2, 2, 9, true>(f, bx, by, bz, part, sm);
-    else fused3_tile<T, 2, 2, 9, false>(f, bx, by, bz, part, sm0);
+    if (bpx) fused3_tile<T, 2, 2, 9, 2>(f, bx, by, bz, part, sm);
+    else if (add) fused3_tile<T, 2, 2, 9, 0>(f, bx, by, bz, part, sm0);
+    else fused3_tile<T, 2, 2, 9, 1>(f, bx, by, bz, part, sm0);
   } else {
-    if (bpx) fused3_tile<T, 2, 2, 27, true>(f, bx, by, bz, part, sm);
-    else fused3_tile<T, 2, 2, 27, false>(f, bx, by, bz, part, sm0);
+    if (bpx) fused3_tile<T, 2, 2, 27, 2>(f, bx, by, bz, part, sm);
+    else if (add) fused3_tile<T, 2, 2, 27, 0>(f, bx, by, bz, part, sm0);
+    else fused3_tile<T, 2, 2, 27, 1>(f, bx, by, bz, part, sm0);
   }
 }
 

@@ -22,6 +22,11 @@ __device__ inline cpx<T> cconjmul(cpx<T> a, cpx<T> b) {  // conj(a) * b
 }
 template <class T>
 __device__ inline cpx<T> czero() { return mk(T(0), T(0)); }
+// Component-wise select.  (A conditional expression on the struct itself may
+// be lowered through private memory, whose accesses share the vector-memory
+// counter with global loads and so force waits on every load in flight.)
+template <class T>
+__device__ inline cpx<T> csel(bool c, cpx<T> a, cpx<T> b) { return mk(c ? a.re : b.re, c ? a.im : b.im); }
 
 // Level sizes are capped so that every vertex index fits 32 bits (the host
 // checks level_max), which keeps the index arithmetic in 32-bit integers.

@@ -415,6 +415,7 @@ struct Engine {
     a.partials = partials;
     a.variant = variant;
     a.tile = tile;
+    a.order = 0;
     return a;
   }
 

@@ -3,11 +3,38 @@
 
 namespace mg {
 
-template <class T, int TYC, int RPT, int ZC, bool BPX>
-__global__ __launch_bounds__(64 * ((3 * TYC + 2) / RPT)) void k_fused3(FusedArgs<T> a) {
-  __shared__ F3Lds<T, TYC, RPT, BPX> sm;
-  double* part = a.partials ? a.partials + 2 * (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) : nullptr;
-  fused3_tile<T, TYC, RPT, ZC, BPX>(a, blockIdx.x, blockIdx.y, blockIdx.z, part, sm);
+// Tile of a block.  Order 0: tiles in launch order (x fastest).  Order 1:
+// blocks are handed to the XCDs round robin (block i runs on XCD i mod 8), so
+// block i is given the (i div 8)-th tile of the i mod 8-th contiguous chunk of
+// tiles numbered y fastest: the tiles an XCD runs at one time are y and x
+// neighbours, and the halo rows they share are fetched into that XCD's L2 once.
+// The mapping is a bijection for any tile count; a different dispatch order
+// changes only the speed.
+__device__ inline void fused3_block_tile(int order, int gx, int gy, int gz, int& bx, int& by, int& bz) {
+  const int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if (order == 0) {
+    bx = lin % gx;
+    by = (lin / gx) % gy;
+    bz = lin / (gx * gy);
+    return;
+  }
+  const int N = gx * gy * gz, q = N >> 3, rem = N & 7;
+  const int k = lin & 7, local = lin >> 3;
+  const int t = k * q + min(k, rem) + local;
+  by = t % gy;
+  bx = (t / gy) % gx;
+  bz = t / (gx * gy);
+}
+
+template <class T, int TYC, int RPT, int ZC, int VAR>
+__global__ __launch_bounds__(64 * ((3 * TYC + 2) / RPT), (3 * TYC + 2) / RPT == 4 ? 3 : 1) void k_fused3(FusedArgs<T> a) {
+  __shared__ F3Lds<T, TYC, RPT, VAR == 2> sm;
+  int bx, by, bz;
+  fused3_block_tile(a.order, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
+  // partial sums are indexed by tile, so the norm's summation order does not
+  // depend on the block order
+  double* part = a.partials ? a.partials + 2 * (bx + gridDim.x * (by + gridDim.y * bz)) : nullptr;
+  fused3_tile<T, TYC, RPT, ZC, VAR>(a, bx, by, bz, part, sm);
 }
 
 template <class T, int ZC, bool BPX>
@@ -21,8 +48,10 @@ __global__ __launch_bounds__(64) void k_fused2(FusedArgs<T> a) {
 // Tile variants of the fused sweep (coarse rows per block, rows per thread,
 // coarse planes per block); the context picks one per problem (default table or
 // autotuning on the device).
-struct TileShape3 { int tyc, rpt, zc; };
-constexpr TileShape3 kTiles3[] = {{6, 2, 9}, {2, 2, 9}, {4, 1, 9}, {2, 1, 9}, {6, 2, 27}, {2, 2, 27}, {4, 1, 27}};
+struct TileShape3 { int tyc, rpt, zc, order; };
+constexpr TileShape3 kTiles3[] = {{6, 2, 9, 0},  {2, 2, 9, 0},  {4, 1, 9, 0}, {2, 1, 9, 0},
+                                  {6, 2, 27, 0}, {2, 2, 27, 0}, {4, 1, 27, 0},
+                                  {2, 2, 9, 1},  {4, 2, 9, 0},  {4, 2, 27, 0}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -32,7 +61,7 @@ int fused_tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
 int fused_tile_index(int dim, int tyc, int rpt, int zc) {
   if (dim == 3) {
     for (int t = 0; t < kNumTiles3; ++t)
-      if (kTiles3[t].tyc == tyc && kTiles3[t].rpt == rpt && kTiles3[t].zc == zc) return t;
+      if (kTiles3[t].tyc == tyc && kTiles3[t].rpt == rpt && kTiles3[t].zc == zc && kTiles3[t].order == 0) return t;
     return -1;
   }
   for (int t = 0; t < kNumTiles2; ++t)
@@ -57,10 +86,13 @@ int fused_partials_blocks(int dim, int n, int tile) {
 }
 
 template <class T, int TYC, int RPT, int ZC>
-static void launch3(const FusedArgs<T>& a, dim3 g, hipStream_t s) {
+static void launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s) {
   constexpr int NT = 64 * ((3 * TYC + 2) / RPT);
-  if (a.variant == 2) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, true>), g, NT, 0, s, a);
-  else hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, false>), g, NT, 0, s, a);
+  FusedArgs<T> a = a0;
+  a.order = kTiles3[a0.tile].order;
+  if (a.variant == 2) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2>), g, NT, 0, s, a);
+  else if (a.variant == 1) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 1>), g, NT, 0, s, a);
+  else hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 0>), g, NT, 0, s, a);
 }
 
 template <class T, int ZC>
@@ -83,7 +115,10 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
       case 3: launch3<T, 2, 1, 9>(a, g, s); break;
       case 4: launch3<T, 6, 2, 27>(a, g, s); break;
       case 5: launch3<T, 2, 2, 27>(a, g, s); break;
-      default: launch3<T, 4, 1, 27>(a, g, s); break;
+      case 6: launch3<T, 4, 1, 27>(a, g, s); break;
+      case 7: launch3<T, 2, 2, 9>(a, g, s); break;
+      case 8: launch3<T, 4, 2, 9>(a, g, s); break;
+      default: launch3<T, 4, 2, 27>(a, g, s); break;
     }
   } else {
     switch (a.tile) {

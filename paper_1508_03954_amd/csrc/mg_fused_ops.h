@@ -31,6 +31,8 @@
 // loaded while the current plane is processed.  R: x-part by DPP shifts, y-part
 // through LDS, z-part in a two-slot ring of coarse planes; one barrier a step.
 #pragma once
+#include <type_traits>
+
 #include "mg_internal.h"
 
 namespace mg {
@@ -52,6 +54,11 @@ __device__ inline cpx<T> f_mac(cpx<T> acc, cpx<T> c, cpx<T> x) {  // acc + c x
 }
 template <class T>
 __device__ inline cpx<T> f_zero() { return mk(T(0), T(0)); }
+// Component-wise select.  (A conditional expression on the struct itself may
+// be lowered through private memory, whose accesses share the vector-memory
+// counter with global loads and so force waits on every load in flight.)
+template <class T>
+__device__ inline cpx<T> f_sel(bool c, cpx<T> a, cpx<T> b) { return mk(c ? a.re : b.re, c ? a.im : b.im); }
 
 __device__ inline int floor_div3(int p) { return p >= 0 ? p / 3 : -((-p + 2) / 3); }
 
@@ -124,35 +131,89 @@ struct F3 {
   static_assert(NG <= NT && TXC * TYC <= NT, "staging needs one thread per coarse point");
 };
 
-// LDS of one 3D tile: restricted x-partials of the computed rows (two planes)
-// and the staged coarse corrections of two planes (BPX: also sc itself).  The
-// z extent does not enter, so tiles that differ only in ZC can share it.
+// LDS of one 3D tile, two slots of everything (steps alternate):
+//   RX  x-restricted residual of the computed rows of one plane,
+//   Gz  z-interpolated coarse correction of one plane (BPX: sc - si),
+//   Sz  (BPX) sc of one coarse plane, used on c-points,
+//   UH  u and its in-row neighbour sum h of each wave's first and last row,
+//       exchanged so that every row of u is formed by one wave only.
+// The z extent does not enter, so tiles that differ only in ZC can share it.
 template <class T, int TYC, int RPT, bool BPX>
 struct F3Lds {
   using G = F3<T, TYC, RPT, 1, BPX>;
   cpx<T> RX[2][G::CY][G::TXC];
   cpx<T> Gz[2][G::GY][G::GX];
   cpx<T> Sz[BPX ? 2 : 1][BPX ? G::GY : 1][BPX ? G::GX : 1];
+  cpx<T> UH[2][G::W][RPT == 1 ? 1 : 2][2][64];
 };
 
-// One tile (bx, by, bz) of the 3D sweep, executed by a whole block of
-// F3<...>::NT threads with LDS `sm`; `part` receives the tile's
-// (sum |r|^2, max |r|) or is null.
-template <class T, int TYC, int RPT, int ZC, bool BPX>
-__device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
-                                   F3Lds<T, TYC, RPT, BPX>& sm) {
-  using G = F3<T, TYC, RPT, ZC, BPX>;
-  constexpr int TXC = G::TXC, TX = G::TX, TY = G::TY, CY = G::CY, IR = G::IR, GX = G::GX, NG = G::NG;
-  auto& RX = sm.RX;
-  auto& Gz = sm.Gz;
-  auto& Sz = sm.Sz;
+// Raw buffer access through a descriptor per plane.  The descriptor's size
+// bounds every access: an offset at or past it loads zero and drops a store
+// (the hardware range check), so the sweep masks by offset instead of by
+// branches.  A fixed sequence of memory instructions per step is what lets
+// the compiler wait for exactly the load a value comes from, and not for the
+// prefetches behind it.
+constexpr unsigned kOOB = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;   // raw (untyped) buffer, 32-bit data format
 
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRawBufferWord3);
+}
+__device__ inline cpx<double> bload(cpx<double>*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+  cpx<double> c;
+  __builtin_memcpy(&c, &v, sizeof(c));
+  return c;
+}
+__device__ inline cpx<float> bload(cpx<float>*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  cpx<float> c;
+  __builtin_memcpy(&c, &v, sizeof(c));
+  return c;
+}
+__device__ inline void bstore(cpx<double> c, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __attribute__((ext_vector_type(4))) unsigned v;
+  __builtin_memcpy(&v, &c, sizeof(c));
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+__device__ inline void bstore(cpx<float> c, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __attribute__((ext_vector_type(2))) unsigned v;
+  __builtin_memcpy(&v, &c, sizeof(c));
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+}
+
+// One tile (bx, by, bz) of the 3D sweep, executed by a whole block of
+// F3<...>::NT threads with LDS `sm`; VAR is the variant (0 add, 1 hb, 2 BPX);
+// `part` receives the tile's (sum |r|^2, max |r|) or is null.
+//
+// Step p of the march (one barrier each) works on two planes: before the
+// barrier it forms u and h on plane p for the thread's rows, starts loading w
+// of plane p+1, publishes the wave's edge rows and stages the coarse
+// correction of plane p+1; after the barrier it completes the stencil rows of
+// plane p, which closes the residual of plane q = p-1 (update, store, norms,
+// injections, x part of R), starts loading b of plane p and the coarse values
+// of plane p+2, and runs the y and z parts of R for plane q-1, whose x part
+// the previous step left in LDS.  Every load is issued where its register is
+// free, so no prefetch is live through the stencil beyond one plane of w and
+// b: that keeps the register count (and so the occupancy) down.
+// Coarse staging: wave k stages coarse row k of the tile; the y and z parts of
+// R: every wave takes an equal share of the tile's coarse points.
+template <class T, int TYC, int RPT, int ZC, int VAR>
+__device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
+                                   F3Lds<T, TYC, RPT, VAR == 2>& sm) {
+  constexpr bool BPX = VAR == 2;
+  using G = F3<T, TYC, RPT, ZC, BPX>;
+  constexpr int TXC = G::TXC, TX = G::TX, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
+  constexpr unsigned CB = sizeof(cpx<T>);
+  constexpr int NPT = TXC * TYC, PPW = (NPT + W - 1) / W;   // coarse points of R per wave
+  static_assert(GY <= W, "one wave per staged coarse row");
+  static_assert(PPW <= 64, "coarse points of R per wave");
   const int tid = threadIdx.x, lane = tid & 63;
-  // the wave index is uniform across a wavefront: keeping it scalar makes every
-  // y-dependent quantity (row validity, weights, row addresses) scalar too
+  // wave index and everything derived from rows is wavefront-uniform (scalar)
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = a.n, nc = a.nc;
-  const int n2 = n * n, nc2 = nc * nc;
+  const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
+  const unsigned pbytes = (unsigned)(n2 * CB), cpbytes = (unsigned)(nc2 * CB);
   const int mx0 = bx * TXC, my0 = by * TYC, mz0 = bz * ZC;
   const int mz1 = min(mz0 + ZC, nc);
   const int x0 = 3 * mx0, y0 = 3 * my0;
@@ -160,189 +221,252 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const bool xin = x >= 1 && x <= n - 2;
   const bool xcomp = lane >= 1 && lane <= 62;
   const bool xown = x >= x0 && x <= min(x0 + TX - 1, n - 1);
-  const int yfirst = y0 - 3 + wv * RPT;            // input row k sits at y = yfirst + k
+  const int ybase = y0 - 2 + wv * RPT;            // first computed row of this wave
   const int yown_hi = min(y0 + TY - 1, n - 1);
   const int zown_lo = 3 * mz0, zown_hi = min(3 * mz1 - 1, n - 1);
-  const bool mask = a.variant != 0;
   const cpx<T> c0 = a.coef[0], c1 = a.coef[1], c2 = a.coef[2], c3 = a.coef[3];
   const cpx<T> ws = a.ws;
-  // x part of the prolongation for this lane
-  const int mxl = x >= 0 ? x / 3 : 0, qx = x - 3 * mxl, gxl = mxl - mx0 + 1;
+  // x part of the prolongation for this lane (the second weight is zero on
+  // coarse columns; its index is clamped so that the read stays in the row)
+  const int mxl = x >= 0 ? x / 3 : -1, qx = x - 3 * mxl, gxl = mxl - mx0 + 1;
+  const int gxl1 = min(gxl + 1, GX - 1);
   const T wx0 = w_lo<T>(qx), wx1 = w_hi<T>(qx);
-  // staging point of this thread (coarse in-plane)
-  const int sgx = tid % GX, sgy = tid / GX;
-  const int smx = mx0 - 1 + sgx, smy = my0 - 1 + sgy;
-  const bool sval = tid < NG && smx >= 0 && smx < nc && smy >= 0 && smy < nc;
-  const int sidx = smy * nc + smx;
+  const bool ccol = qx == 0;
+  auto row_ok = [&](int y) { return y >= 1 && y <= n - 2; };
+  auto plane_ok = [&](int p) { return p >= 1 && p <= n - 2; };
+  // offsets inside a plane: interior vertices for loads, owned ones for stores
+  unsigned vld[RPT], vst[RPT], vcp[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int y = ybase + j;
+    const unsigned off = (unsigned)((y * n + x) * (int)CB);
+    vld[j] = (row_ok(y) && xin) ? off : kOOB;
+    const bool yown = y >= y0 && y <= yown_hi && y >= 0;
+    vst[j] = (yown && xown) ? off : kOOB;
+    // c-point injections: coarse offset inside a coarse plane
+    vcp[j] = (yown && xown && ccol && y % 3 == 0 && x >= 0)
+                 ? (unsigned)(((y / 3) * nc + x / 3) * (int)CB) : kOOB;
+  }
+  const bool top = wv == 0, bot = wv == W - 1;
+  const int yhalo = top ? ybase - 1 : ybase + RPT;   // extra row formed by the edge waves
+  const unsigned vldh = ((top || bot) && row_ok(yhalo) && xin) ? (unsigned)((yhalo * n + x) * (int)CB) : kOOB;
+  // coarse staging: wave wv < GY stages coarse row my0 - 1 + wv, lanes 0 .. GX-1
+  const int smx = mx0 - 1 + lane, smy = my0 - 1 + wv;
+  const bool stager = wv < GY && lane < GX;
+  const unsigned vsg = (stager && smx >= 0 && smx < nc && smy >= 0 && smy < nc)
+                           ? (unsigned)((smy * nc + smx) * (int)CB) : kOOB;
+  // y and z parts of R: coarse point pi of the tile
+  const int pi = wv * PPW + lane;
+  const bool rpt = lane < PPW && pi < NPT;
+  const int lx = rpt ? pi % TXC : 0, ly = rpt ? pi / TXC : 0;
+  const int rmx = mx0 + lx, rmy = my0 + ly;
+  const bool rcin = rmx >= 1 && rmx <= nc - 2 && rmy >= 1 && rmy <= nc - 2;
+  const unsigned vrho = (rpt && rmx < nc && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
 
-  cpx<T> wc[IR], wn[IR], bc[RPT], bn[RPT];
+  auto prsrc = [&](const cpx<T>* base, int p, bool ok) {
+    return plane_rsrc(base + (long long)min(max(p, 0), n - 1) * n2, ok ? pbytes : 0u);
+  };
+  auto crsrc = [&](const cpx<T>* base, int k, bool ok) {
+    return plane_rsrc(base + (long long)min(max(k, 0), nc - 1) * nc2, ok ? cpbytes : 0u);
+  };
+  cpx<T>* tagT = nullptr;
+
+  cpx<T> Wr[RPT], Wh, Br[RPT];
   cpx<T> A[RPT], Np[RPT], Cp[RPT];
   cpx<T> gsc0, gsc1, gsi0, gsi1;
   cpx<T> acc0 = f_zero<T>(), acc1 = f_zero<T>();
   double nsum = 0.0, nmax = 0.0;
 
-  auto plane_ok = [&](int p) { return p >= 1 && p <= n - 2; };
-  auto load_w = [&](int p, cpx<T>* dst) {
+  const int p0 = 3 * mz0 - 3, plast = 3 * mz1;
+  // planes past the tile's last use are not fetched (zero-size descriptors)
+  auto load_w = [&](int p, cpx<T>* dst, cpx<T>& dh) {
+    const auto r = prsrc(a.w, p, plane_ok(p) && p <= plast);
 #pragma unroll
-    for (int k = 0; k < IR; ++k) {
-      const int y = yfirst + k;
-      const cpx<T>* row = a.w + ((long long)p * n2 + (long long)y * n);
-      dst[k] = (plane_ok(p) && y >= 1 && y <= n - 2 && xin) ? row[x] : f_zero<T>();
-    }
+    for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
+    dh = bload(tagT, r, vldh);
   };
-  auto load_b = [&](int q, cpx<T>* dst) {
+  auto load_b = [&](int p, cpx<T>* dst) {
+    const auto r = prsrc(a.b, p, plane_ok(p) && p < plast);
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int y = yfirst + 1 + j;
-      const cpx<T>* row = a.b + ((long long)q * n2 + (long long)y * n);
-      dst[j] = (plane_ok(q) && y >= 1 && y <= n - 2 && xin && xcomp) ? row[x] : f_zero<T>();
-    }
+    for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
   };
+  // coarse values of fine plane p: planes kz and kz+1 (the second only off
+  // coarse planes); coarse boundary planes hold zeros
   auto load_g = [&](int p) {
-    gsc0 = gsc1 = gsi0 = gsi1 = f_zero<T>();
-    if (sval && plane_ok(p)) {
-      const int kz = p / 3, tz = p - 3 * kz;
-      const long long c = (long long)kz * nc2 + sidx;
-      gsc0 = a.scc[c];
-      if (BPX) gsi0 = a.sic[c];
-      if (tz != 0) {
-        gsc1 = a.scc[c + nc2];
-        if (BPX) gsi1 = a.sic[c + nc2];
-      }
+    const int kz = floor_div3(p), tz = p - 3 * kz;
+    const bool ok = plane_ok(p) && p <= plast;
+    const auto r0 = crsrc(a.scc, kz, ok);
+    const auto r1 = crsrc(a.scc, kz + 1, ok && tz != 0);
+    gsc0 = bload(tagT, r0, vsg);
+    gsc1 = bload(tagT, r1, vsg);
+    if (BPX) {
+      gsi0 = bload(tagT, crsrc(a.sic, kz, ok), vsg);
+      gsi1 = bload(tagT, crsrc(a.sic, kz + 1, ok && tz != 0), vsg);
     }
   };
-  auto store_g = [&](int p) {
-    if (tid < NG) {
+  auto store_g = [&](int p, int slot) {
+    if (stager) {
       const int kz = floor_div3(p), tz = p - 3 * kz;
       const cpx<T> g0 = BPX ? f_sub(gsc0, gsi0) : gsc0;
       const cpx<T> g1 = BPX ? f_sub(gsc1, gsi1) : gsc1;
-      Gz[p & 1][sgy][sgx] = tz == 0 ? g0 : f_add(f_scale(w_lo<T>(tz), g0), f_scale(w_hi<T>(tz), g1));
-      if (BPX) Sz[p & 1][sgy][sgx] = gsc0;   // used on c-points only (tz == 0)
+      sm.Gz[slot][wv][lane] = f_sel(tz == 0, g0, f_add(f_scale(w_lo<T>(tz), g0), f_scale(w_hi<T>(tz), g1)));
+      if (BPX) sm.Sz[slot][wv][lane] = gsc0;   // used on c-points only (tz == 0)
+    }
+  };
+  // u = w + P g on plane p at row y (zero off the interior)
+  auto form_u = [&](int p, int slot, int y, cpx<T> w) {
+    const int my = floor_div3(y), qy = y - 3 * my, gy = min(max(my - my0 + 1, 0), GY - 1);
+    cpx<T> g = f_add(f_scale(wx0, sm.Gz[slot][gy][gxl]), f_scale(wx1, sm.Gz[slot][gy][gxl1]));
+    if (qy != 0) {
+      const int gy1 = min(gy + 1, GY - 1);
+      const cpx<T> g1 = f_add(f_scale(wx0, sm.Gz[slot][gy1][gxl]), f_scale(wx1, sm.Gz[slot][gy1][gxl1]));
+      g = f_add(f_scale(w_lo<T>(qy), g), f_scale(w_hi<T>(qy), g1));
+    } else if (BPX && p % 3 == 0) {
+      // BPX keeps si on c-points: there the correction is sc_c itself
+      g = f_sel(ccol, sm.Sz[slot][gy][gxl], g);
+    }
+    return f_sel(plane_ok(p) && row_ok(y) && xin, f_add(w, g), f_zero<T>());
+  };
+  auto hsum = [&](cpx<T> u) { return f_add(dpp_c<kDppLeft>(u), dpp_c<kDppRight>(u)); };
+
+  // y and z parts of R for plane qq, whose x part is in RX[slot]
+  auto rest_yz = [&](int qq, int slot) {
+    cpx<T> v = f_zero<T>();
+#pragma unroll
+    for (int oy = -2; oy <= 2; ++oy) v = f_add(v, f_scale(w_r<T>(oy), sm.RX[slot][3 * ly + 2 + oy][lx]));
+    const int k0 = floor_div3(qq), t = qq - 3 * k0;
+    if (t == 0) {
+      acc0 = f_add(acc0, v);
+    } else if (t == 1) {
+      acc0 = f_add(acc0, f_scale(T(2.0 / 3.0), v));
+      acc1 = f_add(acc1, f_scale(T(1.0 / 3.0), v));
+    } else {
+      acc0 = f_add(acc0, f_scale(T(1.0 / 3.0), v));
+      acc1 = f_add(acc1, f_scale(T(2.0 / 3.0), v));
+    }
+    // coarse plane k0 is complete after its last fine plane (t == 2)
+    const bool done = t == 2 && k0 >= mz0 && k0 < mz1;
+    bstore(f_sel(rcin && k0 >= 1 && k0 <= nc - 2, acc0, f_zero<T>()), crsrc(a.rhoc, k0, done), vrho);
+    if (t == 2) {
+      acc0 = acc1;
+      acc1 = f_zero<T>();
     }
   };
 
-  const int p0 = 3 * mz0 - 3;
   load_g(p0);
-  store_g(p0);
+  store_g(p0, 0);
   load_g(p0 + 1);
-  load_w(p0, wc);
-  load_b(p0 - 1, bc);
+  load_w(p0, Wr, Wh);
+  load_b(p0 - 1, Br);
 #pragma unroll
   for (int j = 0; j < RPT; ++j) { A[j] = f_zero<T>(); Np[j] = f_zero<T>(); Cp[j] = f_zero<T>(); }
   __syncthreads();
 
-  for (int p = p0; p <= 3 * mz1; ++p) {
+  // LDS slot S = (p - p0) & 1; at the start of step p, Wr holds w of plane p,
+  // Br b of plane p-1, and the coarse registers the values of plane p+1
+  auto step = [&](auto S_, int p) {
+    constexpr int S = decltype(S_)::value;
     const int q = p - 1;
-    const int pb = p & 1;
-    // prefetch the next plane
-    load_w(p + 1, wn);
-    load_b(p, bn);
-    // (1) u on plane p: folded iterate plus the prolongated coarse correction
-    const int kz = floor_div3(p), tz = p - 3 * kz;
-    cpx<T> u[IR];
+    cpx<T> u[RPT], h[RPT], uh = f_zero<T>(), hh = f_zero<T>();
+    // (1) u and h on plane p
 #pragma unroll
-    for (int k = 0; k < IR; ++k) {
-      const int y = yfirst + k;
-      cpx<T> v = f_zero<T>();
-      if (plane_ok(p) && xin && y >= 1 && y <= n - 2) {
-        const int my = y / 3, qy = y - 3 * my, gy = my - my0 + 1;
-        if (BPX && qx == 0 && qy == 0 && tz == 0) {
-          v = f_add(wc[k], Sz[pb][gy][gxl]);       // BPX keeps si on c-points: sc_c itself
-        } else {
-          cpx<T> row0 = f_scale(wx0, Gz[pb][gy][gxl]);
-          if (qx != 0) row0 = f_add(row0, f_scale(wx1, Gz[pb][gy][gxl + 1]));
-          cpx<T> g = f_scale(w_lo<T>(qy), row0);
-          if (qy != 0) {
-            cpx<T> row1 = f_scale(wx0, Gz[pb][gy + 1][gxl]);
-            if (qx != 0) row1 = f_add(row1, f_scale(wx1, Gz[pb][gy + 1][gxl + 1]));
-            g = f_add(g, f_scale(w_hi<T>(qy), row1));
-          }
-          v = f_add(wc[k], g);
-        }
-      }
-      u[k] = v;
+    for (int j = 0; j < RPT; ++j) {
+      u[j] = form_u(p, S, ybase + j, Wr[j]);
+      h[j] = hsum(u[j]);
     }
-    // (2) in-row neighbour sums by lane shifts
-    cpx<T> h[IR];
-#pragma unroll
-    for (int k = 0; k < IR; ++k) h[k] = f_add(dpp_c<kDppLeft>(u[k]), dpp_c<kDppRight>(u[k]));
-    // (3) stencil, residual, smoothing update, folded iterate, injections
-    const bool q_in = plane_ok(q);
+    if (top || bot) {
+      uh = form_u(p, S, yhalo, Wh);
+      hh = hsum(uh);
+    }
+    constexpr int LE = RPT == 1 ? 0 : 1;   // slot of the last row (the first row when RPT == 1)
+    sm.UH[S][wv][0][0][lane] = u[0];
+    sm.UH[S][wv][0][1][lane] = h[0];
+    if (LE) {
+      sm.UH[S][wv][LE][0][lane] = u[RPT - 1];
+      sm.UH[S][wv][LE][1][lane] = h[RPT - 1];
+    }
+    // (2) refill w with plane p+1; stage plane p+1's correction
+    load_w(p + 1, Wr, Wh);
+    store_g(p + 1, 1 - S);
+    __syncthreads();
+    // (3) neighbour rows across the wave edges
+    cpx<T> ua = uh, ha = hh, ub = uh, hb = hh;
+    if (!top) {
+      ua = sm.UH[S][wv - 1][LE][0][lane];
+      ha = sm.UH[S][wv - 1][LE][1][lane];
+    }
+    if (!bot) {
+      ub = sm.UH[S][wv + 1][0][0][lane];
+      hb = sm.UH[S][wv + 1][0][1][lane];
+    }
+    // (4) stencil rows of plane p close the residual of plane q
     const bool q_own = q >= zown_lo && q <= zown_hi;
     const bool q_c = q >= 0 && (q % 3) == 0;
+    const auto wo = prsrc(a.wout, q, q_own);
+    const auto co = crsrc(VAR == 0 ? a.sfc : a.sic_out, q / 3, q_own && q_c && VAR != 1);
     cpx<T> r[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const int y = yfirst + 1 + j;
-      const cpx<T> C = u[j + 1];
-      const cpx<T> F2 = f_add(h[j + 1], f_add(u[j], u[j + 2]));
-      const cpx<T> E2 = f_add(h[j], h[j + 2]);
+      const int y = ybase + j;
+      const int jm = j > 0 ? j - 1 : 0, jp = j < RPT - 1 ? j + 1 : RPT - 1;
+      cpx<T> um = u[jm], hm = h[jm], up = u[jp], hp = h[jp];
+      if (j == 0) {
+        um = ua;
+        hm = ha;
+      }
+      if (j == RPT - 1) {
+        up = ub;
+        hp = hb;
+      }
+      const cpx<T> C = u[j];
+      const cpx<T> F2 = f_add(h[j], f_add(um, up));
+      const cpx<T> E2 = f_add(hm, hp);
       const cpx<T> M = f_mac(f_mac(f_mul(c0, C), c1, F2), c2, E2);
       const cpx<T> N = f_mac(f_mac(f_mul(c1, C), c2, F2), c3, E2);
-      const bool in = q_in && xin && xcomp && y >= 1 && y <= n - 2;
-      const cpx<T> rv = in ? f_sub(bc[j], f_add(A[j], N)) : f_zero<T>();
+      const bool in = plane_ok(q) && row_ok(y) && xin && xcomp;
+      const cpx<T> rv = f_sel(in, f_sub(Br[j], f_add(A[j], N)), f_zero<T>());
       const cpx<T> s = f_mul(ws, rv);
-      const bool cp = q_c && qx == 0 && x >= 0 && y >= 0 && (y % 3) == 0;
-      const cpx<T> scm = (mask && cp) ? f_zero<T>() : s;
-      if (q_own && xown && y >= y0 && y <= yown_hi) {
-        cpx<T>* row = a.wout + ((long long)q * n2 + (long long)y * n);
-        row[x] = in ? f_add(Cp[j], scm) : f_zero<T>();
-        if (in) {
-          const double r2 = (double)rv.re * rv.re + (double)rv.im * rv.im;
-          nsum += r2;
-          nmax = fmax(nmax, r2);
-        }
-        if (cp) {
-          const long long ic = (long long)(q / 3) * nc2 + (y / 3) * nc + x / 3;
-          if (a.sfc) a.sfc[ic] = scm;
-          if (BPX) a.sic_out[ic] = s;
-        }
-      }
+      const bool cp = q_c && ccol && x >= 0 && (y % 3) == 0;
+      const cpx<T> scm = f_sel(VAR != 0 && cp, f_zero<T>(), s);
+      bstore(f_sel(in, f_add(Cp[j], scm), f_zero<T>()), wo, vst[j]);
+      if (VAR != 1) bstore(VAR == 0 ? scm : s, co, vcp[j]);
+      const bool own = q_own && vst[j] != kOOB;
+      const double r2 = (double)rv.re * rv.re + (double)rv.im * rv.im;
+      nsum += own ? r2 : 0.0;
+      nmax = fmax(nmax, own ? r2 : 0.0);
       r[j] = rv;
       A[j] = f_add(M, Np[j]);
       Np[j] = N;
       Cp[j] = C;
     }
-    // (4) x-part of R by lane shifts; lanes 3, 6, .., 60 sit on coarse columns
+    // refill b with plane p, the coarse registers with plane p+2
+    load_b(p, Br);
+    load_g(p + 2);
+    // (5) x part of R; lanes 3, 6, .., 60 sit on the owned coarse columns
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const cpx<T> l1 = dpp_c<kDppLeft>(r[j]), l2 = dpp_c<kDppLeft>(l1);
       const cpx<T> r1 = dpp_c<kDppRight>(r[j]), r2 = dpp_c<kDppRight>(r1);
       const cpx<T> rx = f_add(r[j], f_add(f_scale(T(2.0 / 3.0), f_add(l1, r1)), f_scale(T(1.0 / 3.0), f_add(l2, r2))));
-      if (lane >= 3 && lane <= 60 && lane % 3 == 0) RX[pb][wv * RPT + j][lane / 3 - 1] = rx;
+      if (lane >= 3 && lane <= 60 && ccol) sm.RX[1 - S][wv * RPT + j][lane / 3 - 1] = rx;
     }
-    // (5) coarse correction of the next plane into LDS, fetch the one after
-    store_g(p + 1);
-    load_g(p + 2);
+    // (6) y and z parts of R for plane q-1 (its x part is in slot S)
+    rest_yz(q - 1, S);
+  };
+  // two steps per iteration so that slots and register roles are constants
+  int p = p0;
+  for (; p + 1 <= plast; p += 2) {
+    step(std::integral_constant<int, 0>(), p);
+    step(std::integral_constant<int, 1>(), p + 1);
+  }
+  // the remaining step, if any, then R of the last plane
+  if (p <= plast) {
+    step(std::integral_constant<int, 0>(), p);
     __syncthreads();
-    // (6) y-part of R at the owned coarse vertices, ring over coarse planes
-    if (q >= 3 * mz0 - 2 && tid < TXC * TYC) {
-      const int lx = tid % TXC, ly = tid / TXC;
-      const int mx = mx0 + lx, my = my0 + ly;
-      cpx<T> v = f_zero<T>();
-#pragma unroll
-      for (int oy = -2; oy <= 2; ++oy) v = f_add(v, f_scale(w_r<T>(oy), RX[pb][3 * ly + 2 + oy][lx]));
-      const int k0 = floor_div3(q), t = q - 3 * k0;
-      if (t == 0) {
-        acc0 = f_add(acc0, v);
-      } else if (t == 1) {
-        acc0 = f_add(acc0, f_scale(T(2.0 / 3.0), v));
-        acc1 = f_add(acc1, f_scale(T(1.0 / 3.0), v));
-      } else {
-        acc0 = f_add(acc0, f_scale(T(1.0 / 3.0), v));
-        acc1 = f_add(acc1, f_scale(T(2.0 / 3.0), v));
-        if (k0 >= mz0 && k0 < mz1 && mx < nc && my < nc) {
-          const bool cin = k0 >= 1 && k0 <= nc - 2 && mx >= 1 && mx <= nc - 2 && my >= 1 && my <= nc - 2;
-          a.rhoc[(long long)k0 * nc2 + my * nc + mx] = cin ? acc0 : f_zero<T>();
-        }
-        acc0 = acc1;
-        acc1 = f_zero<T>();
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < IR; ++k) wc[k] = wn[k];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) bc[j] = bn[j];
+    rest_yz(plast - 1, 1);
+  } else {
+    __syncthreads();
+    rest_yz(plast - 1, 0);
   }
   if (part) block_reduce_store(nsum, sqrt(nmax), part, G::NT);
 }
@@ -384,8 +508,16 @@ __device__ inline void fused2_wave_tile(const FusedArgs<T>& a, int bx, int by, c
   cpx<T> gsc0, gsc1, gsi0, gsi1, acc0 = f_zero<T>(), acc1 = f_zero<T>();
   double nsum = 0.0, nmax = 0.0;
   auto row_ok = [&](int p) { return p >= 1 && p <= n - 2; };
-  auto load_w = [&](int p) { return (row_ok(p) && xin) ? a.w[(long long)p * n + x] : f_zero<T>(); };
-  auto load_b = [&](int q) { return (row_ok(q) && xin && xcomp) ? a.b[(long long)q * n + x] : f_zero<T>(); };
+  auto load_w = [&](int p) {
+    cpx<T> v = f_zero<T>();
+    if (row_ok(p) && xin) v = a.w[(long long)p * n + x];
+    return v;
+  };
+  auto load_b = [&](int q) {
+    cpx<T> v = f_zero<T>();
+    if (row_ok(q) && xin && xcomp) v = a.b[(long long)q * n + x];
+    return v;
+  };
   auto load_g = [&](int p) {
     gsc0 = gsc1 = gsi0 = gsi1 = f_zero<T>();
     if (sval && row_ok(p)) {
@@ -404,7 +536,7 @@ __device__ inline void fused2_wave_tile(const FusedArgs<T>& a, int bx, int by, c
       const int ky = floor_div3(p), ty = p - 3 * ky;
       const cpx<T> g0 = BPX ? f_sub(gsc0, gsi0) : gsc0;
       const cpx<T> g1 = BPX ? f_sub(gsc1, gsi1) : gsc1;
-      Gz[p & 1][lane] = ty == 0 ? g0 : f_add(f_scale(w_lo<T>(ty), g0), f_scale(w_hi<T>(ty), g1));
+      Gz[p & 1][lane] = f_sel(ty == 0, g0, f_add(f_scale(w_lo<T>(ty), g0), f_scale(w_hi<T>(ty), g1)));
       Sz[p & 1][lane] = gsc0;
     }
   };
@@ -434,12 +566,12 @@ __device__ inline void fused2_wave_tile(const FusedArgs<T>& a, int bx, int by, c
     const cpx<T> M = f_mac(f_mul(c0, u), c1, h);
     const cpx<T> N = f_mac(f_mul(c1, u), c2, h);
     const bool in = row_ok(q) && xin && xcomp;
-    const cpx<T> rv = in ? f_sub(bc, f_add(A, N)) : f_zero<T>();
+    const cpx<T> rv = f_sel(in, f_sub(bc, f_add(A, N)), f_zero<T>());
     const cpx<T> s = f_mul(ws, rv);
     const bool cp = q >= 0 && (q % 3) == 0 && qx == 0 && x >= 0;
-    const cpx<T> scm = (mask && cp) ? f_zero<T>() : s;
+    const cpx<T> scm = f_sel(mask && cp, f_zero<T>(), s);
     if (q >= yown_lo && q <= yown_hi && xown) {
-      a.wout[(long long)q * n + x] = in ? f_add(Cp, scm) : f_zero<T>();
+      a.wout[(long long)q * n + x] = f_sel(in, f_add(Cp, scm), f_zero<T>());
       if (in) {
         const double r2 = (double)rv.re * rv.re + (double)rv.im * rv.im;
         nsum += r2;
@@ -470,7 +602,7 @@ __device__ inline void fused2_wave_tile(const FusedArgs<T>& a, int bx, int by, c
         acc1 = f_add(acc1, f_scale(T(2.0 / 3.0), v));
         if (k0 >= my0 && k0 < my1 && cmx < nc) {
           const bool cin = k0 >= 1 && k0 <= nc - 2 && cmx >= 1 && cmx <= nc - 2;
-          a.rhoc[(long long)k0 * nc + cmx] = cin ? acc0 : f_zero<T>();
+          a.rhoc[(long long)k0 * nc + cmx] = f_sel(cin, acc0, f_zero<T>());
         }
         acc0 = acc1;
         acc1 = f_zero<T>();

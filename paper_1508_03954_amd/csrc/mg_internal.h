@@ -147,6 +147,7 @@ struct FusedArgs {
   double* partials;     // per-block (sum |r|^2, max |r|) or nullptr
   int variant;          // 0 add, 1 hb, 2 bpx
   int tile;             // tile variant, 0 .. fused_tile_count(dim) - 1
+  int order;            // block-to-tile order (set by the launcher from the tile table)
 };
 template <class T>
 hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);

@@ -59,7 +59,9 @@ __global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __re
     int j[3];
     long long i;
     if (!row_vertex<D>(row_, x_, op.n, j, i)) continue;
-    y[i] = is_interior<D>(j, op.n) ? apply_row<T, D>(x, op.n, j, op) : czero<T>();
+    cpx<T> v = czero<T>();
+    if (is_interior<D>(j, op.n)) v = apply_row<T, D>(x, op.n, j, op);
+    y[i] = v;
   }
 }
 
@@ -104,7 +106,9 @@ __global__ void k_uhat(int n, const cpx<T>* __restrict__ u, const cpx<T>* __rest
     int j[3];
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    uh[i] = is_interior<D>(j, n) ? u[i] - prolong_at<T, D>(uc, nc, j) : czero<T>();
+    cpx<T> v = czero<T>();
+    if (is_interior<D>(j, n)) v = u[i] - prolong_at<T, D>(uc, nc, j);
+    uh[i] = v;
   }
 }
 
@@ -211,7 +215,8 @@ __global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> o
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     if (!is_interior<D>(j, n)) { z[i] = czero<T>(); continue; }
-    const cpx<T> id = op.invDv ? op.invDv[i] : op.invD;
+    cpx<T> id = op.invD;
+    if (op.invDv) id = op.invDv[i];
     cpx<T> s = cmul(omega, cmul(id, rho[i]));
     if (!is_lmin) {
       if (variant == 1 && is_cpoint<D>(j)) s = czero<T>();
@@ -240,7 +245,8 @@ __global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> o
           }
           if (!use || !is_interior<D>(k, n)) continue;
           const long long ik = ravel<D>(k, n);
-          const cpx<T> idk = op.invDv ? op.invDv[ik] : op.invD;
+          cpx<T> idk = op.invD;
+          if (op.invDv) idk = op.invDv[ik];
           pis = pis + w * cmul(omega, cmul(idk, rho[ik]));
         }
         s = s - pis;
@@ -299,7 +305,7 @@ __global__ void k_zero_boundary_copy(int n, const cpx<T>* __restrict__ in, cpx<T
     int j[3];
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    out[i] = is_interior<D>(j, n) ? cmul(scale, in[i]) : czero<T>();
+    out[i] = csel(is_interior<D>(j, n), cmul(scale, in[i]), czero<T>());
   }
 }
 

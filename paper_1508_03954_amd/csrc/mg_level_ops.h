@@ -35,11 +35,12 @@ __device__ inline void update_vertex(const OpData<T>& op, const int j[3], long l
   const bool in = is_interior<D>(j, n);
   cpx<T> s = czero<T>();
   if (in) {
-    const cpx<T> id = op.invDv ? op.invDv[i] : op.invD;
+    cpx<T> id = op.invD;
+    if (op.invDv) id = op.invDv[i];
     s = cmul(omega, cmul(id, r[i]));
   }
   const bool cp = is_cpoint<D>(j);
-  const cpx<T> scv = (mask_c && cp) ? czero<T>() : s;
+  const cpx<T> scv = csel(mask_c && cp, czero<T>(), s);
   if (u) {
     if (in) u[i] = u[i] + scv;
   }
@@ -47,7 +48,11 @@ __device__ inline void update_vertex(const OpData<T>& op, const int j[3], long l
   if (cp && (sfc || sic)) {
     int m[3] = {j[0] / 3, j[1] / 3, j[2] / 3};
     const long long ic = ravel<D>(m, nc);
-    if (sfc) sfc[ic] = (sf ? sf[i] : czero<T>()) + scv;
+    if (sfc) {
+      cpx<T> f = czero<T>();
+      if (sf) f = sf[i];
+      sfc[ic] = f + scv;
+    }
     if (sic) sic[ic] = s;
   }
 }
@@ -85,9 +90,13 @@ __device__ inline void post_galerkin_vertex(const OpData<T>& op, const int m[3],
         if (owned) {
           const bool in = is_interior<D>(j, n);
           cpx<T> sv = czero<T>();
-          if (in) sv = cmul(omega, cmul(op.invDv ? op.invDv[i] : op.invD, v));
+          if (in) {
+            cpx<T> id = op.invD;
+            if (op.invDv) id = op.invDv[i];
+            sv = cmul(omega, cmul(id, v));
+          }
           const bool cp = ox == 0 && oy == 0 && oz == 0;
-          const cpx<T> scm = (mask_c && cp) ? czero<T>() : sv;
+          const cpx<T> scm = csel(mask_c && cp, czero<T>(), sv);
           sc[i] = scm;
           if (cp) {
             if (sfc) sfc[ic] = sf[i] + scm;
@@ -97,7 +106,7 @@ __device__ inline void post_galerkin_vertex(const OpData<T>& op, const int m[3],
       }
     }
   }
-  rhoc[ic] = cin ? acc : czero<T>();
+  rhoc[ic] = csel(cin, acc, czero<T>());
 }
 
 }  // namespace mg
