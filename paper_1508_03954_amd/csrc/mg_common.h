@@ -114,20 +114,20 @@ __device__ cpx<T> prolong_at(const cpx<T>* __restrict__ vc, int nc, const int j[
       w0[a] = third; w1[a] = two3; two[a] = true;
     }
   }
+  // all 2^d corners are read (a corner past a coarse vertex repeats it with
+  // weight 0), so the loads are independent and issue together
   cpx<T> acc = czero<T>();
 #pragma unroll
   for (int c = 0; c < (1 << D); ++c) {
     T w = T(1);
     int k[3] = {0, 0, 0};
-    bool use = true;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int bit = (c >> a) & 1;
-      use = use && (!bit || two[a]);
       w *= bit ? w1[a] : w0[a];
       k[a] = m[a] + (two[a] ? bit : 0);
     }
-    if (use) acc = acc + w * vc[ravel<D>(k, nc)];
+    acc = acc + w * vc[ravel<D>(k, nc)];
   }
   return acc;
 }

@@ -428,12 +428,14 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const cpx<T> s = f_mul(ws, rv);
       const bool cp = q_c && ccol && x >= 0 && (y % 3) == 0;
       const cpx<T> scm = f_sel(VAR != 0 && cp, f_zero<T>(), s);
-      bstore(f_sel(in, f_add(Cp[j], scm), f_zero<T>()), wo, vst[j]);
+      // off the interior u, r and s vanish, so the stored value is zero there
+      bstore(f_add(Cp[j], scm), wo, vst[j]);
       if (VAR != 1) bstore(VAR == 0 ? scm : s, co, vcp[j]);
-      const bool own = q_own && vst[j] != kOOB;
-      const double r2 = (double)rv.re * rv.re + (double)rv.im * rv.im;
-      nsum += own ? r2 : 0.0;
-      nmax = fmax(nmax, own ? r2 : 0.0);
+      if (q_own) {
+        const double r2 = vst[j] != kOOB ? (double)rv.re * rv.re + (double)rv.im * rv.im : 0.0;
+        nsum += r2;
+        nmax = fmax(nmax, r2);
+      }
       r[j] = rv;
       A[j] = f_add(M, Np[j]);
       Np[j] = N;
@@ -442,13 +444,21 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     // refill b with plane p, the coarse registers with plane p+2
     load_b(p, Br);
     load_g(p + 2);
-    // (5) x part of R; lanes 3, 6, .., 60 sit on the owned coarse columns
+    // (5) x part of R at the owned coarse columns (lanes 3, 6, .., 60), which
+    // read their neighbours' r from this wave's slot of the other UH buffer
+    // (free during this half step: it is refilled by this wave only, at the
+    // next step)
+    cpx<T>* rr = &sm.UH[1 - S][wv][0][0][0];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const cpx<T> l1 = dpp_c<kDppLeft>(r[j]), l2 = dpp_c<kDppLeft>(l1);
-      const cpx<T> r1 = dpp_c<kDppRight>(r[j]), r2 = dpp_c<kDppRight>(r1);
-      const cpx<T> rx = f_add(r[j], f_add(f_scale(T(2.0 / 3.0), f_add(l1, r1)), f_scale(T(1.0 / 3.0), f_add(l2, r2))));
-      if (lane >= 3 && lane <= 60 && ccol) sm.RX[1 - S][wv * RPT + j][lane / 3 - 1] = rx;
+    for (int j = 0; j < RPT; ++j) rr[64 * j + lane] = r[j];
+    if (lane >= 3 && lane <= 60 && ccol) {
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const cpx<T>* row = rr + 64 * j + lane;
+        const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
+        const cpx<T> rx = f_add(r[j], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
+        sm.RX[1 - S][wv * RPT + j][lane / 3 - 1] = rx;
+      }
     }
     // (6) y and z parts of R for plane q-1 (its x part is in slot S)
     rest_yz(q - 1, S);

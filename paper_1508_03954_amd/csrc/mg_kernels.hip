@@ -146,19 +146,39 @@ __global__ void k_update(OpData<T> op, const cpx<T>* __restrict__ r, cpx<T> omeg
   }
 }
 
-// Coarse post-phase with the Galerkin form, one launch per level l > l_min,
-// one thread per coarse vertex (see post_galerkin_vertex).
+// Coarse post-phase with the Galerkin form, one launch per level l > l_min:
+// eight lanes per coarse vertex, lanes 0..4 take the parts oo = -2..2 of its
+// support (see post_galerkin_part) and a xor-shuffle sums them, so a vertex
+// waits for one round of loads instead of five.
 template <class T, int D>
-__global__ void k_post_galerkin(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c,
-                                cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf, cpx<T>* __restrict__ rhoc,
-                                cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
+__global__ __launch_bounds__(256) void k_post_galerkin(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega,
+                                                       int mask_c, cpx<T>* __restrict__ sc,
+                                                       const cpx<T>* __restrict__ sf, cpx<T>* __restrict__ rhoc,
+                                                       cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
   const int nc = (op.n - 1) / 3 + 1;
-  MG_ROWS(D, nc) {
-    int m[3];
-    long long ic;
-    if (!row_vertex<D>(row_, x_, nc, m, ic)) continue;
-    post_galerkin_vertex<T, D>(op, m, ic, rho, omega, mask_c, sc, sf, rhoc, sfc, sic);
+  const long long Nc = D == 3 ? (long long)nc * nc * nc : (long long)nc * nc;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = g >> 3;
+  const int part = (int)(g & 7);
+  int m[3] = {0, 0, 0};
+  const bool valid = v < Nc;
+  const long long vv = valid ? v : 0;
+  m[0] = (int)(vv % nc);
+  if (D == 3) {
+    m[1] = (int)((vv / nc) % nc);
+    m[2] = (int)(vv / ((long long)nc * nc));
+  } else {
+    m[1] = (int)(vv / nc);
   }
+  cpx<T> p = czero<T>();
+  if (valid && part < 5) p = post_galerkin_part<T, D>(op, m, vv, part - 2, rho, omega, mask_c, sc, sf, sfc, sic);
+  T re = p.re, im = p.im;
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (valid && part == 0) rhoc[vv] = csel(is_interior<D>(m, nc), mk(re, im), czero<T>());
 }
 
 // R v = P^T v: per axis weights 1 - |o|/3 for fine offsets o in [-2, 2] around 3m;
@@ -528,7 +548,9 @@ template <class T>
 hipError_t launch_post_galerkin(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int mask_c,
                                 cpx<T>* sc, const cpx<T>* sf, cpx<T>* rhoc, cpx<T>* sfc, cpx<T>* sic, hipStream_t s) {
   const int nc = (op.n - 1) / 3 + 1;
-  MG_DISPATCH(dim, k_post_galerkin, row_grid(nc, dim), op, rho, omega, mask_c, sc, sf, rhoc, sfc, sic);
+  const long long lanes = 8 * pow_n(nc, dim);
+  MG_DISPATCH(dim, k_post_galerkin, dim3((unsigned)((lanes + 255) / 256)), op, rho, omega, mask_c, sc, sf, rhoc, sfc,
+              sic);
   return hipGetLastError();
 }
 

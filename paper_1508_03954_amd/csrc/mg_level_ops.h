@@ -63,50 +63,83 @@ __device__ inline void update_vertex(const OpData<T>& op, const int j[3], long l
 // every value enters rho_c(m) = (R rho)(m), and on its owned vertices it also
 // forms s = omega rho / D, sc = s (0 on c-points when masked) and the
 // injections sf_c = sf + sc (add), si_c = s (BPX) at 3m.
+//
+// post_galerkin_part does this for the offsets whose outermost component (z in
+// 3D, y in 2D) equals `oo` and returns their part of rho_c(m); all its loads
+// are independent (indices clamped into the grid, values masked by weight).
+template <class T, int D>
+__device__ inline cpx<T> post_galerkin_part(const OpData<T>& op, const int m[3], long long ic, int oo,
+                                            const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c,
+                                            cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf,
+                                            cpx<T>* __restrict__ sfc, cpx<T>* __restrict__ sic) {
+  const int n = op.n, nc = (n - 1) / 3 + 1;
+  constexpr T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
+  const bool cin = is_interior<D>(m, nc);
+  constexpr int IL = D == 3 ? -2 : 0, IH = D == 3 ? 2 : 0;   // the inner y range in 3D
+  cpx<T> acc = czero<T>();
+#pragma unroll
+  for (int oi = IL; oi <= IH; ++oi) {
+#pragma unroll
+    for (int ox = -2; ox <= 2; ++ox) {
+      const int o[3] = {ox, D == 3 ? oi : oo, oo};
+      int j[3] = {0, 0, 0};
+      bool inside = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const int t = 3 * m[a] + o[a];
+        inside = inside && t >= 0 && t < n;
+        j[a] = min(max(t, 0), n - 1);
+      }
+      const unsigned i = (unsigned)ravel<D>(j, n);   // a level below the finest has < 2^31 vertices
+      const cpx<T> v = rho[i];
+      T wt = w[o[0] + 2] * w[o[1] + 2];
+      if (D == 3) wt *= w[o[2] + 2];
+      acc = acc + ((cin && inside) ? wt : T(0)) * v;
+      bool owned = inside;
+#pragma unroll
+      for (int a = 0; a < D; ++a) owned = owned && o[a] >= 0;
+      if (owned) {
+        const bool in = is_interior<D>(j, n);
+        cpx<T> sv = czero<T>();
+        if (in) {
+          cpx<T> id = op.invD;
+          if (op.invDv) id = op.invDv[i];
+          sv = cmul(omega, cmul(id, v));
+        }
+        bool cp = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) cp = cp && o[a] == 0;
+        const cpx<T> scm = csel(mask_c && cp, czero<T>(), sv);
+        sc[i] = scm;
+        if (cp) {
+          if (sfc) sfc[ic] = sf[i] + scm;
+          if (sic) sic[ic] = sv;
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+// The five parts combined in a fixed order (the order of a xor-shuffle
+// reduction over eight lanes holding parts oo = -2..2 in lanes 0..4), so the
+// per-vertex form and the lane-split kernel give identical sums.
+template <class T>
+__device__ inline cpx<T> post_galerkin_combine(const cpx<T> p[5]) {
+  return (((p[0] + p[4]) + p[2]) + (p[1] + p[3]));
+}
+
 template <class T, int D>
 __device__ inline void post_galerkin_vertex(const OpData<T>& op, const int m[3], long long ic,
                                             const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c,
                                             cpx<T>* __restrict__ sc, const cpx<T>* __restrict__ sf,
                                             cpx<T>* __restrict__ rhoc, cpx<T>* __restrict__ sfc,
                                             cpx<T>* __restrict__ sic) {
-  const int n = op.n, nc = (n - 1) / 3 + 1;
-  const T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
-  const bool cin = is_interior<D>(m, nc);
-  cpx<T> acc = czero<T>();
-  const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
-  for (int oz = zlo; oz <= zhi; ++oz) {
-    for (int oy = -2; oy <= 2; ++oy) {
-#pragma unroll
-      for (int ox = -2; ox <= 2; ++ox) {
-        int j[3] = {3 * m[0] + ox, 3 * m[1] + oy, 3 * m[2] + oz};
-        const bool owned = ox >= 0 && oy >= 0 && oz >= 0;
-        bool inside = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) inside = inside && j[a] >= 0 && j[a] < n;
-        if (!inside || !(cin || owned)) continue;
-        const long long i = ravel<D>(j, n);
-        const cpx<T> v = rho[i];
-        acc = acc + (w[ox + 2] * w[oy + 2] * (D == 3 ? w[oz + 2] : T(1))) * v;
-        if (owned) {
-          const bool in = is_interior<D>(j, n);
-          cpx<T> sv = czero<T>();
-          if (in) {
-            cpx<T> id = op.invD;
-            if (op.invDv) id = op.invDv[i];
-            sv = cmul(omega, cmul(id, v));
-          }
-          const bool cp = ox == 0 && oy == 0 && oz == 0;
-          const cpx<T> scm = csel(mask_c && cp, czero<T>(), sv);
-          sc[i] = scm;
-          if (cp) {
-            if (sfc) sfc[ic] = sf[i] + scm;
-            if (sic) sic[ic] = sv;
-          }
-        }
-      }
-    }
-  }
-  rhoc[ic] = csel(cin, acc, czero<T>());
+  const int nc = (op.n - 1) / 3 + 1;
+  cpx<T> p[5];
+#pragma unroll 1
+  for (int k = 0; k < 5; ++k) p[k] = post_galerkin_part<T, D>(op, m, ic, k - 2, rho, omega, mask_c, sc, sf, sfc, sic);
+  rhoc[ic] = csel(is_interior<D>(m, nc), post_galerkin_combine(p), czero<T>());
 }
 
 }  // namespace mg
