@@ -401,7 +401,7 @@ struct Batch : BatchBase {
       P.phase_items[k++] = rows_items(E.lv[l].n);
     }
     if (E.dim == 3) {
-      P.fgx = (nc + F3_TXC - 1) / F3_TXC;
+      P.fgx = f3_xtiles(nc);
       P.fgy = (nc + 1) / 2;
       const int gz = (nc + kBZc3[zc3] - 1) / kBZc3[zc3];
       P.ftiles = P.fgx * P.fgy * gz;

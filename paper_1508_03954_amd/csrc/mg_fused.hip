@@ -73,7 +73,7 @@ static dim3 fused_grid(int dim, int n, int tile) {
   const int nc = (n - 1) / 3 + 1;
   if (dim == 3) {
     const TileShape3 t = kTiles3[tile];
-    return dim3((nc + F3_TXC - 1) / F3_TXC, (nc + t.tyc - 1) / t.tyc, (nc + t.zc - 1) / t.zc);
+    return dim3(f3_xtiles(nc), (nc + t.tyc - 1) / t.tyc, (nc + t.zc - 1) / t.zc);
   }
   const int zc = kTiles2[tile];
   return dim3((nc + F2_TXC - 1) / F2_TXC, (nc + zc - 1) / zc, 1);

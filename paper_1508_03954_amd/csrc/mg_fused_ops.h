@@ -119,6 +119,39 @@ __device__ inline void wave_sync() {
 // 3D
 constexpr int F3_TXC = 20;     // coarse columns per block: 60 owned fine columns + 4 halo = 64 lanes
 
+// x tiling of the 3D sweep.  An interior tile owns 20 coarse columns (60 fine
+// columns, lanes at x0-3 .. x0+60).  The coarse columns on the domain
+// boundary need no restriction (rho is zero there), so the first tile owns
+// columns 0..20 with its lanes at x = 0..63 and the last tile the final 21
+// columns with its lanes ending at x = n-1: 82 coarse columns (the 244^3
+// grid) take 4 tiles instead of 5.
+__host__ __device__ inline int f3_xtiles(int nc) {
+  if (nc <= 22) return 1;
+  if (nc <= 41) return 2;
+  return 2 + (nc - 42 + F3_TXC - 1) / F3_TXC;
+}
+// owned coarse columns [lo, hi) of x tile bx and the x of its lane 0
+__host__ __device__ inline void f3_xtile(int nc, int bx, int& lo, int& hi, int& xs) {
+  const int nt = f3_xtiles(nc), n = 3 * (nc - 1) + 1;
+  if (nt == 1) {
+    lo = 0;
+    hi = nc;
+    xs = 0;
+  } else if (bx == 0) {
+    lo = 0;
+    hi = 21;
+    xs = 0;
+  } else if (bx == nt - 1) {
+    lo = max(nc - 21, 21);
+    hi = nc;
+    xs = n - 64;
+  } else {
+    lo = 21 + (bx - 1) * F3_TXC;
+    hi = min(lo + F3_TXC, nc - 21);
+    xs = 3 * lo - 3;
+  }
+}
+
 template <class T, int TYC, int RPT, int ZC, bool BPX>
 struct F3 {
   static constexpr int TXC = F3_TXC, TX = 3 * TXC, TY = 3 * TYC;
@@ -128,6 +161,7 @@ struct F3 {
   static constexpr int IR = RPT + 2;           // rows of u a thread needs
   static constexpr int GX = TXC + 2, GY = TYC + 2, NG = GX * GY;
   static_assert(CY % RPT == 0, "rows per thread must divide the computed rows");
+  static constexpr int TXR = TXC + 1;          // owned coarse columns of an edge tile
   static_assert(NG <= NT && TXC * TYC <= NT, "staging needs one thread per coarse point");
 };
 
@@ -141,7 +175,7 @@ struct F3 {
 template <class T, int TYC, int RPT, bool BPX>
 struct F3Lds {
   using G = F3<T, TYC, RPT, 1, BPX>;
-  cpx<T> RX[2][G::CY][G::TXC];
+  cpx<T> RX[2][G::CY][G::TXR];
   cpx<T> Gz[2][G::GY][G::GX];
   cpx<T> Sz[BPX ? 2 : 1][BPX ? G::GY : 1][BPX ? G::GX : 1];
   cpx<T> UH[2][G::W][RPT == 1 ? 1 : 2][2][64];
@@ -203,9 +237,9 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
                                    F3Lds<T, TYC, RPT, VAR == 2>& sm) {
   constexpr bool BPX = VAR == 2;
   using G = F3<T, TYC, RPT, ZC, BPX>;
-  constexpr int TXC = G::TXC, TX = G::TX, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
+  constexpr int TXR = G::TXR, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
   constexpr unsigned CB = sizeof(cpx<T>);
-  constexpr int NPT = TXC * TYC, PPW = (NPT + W - 1) / W;   // coarse points of R per wave
+  constexpr int NPT = TXR * TYC, PPW = (NPT + W - 1) / W;   // coarse points of R per wave
   static_assert(GY <= W, "one wave per staged coarse row");
   static_assert(PPW <= 64, "coarse points of R per wave");
   const int tid = threadIdx.x, lane = tid & 63;
@@ -214,13 +248,15 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const int n = a.n, nc = a.nc;
   const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
   const unsigned pbytes = (unsigned)(n2 * CB), cpbytes = (unsigned)(nc2 * CB);
-  const int mx0 = bx * TXC, my0 = by * TYC, mz0 = bz * ZC;
+  int cx_lo, cx_hi, xs;
+  f3_xtile(nc, bx, cx_lo, cx_hi, xs);
+  const int my0 = by * TYC, mz0 = bz * ZC;
   const int mz1 = min(mz0 + ZC, nc);
-  const int x0 = 3 * mx0, y0 = 3 * my0;
-  const int x = x0 - 3 + lane;
+  const int y0 = 3 * my0;
+  const int x = xs + lane;
   const bool xin = x >= 1 && x <= n - 2;
   const bool xcomp = lane >= 1 && lane <= 62;
-  const bool xown = x >= x0 && x <= min(x0 + TX - 1, n - 1);
+  const bool xown = x >= 3 * cx_lo && x <= min(3 * cx_hi - 1, n - 1);
   const int ybase = y0 - 2 + wv * RPT;            // first computed row of this wave
   const int yown_hi = min(y0 + TY - 1, n - 1);
   const int zown_lo = 3 * mz0, zown_hi = min(3 * mz1 - 1, n - 1);
@@ -228,7 +264,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const cpx<T> ws = a.ws;
   // x part of the prolongation for this lane (the second weight is zero on
   // coarse columns; its index is clamped so that the read stays in the row)
-  const int mxl = x >= 0 ? x / 3 : -1, qx = x - 3 * mxl, gxl = mxl - mx0 + 1;
+  const int smx0 = xs / 3;                        // first staged coarse column
+  const int mxl = x / 3, qx = x - 3 * mxl, gxl = mxl - smx0;
   const int gxl1 = min(gxl + 1, GX - 1);
   const T wx0 = w_lo<T>(qx), wx1 = w_hi<T>(qx);
   const bool ccol = qx == 0;
@@ -251,17 +288,17 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const int yhalo = top ? ybase - 1 : ybase + RPT;   // extra row formed by the edge waves
   const unsigned vldh = ((top || bot) && row_ok(yhalo) && xin) ? (unsigned)((yhalo * n + x) * (int)CB) : kOOB;
   // coarse staging: wave wv < GY stages coarse row my0 - 1 + wv, lanes 0 .. GX-1
-  const int smx = mx0 - 1 + lane, smy = my0 - 1 + wv;
+  const int smx = smx0 + lane, smy = my0 - 1 + wv;
   const bool stager = wv < GY && lane < GX;
   const unsigned vsg = (stager && smx >= 0 && smx < nc && smy >= 0 && smy < nc)
                            ? (unsigned)((smy * nc + smx) * (int)CB) : kOOB;
   // y and z parts of R: coarse point pi of the tile
   const int pi = wv * PPW + lane;
   const bool rpt = lane < PPW && pi < NPT;
-  const int lx = rpt ? pi % TXC : 0, ly = rpt ? pi / TXC : 0;
-  const int rmx = mx0 + lx, rmy = my0 + ly;
+  const int lx = rpt ? pi % TXR : 0, ly = rpt ? pi / TXR : 0;
+  const int rmx = cx_lo + lx, rmy = my0 + ly;
   const bool rcin = rmx >= 1 && rmx <= nc - 2 && rmy >= 1 && rmy <= nc - 2;
-  const unsigned vrho = (rpt && rmx < nc && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
+  const unsigned vrho = (rpt && rmx < cx_hi && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
 
   auto prsrc = [&](const cpx<T>* base, int p, bool ok) {
     return plane_rsrc(base + (long long)min(max(p, 0), n - 1) * n2, ok ? pbytes : 0u);
@@ -444,20 +481,20 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     // refill b with plane p, the coarse registers with plane p+2
     load_b(p, Br);
     load_g(p + 2);
-    // (5) x part of R at the owned coarse columns (lanes 3, 6, .., 60), which
-    // read their neighbours' r from this wave's slot of the other UH buffer
-    // (free during this half step: it is refilled by this wave only, at the
-    // next step)
+    // (5) x part of R at the owned coarse columns (lanes 2 .. 61; the boundary
+    // columns need none), which read their neighbours' r from this wave's slot
+    // of the other UH buffer (free during this half step: it is refilled by
+    // this wave only, at the next step)
     cpx<T>* rr = &sm.UH[1 - S][wv][0][0][0];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) rr[64 * j + lane] = r[j];
-    if (lane >= 3 && lane <= 60 && ccol) {
+    if (lane >= 2 && lane <= 61 && ccol && mxl >= cx_lo && mxl < cx_hi) {
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const cpx<T>* row = rr + 64 * j + lane;
         const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
         const cpx<T> rx = f_add(r[j], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
-        sm.RX[1 - S][wv * RPT + j][lane / 3 - 1] = rx;
+        sm.RX[1 - S][wv * RPT + j][mxl - cx_lo] = rx;
       }
     }
     // (6) y and z parts of R for plane q-1 (its x part is in slot S)
