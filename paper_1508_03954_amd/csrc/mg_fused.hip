@@ -51,7 +51,8 @@ __global__ __launch_bounds__(64) void k_fused2(FusedArgs<T> a) {
 struct TileShape3 { int tyc, rpt, zc, order; };
 constexpr TileShape3 kTiles3[] = {{6, 2, 9, 0},  {2, 2, 9, 0},  {4, 1, 9, 0}, {2, 1, 9, 0},
                                   {6, 2, 27, 0}, {2, 2, 27, 0}, {4, 1, 27, 0},
-                                  {2, 2, 9, 1},  {4, 2, 9, 0},  {4, 2, 27, 0}};
+                                  {2, 2, 9, 1},  {4, 2, 9, 0},  {4, 2, 27, 0}, {2, 2, 6, 0},
+                                  {2, 2, 21, 0}, {4, 2, 28, 0}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -118,7 +119,10 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
       case 6: launch3<T, 4, 1, 27>(a, g, s); break;
       case 7: launch3<T, 2, 2, 9>(a, g, s); break;
       case 8: launch3<T, 4, 2, 9>(a, g, s); break;
-      default: launch3<T, 4, 2, 27>(a, g, s); break;
+      case 9: launch3<T, 4, 2, 27>(a, g, s); break;
+      case 10: launch3<T, 2, 2, 6>(a, g, s); break;
+      case 11: launch3<T, 2, 2, 21>(a, g, s); break;
+      default: launch3<T, 4, 2, 28>(a, g, s); break;
     }
   } else {
     switch (a.tile) {
