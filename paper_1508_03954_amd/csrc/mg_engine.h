@@ -324,9 +324,46 @@ struct Engine {
     return zero_helpers();
   }
 
+  // Number of coarsest levels (from l_min) handled by the single-block small-
+  // level kernels: at most kSmallVertices vertices each, never the finest; 0
+  // when fewer than two qualify or when the coarse right-hand side is not in
+  // the Galerkin form.
+  int small_levels() const {
+    if (!galerkin) return 0;
+    int k = 0;
+    while (k < kSmallMax && lmin + k < L && lv[lmin + k].N <= (size_t)kSmallVertices) ++k;
+    return k >= 2 ? k : 0;
+  }
+
+  SmallArgs<T> small_args(int nl) const {
+    SmallArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.dim = dim;
+    a.nl = nl;
+    a.variant = variant;
+    for (int k = 0; k < nl; ++k) {
+      const Level<T>& v = lv[lmin + k];
+      a.lv[k].n = v.n;
+      a.lv[k].u = v.u;
+      a.lv[k].b = v.b;
+      a.lv[k].sc = v.sc;
+      a.lv[k].sf = v.sf;
+      a.lv[k].si = v.si;
+      a.lv[k].op = v.op;
+      a.lv[k].omega = to_c<T>(omega_level(scheme, omega, omega_L, L - (lmin + k), iter));
+    }
+    return a;
+  }
+
   // Descent (pre-phase) on the coarse levels l_min .. L-1.
   int pre_coarse() {
-    for (int l = lmin; l < L; ++l) {
+    int l0 = lmin;
+    const int ns = small_levels();
+    if (ns) {
+      MG_HIP(launch_small_pre<T>(small_args(ns), s));
+      l0 = lmin + ns;
+    }
+    for (int l = l0; l < L; ++l) {
       Level<T>& v = lv[l];
       const bool hc = l > lmin;
       MG_HIP(launch_pre<T>(dim, v.n, v.u, v.sc, v.sf, hc ? lv[l - 1].sc : nullptr, hc ? lv[l - 1].si : nullptr,
@@ -366,9 +403,19 @@ struct Engine {
     }
     MG_TRY(mark(false));
     cur = 1 - cur;
-    MG_HIP(launch_finish_sum_max(partials, nparts, hist + 2 * k, s));
-    // Backtracking (post-phase) on the coarse levels L-1 .. l_min.
+    const int ns = small_levels();
+    if (!ns) MG_HIP(launch_finish_sum_max(partials, nparts, hist + 2 * k, s));
+    // Backtracking (post-phase) on the coarse levels L-1 .. l_min; the smallest
+    // ones, the coarsest update and the norm's second stage in one block.
     for (int l = L - 1; l >= lmin; --l) {
+      if (ns && l < lmin + ns) {
+        SmallArgs<T> a = small_args(ns);
+        a.partials = partials;
+        a.nparts = nparts;
+        a.out = hist + 2 * k;
+        MG_HIP(launch_small_post<T>(a, s));
+        break;
+      }
       Level<T>& v = lv[l];
       const bool hcc = l > lmin;
       Level<T>* cc = hcc ? &lv[l - 1] : nullptr;

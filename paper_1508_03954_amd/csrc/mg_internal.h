@@ -130,6 +130,33 @@ hipError_t launch_grad_potential(int dim, int n, cpx<double> etad, const cpx<dou
 hipError_t launch_finish_sum_max(const double* partials, int count, double* out, hipStream_t s);
 hipError_t launch_finish_sum2(const double* partials, int count, double* out, hipStream_t s);
 
+// The smallest coarse levels (a few thousand vertices at most) in one
+// single-block launch each way: descent of all of them, or Galerkin
+// backtracking of all of them plus the coarsest update and the norm's second
+// reduction stage.  lv[k] is level l_min + k.
+constexpr int kSmallMax = 4;
+constexpr int kSmallVertices = 4096;
+constexpr int kSmallThreads = 1024;
+template <class T>
+struct SmallLevel {
+  int n;
+  cpx<T>*u, *b, *sc, *sf, *si;
+  OpData<T> op;
+  cpx<T> omega;
+};
+template <class T>
+struct SmallArgs {
+  int dim, nl, variant;
+  SmallLevel<T> lv[kSmallMax];
+  const double* partials;   // post: block partials of the finest sweep, or nullptr
+  int nparts;
+  double* out;              // post: (sum |r|^2, max |r|)
+};
+template <class T>
+hipError_t launch_small_pre(const SmallArgs<T>& a, hipStream_t s);
+template <class T>
+hipError_t launch_small_post(const SmallArgs<T>& a, hipStream_t s);
+
 // Fused finest-level sweep (GALERKIN form, constant phi); see mg_fused.hip.
 template <class T>
 struct FusedArgs {

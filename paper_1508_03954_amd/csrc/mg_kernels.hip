@@ -454,17 +454,24 @@ __global__ void k_grad_potential(int n, cpx<double> etad, const cpx<double>* __r
 // Second reduction stage, one block of 256 threads: thread t folds partials
 // t, t+256, ... in order, then a fixed tree; the result does not depend on
 // timing, so repeated runs agree bitwise.
+// Second reduction stage, fixed order: 256 strided partial sums, then a
+// tree.  Works in any block of at least 256 threads (the others only join the
+// barriers).
 template <bool MAX2>
-__global__ void k_finish(const double* __restrict__ partials, int count, double* out) {
+__device__ inline void finish_block(const double* __restrict__ partials, int count, double* out) {
   __shared__ double s0[256], s1[256];
   const int t = threadIdx.x;
-  double a = 0, b = 0;
-  for (int i = t; i < count; i += 256) {
-    a += partials[2 * i];
-    b = MAX2 ? fmax(b, partials[2 * i + 1]) : b + partials[2 * i + 1];
+  if (t < 256) {
+    double a = 0, b = 0;
+    // unrolled so that the loads issue together; the sums keep index order
+#pragma unroll 8
+    for (int i = t; i < count; i += 256) {
+      a += partials[2 * i];
+      b = MAX2 ? fmax(b, partials[2 * i + 1]) : b + partials[2 * i + 1];
+    }
+    s0[t] = a;
+    s1[t] = b;
   }
-  s0[t] = a;
-  s1[t] = b;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (t < w) {
@@ -478,6 +485,82 @@ __global__ void k_finish(const double* __restrict__ partials, int count, double*
     out[1] = s1[0];
   }
 }
+
+template <bool MAX2>
+__global__ void k_finish(const double* __restrict__ partials, int count, double* out) {
+  finish_block<MAX2>(partials, count, out);
+}
+
+// The smallest coarse levels in one block (see SmallArgs).
+template <class T, int D>
+__device__ inline void small_unravel(long long i, int n, int j[3]) {
+  j[0] = (int)(i % n);
+  if (D == 3) {
+    j[1] = (int)((i / n) % n);
+    j[2] = (int)(i / ((long long)n * n));
+  } else {
+    j[1] = (int)(i / n);
+    j[2] = 0;
+  }
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(kSmallThreads) void k_small_pre(SmallArgs<T> a) {
+  for (int k = 0; k < a.nl; ++k) {
+    const SmallLevel<T>& v = a.lv[k];
+    const long long N = D == 3 ? (long long)v.n * v.n * v.n : (long long)v.n * v.n;
+    const bool hc = k > 0;
+    for (long long i = threadIdx.x; i < N; i += blockDim.x) {
+      int j[3];
+      small_unravel<T, D>(i, v.n, j);
+      pre_vertex<T, D>(v.n, j, i, v.u, v.sc, v.sf, hc ? a.lv[k - 1].sc : nullptr, hc ? a.lv[k - 1].si : nullptr,
+                       hc ? 1 : 0, a.variant == 2 ? 1 : 0);
+    }
+    __syncthreads();
+  }
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(kSmallThreads) void k_small_post(SmallArgs<T> a) {
+  const bool add = a.variant == 0, bpx = a.variant == 2;
+  // Galerkin backtracking of levels l_min + nl - 1 .. l_min + 1: eight lanes
+  // per coarse vertex, as k_post_galerkin
+  for (int k = a.nl - 1; k >= 1; --k) {
+    const SmallLevel<T>& v = a.lv[k];
+    const SmallLevel<T>& c = a.lv[k - 1];
+    const long long Nc = D == 3 ? (long long)c.n * c.n * c.n : (long long)c.n * c.n;
+    for (long long g = threadIdx.x; g < 8 * Nc; g += blockDim.x) {
+      const long long vv = g >> 3;
+      const int part = (int)(g & 7);
+      int m[3];
+      small_unravel<T, D>(vv, c.n, m);
+      cpx<T> p = czero<T>();
+      if (part < 5)
+        p = post_galerkin_part<T, D>(v.op, m, vv, part - 2, v.b, v.omega, add ? 0 : 1, v.sc, v.sf,
+                                     add ? c.sf : nullptr, bpx ? c.si : nullptr);
+      T re = p.re, im = p.im;
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+      }
+      if (part == 0) c.b[vv] = csel(is_interior<D>(m, c.n), mk(re, im), czero<T>());
+    }
+    __syncthreads();
+  }
+  // coarsest level: pointwise update from its residual
+  {
+    const SmallLevel<T>& v = a.lv[0];
+    const long long N = D == 3 ? (long long)v.n * v.n * v.n : (long long)v.n * v.n;
+    for (long long i = threadIdx.x; i < N; i += blockDim.x) {
+      int j[3];
+      small_unravel<T, D>(i, v.n, j);
+      update_vertex<T, D>(v.op, j, i, v.b, v.omega, 0, nullptr, v.sc, v.sf, nullptr, nullptr);
+    }
+  }
+  if (a.partials) finish_block<true>(a.partials, a.nparts, a.out);
+}
+
 
 // ---------------------------------------------------------------------------
 // Launch wrappers.
@@ -660,6 +743,22 @@ hipError_t launch_finish_sum_max(const double* partials, int count, double* out,
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_small_pre(const SmallArgs<T>& a, hipStream_t s) {
+  if (a.nl < 1 || a.nl > kSmallMax) return hipErrorInvalidValue;
+  if (a.dim == 3) hipLaunchKernelGGL((k_small_pre<T, 3>), dim3(1), kSmallThreads, 0, s, a);
+  else hipLaunchKernelGGL((k_small_pre<T, 2>), dim3(1), kSmallThreads, 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_small_post(const SmallArgs<T>& a, hipStream_t s) {
+  if (a.nl < 1 || a.nl > kSmallMax) return hipErrorInvalidValue;
+  if (a.dim == 3) hipLaunchKernelGGL((k_small_post<T, 3>), dim3(1), kSmallThreads, 0, s, a);
+  else hipLaunchKernelGGL((k_small_post<T, 2>), dim3(1), kSmallThreads, 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_finish_sum2(const double* partials, int count, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finish<false>, dim3(1), 256, 0, s, partials, count, out);
   return hipGetLastError();
@@ -674,6 +773,8 @@ hipError_t launch_finish_sum2(const double* partials, int count, double* out, hi
   template hipError_t launch_uhat<T>(int, int, const cpx<T>*, const cpx<T>*, cpx<T>*, hipStream_t);             \
   template hipError_t launch_resid<T>(int, const OpData<T>&, const cpx<T>*, const cpx<T>*, cpx<T>*, double*,     \
                                       int*, hipStream_t);                                                       \
+  template hipError_t launch_small_pre<T>(const SmallArgs<T>&, hipStream_t);                                     \
+  template hipError_t launch_small_post<T>(const SmallArgs<T>&, hipStream_t);                                    \
   template hipError_t launch_post_galerkin<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, cpx<T>*,        \
                                               const cpx<T>*, cpx<T>*, cpx<T>*, cpx<T>*, hipStream_t);            \
   template hipError_t launch_update<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, cpx<T>*, cpx<T>*,      \
