@@ -551,21 +551,35 @@ struct Engine {
     }
   }
 
-  // z = B v (zero-start cycle); v, z finest-size T buffers; v's boundary ignored.
-  int precondition(const cpx<T>* v, cpx<T>* z) {
-    MG_TRY(ensure_scratch());
+  // z = B v (zero-start cycle); v, z finest-size T buffers.  v's boundary is
+  // ignored, unless `clean` promises it is zero already (then v is read in place).
+  int precondition(const cpx<T>* v, cpx<T>* z, bool clean = false) {
+    const cpx<T>* rhoL = v;
+    if (!clean) {
+      MG_TRY(ensure_scratch());
+      MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, v, tR, mk(T(1), T(0)), s));
+      rhoL = tR;
+    }
     const int it = 1;
-    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, v, tR, mk(T(1), T(0)), s));
     for (int l = L; l > lmin; --l) {
-      const cpx<T>* src = l == L ? tR : lv[l].pr;
+      const cpx<T>* src = l == L ? rhoL : lv[l].pr;
       MG_HIP(launch_restrict<T>(dim, lv[l - 1].n, src, lv[l - 1].pr, s));
     }
     for (int l = lmin; l <= L; ++l) {
       const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, it);
-      const cpx<T>* rho = l == L ? tR : lv[l].pr;
+      const cpx<T>* rho = l == L ? rhoL : lv[l].pr;
       cpx<T>* out = l == L ? z : lv[l].pz;
-      const cpx<T>* zc = l > lmin ? lv[l - 1].pz : nullptr;
-      MG_HIP(launch_prec_up<T>(dim, lv[l].op, rho, to_c<T>(wl), variant, l == lmin ? 1 : 0, zc, out, s));
+      const cpx<T>* gc = nullptr;
+      if (l > lmin) {
+        gc = lv[l - 1].pz;
+        if (variant == MG_BPX) {
+          // rho_(l-1) (in pr) has been used by now: it holds g
+          MG_HIP(launch_prec_g<T>(dim, lv[l].op, rho, to_c<T>(wl), lv[l - 1].pz, lv[l - 1].pr, s));
+          gc = lv[l - 1].pr;
+        }
+      }
+      MG_HIP(launch_prec_up<T>(dim, lv[l].op, rho, to_c<T>(wl), variant == MG_HB ? 1 : 0, l == lmin ? 1 : 0, gc, out,
+                               s));
     }
     return MG_OK;
   }
@@ -626,7 +640,7 @@ struct Engine {
       MG_TRY(dot(rh, r, &rho_new));
       const complex<double> beta = (rho_new / rho) * (alpha / om);
       MG_HIP(launch_bicg_p<T>(N, r, v, to_c<double>(beta), to_c<double>(om), p, s));
-      MG_TRY(precondition(p, y));
+      MG_TRY(precondition(p, y, true));
       MG_HIP(launch_apply<T>(dim, op, y, v, s));
       complex<double> rhv;
       MG_TRY(dot(rh, v, &rhv));
@@ -642,7 +656,7 @@ struct Engine {
         status = MG_OK;
         break;
       }
-      MG_TRY(precondition(sv, z));
+      MG_TRY(precondition(sv, z, true));
       MG_HIP(launch_apply<T>(dim, op, z, t, s));
       complex<double> ts, tt;
       MG_TRY(dot(t, sv, &ts));

@@ -1,4 +1,6 @@
 // Fused finest-level sweep: standalone kernels, tile table and launchers.
+#include <cstring>
+
 #include "mg_fused_ops.h"
 
 namespace mg {
@@ -134,6 +136,53 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
   }
   return hipGetLastError();
 }
+
+// y = H x or r = b - H x (constant phi, 3D) with the sweep's march: 2 x 2
+// coarse-row tiles, z extent 21, no coarse levels.
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_stencil3(FusedArgs<T> a) {
+  __shared__ F3Lds<T, 2, 2, false, false> sm;
+  double* part = a.partials ? a.partials + 2 * (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) : nullptr;
+  fused3_tile<T, 2, 2, 21, 1, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, part, sm);
+}
+
+static dim3 stencil3_grid(int n) {
+  const int nc = (n - 1) / 3 + 1;
+  return dim3(f3_xtiles(nc), (nc + 1) / 2, (nc + 20) / 21);
+}
+
+int stencil3_blocks(int n) {
+  if (n < 10 || (n - 1) % 3 != 0) return -1;
+  const dim3 g = stencil3_grid(n);
+  return (int)(g.x * g.y * g.z);
+}
+
+template <class T>
+hipError_t launch_stencil3(int apply, int n, const cpx<T>* coef, const cpx<T>* b, const cpx<T>* x, cpx<T>* out,
+                           double* partials, int* nparts, hipStream_t s) {
+  const int blocks = stencil3_blocks(n);
+  if (blocks < 0) return hipErrorInvalidValue;
+  FusedArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nc = (n - 1) / 3 + 1;
+  a.w = x;
+  a.wout = out;
+  a.b = b;
+  for (int q = 0; q < 4; ++q) a.coef[q] = coef[q];
+  a.partials = partials;
+  a.variant = 1;
+  const dim3 g = stencil3_grid(n);
+  if (apply) hipLaunchKernelGGL((k_stencil3<T, kApply>), g, 256, 0, s, a);
+  else hipLaunchKernelGGL((k_stencil3<T, kResid>), g, 256, 0, s, a);
+  if (nparts) *nparts = blocks;
+  return hipGetLastError();
+}
+
+template hipError_t launch_stencil3<double>(int, int, const cpx<double>*, const cpx<double>*, const cpx<double>*,
+                                            cpx<double>*, double*, int*, hipStream_t);
+template hipError_t launch_stencil3<float>(int, int, const cpx<float>*, const cpx<float>*, const cpx<float>*,
+                                           cpx<float>*, double*, int*, hipStream_t);
 
 template hipError_t launch_fused<double>(int, const FusedArgs<double>&, hipStream_t);
 template hipError_t launch_fused<float>(int, const FusedArgs<float>&, hipStream_t);

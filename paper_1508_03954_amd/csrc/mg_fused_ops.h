@@ -172,12 +172,14 @@ struct F3 {
 //   UH  u and its in-row neighbour sum h of each wave's first and last row,
 //       exchanged so that every row of u is formed by one wave only.
 // The z extent does not enter, so tiles that differ only in ZC can share it.
-template <class T, int TYC, int RPT, bool BPX>
+// Without SWEEP (the plain operator marches) only UH is used; the others
+// shrink to one entry.
+template <class T, int TYC, int RPT, bool BPX, bool SWEEP = true>
 struct F3Lds {
   using G = F3<T, TYC, RPT, 1, BPX>;
-  cpx<T> RX[2][G::CY][G::TXR];
-  cpx<T> Gz[2][G::GY][G::GX];
-  cpx<T> Sz[BPX ? 2 : 1][BPX ? G::GY : 1][BPX ? G::GX : 1];
+  cpx<T> RX[SWEEP ? 2 : 1][SWEEP ? G::CY : 1][SWEEP ? G::TXR : 1];
+  cpx<T> Gz[SWEEP ? 2 : 1][SWEEP ? G::GY : 1][SWEEP ? G::GX : 1];
+  cpx<T> Sz[BPX && SWEEP ? 2 : 1][BPX && SWEEP ? G::GY : 1][BPX && SWEEP ? G::GX : 1];
   cpx<T> UH[2][G::W][RPT == 1 ? 1 : 2][2][64];
 };
 
@@ -232,9 +234,13 @@ __device__ inline void bstore(cpx<float> c, __amdgpu_buffer_rsrc_t r, unsigned o
 // b: that keeps the register count (and so the occupancy) down.
 // Coarse staging: wave k stages coarse row k of the tile; the y and z parts of
 // R: every wave takes an equal share of the tile's coarse points.
-template <class T, int TYC, int RPT, int ZC, int VAR>
+// MODE kSweep: the fused sweep.  kResid / kApply: the same march without the
+// coarse levels, storing r = b - H w (with its partial norms) or y = H w.
+constexpr int kSweep = 0, kResid = 1, kApply = 2;
+
+template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep>
 __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
-                                   F3Lds<T, TYC, RPT, VAR == 2>& sm) {
+                                   F3Lds<T, TYC, RPT, VAR == 2, MODE == kSweep>& sm) {
   constexpr bool BPX = VAR == 2;
   using G = F3<T, TYC, RPT, ZC, BPX>;
   constexpr int TXR = G::TXR, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
@@ -352,6 +358,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   };
   // u = w + P g on plane p at row y (zero off the interior)
   auto form_u = [&](int p, int slot, int y, cpx<T> w) {
+    if (MODE != kSweep) return w;   // loads already vanish off the interior
     const int my = floor_div3(y), qy = y - 3 * my, gy = min(max(my - my0 + 1, 0), GY - 1);
     cpx<T> g = f_add(f_scale(wx0, sm.Gz[slot][gy][gxl]), f_scale(wx1, sm.Gz[slot][gy][gxl1]));
     if (qy != 0) {
@@ -390,11 +397,13 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
   };
 
-  load_g(p0);
-  store_g(p0, 0);
-  load_g(p0 + 1);
+  if (MODE == kSweep) {
+    load_g(p0);
+    store_g(p0, 0);
+    load_g(p0 + 1);
+  }
   load_w(p0, Wr, Wh);
-  load_b(p0 - 1, Br);
+  if (MODE != kApply) load_b(p0 - 1, Br);
 #pragma unroll
   for (int j = 0; j < RPT; ++j) { A[j] = f_zero<T>(); Np[j] = f_zero<T>(); Cp[j] = f_zero<T>(); }
   __syncthreads();
@@ -424,7 +433,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
     // (2) refill w with plane p+1; stage plane p+1's correction
     load_w(p + 1, Wr, Wh);
-    store_g(p + 1, 1 - S);
+    if (MODE == kSweep) store_g(p + 1, 1 - S);
     __syncthreads();
     // (3) neighbour rows across the wave edges
     cpx<T> ua = uh, ha = hh, ub = uh, hb = hh;
@@ -461,13 +470,23 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const cpx<T> M = f_mac(f_mac(f_mul(c0, C), c1, F2), c2, E2);
       const cpx<T> N = f_mac(f_mac(f_mul(c1, C), c2, F2), c3, E2);
       const bool in = plane_ok(q) && row_ok(y) && xin && xcomp;
+      if (MODE == kApply) {
+        bstore(f_sel(in, f_add(A[j], N), f_zero<T>()), wo, vst[j]);
+        A[j] = f_add(M, Np[j]);
+        Np[j] = N;
+        continue;
+      }
       const cpx<T> rv = f_sel(in, f_sub(Br[j], f_add(A[j], N)), f_zero<T>());
-      const cpx<T> s = f_mul(ws, rv);
-      const bool cp = q_c && ccol && x >= 0 && (y % 3) == 0;
-      const cpx<T> scm = f_sel(VAR != 0 && cp, f_zero<T>(), s);
-      // off the interior u, r and s vanish, so the stored value is zero there
-      bstore(f_add(Cp[j], scm), wo, vst[j]);
-      if (VAR != 1) bstore(VAR == 0 ? scm : s, co, vcp[j]);
+      if (MODE == kSweep) {
+        const cpx<T> s = f_mul(ws, rv);
+        const bool cp = q_c && ccol && x >= 0 && (y % 3) == 0;
+        const cpx<T> scm = f_sel(VAR != 0 && cp, f_zero<T>(), s);
+        // off the interior u, r and s vanish, so the stored value is zero there
+        bstore(f_add(Cp[j], scm), wo, vst[j]);
+        if (VAR != 1) bstore(VAR == 0 ? scm : s, co, vcp[j]);
+      } else {
+        bstore(rv, wo, vst[j]);
+      }
       if (q_own) {
         const double r2 = vst[j] != kOOB ? (double)rv.re * rv.re + (double)rv.im * rv.im : 0.0;
         nsum += r2;
@@ -478,8 +497,10 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       Np[j] = N;
       Cp[j] = C;
     }
+    if (MODE == kApply) return;
     // refill b with plane p, the coarse registers with plane p+2
     load_b(p, Br);
+    if (MODE != kSweep) return;
     load_g(p + 2);
     // (5) x part of R at the owned coarse columns (lanes 2 .. 61; the boundary
     // columns need none), which read their neighbours' r from this wave's slot
@@ -509,9 +530,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   // the remaining step, if any, then R of the last plane
   if (p <= plast) {
     step(std::integral_constant<int, 0>(), p);
-    __syncthreads();
-    rest_yz(plast - 1, 1);
-  } else {
+    if (MODE == kSweep) {
+      __syncthreads();
+      rest_yz(plast - 1, 1);
+    }
+  } else if (MODE == kSweep) {
     __syncthreads();
     rest_yz(plast - 1, 0);
   }

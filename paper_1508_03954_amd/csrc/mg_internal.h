@@ -80,10 +80,15 @@ hipError_t launch_restrict(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStr
 template <class T>
 hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s);
 
-// Zero-start cycle pieces: z_l = Lop(omega D^-1 rho_l) + P z_(l-1).
+// Zero-start cycle pieces: z_l = Lop(omega D^-1 rho_l) + P z_(l-1), written
+// as z_l = s_l (masked on c-points for hb) + P g with g = z_(l-1), or for BPX
+// g = z_(l-1) - I s_l (launch_prec_g).
 template <class T>
-hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int variant,
-                          int is_lmin, const cpx<T>* zc, cpx<T>* z, hipStream_t s);
+hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int mask_c,
+                          int is_lmin, const cpx<T>* gc, cpx<T>* z, hipStream_t s);
+template <class T>
+hipError_t launch_prec_g(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, const cpx<T>* zc, cpx<T>* g,
+                         hipStream_t s);
 
 template <class T>
 hipError_t launch_cellavg(int dim, int n, const cpx<T>* phi, cpx<T>* phibar, int conj, hipStream_t s);
@@ -179,6 +184,13 @@ struct FusedArgs {
 template <class T>
 hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);
 int fused_tile_count(int dim);
+// 3D constant-phi operator with the sweep's march: y = H x (apply != 0) or
+// r = b - H x with per-block partial norms (when partials != nullptr; their
+// count, stencil3_blocks(n), goes to *nparts).  Needs n = 3k + 1 >= 10.
+int stencil3_blocks(int n);
+template <class T>
+hipError_t launch_stencil3(int apply, int n, const cpx<T>* coef, const cpx<T>* b, const cpx<T>* x, cpx<T>* out,
+                           double* partials, int* nparts, hipStream_t s);
 int fused_partials_blocks(int dim, int n, int tile);  // -1 if unsupported
 // Tile variant with the given shape (3D: coarse rows, rows per thread, coarse
 // planes; 2D: coarse rows zc only), or -1.

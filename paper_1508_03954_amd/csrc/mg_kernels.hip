@@ -183,31 +183,57 @@ __global__ __launch_bounds__(256) void k_post_galerkin(OpData<T> op, const cpx<T
 
 // R v = P^T v: per axis weights 1 - |o|/3 for fine offsets o in [-2, 2] around 3m;
 // zero on the coarse boundary.
+// Part of (R v)(m) over the offsets whose outermost component (z in 3D, y in
+// 2D) is oo; all loads independent (indices clamped, boundary m gives 0 later).
 template <class T, int D>
-__global__ void k_restrict(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
-  const int nf = 3 * (nc - 1) + 1;
-  const T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
-  MG_ROWS(D, nc) {
-    int m[3];
-    long long i;
-    if (!row_vertex<D>(row_, x_, nc, m, i)) continue;
-    if (!is_interior<D>(m, nc)) { vc[i] = czero<T>(); continue; }
-    cpx<T> acc = czero<T>();
-    const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
-    for (int oz = zlo; oz <= zhi; ++oz) {
-      cpx<T> accy = czero<T>();
-      for (int oy = -2; oy <= 2; ++oy) {
-        cpx<T> accx = czero<T>();
-        for (int ox = -2; ox <= 2; ++ox) {
-          int j[3] = {3 * m[0] + ox, 3 * m[1] + oy, 3 * m[2] + oz};
-          accx = accx + w[ox + 2] * vf[ravel<D>(j, nf)];
-        }
-        accy = accy + w[oy + 2] * accx;
-      }
-      acc = acc + (D == 3 ? w[oz + 2] : T(1)) * accy;
+__device__ inline cpx<T> restrict_part(const cpx<T>* __restrict__ vf, int nf, const int m[3], int oo) {
+  constexpr T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
+  constexpr int IL = D == 3 ? -2 : 0, IH = D == 3 ? 2 : 0;
+  cpx<T> acc = czero<T>();
+#pragma unroll
+  for (int oi = IL; oi <= IH; ++oi) {
+    cpx<T> accx = czero<T>();
+#pragma unroll
+    for (int ox = -2; ox <= 2; ++ox) {
+      const int o[3] = {ox, D == 3 ? oi : oo, oo};
+      int j[3] = {0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < D; ++q) j[q] = min(max(3 * m[q] + o[q], 0), nf - 1);
+      accx = accx + w[ox + 2] * vf[(unsigned)ravel<D>(j, nf)];
     }
-    vc[i] = acc;
+    acc = acc + (D == 3 ? w[oi + 2] * w[oo + 2] : w[oo + 2]) * accx;
   }
+  return acc;
+}
+
+// R v = P^T v (weights 1 - |o|/3 per axis around 3m; zero on the coarse
+// boundary): eight lanes per coarse vertex, lanes 0..4 take the parts
+// oo = -2..2, summed by a xor shuffle.
+template <class T, int D>
+__global__ __launch_bounds__(256) void k_restrict(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
+  const int nf = 3 * (nc - 1) + 1;
+  const long long Nc = D == 3 ? (long long)nc * nc * nc : (long long)nc * nc;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = g >> 3;
+  const int part = (int)(g & 7);
+  const bool valid = v < Nc;
+  const long long vv = valid ? v : 0;
+  int m[3] = {(int)(vv % nc), 0, 0};
+  if (D == 3) {
+    m[1] = (int)((vv / nc) % nc);
+    m[2] = (int)(vv / ((long long)nc * nc));
+  } else {
+    m[1] = (int)(vv / nc);
+  }
+  cpx<T> p = czero<T>();
+  if (valid && part < 5) p = restrict_part<T, D>(vf, nf, m, part - 2);
+  T re = p.re, im = p.im;
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (valid && part == 0) vc[vv] = csel(is_interior<D>(m, nc), mk(re, im), czero<T>());
 }
 
 template <class T, int D>
@@ -225,55 +251,53 @@ __global__ void k_inject(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restri
 // Zero-start cycle, upward part on one level:
 //   s = omega rho / D;  z = Lop(s) + P z_c, Lop = id (add), c-point mask (hb),
 //   s - P I s (BPX); on the coarsest level z = s.
+// Zero-start cycle, one level going up: z = Lop(omega D^-1 rho) + P g with
+// g the coarse correction (BPX: already minus I s, see k_prec_g); hb masks s
+// on c-points (mask_c); the coarsest level has no g.
 template <class T, int D>
-__global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int variant, int is_lmin,
-                          const cpx<T>* __restrict__ zc, cpx<T>* __restrict__ z) {
+__global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c, int is_lmin,
+                          const cpx<T>* __restrict__ gc, cpx<T>* __restrict__ z) {
   const int n = op.n;
   const int nc = (n - 1) / 3 + 1;
   MG_ROWS(D, n) {
     int j[3];
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    if (!is_interior<D>(j, n)) { z[i] = czero<T>(); continue; }
-    cpx<T> id = op.invD;
-    if (op.invDv) id = op.invDv[i];
-    cpx<T> s = cmul(omega, cmul(id, rho[i]));
-    if (!is_lmin) {
-      if (variant == 1 && is_cpoint<D>(j)) s = czero<T>();
-      if (variant == 2) {
-        // (P I s)_j: interpolate the c-point values of s around j.
-        const T third = T(1.0 / 3.0), two3 = T(2.0 / 3.0);
-        int m[3] = {0, 0, 0};
-        T w0[3] = {1, 1, 1}, w1[3] = {0, 0, 0};
-        bool two[3] = {false, false, false};
-        for (int a = 0; a < D; ++a) {
-          const int q = j[a] % 3;
-          m[a] = j[a] / 3;
-          if (q == 1) { w0[a] = two3; w1[a] = third; two[a] = true; }
-          else if (q == 2) { w0[a] = third; w1[a] = two3; two[a] = true; }
-        }
-        cpx<T> pis = czero<T>();
-        for (int c = 0; c < (1 << D); ++c) {
-          T w = T(1);
-          int k[3] = {0, 0, 0};
-          bool use = true;
-          for (int a = 0; a < D; ++a) {
-            const int bit = (c >> a) & 1;
-            if (bit && !two[a]) { use = false; break; }
-            w *= bit ? w1[a] : w0[a];
-            k[a] = 3 * (m[a] + bit);
-          }
-          if (!use || !is_interior<D>(k, n)) continue;
-          const long long ik = ravel<D>(k, n);
-          cpx<T> idk = op.invD;
-          if (op.invDv) idk = op.invDv[ik];
-          pis = pis + w * cmul(omega, cmul(idk, rho[ik]));
-        }
-        s = s - pis;
+    cpx<T> out = czero<T>();
+    if (is_interior<D>(j, n)) {
+      cpx<T> id = op.invD;
+      if (op.invDv) id = op.invDv[i];
+      cpx<T> s = cmul(omega, cmul(id, rho[i]));
+      if (!is_lmin) {
+        s = csel(mask_c && is_cpoint<D>(j), czero<T>(), s);
+        s = s + prolong_at<T, D>(gc, nc, j);
       }
-      s = s + prolong_at<T, D>(zc, nc, j);
+      out = s;
     }
-    z[i] = s;
+    z[i] = out;
+  }
+}
+
+// BPX coarse correction of the zero-start cycle at level l (op): on coarse
+// vertex m, g = z_c(m) - (I s)(m) with s = omega D^-1 rho at 3m, so that
+// z = s + P g = s - P I s + P z_c.
+template <class T, int D>
+__global__ void k_prec_g(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, const cpx<T>* __restrict__ zc,
+                         cpx<T>* __restrict__ g) {
+  const int n = op.n, nc = (n - 1) / 3 + 1;
+  MG_ROWS(D, nc) {
+    int m[3];
+    long long ic;
+    if (!row_vertex<D>(row_, x_, nc, m, ic)) continue;
+    const int j[3] = {3 * m[0], 3 * m[1], D == 3 ? 3 * m[2] : 0};
+    cpx<T> q = czero<T>();
+    if (is_interior<D>(j, n)) {
+      const long long i = ravel<D>(j, n);
+      cpx<T> id = op.invD;
+      if (op.invDv) id = op.invDv[i];
+      q = cmul(omega, cmul(id, rho[i]));
+    }
+    g[ic] = zc[ic] - q;
   }
 }
 
@@ -590,6 +614,8 @@ static inline dim3 row_grid(int n, int dim, int max_row_blocks = 65535) {
 
 template <class T>
 hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y, hipStream_t s) {
+  if (dim == 3 && !op.phibar && stencil3_blocks(op.n) > 0)
+    return launch_stencil3<T>(1, op.n, op.coef, nullptr, x, y, nullptr, nullptr, s);
   MG_DISPATCH(dim, k_apply, row_grid(op.n, dim), op, x, y);
   return hipGetLastError();
 }
@@ -617,6 +643,9 @@ hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>
 template <class T>
 hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
                         double* partials, int* nparts, hipStream_t s) {
+  const int sb = dim == 3 && !op.phibar ? stencil3_blocks(op.n) : -1;
+  if (sb > 0 && (!partials || sb <= kRedBlocks))
+    return launch_stencil3<T>(0, op.n, op.coef, b, x, r, partials, nparts, s);
   dim3 g = row_grid(op.n, dim);
   if (partials) {
     const int gx = (int)g.x;
@@ -646,7 +675,8 @@ hipError_t launch_update(int dim, const OpData<T>& op, const cpx<T>* r, cpx<T> o
 
 template <class T>
 hipError_t launch_restrict(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s) {
-  MG_DISPATCH(dim, k_restrict, row_grid(nc, dim), nc, vf, vc);
+  const long long lanes = 8 * pow_n(nc, dim);
+  MG_DISPATCH(dim, k_restrict, dim3((unsigned)((lanes + 255) / 256)), nc, vf, vc);
   return hipGetLastError();
 }
 
@@ -657,9 +687,17 @@ hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStrea
 }
 
 template <class T>
-hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int variant, int is_lmin,
-                          const cpx<T>* zc, cpx<T>* z, hipStream_t s) {
-  MG_DISPATCH(dim, k_prec_up, row_grid(op.n, dim), op, rho, omega, variant, is_lmin, zc, z);
+hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int mask_c, int is_lmin,
+                          const cpx<T>* gc, cpx<T>* z, hipStream_t s) {
+  MG_DISPATCH(dim, k_prec_up, row_grid(op.n, dim), op, rho, omega, mask_c, is_lmin, gc, z);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_prec_g(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, const cpx<T>* zc, cpx<T>* g,
+                         hipStream_t s) {
+  const int nc = (op.n - 1) / 3 + 1;
+  MG_DISPATCH(dim, k_prec_g, row_grid(nc, dim), op, rho, omega, zc, g);
   return hipGetLastError();
 }
 
@@ -783,6 +821,8 @@ hipError_t launch_finish_sum2(const double* partials, int count, double* out, hi
   template hipError_t launch_inject<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                          \
   template hipError_t launch_prec_up<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, int, const cpx<T>*,   \
                                         cpx<T>*, hipStream_t);                                                  \
+  template hipError_t launch_prec_g<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, const cpx<T>*, cpx<T>*,     \
+                                       hipStream_t);                                                            \
   template hipError_t launch_cellavg<T>(int, int, const cpx<T>*, cpx<T>*, int, hipStream_t);                    \
   template hipError_t launch_invdiag<T>(int, const OpData<T>&, cpx<T>*, hipStream_t);                           \
   template hipError_t launch_zero_boundary_copy<T>(int, int, const cpx<T>*, cpx<T>*, cpx<T>, hipStream_t);      \
