@@ -255,7 +255,9 @@ struct Engine {
         max_blocks = std::max(max_blocks, fused_partials_blocks(dim, lv[L].n, t));
       set_tile(default_tile());
     }
-    MG_TRY(alloc_c(&partials, 2 * (size_t)max_blocks));
+    // (sum, max) pairs per block, or up to four sums per block of the fused
+    // Krylov kernels
+    MG_TRY(alloc_c(&partials, std::max<size_t>(2 * (size_t)max_blocks, 4 * (size_t)kRedBlocks)));
     partials_cap = max_blocks;
     MG_TRY(alloc_c(&red, 4));
     MG_TRY(ensure_hist(64));
@@ -604,8 +606,18 @@ struct Engine {
     return MG_OK;
   }
 
+  // Reduced values of a fused Krylov kernel (nvals sums over kRedBlocks blocks).
+  int finish(int nvals, double* h) {
+    MG_HIP(launch_finishN(nvals, partials, kRedBlocks, red, s));
+    MG_HIP(hipMemcpyAsync(h, red, nvals * sizeof(double), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    return MG_OK;
+  }
+
   // Right-preconditioned BiCGStab (van der Vorst) on H x = b, T-precision vectors,
   // FP64 scalars.  b, x finest-size T buffers (x: initial guess in, result out).
+  // Per iteration: two zero-start cycles, two operator applications and four
+  // fused vector passes, each returning its scalars to the host.
   int bicgstab(const cpx<T>* b_in, cpx<T>* x, double rtol, int maxit, int* its, double* relres) {
     MG_TRY(ensure_krylov());
     MG_TRY(ensure_scratch());
@@ -630,14 +642,14 @@ struct Engine {
     complex<double> rho = 1.0, alpha = 1.0, om = 1.0;
     double rn;
     MG_TRY(norm2(r, &rn));
+    complex<double> rho_new = rn * rn;   // (rh, r) with rh = r
     double rel = rn / bnorm;
     const double r0 = rel;
     int it = 0;
     int status = MG_ENOTCONV;
     if (rel <= rtol) status = MG_OK;
+    double h[3];
     for (it = 1; it <= maxit && status == MG_ENOTCONV; ++it) {
-      complex<double> rho_new;
-      MG_TRY(dot(rh, r, &rho_new));
       const complex<double> beta = (rho_new / rho) * (alpha / om);
       MG_HIP(launch_bicg_p<T>(N, r, v, to_c<double>(beta), to_c<double>(om), p, s));
       MG_TRY(precondition(p, y, true));
@@ -645,11 +657,10 @@ struct Engine {
       complex<double> rhv;
       MG_TRY(dot(rh, v, &rhv));
       alpha = rho_new / rhv;
-      // s = r - alpha v
-      MG_HIP(hipMemcpyAsync(sv, r, N * sizeof(cpx<T>), hipMemcpyDeviceToDevice, s));
-      MG_HIP(launch_axpby<T>(N, to_c<double>(-alpha), v, mk(1.0, 0.0), sv, s));
-      double sn;
-      MG_TRY(norm2(sv, &sn));
+      // s = r - alpha v and |s|
+      MG_HIP(launch_bicg_s<T>(N, r, v, to_c<double>(alpha), sv, partials, s));
+      MG_TRY(finish(1, h));
+      const double sn = std::sqrt(h[0]);
       if (sn / bnorm <= rtol) {
         MG_HIP(launch_axpby<T>(N, to_c<double>(alpha), y, mk(1.0, 0.0), x, s));
         rel = sn / bnorm;
@@ -658,13 +669,15 @@ struct Engine {
       }
       MG_TRY(precondition(sv, z, true));
       MG_HIP(launch_apply<T>(dim, op, z, t, s));
-      complex<double> ts, tt;
-      MG_TRY(dot(t, sv, &ts));
-      MG_TRY(dot(t, t, &tt));
-      om = ts / tt;
-      MG_HIP(launch_bicg_xr<T>(N, x, y, z, to_c<double>(alpha), to_c<double>(om), r, sv, t, s));
+      MG_HIP(launch_bicg_ts<T>(N, t, sv, partials, s));
+      MG_TRY(finish(3, h));
+      om = complex<double>(h[0], h[1]) / h[2];
+      // x += alpha y + om z; r = s - om t; |r| and (rh, r) for the next step
+      MG_HIP(launch_bicg_xr2<T>(N, x, y, z, to_c<double>(alpha), to_c<double>(om), r, sv, t, rh, partials, s));
+      MG_TRY(finish(3, h));
       rho = rho_new;
-      MG_TRY(norm2(r, &rn));
+      rho_new = complex<double>(h[1], h[2]);
+      rn = std::sqrt(h[0]);
       rel = rn / bnorm;
       if (!std::isfinite(rel) || rel > 1e8 * std::max(r0, 1e-300)) {
         status = MG_EDIVERGED;

@@ -123,6 +123,22 @@ template <class T>
 hipError_t launch_bicg_xr(size_t count, cpx<T>* x, const cpx<T>* y, const cpx<T>* z, cpx<double> a,
                           cpx<double> w, cpx<T>* r, const cpx<T>* sv, const cpx<T>* t, hipStream_t s);
 
+// Fused BiCGStab steps; partials hold N doubles per block (kRedBlocks blocks),
+// reduced by launch_finishN:
+//   bicg_s   (N = 1): s = r - a v, |s|^2
+//   bicg_ts  (N = 3): conj(t).s (re, im), |t|^2
+//   bicg_xr2 (N = 3): x += a y + w z, r = s - w t, |r|^2, conj(rh).r (re, im)
+template <class T>
+hipError_t launch_bicg_s(size_t count, const cpx<T>* r, const cpx<T>* v, cpx<double> a, cpx<T>* sv, double* partials,
+                         hipStream_t s);
+template <class T>
+hipError_t launch_bicg_ts(size_t count, const cpx<T>* t, const cpx<T>* sv, double* partials, hipStream_t s);
+template <class T>
+hipError_t launch_bicg_xr2(size_t count, cpx<T>* x, const cpx<T>* y, const cpx<T>* z, cpx<double> a, cpx<double> w,
+                           cpx<T>* r, const cpx<T>* sv, const cpx<T>* t, const cpx<T>* rh, double* partials,
+                           hipStream_t s);
+hipError_t launch_finishN(int nvals, const double* partials, int count, double* out, hipStream_t s);
+
 // Residual-refinement helpers: out64 += scale * in32 (in place FP64 accumulate).
 hipError_t launch_accum32(size_t count, const cpx<float>* e, double scale, cpx<double>* u, hipStream_t s);
 

@@ -52,6 +52,30 @@ __device__ inline void block_sum2(double s0, double s1, double* partials) {
   }
 }
 
+// N sums per block (wave shuffles, then waves in order), for the fused
+// Krylov kernels: partials[N * block + k].
+template <int N>
+__device__ inline void block_sumN(double (&v)[N], double* partials) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  __shared__ double acc[N][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double x = 0;
+      for (int w = 0; w < nw; ++w) x += acc[k][w];
+      partials[N * blockIdx.x + k] = x;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 template <class T, int D>
 __global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
@@ -420,6 +444,80 @@ __global__ void k_bicg_xr(size_t count, cpx<T>* __restrict__ x, const cpx<T>* __
               T(xv.im + a.re * yv.im + a.im * yv.re + w.re * zv.im + w.im * zv.re));
     r[i] = mk(T(s.re - (w.re * tv.re - w.im * tv.im)), T(s.im - (w.re * tv.im + w.im * tv.re)));
   }
+}
+
+// s = r - a v, partial |s|^2.
+template <class T>
+__global__ void k_bicg_s(size_t count, const cpx<T>* __restrict__ r, const cpx<T>* __restrict__ v, cpx<double> a,
+                         cpx<T>* __restrict__ sv, double* partials) {
+  double acc[1] = {0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> rv = r[i], vv = v[i];
+    const cpx<T> o = mk(T(rv.re - (a.re * vv.re - a.im * vv.im)), T(rv.im - (a.re * vv.im + a.im * vv.re)));
+    sv[i] = o;
+    acc[0] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  block_sumN<1>(acc, partials);
+}
+
+// conj(t) . s and |t|^2 in one pass.
+template <class T>
+__global__ void k_bicg_ts(size_t count, const cpx<T>* __restrict__ t, const cpx<T>* __restrict__ sv, double* partials) {
+  double acc[3] = {0, 0, 0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> x = t[i], y = sv[i];
+    acc[0] += (double)x.re * y.re + (double)x.im * y.im;
+    acc[1] += (double)x.re * y.im - (double)x.im * y.re;
+    acc[2] += (double)x.re * x.re + (double)x.im * x.im;
+  }
+  block_sumN<3>(acc, partials);
+}
+
+// x += a y + w z ; r = s - w t ; partial |r|^2 and conj(rh) . r.
+template <class T>
+__global__ void k_bicg_xr2(size_t count, cpx<T>* __restrict__ x, const cpx<T>* __restrict__ y,
+                           const cpx<T>* __restrict__ z, cpx<double> a, cpx<double> w, cpx<T>* __restrict__ r,
+                           const cpx<T>* __restrict__ sv, const cpx<T>* __restrict__ t, const cpx<T>* __restrict__ rh,
+                           double* partials) {
+  double acc[3] = {0, 0, 0};
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const cpx<T> xv = x[i], yv = y[i], zv = z[i], s = sv[i], tv = t[i], hv = rh[i];
+    x[i] = mk(T(xv.re + a.re * yv.re - a.im * yv.im + w.re * zv.re - w.im * zv.im),
+              T(xv.im + a.re * yv.im + a.im * yv.re + w.re * zv.im + w.im * zv.re));
+    const cpx<T> o = mk(T(s.re - (w.re * tv.re - w.im * tv.im)), T(s.im - (w.re * tv.im + w.im * tv.re)));
+    r[i] = o;
+    acc[0] += (double)o.re * o.re + (double)o.im * o.im;
+    acc[1] += (double)hv.re * o.re + (double)hv.im * o.im;
+    acc[2] += (double)hv.re * o.im - (double)hv.im * o.re;
+  }
+  block_sumN<3>(acc, partials);
+}
+
+// Second stage of block_sumN: out[k] = sum over blocks in block order, by 256
+// strided partial sums and a tree (as the other second stages).
+template <int N>
+__global__ void k_finishN(const double* __restrict__ partials, int count, double* out) {
+  __shared__ double sh[N][256];
+  const int t = threadIdx.x;
+  double a[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) a[k] = 0;
+#pragma unroll 4
+  for (int i = t; i < count; i += 256)
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] += partials[N * i + k];
+#pragma unroll
+  for (int k = 0; k < N; ++k) sh[k][t] = a[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int k = 0; k < N; ++k) sh[k][t] += sh[k][t + w];
+    __syncthreads();
+  }
+  if (t == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[k] = sh[k][0];
 }
 
 __global__ void k_accum32(size_t count, const cpx<float>* __restrict__ e, double scale, cpx<double>* __restrict__ u) {
@@ -797,6 +895,34 @@ hipError_t launch_small_post(const SmallArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_bicg_s(size_t count, const cpx<T>* r, const cpx<T>* v, cpx<double> a, cpx<T>* sv, double* partials,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_s<T>, dim3(kRedBlocks), 256, 0, s, count, r, v, a, sv, partials);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bicg_ts(size_t count, const cpx<T>* t, const cpx<T>* sv, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_ts<T>, dim3(kRedBlocks), 256, 0, s, count, t, sv, partials);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_bicg_xr2(size_t count, cpx<T>* x, const cpx<T>* y, const cpx<T>* z, cpx<double> a, cpx<double> w,
+                           cpx<T>* r, const cpx<T>* sv, const cpx<T>* t, const cpx<T>* rh, double* partials,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_xr2<T>, dim3(kRedBlocks), 256, 0, s, count, x, y, z, a, w, r, sv, t, rh, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_finishN(int nvals, const double* partials, int count, double* out, hipStream_t s) {
+  if (nvals == 1) hipLaunchKernelGGL(k_finishN<1>, dim3(1), 256, 0, s, partials, count, out);
+  else if (nvals == 3) hipLaunchKernelGGL(k_finishN<3>, dim3(1), 256, 0, s, partials, count, out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_finish_sum2(const double* partials, int count, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finish<false>, dim3(1), 256, 0, s, partials, count, out);
   return hipGetLastError();
@@ -811,6 +937,12 @@ hipError_t launch_finish_sum2(const double* partials, int count, double* out, hi
   template hipError_t launch_uhat<T>(int, int, const cpx<T>*, const cpx<T>*, cpx<T>*, hipStream_t);             \
   template hipError_t launch_resid<T>(int, const OpData<T>&, const cpx<T>*, const cpx<T>*, cpx<T>*, double*,     \
                                       int*, hipStream_t);                                                       \
+  template hipError_t launch_bicg_s<T>(size_t, const cpx<T>*, const cpx<T>*, cpx<double>, cpx<T>*, double*,      \
+                                       hipStream_t);                                                            \
+  template hipError_t launch_bicg_ts<T>(size_t, const cpx<T>*, const cpx<T>*, double*, hipStream_t);              \
+  template hipError_t launch_bicg_xr2<T>(size_t, cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<double>, cpx<double>, \
+                                         cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*, double*,          \
+                                         hipStream_t);                                                          \
   template hipError_t launch_small_pre<T>(const SmallArgs<T>&, hipStream_t);                                     \
   template hipError_t launch_small_post<T>(const SmallArgs<T>&, hipStream_t);                                    \
   template hipError_t launch_post_galerkin<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, cpx<T>*,        \
