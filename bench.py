@@ -69,9 +69,9 @@ def traffic_from_profiles(tile):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_sha256") != fused_source_digest() or rec.get("tile") != tile:
+    if rec.get("kernel_sha256") != fused_source_digest():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("tiles", {}).get(str(tile), {}).get("bytes_per_launch")
 
 
 def time_cycles(s, steps, warmup, torch):

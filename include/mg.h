@@ -91,6 +91,9 @@ typedef struct {
   int conjugate;             /* 1: operator is H^H = conj(H) (adjoint solves)      */
   int restrict_form;         /* MG_RESTRICT_*                                      */
   int sweep;                 /* MG_SWEEP_*                                         */
+  double inner_rtol;         /* MG_FP32_REFINE: relative residual each complex64   */
+                             /* inner solve aims for (0: 1e-4); an outer step      */
+                             /* then reduces the FP64 residual by about this much  */
 } mg_params;
 
 /* Fills *p with: dim 3, levels 1..3, theta 0, phi 0, constant, BPX, CONST,

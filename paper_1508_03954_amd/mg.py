@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
         ("theta", ctypes.c_double), ("phi", c128), ("phi_field", ctypes.c_void_p),
         ("variant", ctypes.c_int), ("omega_scheme", ctypes.c_int), ("omega", c128),
         ("omega_L", ctypes.c_int), ("precision", ctypes.c_int), ("conjugate", ctypes.c_int),
-        ("restrict_form", ctypes.c_int), ("sweep", ctypes.c_int),
+        ("restrict_form", ctypes.c_int), ("sweep", ctypes.c_int), ("inner_rtol", ctypes.c_double),
     ]
 
 
@@ -123,7 +123,7 @@ def _ptr(t) -> int:
 def make_params(dim: int, level_max: int, level_min: int = 1, theta: float = 0.0, phi: complex = 0.0,
                 phi_field=None, variant: str = "bpx", omega_scheme: str = "const", omega: complex = 0.6,
                 omega_L: int = 1, precision: str = "fp64", conjugate: bool = False, restrict_form: str = "auto",
-                sweep: str = "auto"):
+                sweep: str = "auto", inner_rtol: float = 0.0):
     """mg_params from keyword values; returns (params, device phi field kept alive or None)."""
     import torch
     lib = load_library()
@@ -144,6 +144,7 @@ def make_params(dim: int, level_max: int, level_min: int = 1, theta: float = 0.0
     p.conjugate = 1 if conjugate else 0
     p.restrict_form = RESTRICT_FORMS[restrict_form]
     p.sweep = SWEEPS[sweep]
+    p.inner_rtol = inner_rtol
     return p, keep
 
 
@@ -153,11 +154,11 @@ class Solver:
     def __init__(self, dim: int, level_max: int, level_min: int = 1, theta: float = 0.0,
                  phi: complex = 0.0, phi_field=None, variant: str = "bpx", omega_scheme: str = "const",
                  omega: complex = 0.6, omega_L: int = 1, precision: str = "fp64", conjugate: bool = False,
-                 restrict_form: str = "auto", sweep: str = "auto", stream=None):
+                 restrict_form: str = "auto", sweep: str = "auto", stream=None, inner_rtol: float = 0.0):
         import torch
         lib = load_library()
         p, keep = make_params(dim, level_max, level_min, theta, phi, phi_field, variant, omega_scheme, omega,
-                              omega_L, precision, conjugate, restrict_form, sweep)
+                              omega_L, precision, conjugate, restrict_form, sweep, inner_rtol)
         self._phi_keep = keep
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         ctx = ctypes.c_void_p()
