@@ -259,7 +259,8 @@ int mg_batch_configs(void);
  * item is published, and the XCD and workgroup that ran it.
  * mg_batch_get_trace copies the last cycle's record: 8 values per item in
  * queue order -- problem, phase, tile, kind (0 descent, 1/2 finest sweep 3D/2D,
- * 3 Galerkin backtracking, 4 coarsest update, 5 norm), wait start, ready,
+ * 3 Galerkin backtracking, 4 coarsest update, 5 norm, 6 seam rows of the 3D
+ * sweep's restriction), wait start, ready,
  * done, XCD << 16 | workgroup -- for min(cap, count) items; *count receives
  * the number of items.  Synchronises. */
 int mg_batch_trace(mg_batch* batch, int enable);

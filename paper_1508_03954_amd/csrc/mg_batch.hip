@@ -3,8 +3,8 @@
 // persistent kernel launch.
 //
 // Work items are (problem, phase, tile).  The phases of one problem's cycle
-// are its coarse pre-phases (levels l_min .. L-1), the fused finest sweep, the
-// coarse Galerkin post-phases (levels L-1 .. l_min+1), the coarsest update and
+// are its coarse pre-phases (levels l_min .. L-1), the fused finest sweep (in
+// 3D followed by the seam rows of its restriction), the coarse Galerkin post-phases (levels L-1 .. l_min+1), the coarsest update and
 // the residual-norm reduction; each phase depends on all tiles of the
 // previous phase of the same problem and on nothing else.  A resident grid of
 // workgroups pulls items from an atomic queue ordered so that every item comes
@@ -26,13 +26,14 @@
 
 namespace mg {
 
-enum BatchKind { BK_PRE = 0, BK_FUSED3 = 1, BK_FUSED2 = 2, BK_POST = 3, BK_UPDATE = 4, BK_NORM = 5 };
+enum BatchKind { BK_PRE = 0, BK_FUSED3 = 1, BK_FUSED2 = 2, BK_POST = 3, BK_UPDATE = 4, BK_NORM = 5, BK_SEAM = 6 };
 constexpr int kBMaxPhases = 16;
 constexpr int kBMaxLevels = 8;
-constexpr int kBRows = 16;          // rows of a coarse level per item (4 per wavefront)
-constexpr int kBThreads = 256;
-// 3D tiles usable by a 256-thread workgroup: coarse rows 2, rows per thread 2;
-// z extent selectable.  2D: one tile per wavefront, four per item.
+constexpr int kBWaves = 3;
+constexpr int kBThreads = 64 * kBWaves;
+constexpr int kBRows = 4 * kBWaves;  // rows of a coarse level per item (4 per wavefront)
+// 3D tiles of a 3-wave workgroup: coarse rows 2, rows per thread 2; z extent
+// selectable.  2D: one tile per wavefront, three per item.
 constexpr int kBZc3[] = {9, 27};
 constexpr int kBZc2[] = {1, 2, 4, 8};
 // configurations: z extent (3D) x z extent (2D) x queue order
@@ -59,6 +60,7 @@ struct BProb {
   BLevel<T> lv[kBMaxLevels];
   cpx<T>* w[2];
   cpx<T>* si2[2];
+  cpx<T>* spill;                    // seam rows of the 3D sweep's restriction
   cpx<T> wsL;
   double* part;
 };
@@ -87,13 +89,13 @@ __device__ inline unsigned xcc_id() {
   return x & 0xf;
 }
 
-// Coarse-level row items: wave w handles rows tile*kBRows + w + 4k.
+// Coarse-level row items: wave w handles rows tile*kBRows + w + kBWaves k.
 template <class T, int D, class F>
 __device__ inline void for_rows(int n, int tile, F f) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nrows = D == 3 ? n * n : n;
-  for (int k = 0; k < kBRows / 4; ++k) {
-    const int row = tile * kBRows + wv + 4 * k;
+  for (int k = 0; k < kBRows / kBWaves; ++k) {
+    const int row = tile * kBRows + wv + kBWaves * k;
     if (row >= nrows) break;
     for (int x = lane; x < n; x += 64) {
       int j[3];
@@ -122,6 +124,7 @@ __device__ inline FusedArgs<T> batch_fused_args(const BProb<T>& P, int cyc) {
   f.rhoc = P.lv[L - 1].b;
   f.sfc = add ? P.lv[L - 1].sf : nullptr;
   f.sic_out = bpx ? P.si2[1 - ps] : nullptr;
+  f.spill = P.spill;
   for (int q = 0; q < 4; ++q) f.coef[q] = P.lv[L].op.coef[q];
   f.ws = P.wsL;
   f.partials = nullptr;
@@ -205,9 +208,27 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
     for_rows<T, D>(v.n, tile, [&](const int j[3], long long i) {
       update_vertex<T, D>(v.op, j, i, v.b, v.omega, 0, nullptr, v.sc, v.sf, nullptr, nullptr);
     });
+  } else if (kind == BK_SEAM) {
+    // rho_c += the seam rows of the 3D restriction (rows (s + 1) 2 of each coarse plane)
+    const BLevel<T>& c = P.lv[P.L - 1];
+    const int nc = c.n, nty = P.fgy, nseam = nty - 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < kBRows / kBWaves; ++k) {
+      const int row = tile * kBRows + wv + kBWaves * k;
+      if (row >= nc * nseam) break;
+      const int mz = row / nseam, sidx = row - mz * nseam, my = 2 * (sidx + 1);
+      if (mz < 1 || mz > nc - 2 || my > nc - 2) continue;
+      for (int mx = lane; mx < nc; mx += 64) {
+        if (mx < 1 || mx > nc - 2) continue;
+        cpx<T>& d = c.b[((long long)mz * nc + my) * nc + mx];
+        const cpx<T> e = P.spill[((long long)mz * nty + sidx) * nc + mx];
+        d = mk(d.re + e.re, d.im + e.im);
+      }
+    }
   } else if (kind == BK_NORM) {
-    // the fixed-order second stage of the single-problem path
-    __shared__ double s0[kBThreads], s1[kBThreads];
+    // the fixed-order second stage of the single-problem path (a tree over
+    // 256 entries, the last 64 zero)
+    __shared__ double s0[256], s1[256];
     const int t = threadIdx.x;
     double a = 0, b = 0;
     for (int i = t; i < P.ftiles; i += kBThreads) {
@@ -216,8 +237,12 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
     }
     s0[t] = a;
     s1[t] = b;
+    if (t < 256 - kBThreads) {
+      s0[kBThreads + t] = 0.0;
+      s1[kBThreads + t] = 0.0;
+    }
     __syncthreads();
-    for (int w = kBThreads / 2; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
       if (t < w) {
         s0[t] += s0[t + w];
         s1[t] = fmax(s1[t], s1[t + w]);
@@ -233,7 +258,7 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
       if (D == 3) batch_fused3<T>(&P, A.cyc, tile, *f3lds);
     } else if (D == 2) {
       const int wv = threadIdx.x >> 6;
-      const int id = 4 * tile + wv;
+      const int id = kBWaves * tile + wv;
       if (id < P.ftiles) batch_fused2<T>(&P, A.cyc, id, Gz2[wv], Sz2[wv]);
     }
   }
@@ -242,8 +267,8 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
 template <class T>
 __global__ __launch_bounds__(kBThreads, 2) void k_batch_cycle(BatchArgs<T> A) {
   __shared__ int s_item, s_ok;
-  __shared__ cpx<T> Gz2[4][2][F2_GX];
-  __shared__ cpx<T> Sz2[4][2][F2_GX];
+  __shared__ cpx<T> Gz2[kBWaves][2][F2_GX];
+  __shared__ cpx<T> Sz2[kBWaves][2][F2_GX];
   __shared__ F3Lds<T, 2, 2, true> f3lds;
   // Thread 0 claims items and publishes completions; every step it takes is
   // followed by a workgroup barrier before any other thread depends on it, and
@@ -378,6 +403,7 @@ struct Batch : BatchBase {
     }
     P.w[0] = E.w[0];
     P.w[1] = E.w[1];
+    P.spill = E.spill;
     P.si2[0] = E.lv[E.L - 1].si;
     P.si2[1] = E.si_alt ? E.si_alt : E.lv[E.L - 1].si;
     P.parw = E.cur;
@@ -402,17 +428,20 @@ struct Batch : BatchBase {
     }
     if (E.dim == 3) {
       P.fgx = f3_xtiles(nc);
-      P.fgy = (nc + 1) / 2;
+      P.fgy = f3_ytiles(nc, 2);
       const int gz = (nc + kBZc3[zc3] - 1) / kBZc3[zc3];
       P.ftiles = P.fgx * P.fgy * gz;
       P.phase_kind[k] = BK_FUSED3;
       P.phase_items[k] = P.ftiles;
+      P.phase_level[k++] = E.L;
+      P.phase_kind[k] = BK_SEAM;
+      P.phase_items[k] = (nc * (P.fgy - 1) + kBRows - 1) / kBRows;
     } else {
       P.fgx = (nc + F2_TXC - 1) / F2_TXC;
       P.fgy = (nc + kBZc2[zc2] - 1) / kBZc2[zc2];
       P.ftiles = P.fgx * P.fgy;
       P.phase_kind[k] = BK_FUSED2;
-      P.phase_items[k] = (P.ftiles + 3) / 4;
+      P.phase_items[k] = (P.ftiles + kBWaves - 1) / kBWaves;
     }
     (void)nL;
     P.phase_level[k++] = E.L;

@@ -129,6 +129,7 @@ struct Engine {
   int cur = 0;
   cpx<T>* si_alt = nullptr;    // second si buffer of level L-1 (fused BPX sweep reads old, writes new)
   cpx<T>* tune_c = nullptr;    // coarse scratch for the autotuner
+  cpx<T>* spill = nullptr;     // seam rows of the 3D fused sweep's restriction
   cpx<T>*tA = nullptr, *tR = nullptr, *tRh = nullptr;
   double* partials = nullptr;  // 2 * max(kRedBlocks, fused blocks)
   double* red = nullptr;       // 2 doubles
@@ -249,6 +250,7 @@ struct Engine {
       }
     }
     if (fused && variant == MG_BPX) MG_TRY(alloc_c(&si_alt, lv[L - 1].N));
+    if (fused && dim == 3) MG_TRY(alloc_c(&spill, fused_spill_count(dim, lv[L].n)));
     int max_blocks = kRedBlocks;
     if (fused) {
       for (int t = 0; t < fused_tile_count(dim); ++t)
@@ -266,11 +268,11 @@ struct Engine {
 
   int tile = 0;
 
-  // Default tile: small tiles while the coarse grid is small (more blocks),
-  // otherwise the tallest tile with the short z chunk.
+  // Default tile: short z chunks while the grid is small (more blocks),
+  // otherwise 2 coarse rows by 21 coarse planes.
   int default_tile() const {
     if (dim == 2) return lv[L].n <= 250 ? 1 : 0;
-    return lv[L].n <= 82 ? 1 : 0;
+    return fused_tile_index(3, 2, 2, lv[L].n <= 82 ? 9 : 21);
   }
   void set_tile(int t) {
     tile = t;
@@ -388,6 +390,8 @@ struct Engine {
     if (fused) {
       FusedArgs<T> a = fused_args(w[1 - cur], c->b, c->sf, si_alt, wL.real(), wL.imag());
       MG_HIP(launch_fused<T>(dim, a, s));
+      MG_TRY(mark(false));
+      MG_HIP(launch_fused_seam<T>(dim, a, s));
       if (variant == MG_BPX) std::swap(c->si, si_alt);
       nparts = fused_blocks;
     } else {
@@ -402,8 +406,8 @@ struct Engine {
                               (hc && variant == MG_ADD) ? c->sf : nullptr, (hc && variant == MG_BPX) ? c->si : nullptr,
                               s));
       if (hc) MG_HIP(launch_restrict<T>(dim, c->n, galerkin ? tR : tRh, c->b, s));
+      MG_TRY(mark(false));
     }
-    MG_TRY(mark(false));
     cur = 1 - cur;
     const int ns = small_levels();
     if (!ns) MG_HIP(launch_finish_sum_max(partials, nparts, hist + 2 * k, s));
@@ -463,6 +467,7 @@ struct Engine {
     a.ws = to_c<T>(complex<double>(wL_re, wL_im) * complex<double>(f.op.invD.re, f.op.invD.im));
     a.partials = partials;
     a.variant = variant;
+    a.spill = spill;
     a.tile = tile;
     a.order = 0;
     return a;
@@ -486,8 +491,12 @@ struct Engine {
       set_tile(t);
       FusedArgs<T> a = fused_args(tA, c->pr, tune_c, c->pz, omega.real(), omega.imag());
       MG_HIP(launch_fused<T>(dim, a, s));  // warm-up
+      MG_HIP(launch_fused_seam<T>(dim, a, s));
       MG_HIP(hipEventRecord(e0, s));
-      for (int k = 0; k < reps; ++k) MG_HIP(launch_fused<T>(dim, a, s));
+      for (int k = 0; k < reps; ++k) {
+        MG_HIP(launch_fused<T>(dim, a, s));
+        MG_HIP(launch_fused_seam<T>(dim, a, s));
+      }
       MG_HIP(hipEventRecord(e1, s));
       MG_HIP(hipEventSynchronize(e1));
       float ms = 0;

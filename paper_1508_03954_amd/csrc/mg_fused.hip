@@ -1,4 +1,5 @@
 // Fused finest-level sweep: standalone kernels, tile table and launchers.
+#include <algorithm>
 #include <cstring>
 
 #include "mg_fused_ops.h"
@@ -29,7 +30,7 @@ __device__ inline void fused3_block_tile(int order, int gx, int gy, int gz, int&
 }
 
 template <class T, int TYC, int RPT, int ZC, int VAR>
-__global__ __launch_bounds__(64 * ((3 * TYC + 2) / RPT), (3 * TYC + 2) / RPT == 4 ? 3 : 1) void k_fused3(FusedArgs<T> a) {
+__global__ __launch_bounds__(64 * (3 * TYC / RPT), 3) void k_fused3(FusedArgs<T> a) {
   __shared__ F3Lds<T, TYC, RPT, VAR == 2> sm;
   int bx, by, bz;
   fused3_block_tile(a.order, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
@@ -51,10 +52,9 @@ __global__ __launch_bounds__(64) void k_fused2(FusedArgs<T> a) {
 // coarse planes per block); the context picks one per problem (default table or
 // autotuning on the device).
 struct TileShape3 { int tyc, rpt, zc, order; };
-constexpr TileShape3 kTiles3[] = {{6, 2, 9, 0},  {2, 2, 9, 0},  {4, 1, 9, 0}, {2, 1, 9, 0},
-                                  {6, 2, 27, 0}, {2, 2, 27, 0}, {4, 1, 27, 0},
-                                  {2, 2, 9, 1},  {4, 2, 9, 0},  {4, 2, 27, 0}, {2, 2, 6, 0},
-                                  {2, 2, 21, 0}, {4, 2, 28, 0}};
+constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0},  {2, 2, 14, 0}, {2, 2, 21, 0}, {2, 2, 27, 0},
+                                  {2, 2, 28, 0}, {4, 2, 14, 0}, {4, 2, 21, 0}, {4, 2, 28, 0},
+                                  {2, 1, 14, 0}, {2, 1, 21, 0}, {2, 2, 9, 1},  {2, 2, 21, 1}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -90,7 +90,7 @@ int fused_partials_blocks(int dim, int n, int tile) {
 
 template <class T, int TYC, int RPT, int ZC>
 static void launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s) {
-  constexpr int NT = 64 * ((3 * TYC + 2) / RPT);
+  constexpr int NT = F3<T, TYC, RPT, ZC, false>::NT;
   FusedArgs<T> a = a0;
   a.order = kTiles3[a0.tile].order;
   if (a.variant == 2) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2>), g, NT, 0, s, a);
@@ -109,22 +109,22 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
   if (a.nc != (a.n - 1) / 3 + 1 || a.n < 10) return hipErrorInvalidValue;
   if (a.tile < 0 || a.tile >= fused_tile_count(dim)) return hipErrorInvalidValue;
   if (a.variant == 2 && (a.sic == nullptr || a.sic_out == nullptr || a.sic == a.sic_out)) return hipErrorInvalidValue;
+  if (dim == 3 && a.spill == nullptr) return hipErrorInvalidValue;
   const dim3 g = fused_grid(dim, a.n, a.tile);
   if (dim == 3) {
     switch (a.tile) {
-      case 0: launch3<T, 6, 2, 9>(a, g, s); break;
-      case 1: launch3<T, 2, 2, 9>(a, g, s); break;
-      case 2: launch3<T, 4, 1, 9>(a, g, s); break;
-      case 3: launch3<T, 2, 1, 9>(a, g, s); break;
-      case 4: launch3<T, 6, 2, 27>(a, g, s); break;
-      case 5: launch3<T, 2, 2, 27>(a, g, s); break;
-      case 6: launch3<T, 4, 1, 27>(a, g, s); break;
-      case 7: launch3<T, 2, 2, 9>(a, g, s); break;
-      case 8: launch3<T, 4, 2, 9>(a, g, s); break;
-      case 9: launch3<T, 4, 2, 27>(a, g, s); break;
-      case 10: launch3<T, 2, 2, 6>(a, g, s); break;
-      case 11: launch3<T, 2, 2, 21>(a, g, s); break;
-      default: launch3<T, 4, 2, 28>(a, g, s); break;
+      case 0: launch3<T, 2, 2, 9>(a, g, s); break;
+      case 1: launch3<T, 2, 2, 14>(a, g, s); break;
+      case 2: launch3<T, 2, 2, 21>(a, g, s); break;
+      case 3: launch3<T, 2, 2, 27>(a, g, s); break;
+      case 4: launch3<T, 2, 2, 28>(a, g, s); break;
+      case 5: launch3<T, 4, 2, 14>(a, g, s); break;
+      case 6: launch3<T, 4, 2, 21>(a, g, s); break;
+      case 7: launch3<T, 4, 2, 28>(a, g, s); break;
+      case 8: launch3<T, 2, 1, 14>(a, g, s); break;
+      case 9: launch3<T, 2, 1, 21>(a, g, s); break;
+      case 10: launch3<T, 2, 2, 9>(a, g, s); break;
+      default: launch3<T, 2, 2, 21>(a, g, s); break;
     }
   } else {
     switch (a.tile) {
@@ -137,10 +137,52 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Seam rows of the 3D restriction: rho_c at coarse row (s + 1) TYC gains the
+// share of fine rows 3 (s + 1) TYC - 2 and - 1, restricted by y tile s (see
+// f3_ytiles); one addition per vertex, so the result does not depend on the
+// order of the tiles.
+template <class T>
+__global__ __launch_bounds__(256) void k_seam3(cpx<T>* __restrict__ rhoc, const cpx<T>* __restrict__ spill, int nc,
+                                               int tyc) {
+  const int nty = f3_ytiles(nc, tyc), nseam = nty - 1;
+  const long long total = (long long)nc * nseam * nc;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
+    const int mx = (int)(i % nc);
+    const long long t = i / nc;
+    const int sidx = (int)(t % nseam), mz = (int)(t / nseam);
+    const int my = (sidx + 1) * tyc;
+    if (mx < 1 || mx > nc - 2 || mz < 1 || mz > nc - 2 || my > nc - 2) continue;
+    cpx<T>& d = rhoc[((long long)mz * nc + my) * nc + mx];
+    const cpx<T> e = spill[((long long)mz * nty + sidx) * nc + mx];
+    d = mk(d.re + e.re, d.im + e.im);
+  }
+}
+
+template <class T>
+hipError_t launch_fused_seam(int dim, const FusedArgs<T>& a, hipStream_t s) {
+  if (dim != 3) return hipSuccess;
+  if (a.tile < 0 || a.tile >= kNumTiles3 || a.spill == nullptr || a.rhoc == nullptr) return hipErrorInvalidValue;
+  const int tyc = kTiles3[a.tile].tyc, nseam = f3_ytiles(a.nc, tyc) - 1;
+  if (nseam < 1) return hipSuccess;
+  const long long total = (long long)a.nc * nseam * a.nc;
+  const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_seam3<T>, dim3(blocks), dim3(256), 0, s, a.rhoc, a.spill, a.nc, tyc);
+  return hipGetLastError();
+}
+
+size_t fused_spill_count(int dim, int n) {
+  if (dim != 3) return 0;
+  const int nc = (n - 1) / 3 + 1;
+  size_t m = 0;
+  for (int t = 0; t < kNumTiles3; ++t)
+    m = std::max(m, (size_t)nc * (size_t)f3_ytiles(nc, kTiles3[t].tyc) * (size_t)nc);
+  return m;
+}
+
 // y = H x or r = b - H x (constant phi, 3D) with the sweep's march: 2 x 2
 // coarse-row tiles, z extent 21, no coarse levels.
 template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_stencil3(FusedArgs<T> a) {
+__global__ __launch_bounds__(192, 3) void k_stencil3(FusedArgs<T> a) {
   __shared__ F3Lds<T, 2, 2, false, false> sm;
   double* part = a.partials ? a.partials + 2 * (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) : nullptr;
   fused3_tile<T, 2, 2, 21, 1, MODE>(a, blockIdx.x, blockIdx.y, blockIdx.z, part, sm);
@@ -173,8 +215,10 @@ hipError_t launch_stencil3(int apply, int n, const cpx<T>* coef, const cpx<T>* b
   a.partials = partials;
   a.variant = 1;
   const dim3 g = stencil3_grid(n);
-  if (apply) hipLaunchKernelGGL((k_stencil3<T, kApply>), g, 256, 0, s, a);
-  else hipLaunchKernelGGL((k_stencil3<T, kResid>), g, 256, 0, s, a);
+  constexpr int NT = F3<T, 2, 2, 21, false>::NT;
+  static_assert(NT == 192, "k_stencil3 launch bounds");
+  if (apply) hipLaunchKernelGGL((k_stencil3<T, kApply>), g, NT, 0, s, a);
+  else hipLaunchKernelGGL((k_stencil3<T, kResid>), g, NT, 0, s, a);
   if (nparts) *nparts = blocks;
   return hipGetLastError();
 }
@@ -186,5 +230,7 @@ template hipError_t launch_stencil3<float>(int, int, const cpx<float>*, const cp
 
 template hipError_t launch_fused<double>(int, const FusedArgs<double>&, hipStream_t);
 template hipError_t launch_fused<float>(int, const FusedArgs<float>&, hipStream_t);
+template hipError_t launch_fused_seam<double>(int, const FusedArgs<double>&, hipStream_t);
+template hipError_t launch_fused_seam<float>(int, const FusedArgs<float>&, hipStream_t);
 
 }  // namespace mg

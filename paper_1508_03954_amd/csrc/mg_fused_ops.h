@@ -20,16 +20,19 @@
 // Work decomposition (3D).  A block owns a box of coarse vertices: 20 x TYC in
 // the plane and ZC coarse planes.  Its fine vertices (3m .. 3m+2 per axis) are
 // written by it alone.  R at a coarse vertex m needs r on fine offsets -2..2
-// around 3m, so r is computed on the owned fine box extended by two vertices
-// towards lower x and y, and u on one more vertex on each side: 64 columns,
-// exactly one wavefront, lane l at x = x0 - 3 + l.  x-neighbours are exchanged
-// with DPP wave shifts (no LDS); each thread keeps RPT consecutive rows (and
-// the two rows around them) in registers; the block marches through z one fine
-// plane per step.  The 27-point stencil row at plane p splits into an in-plane
-// part M_p and a neighbour-plane part N_p, so H u at plane p-1 is
-// M_(p-1) + N_(p-2) + N_p, carried in registers.  The next plane's w and b are
-// loaded while the current plane is processed.  R: x-part by DPP shifts, y-part
-// through LDS, z-part in a two-slot ring of coarse planes; one barrier a step.
+// around 3m.  Along x and z, r is computed on the owned fine box extended by
+// two vertices towards lower x and z, and u on one more vertex on each side:
+// 64 columns, exactly one wavefront, lane l at x = x0 - 3 + l.  Along y, r is
+// computed on the owned rows only (u on one more row each side); the share of
+// the two rows above the tile in R at its first coarse row is restricted by
+// the tile above and handed over through a seam array.  x-neighbours are
+// exchanged with DPP wave shifts (no LDS); each thread keeps RPT consecutive
+// rows in registers; the block marches through z one fine plane per step.
+// The 27-point stencil row at plane p splits into an in-plane part M_p and a
+// neighbour-plane part N_p, so H u at plane p-1 is M_(p-1) + N_(p-2) + N_p,
+// carried in registers.  The next plane's w and b are loaded while the
+// current plane is processed.  R: x and y parts through LDS, z part in a
+// two-plane register ring; one barrier a step.
 #pragma once
 #include <type_traits>
 
@@ -155,18 +158,20 @@ __host__ __device__ inline void f3_xtile(int nc, int bx, int& lo, int& hi, int& 
 template <class T, int TYC, int RPT, int ZC, bool BPX>
 struct F3 {
   static constexpr int TXC = F3_TXC, TX = 3 * TXC, TY = 3 * TYC;
-  static constexpr int CY = TY + 2;            // computed rows y0-2 .. y0+TY-1
-  static constexpr int W = CY / RPT;           // waves per block
+  static constexpr int W = TY / RPT;           // waves per block: wave k computes rows y0 + k RPT ..
   static constexpr int NT = 64 * W;
-  static constexpr int IR = RPT + 2;           // rows of u a thread needs
-  static constexpr int GX = TXC + 2, GY = TYC + 2, NG = GX * GY;
-  static_assert(CY % RPT == 0, "rows per thread must divide the computed rows");
+  static constexpr int GX = TXC + 2, GY = TYC + 2;
   static constexpr int TXR = TXC + 1;          // owned coarse columns of an edge tile
-  static_assert(NG <= NT && TXC * TYC <= NT, "staging needs one thread per coarse point");
+  static_assert(TY % RPT == 0, "rows per thread must divide the owned rows");
+  static_assert(W >= 2, "the first and the last wave form one halo row each");
+  static_assert(RPT <= 4, "the x part of R stages a wave's rows in its UH slot");
+  static_assert(GX <= 32 && GY <= 2 * W, "coarse staging: two coarse rows per wave");
 };
 
 // LDS of one 3D tile, two slots of everything (steps alternate):
-//   RX  x-restricted residual of the computed rows of one plane,
+//   RX  x-restricted residual of the owned rows of one plane, at rows 2 ..
+//       TY+1 between zero rows (two above, three below), so that the y part
+//       of R reads five rows at fixed offsets for every coarse row of the tile,
 //   Gz  z-interpolated coarse correction of one plane (BPX: sc - si),
 //   Sz  (BPX) sc of one coarse plane, used on c-points,
 //   UH  u and its in-row neighbour sum h of each wave's first and last row,
@@ -177,7 +182,7 @@ struct F3 {
 template <class T, int TYC, int RPT, bool BPX, bool SWEEP = true>
 struct F3Lds {
   using G = F3<T, TYC, RPT, 1, BPX>;
-  cpx<T> RX[SWEEP ? 2 : 1][SWEEP ? G::CY : 1][SWEEP ? G::TXR : 1];
+  cpx<T> RX[SWEEP ? 2 : 1][SWEEP ? G::TY + 5 : 1][SWEEP ? G::TXR : 1];
   cpx<T> Gz[SWEEP ? 2 : 1][SWEEP ? G::GY : 1][SWEEP ? G::GX : 1];
   cpx<T> Sz[BPX && SWEEP ? 2 : 1][BPX && SWEEP ? G::GY : 1][BPX && SWEEP ? G::GX : 1];
   cpx<T> UH[2][G::W][RPT == 1 ? 1 : 2][2][64];
@@ -192,8 +197,15 @@ struct F3Lds {
 constexpr unsigned kOOB = 0x80000000u;
 constexpr int kRawBufferWord3 = 0x00020000;   // raw (untyped) buffer, 32-bit data format
 
+// Every operand is wave-uniform; readfirstlane keeps the descriptor in scalar
+// registers even where the compiler has parked a value in a vector register
+// (a descriptor in vector registers would need a loop over its distinct values).
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRawBufferWord3);
+  const unsigned long long b = reinterpret_cast<unsigned long long>(base);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  void* p = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), kRawBufferWord3);
 }
 __device__ inline cpx<double> bload(cpx<double>*, __amdgpu_buffer_rsrc_t r, unsigned off) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
@@ -218,6 +230,14 @@ __device__ inline void bstore(cpx<float> c, __amdgpu_buffer_rsrc_t r, unsigned o
   __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
 }
 
+// Seam array of the 3D sweep's restriction.  A tile computes r on its own
+// rows only, so R at its first coarse row 3 my0 misses fine rows 3 my0 - 2 and
+// 3 my0 - 1, which belong to the tile above (by - 1).  That tile restricts
+// them to coarse row my0 (its "seam row") and stores the result in the seam
+// array, plane kz, row by - 1; a second pass (k_seam3) adds it to rho_c.
+// Layout: [coarse plane][y tile][coarse column], nty = ceil(nc / TYC) rows a plane.
+__host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1) / tyc; }
+
 // One tile (bx, by, bz) of the 3D sweep, executed by a whole block of
 // F3<...>::NT threads with LDS `sm`; VAR is the variant (0 add, 1 hb, 2 BPX);
 // `part` receives the tile's (sum |r|^2, max |r|) or is null.
@@ -232,8 +252,11 @@ __device__ inline void bstore(cpx<float> c, __amdgpu_buffer_rsrc_t r, unsigned o
 // the previous step left in LDS.  Every load is issued where its register is
 // free, so no prefetch is live through the stencil beyond one plane of w and
 // b: that keeps the register count (and so the occupancy) down.
-// Coarse staging: wave k stages coarse row k of the tile; the y and z parts of
-// R: every wave takes an equal share of the tile's coarse points.
+// Rows: the block computes r on its TY owned rows only, and u on one more row
+// on each side (formed by the first and the last wave).  Coarse staging: wave
+// k stages coarse rows 2k and 2k+1 (one per half wave).  The y and z parts of
+// R: every wave takes an equal share of the tile's coarse points, i.e. of its
+// owned coarse rows and of the seam row below them.
 // MODE kSweep: the fused sweep.  kResid / kApply: the same march without the
 // coarse levels, storing r = b - H w (with its partial norms) or y = H w.
 constexpr int kSweep = 0, kResid = 1, kApply = 2;
@@ -245,8 +268,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   using G = F3<T, TYC, RPT, ZC, BPX>;
   constexpr int TXR = G::TXR, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
   constexpr unsigned CB = sizeof(cpx<T>);
-  constexpr int NPT = TXR * TYC, PPW = (NPT + W - 1) / W;   // coarse points of R per wave
-  static_assert(GY <= W, "one wave per staged coarse row");
+  // coarse points of R: the TYC owned coarse rows and the seam row
+  constexpr int NPT = TXR * (TYC + 1), PPW = (NPT + W - 1) / W;
   static_assert(PPW <= 64, "coarse points of R per wave");
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index and everything derived from rows is wavefront-uniform (scalar)
@@ -254,6 +277,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const int n = a.n, nc = a.nc;
   const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
   const unsigned pbytes = (unsigned)(n2 * CB), cpbytes = (unsigned)(nc2 * CB);
+  const int nty = f3_ytiles(nc, TYC);
+  const unsigned spbytes = (unsigned)((long long)nty * nc * CB);
   int cx_lo, cx_hi, xs;
   f3_xtile(nc, bx, cx_lo, cx_hi, xs);
   const int my0 = by * TYC, mz0 = bz * ZC;
@@ -263,7 +288,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const bool xin = x >= 1 && x <= n - 2;
   const bool xcomp = lane >= 1 && lane <= 62;
   const bool xown = x >= 3 * cx_lo && x <= min(3 * cx_hi - 1, n - 1);
-  const int ybase = y0 - 2 + wv * RPT;            // first computed row of this wave
+  const int ybase = y0 + wv * RPT;                // first row of this wave
   const int yown_hi = min(y0 + TY - 1, n - 1);
   const int zown_lo = 3 * mz0, zown_hi = min(3 * mz1 - 1, n - 1);
   const cpx<T> c0 = a.coef[0], c1 = a.coef[1], c2 = a.coef[2], c3 = a.coef[3];
@@ -284,34 +309,38 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     const int y = ybase + j;
     const unsigned off = (unsigned)((y * n + x) * (int)CB);
     vld[j] = (row_ok(y) && xin) ? off : kOOB;
-    const bool yown = y >= y0 && y <= yown_hi && y >= 0;
-    vst[j] = (yown && xown) ? off : kOOB;
+    vst[j] = (y <= yown_hi && xown) ? off : kOOB;
     // c-point injections: coarse offset inside a coarse plane
-    vcp[j] = (yown && xown && ccol && y % 3 == 0 && x >= 0)
+    vcp[j] = (y <= yown_hi && xown && ccol && y % 3 == 0 && x >= 0)
                  ? (unsigned)(((y / 3) * nc + x / 3) * (int)CB) : kOOB;
   }
   const bool top = wv == 0, bot = wv == W - 1;
-  const int yhalo = top ? ybase - 1 : ybase + RPT;   // extra row formed by the edge waves
+  const int yhalo = top ? y0 - 1 : y0 + TY;       // extra row formed by the edge waves
   const unsigned vldh = ((top || bot) && row_ok(yhalo) && xin) ? (unsigned)((yhalo * n + x) * (int)CB) : kOOB;
-  // coarse staging: wave wv < GY stages coarse row my0 - 1 + wv, lanes 0 .. GX-1
-  const int smx = smx0 + lane, smy = my0 - 1 + wv;
-  const bool stager = wv < GY && lane < GX;
+  // coarse staging: half wave h of wave wv stages coarse row my0 - 1 + 2 wv + h
+  const int sr = 2 * wv + (lane >> 5), sx = lane & 31;
+  const int smx = smx0 + sx, smy = my0 - 1 + sr;
+  const bool stager = sr < GY && sx < GX;
   const unsigned vsg = (stager && smx >= 0 && smx < nc && smy >= 0 && smy < nc)
                            ? (unsigned)((smy * nc + smx) * (int)CB) : kOOB;
-  // y and z parts of R: coarse point pi of the tile
+  // y and z parts of R: coarse point pi of the tile (rows ly < TYC owned, ly == TYC the seam row)
   const int pi = wv * PPW + lane;
   const bool rpt = lane < PPW && pi < NPT;
   const int lx = rpt ? pi % TXR : 0, ly = rpt ? pi / TXR : 0;
   const int rmx = cx_lo + lx, rmy = my0 + ly;
   const bool rcin = rmx >= 1 && rmx <= nc - 2 && rmy >= 1 && rmy <= nc - 2;
-  const unsigned vrho = (rpt && rmx < cx_hi && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
+  const bool rcol = rpt && rmx < cx_hi;
+  const unsigned vrho = (rcol && ly < TYC && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
+  const unsigned vspl = (rcol && ly == TYC && rmy <= nc - 2) ? (unsigned)((by * nc + rmx) * (int)CB) : kOOB;
 
-  auto prsrc = [&](const cpx<T>* base, int p, bool ok) {
-    return plane_rsrc(base + (long long)min(max(p, 0), n - 1) * n2, ok ? pbytes : 0u);
+  // Plane descriptors.  A plane that is not accessed gets size zero, so its
+  // base address is never used (it may lie outside the array).
+  const long long pstride = n2 * CB, cstride = nc2 * CB, sstride = (long long)nty * nc * CB;
+  auto at = [](const void* base, long long ofs) {
+    return reinterpret_cast<const void*>(reinterpret_cast<uintptr_t>(base) + (uintptr_t)ofs);
   };
-  auto crsrc = [&](const cpx<T>* base, int k, bool ok) {
-    return plane_rsrc(base + (long long)min(max(k, 0), nc - 1) * nc2, ok ? cpbytes : 0u);
-  };
+  auto frs = [&](const cpx<T>* base, long long ofs, bool ok) { return plane_rsrc(at(base, ofs), ok ? pbytes : 0u); };
+  auto crs = [&](const cpx<T>* base, long long ofs, bool ok) { return plane_rsrc(at(base, ofs), ok ? cpbytes : 0u); };
   cpx<T>* tagT = nullptr;
 
   cpx<T> Wr[RPT], Wh, Br[RPT];
@@ -320,44 +349,47 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   cpx<T> acc0 = f_zero<T>(), acc1 = f_zero<T>();
   double nsum = 0.0, nmax = 0.0;
 
+  // The march runs over fine planes p = p0 .. plast with p0 = 3 (mz0 - 1), so
+  // p mod 3 is known from the step's position in a group of six (which also
+  // fixes the LDS slot); kb = coarse plane of the group's first fine plane.
   const int p0 = 3 * mz0 - 3, plast = 3 * mz1;
   // planes past the tile's last use are not fetched (zero-size descriptors)
-  auto load_w = [&](int p, cpx<T>* dst, cpx<T>& dh) {
-    const auto r = prsrc(a.w, p, plane_ok(p) && p <= plast);
+  auto load_w = [&](int p, long long ofs, cpx<T>* dst, cpx<T>& dh) {
+    const auto r = frs(a.w, ofs, plane_ok(p) && p <= plast);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
     dh = bload(tagT, r, vldh);
   };
-  auto load_b = [&](int p, cpx<T>* dst) {
-    const auto r = prsrc(a.b, p, plane_ok(p) && p < plast);
+  // the first residual plane used is p0 + 1 (the lowest fine plane of R at coarse plane mz0)
+  auto load_b = [&](int p, long long ofs, cpx<T>* dst) {
+    const auto r = frs(a.b, ofs, plane_ok(p) && p > p0 && p < plast);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
   };
-  // coarse values of fine plane p: planes kz and kz+1 (the second only off
-  // coarse planes); coarse boundary planes hold zeros
-  auto load_g = [&](int p) {
-    const int kz = floor_div3(p), tz = p - 3 * kz;
+  // coarse values of fine plane p = 3 kz + TZ: planes kz and kz+1 (the second
+  // only off coarse planes); coarse boundary planes hold zeros
+  auto load_g = [&](auto TZ_, int p, long long kofs) {
+    constexpr int TZ = decltype(TZ_)::value;
     const bool ok = plane_ok(p) && p <= plast;
-    const auto r0 = crsrc(a.scc, kz, ok);
-    const auto r1 = crsrc(a.scc, kz + 1, ok && tz != 0);
-    gsc0 = bload(tagT, r0, vsg);
-    gsc1 = bload(tagT, r1, vsg);
+    gsc0 = bload(tagT, crs(a.scc, kofs, ok), vsg);
+    gsc1 = bload(tagT, crs(a.scc, kofs + cstride, ok && TZ != 0), vsg);
     if (BPX) {
-      gsi0 = bload(tagT, crsrc(a.sic, kz, ok), vsg);
-      gsi1 = bload(tagT, crsrc(a.sic, kz + 1, ok && tz != 0), vsg);
+      gsi0 = bload(tagT, crs(a.sic, kofs, ok), vsg);
+      gsi1 = bload(tagT, crs(a.sic, kofs + cstride, ok && TZ != 0), vsg);
     }
   };
-  auto store_g = [&](int p, int slot) {
+  auto store_g = [&](auto TZ_, int slot) {
+    constexpr int TZ = decltype(TZ_)::value;
     if (stager) {
-      const int kz = floor_div3(p), tz = p - 3 * kz;
       const cpx<T> g0 = BPX ? f_sub(gsc0, gsi0) : gsc0;
       const cpx<T> g1 = BPX ? f_sub(gsc1, gsi1) : gsc1;
-      sm.Gz[slot][wv][lane] = f_sel(tz == 0, g0, f_add(f_scale(w_lo<T>(tz), g0), f_scale(w_hi<T>(tz), g1)));
-      if (BPX) sm.Sz[slot][wv][lane] = gsc0;   // used on c-points only (tz == 0)
+      sm.Gz[slot][sr][sx] = TZ == 0 ? g0 : f_add(f_scale(w_lo<T>(TZ), g0), f_scale(w_hi<T>(TZ), g1));
+      if (BPX) sm.Sz[slot][sr][sx] = gsc0;   // used on c-points only (TZ == 0)
     }
   };
-  // u = w + P g on plane p at row y (zero off the interior)
-  auto form_u = [&](int p, int slot, int y, cpx<T> w) {
+  // u = w + P g on plane p (p mod 3 = PT) at row y (zero off the interior)
+  auto form_u = [&](auto PT_, int p, int slot, int y, cpx<T> w) {
+    constexpr int PT = decltype(PT_)::value;
     if (MODE != kSweep) return w;   // loads already vanish off the interior
     const int my = floor_div3(y), qy = y - 3 * my, gy = min(max(my - my0 + 1, 0), GY - 1);
     cpx<T> g = f_add(f_scale(wx0, sm.Gz[slot][gy][gxl]), f_scale(wx1, sm.Gz[slot][gy][gxl1]));
@@ -365,7 +397,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const int gy1 = min(gy + 1, GY - 1);
       const cpx<T> g1 = f_add(f_scale(wx0, sm.Gz[slot][gy1][gxl]), f_scale(wx1, sm.Gz[slot][gy1][gxl1]));
       g = f_add(f_scale(w_lo<T>(qy), g), f_scale(w_hi<T>(qy), g1));
-    } else if (BPX && p % 3 == 0) {
+    } else if (BPX && PT == 0) {
       // BPX keeps si on c-points: there the correction is sc_c itself
       g = f_sel(ccol, sm.Sz[slot][gy][gxl], g);
     }
@@ -373,55 +405,69 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   };
   auto hsum = [&](cpx<T> u) { return f_add(dpp_c<kDppLeft>(u), dpp_c<kDppRight>(u)); };
 
-  // y and z parts of R for plane qq, whose x part is in RX[slot]
-  auto rest_yz = [&](int qq, int slot) {
+  // y and z parts of R for fine plane 3 k0 + TQ, whose x part is in RX[slot]
+  // (fine rows outside the tile read the zero rows: the seam row takes the
+  // tile's last two)
+  auto rest_yz = [&](auto TQ_, int k0, long long kofs, int slot) {
+    constexpr int TQ = decltype(TQ_)::value;
     cpx<T> v = f_zero<T>();
 #pragma unroll
     for (int oy = -2; oy <= 2; ++oy) v = f_add(v, f_scale(w_r<T>(oy), sm.RX[slot][3 * ly + 2 + oy][lx]));
-    const int k0 = floor_div3(qq), t = qq - 3 * k0;
-    if (t == 0) {
+    if (TQ == 0) {
       acc0 = f_add(acc0, v);
-    } else if (t == 1) {
+    } else if (TQ == 1) {
       acc0 = f_add(acc0, f_scale(T(2.0 / 3.0), v));
       acc1 = f_add(acc1, f_scale(T(1.0 / 3.0), v));
     } else {
       acc0 = f_add(acc0, f_scale(T(1.0 / 3.0), v));
       acc1 = f_add(acc1, f_scale(T(2.0 / 3.0), v));
-    }
-    // coarse plane k0 is complete after its last fine plane (t == 2)
-    const bool done = t == 2 && k0 >= mz0 && k0 < mz1;
-    bstore(f_sel(rcin && k0 >= 1 && k0 <= nc - 2, acc0, f_zero<T>()), crsrc(a.rhoc, k0, done), vrho);
-    if (t == 2) {
+      // coarse plane k0 is complete after its last fine plane
+      const bool done = k0 >= mz0 && k0 < mz1;
+      const cpx<T> val = f_sel(rcin && k0 >= 1 && k0 <= nc - 2, acc0, f_zero<T>());
+      bstore(val, crs(a.rhoc, kofs, done), vrho);
+      bstore(val, plane_rsrc(at(a.spill, (long long)k0 * sstride), done ? spbytes : 0u), vspl);
       acc0 = acc1;
       acc1 = f_zero<T>();
     }
   };
 
   if (MODE == kSweep) {
-    load_g(p0);
-    store_g(p0, 0);
-    load_g(p0 + 1);
+    const long long k0ofs = (long long)(mz0 - 1) * cstride;
+    load_g(std::integral_constant<int, 0>(), p0, k0ofs);
+    store_g(std::integral_constant<int, 0>(), 0);
+    load_g(std::integral_constant<int, 1>(), p0 + 1, k0ofs);
   }
-  load_w(p0, Wr, Wh);
-  if (MODE != kApply) load_b(p0 - 1, Br);
+  load_w(p0, (long long)p0 * pstride, Wr, Wh);
+  if (MODE != kApply) load_b(p0 - 1, (long long)(p0 - 1) * pstride, Br);
 #pragma unroll
   for (int j = 0; j < RPT; ++j) { A[j] = f_zero<T>(); Np[j] = f_zero<T>(); Cp[j] = f_zero<T>(); }
+  if (MODE == kSweep) {
+    // the zero rows of RX (both slots); nothing writes them later
+    constexpr int NZ = 2 * 5 * TXR;
+    for (int i = tid; i < NZ; i += G::NT) {
+      const int sl = i / (5 * TXR), k = (i / TXR) % 5, c = i % TXR;
+      sm.RX[sl][k < 2 ? k : TY + k][c] = f_zero<T>();
+    }
+  }
   __syncthreads();
 
-  // LDS slot S = (p - p0) & 1; at the start of step p, Wr holds w of plane p,
-  // Br b of plane p-1, and the coarse registers the values of plane p+1
-  auto step = [&](auto S_, int p) {
-    constexpr int S = decltype(S_)::value;
+  // Step K of a group (p = p0 + 6i + K, kb = mz0 - 1 + 2i): LDS slot S = K & 1;
+  // at its start Wr holds w of plane p, Br b of plane p-1, and the coarse
+  // registers the values of plane p+1
+  auto step = [&](auto K_, int p, int kb) {
+    constexpr int K = decltype(K_)::value;
+    constexpr int S = K & 1, PT = K % 3;
     const int q = p - 1;
+    const long long pofs = (long long)p * pstride, kofs = (long long)kb * cstride;
     cpx<T> u[RPT], h[RPT], uh = f_zero<T>(), hh = f_zero<T>();
     // (1) u and h on plane p
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      u[j] = form_u(p, S, ybase + j, Wr[j]);
+      u[j] = form_u(std::integral_constant<int, PT>(), p, S, ybase + j, Wr[j]);
       h[j] = hsum(u[j]);
     }
     if (top || bot) {
-      uh = form_u(p, S, yhalo, Wh);
+      uh = form_u(std::integral_constant<int, PT>(), p, S, yhalo, Wh);
       hh = hsum(uh);
     }
     constexpr int LE = RPT == 1 ? 0 : 1;   // slot of the last row (the first row when RPT == 1)
@@ -432,8 +478,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       sm.UH[S][wv][LE][1][lane] = h[RPT - 1];
     }
     // (2) refill w with plane p+1; stage plane p+1's correction
-    load_w(p + 1, Wr, Wh);
-    if (MODE == kSweep) store_g(p + 1, 1 - S);
+    load_w(p + 1, pofs + pstride, Wr, Wh);
+    if (MODE == kSweep) store_g(std::integral_constant<int, (K + 1) % 3>(), 1 - S);
     __syncthreads();
     // (3) neighbour rows across the wave edges
     cpx<T> ua = uh, ha = hh, ub = uh, hb = hh;
@@ -445,11 +491,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       ub = sm.UH[S][wv + 1][0][0][lane];
       hb = sm.UH[S][wv + 1][0][1][lane];
     }
-    // (4) stencil rows of plane p close the residual of plane q
+    // (4) stencil rows of plane p close the residual of plane q (a c-plane when K % 3 == 1)
     const bool q_own = q >= zown_lo && q <= zown_hi;
-    const bool q_c = q >= 0 && (q % 3) == 0;
-    const auto wo = prsrc(a.wout, q, q_own);
-    const auto co = crsrc(VAR == 0 ? a.sfc : a.sic_out, q / 3, q_own && q_c && VAR != 1);
+    constexpr bool q_c = K % 3 == 1;
+    const auto wo = frs(a.wout, pofs - pstride, q_own);
+    const auto co = crs(VAR == 0 ? a.sfc : a.sic_out, kofs + (K / 3) * cstride, q_own && q_c && VAR != 1);
     cpx<T> r[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -479,11 +525,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const cpx<T> rv = f_sel(in, f_sub(Br[j], f_add(A[j], N)), f_zero<T>());
       if (MODE == kSweep) {
         const cpx<T> s = f_mul(ws, rv);
-        const bool cp = q_c && ccol && x >= 0 && (y % 3) == 0;
+        const bool cp = q_c && q >= 0 && ccol && x >= 0 && (y % 3) == 0;
         const cpx<T> scm = f_sel(VAR != 0 && cp, f_zero<T>(), s);
         // off the interior u, r and s vanish, so the stored value is zero there
         bstore(f_add(Cp[j], scm), wo, vst[j]);
-        if (VAR != 1) bstore(VAR == 0 ? scm : s, co, vcp[j]);
+        if (VAR != 1 && q_c) bstore(VAR == 0 ? scm : s, co, vcp[j]);
       } else {
         bstore(rv, wo, vst[j]);
       }
@@ -499,9 +545,9 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
     if (MODE == kApply) return;
     // refill b with plane p, the coarse registers with plane p+2
-    load_b(p, Br);
+    load_b(p, pofs, Br);
     if (MODE != kSweep) return;
-    load_g(p + 2);
+    load_g(std::integral_constant<int, (K + 2) % 3>(), p + 2, kofs + ((K + 2) / 3) * cstride);
     // (5) x part of R at the owned coarse columns (lanes 2 .. 61; the boundary
     // columns need none), which read their neighbours' r from this wave's slot
     // of the other UH buffer (free during this half step: it is refilled by
@@ -515,28 +561,36 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
         const cpx<T>* row = rr + 64 * j + lane;
         const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
         const cpx<T> rx = f_add(r[j], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
-        sm.RX[1 - S][wv * RPT + j][mxl - cx_lo] = rx;
+        sm.RX[1 - S][2 + wv * RPT + j][mxl - cx_lo] = rx;
       }
     }
-    // (6) y and z parts of R for plane q-1 (its x part is in slot S)
-    rest_yz(q - 1, S);
+    // (6) y and z parts of R for plane q-1 = p-2 (its x part is in slot S)
+    constexpr int KR = K < 2 ? -1 : (K < 5 ? 0 : 1);   // floor((K - 2) / 3)
+    rest_yz(std::integral_constant<int, (K + 1) % 3>(), kb + KR, kofs + KR * cstride, S);
   };
-  // two steps per iteration so that slots and register roles are constants
-  int p = p0;
-  for (; p + 1 <= plast; p += 2) {
-    step(std::integral_constant<int, 0>(), p);
-    step(std::integral_constant<int, 1>(), p + 1);
+  // six steps per iteration, so that plane phases, slots and register roles
+  // are constants; the slot left holding the x part of R of plane plast-1
+  int p = p0, kb = mz0 - 1, last = 0;
+  for (;;) {
+    step(std::integral_constant<int, 0>(), p, kb);
+    if (p + 1 > plast) { last = 1; break; }
+    step(std::integral_constant<int, 1>(), p + 1, kb);
+    if (p + 2 > plast) { last = 0; break; }
+    step(std::integral_constant<int, 2>(), p + 2, kb);
+    if (p + 3 > plast) { last = 1; break; }
+    step(std::integral_constant<int, 3>(), p + 3, kb);
+    if (p + 4 > plast) { last = 0; break; }
+    step(std::integral_constant<int, 4>(), p + 4, kb);
+    if (p + 5 > plast) { last = 1; break; }
+    step(std::integral_constant<int, 5>(), p + 5, kb);
+    p += 6;
+    kb += 2;
+    if (p > plast) { last = 0; break; }
   }
-  // the remaining step, if any, then R of the last plane
-  if (p <= plast) {
-    step(std::integral_constant<int, 0>(), p);
-    if (MODE == kSweep) {
-      __syncthreads();
-      rest_yz(plast - 1, 1);
-    }
-  } else if (MODE == kSweep) {
+  // R of the last plane plast - 1 = 3 (mz1 - 1) + 2
+  if (MODE == kSweep) {
     __syncthreads();
-    rest_yz(plast - 1, 0);
+    rest_yz(std::integral_constant<int, 2>(), mz1 - 1, (long long)(mz1 - 1) * cstride, last);
   }
   if (part) block_reduce_store(nsum, sqrt(nmax), part, G::NT);
 }

@@ -190,6 +190,7 @@ struct FusedArgs {
   cpx<T>* rhoc;         // coarse b slot <- R r
   cpx<T>* sfc;          // coarse sf <- I sc (ADD) or nullptr
   cpx<T>* sic_out;      // coarse si <- I s (BPX) or nullptr
+  cpx<T>* spill;        // 3D: seam rows of R (fused_spill_count(3, n) entries), added by launch_fused_seam
   cpx<T> coef[4];
   cpx<T> ws;            // omega * (1 / D)
   double* partials;     // per-block (sum |r|^2, max |r|) or nullptr
@@ -199,6 +200,11 @@ struct FusedArgs {
 };
 template <class T>
 hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);
+// Second pass of a 3D sweep: rho_c += the seam rows of R (no-op in 2D).
+template <class T>
+hipError_t launch_fused_seam(int dim, const FusedArgs<T>& a, hipStream_t s);
+// Entries of the seam array a sweep of any tile variant needs (0 in 2D).
+size_t fused_spill_count(int dim, int n);
 int fused_tile_count(int dim);
 // 3D constant-phi operator with the sweep's march: y = H x (apply != 0) or
 // r = b - H x with per-block partial norms (when partials != nullptr; their
