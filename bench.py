@@ -74,7 +74,15 @@ def traffic_from_profiles(tile):
     return rec.get("tiles", {}).get(str(tile), {}).get("bytes_per_launch")
 
 
-def time_cycles(s, steps, warmup, torch):
+def time_cycles(s, steps, warmup, torch, ramp_s=0.3):
+    """W untimed warmup cycles, then K timed ones.  Before the warmup the device
+    runs untimed cycles for ramp_s seconds, so that the timed cycles run at the
+    clocks of a loaded GPU (a cold device ramps its clocks over the first tenths
+    of a second)."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < ramp_s:
+        s.cycle(20, norms=False)
+        torch.cuda.synchronize()
     s.cycle(warmup, norms=False)
     torch.cuda.synchronize()
     s.time_sweeps(True)
@@ -280,6 +288,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_ramp_s": 0.3,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",

@@ -192,7 +192,9 @@ int mg_set_tile(mg_ctx* ctx, int tile);
 
 /* Autotuner of the fused sweep: launches every tile variant `reps` times on the
  * context's current data, writing into scratch buffers (the cycle state is not
- * modified), times the launches with HIP events and selects the fastest.
+ * modified), times each launch (with its seam pass) with HIP events after
+ * filling two finest-size scratch arrays, so that the caches hold other data
+ * as they do inside a cycle, and selects the fastest.
  * best_tile / best_us (average microseconds per launch) may be NULL;
  * times_us, when not NULL, receives one average per variant (mg_tiles count).
  * Synchronises. */

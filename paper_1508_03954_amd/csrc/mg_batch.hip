@@ -211,7 +211,7 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
   } else if (kind == BK_SEAM) {
     // rho_c += the seam rows of the 3D restriction (rows (s + 1) 2 of each coarse plane)
     const BLevel<T>& c = P.lv[P.L - 1];
-    const int nc = c.n, nty = P.fgy, nseam = nty - 1;
+    const int nc = c.n, nseam = P.fgy - 1;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int k = 0; k < kBRows / kBWaves; ++k) {
       const int row = tile * kBRows + wv + kBWaves * k;
@@ -221,7 +221,7 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
       for (int mx = lane; mx < nc; mx += 64) {
         if (mx < 1 || mx > nc - 2) continue;
         cpx<T>& d = c.b[((long long)mz * nc + my) * nc + mx];
-        const cpx<T> e = P.spill[((long long)mz * nty + sidx) * nc + mx];
+        const cpx<T> e = P.spill[((long long)mz * nc + my) * nc + mx];
         d = mk(d.re + e.re, d.im + e.im);
       }
     }

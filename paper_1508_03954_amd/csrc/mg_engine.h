@@ -473,7 +473,10 @@ struct Engine {
     return a;
   }
 
-  // Times every tile variant of the fused sweep on scratch outputs; keeps the best.
+  // Times every tile variant of the fused sweep (with its seam pass) on scratch
+  // outputs; keeps the best.  Each timed launch follows a fill of two
+  // finest-size scratch arrays, so that it starts with the caches holding
+  // other data, as a sweep inside a cycle does.
   int autotune(int reps, int* best_tile, double* best_us, double* times) {
     if (!fused) return fail(MG_EINVAL, "the context has no fused sweep");
     MG_TRY(ensure_scratch());
@@ -482,34 +485,40 @@ struct Engine {
     }
     Level<T>* c = &lv[L - 1];
     const int saved = tile;
-    hipEvent_t e0, e1;
-    MG_HIP(hipEventCreate(&e0));
-    MG_HIP(hipEventCreate(&e1));
+    reps = std::max(reps, 1);
+    std::vector<hipEvent_t> ev2(2 * (size_t)reps, nullptr);
+    for (auto& e : ev2) MG_HIP(hipEventCreate(&e));
     int best = saved;
     double best_t = 1e300;
+    const size_t flush_bytes = NL() * sizeof(cpx<T>);
     for (int t = 0; t < fused_tile_count(dim); ++t) {
       set_tile(t);
       FusedArgs<T> a = fused_args(tA, c->pr, tune_c, c->pz, omega.real(), omega.imag());
       MG_HIP(launch_fused<T>(dim, a, s));  // warm-up
       MG_HIP(launch_fused_seam<T>(dim, a, s));
-      MG_HIP(hipEventRecord(e0, s));
       for (int k = 0; k < reps; ++k) {
+        MG_HIP(launch_fill(tR, flush_bytes, s));
+        MG_HIP(launch_fill(tRh, flush_bytes, s));
+        MG_HIP(hipEventRecord(ev2[2 * k], s));
         MG_HIP(launch_fused<T>(dim, a, s));
         MG_HIP(launch_fused_seam<T>(dim, a, s));
+        MG_HIP(hipEventRecord(ev2[2 * k + 1], s));
       }
-      MG_HIP(hipEventRecord(e1, s));
-      MG_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      MG_HIP(hipEventElapsedTime(&ms, e0, e1));
-      const double us = 1e3 * ms / std::max(reps, 1);
+      MG_HIP(hipEventSynchronize(ev2[2 * reps - 1]));
+      double total = 0;
+      for (int k = 0; k < reps; ++k) {
+        float ms = 0;
+        MG_HIP(hipEventElapsedTime(&ms, ev2[2 * k], ev2[2 * k + 1]));
+        total += ms;
+      }
+      const double us = 1e3 * total / reps;
       if (times) times[t] = us;
       if (us < best_t) {
         best_t = us;
         best = t;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto& e : ev2) (void)hipEventDestroy(e);
     set_tile(best);
     if (best_tile) *best_tile = best;
     if (best_us) *best_us = best_t;

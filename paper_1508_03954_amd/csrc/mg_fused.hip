@@ -138,13 +138,13 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
 }
 
 // Seam rows of the 3D restriction: rho_c at coarse row (s + 1) TYC gains the
-// share of fine rows 3 (s + 1) TYC - 2 and - 1, restricted by y tile s (see
-// f3_ytiles); one addition per vertex, so the result does not depend on the
-// order of the tiles.
+// share of fine rows 3 (s + 1) TYC - 2 and - 1, restricted by y tile s into
+// the same vertex of the seam array (see f3_ytiles); one addition per vertex,
+// so the result does not depend on the order of the tiles.
 template <class T>
 __global__ __launch_bounds__(256) void k_seam3(cpx<T>* __restrict__ rhoc, const cpx<T>* __restrict__ spill, int nc,
                                                int tyc) {
-  const int nty = f3_ytiles(nc, tyc), nseam = nty - 1;
+  const int nseam = f3_ytiles(nc, tyc) - 1;
   const long long total = (long long)nc * nseam * nc;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
     const int mx = (int)(i % nc);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_seam3(cpx<T>* __restrict__ rhoc, const 
     const int my = (sidx + 1) * tyc;
     if (mx < 1 || mx > nc - 2 || mz < 1 || mz > nc - 2 || my > nc - 2) continue;
     cpx<T>& d = rhoc[((long long)mz * nc + my) * nc + mx];
-    const cpx<T> e = spill[((long long)mz * nty + sidx) * nc + mx];
+    const cpx<T> e = spill[((long long)mz * nc + my) * nc + mx];
     d = mk(d.re + e.re, d.im + e.im);
   }
 }
@@ -172,11 +172,8 @@ hipError_t launch_fused_seam(int dim, const FusedArgs<T>& a, hipStream_t s) {
 
 size_t fused_spill_count(int dim, int n) {
   if (dim != 3) return 0;
-  const int nc = (n - 1) / 3 + 1;
-  size_t m = 0;
-  for (int t = 0; t < kNumTiles3; ++t)
-    m = std::max(m, (size_t)nc * (size_t)f3_ytiles(nc, kTiles3[t].tyc) * (size_t)nc);
-  return m;
+  const size_t nc = (n - 1) / 3 + 1;
+  return nc * nc * nc;
 }
 
 // y = H x or r = b - H x (constant phi, 3D) with the sweep's march: 2 x 2

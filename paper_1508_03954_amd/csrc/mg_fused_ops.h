@@ -234,8 +234,9 @@ __device__ inline void bstore(cpx<float> c, __amdgpu_buffer_rsrc_t r, unsigned o
 // rows only, so R at its first coarse row 3 my0 misses fine rows 3 my0 - 2 and
 // 3 my0 - 1, which belong to the tile above (by - 1).  That tile restricts
 // them to coarse row my0 (its "seam row") and stores the result in the seam
-// array, plane kz, row by - 1; a second pass (k_seam3) adds it to rho_c.
-// Layout: [coarse plane][y tile][coarse column], nty = ceil(nc / TYC) rows a plane.
+// array at the same coarse vertex; a second pass (k_seam3) adds it to rho_c
+// at the seam rows.  The seam array has the layout of a coarse level (only
+// its seam rows are written), so both stores share one offset per point.
 __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1) / tyc; }
 
 // One tile (bx, by, bz) of the 3D sweep, executed by a whole block of
@@ -277,8 +278,6 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const int n = a.n, nc = a.nc;
   const long long n2 = (long long)n * n, nc2 = (long long)nc * nc;
   const unsigned pbytes = (unsigned)(n2 * CB), cpbytes = (unsigned)(nc2 * CB);
-  const int nty = f3_ytiles(nc, TYC);
-  const unsigned spbytes = (unsigned)((long long)nty * nc * CB);
   int cx_lo, cx_hi, xs;
   f3_xtile(nc, bx, cx_lo, cx_hi, xs);
   const int my0 = by * TYC, mz0 = bz * ZC;
@@ -331,11 +330,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const bool rcin = rmx >= 1 && rmx <= nc - 2 && rmy >= 1 && rmy <= nc - 2;
   const bool rcol = rpt && rmx < cx_hi;
   const unsigned vrho = (rcol && ly < TYC && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
-  const unsigned vspl = (rcol && ly == TYC && rmy <= nc - 2) ? (unsigned)((by * nc + rmx) * (int)CB) : kOOB;
+  const unsigned vspl = (rcol && ly == TYC && rmy <= nc - 2) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
 
   // Plane descriptors.  A plane that is not accessed gets size zero, so its
   // base address is never used (it may lie outside the array).
-  const long long pstride = n2 * CB, cstride = nc2 * CB, sstride = (long long)nty * nc * CB;
+  const long long pstride = n2 * CB, cstride = nc2 * CB;
   auto at = [](const void* base, long long ofs) {
     return reinterpret_cast<const void*>(reinterpret_cast<uintptr_t>(base) + (uintptr_t)ofs);
   };
@@ -425,7 +424,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const bool done = k0 >= mz0 && k0 < mz1;
       const cpx<T> val = f_sel(rcin && k0 >= 1 && k0 <= nc - 2, acc0, f_zero<T>());
       bstore(val, crs(a.rhoc, kofs, done), vrho);
-      bstore(val, plane_rsrc(at(a.spill, (long long)k0 * sstride), done ? spbytes : 0u), vspl);
+      bstore(val, crs(a.spill, kofs, done), vspl);
       acc0 = acc1;
       acc1 = f_zero<T>();
     }
@@ -497,6 +496,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     const auto wo = frs(a.wout, pofs - pstride, q_own);
     const auto co = crs(VAR == 0 ? a.sfc : a.sic_out, kofs + (K / 3) * cstride, q_own && q_c && VAR != 1);
     cpx<T> r[RPT];
+    double s2 = 0.0, m2 = 0.0;   // this plane's share of the norms
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int y = ybase + j;
@@ -533,17 +533,19 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       } else {
         bstore(rv, wo, vst[j]);
       }
-      if (q_own) {
-        const double r2 = vst[j] != kOOB ? (double)rv.re * rv.re + (double)rv.im * rv.im : 0.0;
-        nsum += r2;
-        nmax = fmax(nmax, r2);
-      }
+      const double r2 = vst[j] != kOOB ? (double)rv.re * rv.re + (double)rv.im * rv.im : 0.0;
+      s2 += r2;
+      m2 = r2 > m2 ? r2 : m2;
       r[j] = rv;
       A[j] = f_add(M, Np[j]);
       Np[j] = N;
       Cp[j] = C;
     }
     if (MODE == kApply) return;
+    if (q_own) {
+      nsum += s2;
+      nmax = m2 > nmax ? m2 : nmax;
+    }
     // refill b with plane p, the coarse registers with plane p+2
     load_b(p, pofs, Br);
     if (MODE != kSweep) return;
