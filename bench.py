@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the hb-variant and time-to-residual runs")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--ramp-s", type=float, default=0.3,
+                    help="seconds of untimed cycles before the warmup cycles (device clock ramp)")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile variant of the fused sweep (no autotune)")
     ap.add_argument("--refine-level", type=int, default=0,
                     help="also solve the 3D k=40 problem at this level with complex64 refinement vs FP64 (0: skip)")
@@ -267,7 +269,7 @@ def main():
         best, best_us, times = s.autotune(reps=5)
         tune = {"tile": best, "us_per_tile": [round(t, 1) for t in times]}
         log(f"[bench] autotune: tile {best} ({best_us:.1f} us); all: {', '.join(f'{t:.1f}' for t in times)}")
-    ms_step, sweep_ms, nsw = time_cycles(s, args.steps, args.warmup, torch)
+    ms_step, sweep_ms, nsw = time_cycles(s, args.steps, args.warmup, torch, args.ramp_s)
     ups = updates_per_cycle(dim, L)
     value = ups / (ms_step * 1e-3)
     fb = fused_bytes(dim, L, args.variant)
@@ -288,7 +290,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "warmup_ramp_s": 0.3,
+        "warmup_ramp_s": args.ramp_s,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -323,7 +325,7 @@ def main():
         s2, b2 = make(other)
         if args.sweep != "generic" and not args.no_autotune and args.tile is None:
             s2.autotune(reps=5)
-        ms2, sw2, _ = time_cycles(s2, args.steps, args.warmup, torch)
+        ms2, sw2, _ = time_cycles(s2, args.steps, args.warmup, torch, args.ramp_s)
         out["extra_variant"] = {"variant": other, "value": ups / (ms2 * 1e-3), "ms_per_step": ms2,
                                 "sweep_us": sw2 * 1e3,
                                 "sweep_GBs": fused_bytes(dim, L, other) / (sw2 * 1e-3) / 1e9}
