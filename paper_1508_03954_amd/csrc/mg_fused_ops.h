@@ -269,9 +269,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   using G = F3<T, TYC, RPT, ZC, BPX>;
   constexpr int TXR = G::TXR, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
   constexpr unsigned CB = sizeof(cpx<T>);
-  // coarse points of R: the TYC owned coarse rows and the seam row
-  constexpr int NPT = TXR * (TYC + 1), PPW = (NPT + W - 1) / W;
-  static_assert(PPW <= 64, "coarse points of R per wave");
+  // coarse points of R: the TYC owned coarse rows and the seam row, taken by
+  // NWR waves in the middle of the block (the edge waves form the halo rows)
+  constexpr int NPT = TXR * (TYC + 1), NWR = (NPT + 63) / 64, WR0 = (W - NWR) / 2;
+  static_assert(NWR <= W, "coarse points of R per block");
+  static_assert(RPT * TXR <= 64, "x part of R: one lane per row and coarse column");
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index and everything derived from rows is wavefront-uniform (scalar)
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -323,11 +325,17 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const unsigned vsg = (stager && smx >= 0 && smx < nc && smy >= 0 && smy < nc)
                            ? (unsigned)((smy * nc + smx) * (int)CB) : kOOB;
   // y and z parts of R: coarse point pi of the tile (rows ly < TYC owned, ly == TYC the seam row)
-  const int pi = wv * PPW + lane;
-  const bool rpt = lane < PPW && pi < NPT;
+  const bool rwave = wv >= WR0 && wv < WR0 + NWR;   // wave-uniform
+  const int pi = (wv - WR0) * 64 + lane;
+  const bool rpt = rwave && pi < NPT;
   const int lx = rpt ? pi % TXR : 0, ly = rpt ? pi / TXR : 0;
   const int rmx = cx_lo + lx, rmy = my0 + ly;
   const bool rcin = rmx >= 1 && rmx <= nc - 2 && rmy >= 1 && rmy <= nc - 2;
+  // x part of R: lane l takes row xr_j = l / TXR of its wave and owned coarse
+  // column cx_lo + xr_c, whose fine column sits at lane xr_l of that row
+  const int xr_j = lane / TXR, xr_c = lane - xr_j * TXR, xr_l = 3 * (cx_lo + xr_c) - xs;
+  const bool xr_ok = xr_j < RPT && cx_lo + xr_c < cx_hi && xr_l >= 2 && xr_l <= 61;
+  const int xr_at = 64 * min(xr_j, RPT - 1) + min(max(xr_l, 2), 61);
   const bool rcol = rpt && rmx < cx_hi;
   const unsigned vrho = (rcol && ly < TYC && rmy < nc) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
   const unsigned vspl = (rcol && ly == TYC && rmy <= nc - 2) ? (unsigned)((rmy * nc + rmx) * (int)CB) : kOOB;
@@ -550,25 +558,22 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     load_b(p, pofs, Br);
     if (MODE != kSweep) return;
     load_g(std::integral_constant<int, (K + 2) % 3>(), p + 2, kofs + ((K + 2) / 3) * cstride);
-    // (5) x part of R at the owned coarse columns (lanes 2 .. 61; the boundary
-    // columns need none), which read their neighbours' r from this wave's slot
-    // of the other UH buffer (free during this half step: it is refilled by
-    // this wave only, at the next step)
+    // (5) x part of R at the owned coarse columns (the boundary columns need
+    // none): the wave's rows go to this wave's slot of the other UH buffer
+    // (free during this half step: it is refilled by this wave only, at the
+    // next step), and lane l reads row l / TXR around coarse column l % TXR
     cpx<T>* rr = &sm.UH[1 - S][wv][0][0][0];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) rr[64 * j + lane] = r[j];
-    if (lane >= 2 && lane <= 61 && ccol && mxl >= cx_lo && mxl < cx_hi) {
-#pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const cpx<T>* row = rr + 64 * j + lane;
-        const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
-        const cpx<T> rx = f_add(r[j], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
-        sm.RX[1 - S][2 + wv * RPT + j][mxl - cx_lo] = rx;
-      }
+    if (xr_ok) {
+      const cpx<T>* row = rr + xr_at;
+      const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
+      const cpx<T> rx = f_add(row[0], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
+      sm.RX[1 - S][2 + wv * RPT + xr_j][xr_c] = rx;
     }
     // (6) y and z parts of R for plane q-1 = p-2 (its x part is in slot S)
     constexpr int KR = K < 2 ? -1 : (K < 5 ? 0 : 1);   // floor((K - 2) / 3)
-    rest_yz(std::integral_constant<int, (K + 1) % 3>(), kb + KR, kofs + KR * cstride, S);
+    if (rwave) rest_yz(std::integral_constant<int, (K + 1) % 3>(), kb + KR, kofs + KR * cstride, S);
   };
   // six steps per iteration, so that plane phases, slots and register roles
   // are constants; the slot left holding the x part of R of plane plast-1
@@ -592,7 +597,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   // R of the last plane plast - 1 = 3 (mz1 - 1) + 2
   if (MODE == kSweep) {
     __syncthreads();
-    rest_yz(std::integral_constant<int, 2>(), mz1 - 1, (long long)(mz1 - 1) * cstride, last);
+    if (rwave) rest_yz(std::integral_constant<int, 2>(), mz1 - 1, (long long)(mz1 - 1) * cstride, last);
   }
   if (part) block_reduce_store(nsum, sqrt(nmax), part, G::NT);
 }
