@@ -165,7 +165,7 @@ struct F3 {
   static_assert(TY % RPT == 0, "rows per thread must divide the owned rows");
   static_assert(W >= 2, "the first and the last wave form one halo row each");
   static_assert(RPT <= 4, "the x part of R stages a wave's rows in its UH slot");
-  static_assert(GX <= 32 && GY <= 2 * W, "coarse staging: two coarse rows per wave");
+  static_assert(GX <= 32, "coarse staging: one coarse row per half wave");
 };
 
 // LDS of one 3D tile, two slots of everything (steps alternate):
@@ -254,10 +254,11 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // free, so no prefetch is live through the stencil beyond one plane of w and
 // b: that keeps the register count (and so the occupancy) down.
 // Rows: the block computes r on its TY owned rows only, and u on one more row
-// on each side (formed by the first and the last wave).  Coarse staging: wave
-// k stages coarse rows 2k and 2k+1 (one per half wave).  The y and z parts of
-// R: every wave takes an equal share of the tile's coarse points, i.e. of its
-// owned coarse rows and of the seam row below them.
+// on each side (formed by the first and the last wave).  Work that not every
+// wave needs goes to different waves: the y and z parts of R (the tile's
+// owned coarse rows and the seam row below them) to the fewest middle waves
+// that hold all its coarse points, the coarse staging to the other waves, two
+// coarse rows each (one per half wave).
 // MODE kSweep: the fused sweep.  kResid / kApply: the same march without the
 // coarse levels, storing r = b - H w (with its partial norms) or y = H w.
 constexpr int kSweep = 0, kResid = 1, kApply = 2;
@@ -274,6 +275,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   constexpr int NPT = TXR * (TYC + 1), NWR = (NPT + 63) / 64, WR0 = (W - NWR) / 2;
   static_assert(NWR <= W, "coarse points of R per block");
   static_assert(RPT * TXR <= 64, "x part of R: one lane per row and coarse column");
+  static_assert(GY <= 2 * (W - NWR), "coarse staging: two coarse rows per wave without R points");
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index and everything derived from rows is wavefront-uniform (scalar)
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -318,14 +320,17 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   const bool top = wv == 0, bot = wv == W - 1;
   const int yhalo = top ? y0 - 1 : y0 + TY;       // extra row formed by the edge waves
   const unsigned vldh = ((top || bot) && row_ok(yhalo) && xin) ? (unsigned)((yhalo * n + x) * (int)CB) : kOOB;
-  // coarse staging: half wave h of wave wv stages coarse row my0 - 1 + 2 wv + h
-  const int sr = 2 * wv + (lane >> 5), sx = lane & 31;
+  // coarse staging by the waves that take no R points: staging wave k (in
+  // wave order) stages coarse rows my0 - 1 + 2k and 2k + 1, one per half wave
+  const bool rwave = wv >= WR0 && wv < WR0 + NWR;   // wave-uniform
+  const int sidx = wv < WR0 ? wv : wv - NWR;
+  const bool swave = !rwave && 2 * sidx < GY;       // wave-uniform
+  const int sr = 2 * sidx + (lane >> 5), sx = lane & 31;
   const int smx = smx0 + sx, smy = my0 - 1 + sr;
-  const bool stager = sr < GY && sx < GX;
+  const bool stager = swave && sr < GY && sx < GX;
   const unsigned vsg = (stager && smx >= 0 && smx < nc && smy >= 0 && smy < nc)
                            ? (unsigned)((smy * nc + smx) * (int)CB) : kOOB;
   // y and z parts of R: coarse point pi of the tile (rows ly < TYC owned, ly == TYC the seam row)
-  const bool rwave = wv >= WR0 && wv < WR0 + NWR;   // wave-uniform
   const int pi = (wv - WR0) * 64 + lane;
   const bool rpt = rwave && pi < NPT;
   const int lx = rpt ? pi % TXR : 0, ly = rpt ? pi / TXR : 0;
@@ -440,9 +445,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
 
   if (MODE == kSweep) {
     const long long k0ofs = (long long)(mz0 - 1) * cstride;
-    load_g(std::integral_constant<int, 0>(), p0, k0ofs);
-    store_g(std::integral_constant<int, 0>(), 0);
-    load_g(std::integral_constant<int, 1>(), p0 + 1, k0ofs);
+    if (swave) {
+      load_g(std::integral_constant<int, 0>(), p0, k0ofs);
+      store_g(std::integral_constant<int, 0>(), 0);
+      load_g(std::integral_constant<int, 1>(), p0 + 1, k0ofs);
+    }
   }
   load_w(p0, (long long)p0 * pstride, Wr, Wh);
   if (MODE != kApply) load_b(p0 - 1, (long long)(p0 - 1) * pstride, Br);
@@ -486,7 +493,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
     // (2) refill w with plane p+1; stage plane p+1's correction
     load_w(p + 1, pofs + pstride, Wr, Wh);
-    if (MODE == kSweep) store_g(std::integral_constant<int, (K + 1) % 3>(), 1 - S);
+    if (MODE == kSweep && swave) store_g(std::integral_constant<int, (K + 1) % 3>(), 1 - S);
     __syncthreads();
     // (3) neighbour rows across the wave edges
     cpx<T> ua = uh, ha = hh, ub = uh, hb = hh;
@@ -557,7 +564,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     // refill b with plane p, the coarse registers with plane p+2
     load_b(p, pofs, Br);
     if (MODE != kSweep) return;
-    load_g(std::integral_constant<int, (K + 2) % 3>(), p + 2, kofs + ((K + 2) / 3) * cstride);
+    if (swave) load_g(std::integral_constant<int, (K + 2) % 3>(), p + 2, kofs + ((K + 2) / 3) * cstride);
     // (5) x part of R at the owned coarse columns (the boundary columns need
     // none): the wave's rows go to this wave's slot of the other UH buffer
     // (free during this half step: it is refilled by this wave only, at the
