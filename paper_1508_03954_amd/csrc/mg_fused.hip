@@ -29,15 +29,17 @@ __device__ inline void fused3_block_tile(int order, int gx, int gy, int gz, int&
   bz = t / (gx * gy);
 }
 
-template <class T, int TYC, int RPT, int ZC, int VAR>
-__global__ __launch_bounds__(64 * (3 * TYC / RPT), 3) void k_fused3(FusedArgs<T> a) {
+// PF > 1 tiles keep PF planes of loads in flight and take more registers:
+// they are meant for grids with few waves per CU, so they ask for 2 waves per SIMD.
+template <class T, int TYC, int RPT, int ZC, int VAR, int PF>
+__global__ __launch_bounds__(64 * (3 * TYC / RPT), PF == 1 ? 3 : 2) void k_fused3(FusedArgs<T> a) {
   __shared__ F3Lds<T, TYC, RPT, VAR == 2> sm;
   int bx, by, bz;
   fused3_block_tile(a.order, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
   // partial sums are indexed by tile, so the norm's summation order does not
   // depend on the block order
   double* part = a.partials ? a.partials + 2 * (bx + gridDim.x * (by + gridDim.y * bz)) : nullptr;
-  fused3_tile<T, TYC, RPT, ZC, VAR>(a, bx, by, bz, part, sm);
+  fused3_tile<T, TYC, RPT, ZC, VAR, kSweep, PF>(a, bx, by, bz, part, sm);
 }
 
 template <class T, int ZC, bool BPX>
@@ -49,12 +51,13 @@ __global__ __launch_bounds__(64) void k_fused2(FusedArgs<T> a) {
 }
 
 // Tile variants of the fused sweep (coarse rows per block, rows per thread,
-// coarse planes per block); the context picks one per problem (default table or
-// autotuning on the device).
-struct TileShape3 { int tyc, rpt, zc, order; };
-constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0},  {2, 2, 14, 0}, {2, 2, 21, 0}, {2, 2, 27, 0},
-                                  {2, 2, 28, 0}, {4, 2, 14, 0}, {4, 2, 21, 0}, {4, 2, 28, 0},
-                                  {2, 1, 14, 0}, {2, 1, 21, 0}, {2, 2, 9, 1},  {2, 2, 21, 1}};
+// coarse planes per block, block order, prefetch depth); the context picks one
+// per problem (default table or autotuning on the device).
+struct TileShape3 { int tyc, rpt, zc, order, pf; };
+constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0, 1},  {2, 2, 14, 0, 1}, {2, 2, 21, 0, 1}, {2, 2, 27, 0, 1},
+                                  {2, 2, 28, 0, 1}, {4, 2, 14, 0, 1}, {4, 2, 21, 0, 1}, {4, 2, 28, 0, 1},
+                                  {2, 1, 14, 0, 1}, {2, 1, 21, 0, 1}, {2, 2, 9, 1, 1},  {2, 2, 21, 1, 1},
+                                  {4, 2, 28, 0, 2}, {4, 2, 28, 0, 3}, {2, 2, 28, 0, 2}, {2, 2, 28, 0, 3}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -64,7 +67,9 @@ int fused_tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
 int fused_tile_index(int dim, int tyc, int rpt, int zc) {
   if (dim == 3) {
     for (int t = 0; t < kNumTiles3; ++t)
-      if (kTiles3[t].tyc == tyc && kTiles3[t].rpt == rpt && kTiles3[t].zc == zc && kTiles3[t].order == 0) return t;
+      if (kTiles3[t].tyc == tyc && kTiles3[t].rpt == rpt && kTiles3[t].zc == zc && kTiles3[t].order == 0 &&
+          kTiles3[t].pf == 1)
+        return t;
     return -1;
   }
   for (int t = 0; t < kNumTiles2; ++t)
@@ -88,14 +93,14 @@ int fused_partials_blocks(int dim, int n, int tile) {
   return (int)(g.x * g.y * g.z);
 }
 
-template <class T, int TYC, int RPT, int ZC>
+template <class T, int TYC, int RPT, int ZC, int PF = 1>
 static void launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s) {
   constexpr int NT = F3<T, TYC, RPT, ZC, false>::NT;
   FusedArgs<T> a = a0;
   a.order = kTiles3[a0.tile].order;
-  if (a.variant == 2) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2>), g, NT, 0, s, a);
-  else if (a.variant == 1) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 1>), g, NT, 0, s, a);
-  else hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 0>), g, NT, 0, s, a);
+  if (a.variant == 2) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2, PF>), g, NT, 0, s, a);
+  else if (a.variant == 1) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 1, PF>), g, NT, 0, s, a);
+  else hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 0, PF>), g, NT, 0, s, a);
 }
 
 template <class T, int ZC>
@@ -124,7 +129,11 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
       case 8: launch3<T, 2, 1, 14>(a, g, s); break;
       case 9: launch3<T, 2, 1, 21>(a, g, s); break;
       case 10: launch3<T, 2, 2, 9>(a, g, s); break;
-      default: launch3<T, 2, 2, 21>(a, g, s); break;
+      case 11: launch3<T, 2, 2, 21>(a, g, s); break;
+      case 12: launch3<T, 4, 2, 28, 2>(a, g, s); break;
+      case 13: launch3<T, 4, 2, 28, 3>(a, g, s); break;
+      case 14: launch3<T, 2, 2, 28, 2>(a, g, s); break;
+      default: launch3<T, 2, 2, 28, 3>(a, g, s); break;
     }
   } else {
     switch (a.tile) {

@@ -263,7 +263,10 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // coarse levels, storing r = b - H w (with its partial norms) or y = H w.
 constexpr int kSweep = 0, kResid = 1, kApply = 2;
 
-template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep>
+// PF: prefetch depth of w and b in planes (1, 2 or 3).  With PF > 1 each wave
+// keeps the loads of PF planes in flight (PF register sets used in turn): for
+// grids whose tiles leave few waves per CU, latency is hidden per wave.
+template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep, int PF = 1>
 __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
                                    F3Lds<T, TYC, RPT, VAR == 2, MODE == kSweep>& sm) {
   constexpr bool BPX = VAR == 2;
@@ -355,7 +358,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   auto crs = [&](const cpx<T>* base, long long ofs, bool ok) { return plane_rsrc(at(base, ofs), ok ? cpbytes : 0u); };
   cpx<T>* tagT = nullptr;
 
-  cpx<T> Wr[RPT], Wh, Br[RPT];
+  static_assert(PF >= 1 && PF <= 3, "prefetch depth (a divisor of the six-step group)");
+  cpx<T> Wr[PF][RPT], Wh[PF], Br[PF][RPT];
   cpx<T> A[RPT], Np[RPT], Cp[RPT];
   cpx<T> gsc0, gsc1, gsi0, gsi1;
   cpx<T> acc0 = f_zero<T>(), acc1 = f_zero<T>();
@@ -451,8 +455,12 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       load_g(std::integral_constant<int, 1>(), p0 + 1, k0ofs);
     }
   }
-  load_w(p0, (long long)p0 * pstride, Wr, Wh);
-  if (MODE != kApply) load_b(p0 - 1, (long long)(p0 - 1) * pstride, Br);
+#pragma unroll
+  for (int i = 0; i < PF; ++i) load_w(p0 + i, (long long)(p0 + i) * pstride, Wr[i], Wh[i]);
+  if (MODE != kApply) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) load_b(p0 - 1 + i, (long long)(p0 - 1 + i) * pstride, Br[i]);
+  }
 #pragma unroll
   for (int j = 0; j < RPT; ++j) { A[j] = f_zero<T>(); Np[j] = f_zero<T>(); Cp[j] = f_zero<T>(); }
   if (MODE == kSweep) {
@@ -466,22 +474,24 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   __syncthreads();
 
   // Step K of a group (p = p0 + 6i + K, kb = mz0 - 1 + 2i): LDS slot S = K & 1;
-  // at its start Wr holds w of plane p, Br b of plane p-1, and the coarse
+  // at its start Wr[E] holds w of plane p, Br[E] b of plane p-1 (the other
+  // PF - 1 sets have the loads of the next planes in flight), and the coarse
   // registers the values of plane p+1
   auto step = [&](auto K_, int p, int kb) {
     constexpr int K = decltype(K_)::value;
     constexpr int S = K & 1, PT = K % 3;
+    constexpr int E = K % PF;   // register set of w(p) and b(p-1)
     const int q = p - 1;
     const long long pofs = (long long)p * pstride, kofs = (long long)kb * cstride;
     cpx<T> u[RPT], h[RPT], uh = f_zero<T>(), hh = f_zero<T>();
     // (1) u and h on plane p
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      u[j] = form_u(std::integral_constant<int, PT>(), p, S, ybase + j, Wr[j]);
+      u[j] = form_u(std::integral_constant<int, PT>(), p, S, ybase + j, Wr[E][j]);
       h[j] = hsum(u[j]);
     }
     if (top || bot) {
-      uh = form_u(std::integral_constant<int, PT>(), p, S, yhalo, Wh);
+      uh = form_u(std::integral_constant<int, PT>(), p, S, yhalo, Wh[E]);
       hh = hsum(uh);
     }
     constexpr int LE = RPT == 1 ? 0 : 1;   // slot of the last row (the first row when RPT == 1)
@@ -491,8 +501,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       sm.UH[S][wv][LE][0][lane] = u[RPT - 1];
       sm.UH[S][wv][LE][1][lane] = h[RPT - 1];
     }
-    // (2) refill w with plane p+1; stage plane p+1's correction
-    load_w(p + 1, pofs + pstride, Wr, Wh);
+    // (2) refill w with plane p+PF; stage plane p+1's correction
+    load_w(p + PF, pofs + PF * pstride, Wr[E], Wh[E]);
     if (MODE == kSweep && swave) store_g(std::integral_constant<int, (K + 1) % 3>(), 1 - S);
     __syncthreads();
     // (3) neighbour rows across the wave edges
@@ -537,7 +547,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
         Np[j] = N;
         continue;
       }
-      const cpx<T> rv = f_sel(in, f_sub(Br[j], f_add(A[j], N)), f_zero<T>());
+      const cpx<T> rv = f_sel(in, f_sub(Br[E][j], f_add(A[j], N)), f_zero<T>());
       if (MODE == kSweep) {
         const cpx<T> s = f_mul(ws, rv);
         const bool cp = q_c && q >= 0 && ccol && x >= 0 && (y % 3) == 0;
@@ -561,8 +571,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       nsum += s2;
       nmax = m2 > nmax ? m2 : nmax;
     }
-    // refill b with plane p, the coarse registers with plane p+2
-    load_b(p, pofs, Br);
+    // refill b with plane p+PF-1, the coarse registers with plane p+2
+    load_b(p + PF - 1, pofs + (PF - 1) * pstride, Br[E]);
     if (MODE != kSweep) return;
     if (swave) load_g(std::integral_constant<int, (K + 2) % 3>(), p + 2, kofs + ((K + 2) / 3) * cstride);
     // (5) x part of R at the owned coarse columns (the boundary columns need
