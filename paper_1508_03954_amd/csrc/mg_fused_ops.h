@@ -361,7 +361,10 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   static_assert(PF >= 1 && PF <= 3, "prefetch depth (a divisor of the six-step group)");
   cpx<T> Wr[PF][RPT], Wh[PF], Br[PF][RPT];
   cpx<T> A[RPT], Np[RPT], Cp[RPT];
-  cpx<T> gsc0, gsc1, gsi0, gsi1;
+  // coarse prefetch depth: with PF > 1 the coarse values of two planes are in
+  // flight (register set = parity of the fine plane relative to p0)
+  constexpr int GF = PF == 1 ? 1 : 2;
+  cpx<T> gsc0[GF], gsc1[GF], gsi0[GF], gsi1[GF];
   cpx<T> acc0 = f_zero<T>(), acc1 = f_zero<T>();
   double nsum = 0.0, nmax = 0.0;
 
@@ -384,23 +387,23 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   };
   // coarse values of fine plane p = 3 kz + TZ: planes kz and kz+1 (the second
   // only off coarse planes); coarse boundary planes hold zeros
-  auto load_g = [&](auto TZ_, int p, long long kofs) {
-    constexpr int TZ = decltype(TZ_)::value;
+  auto load_g = [&](auto TZ_, auto G_, int p, long long kofs) {
+    constexpr int TZ = decltype(TZ_)::value, G = decltype(G_)::value;
     const bool ok = plane_ok(p) && p <= plast;
-    gsc0 = bload(tagT, crs(a.scc, kofs, ok), vsg);
-    gsc1 = bload(tagT, crs(a.scc, kofs + cstride, ok && TZ != 0), vsg);
+    gsc0[G] = bload(tagT, crs(a.scc, kofs, ok), vsg);
+    gsc1[G] = bload(tagT, crs(a.scc, kofs + cstride, ok && TZ != 0), vsg);
     if (BPX) {
-      gsi0 = bload(tagT, crs(a.sic, kofs, ok), vsg);
-      gsi1 = bload(tagT, crs(a.sic, kofs + cstride, ok && TZ != 0), vsg);
+      gsi0[G] = bload(tagT, crs(a.sic, kofs, ok), vsg);
+      gsi1[G] = bload(tagT, crs(a.sic, kofs + cstride, ok && TZ != 0), vsg);
     }
   };
-  auto store_g = [&](auto TZ_, int slot) {
-    constexpr int TZ = decltype(TZ_)::value;
+  auto store_g = [&](auto TZ_, auto G_, int slot) {
+    constexpr int TZ = decltype(TZ_)::value, G = decltype(G_)::value;
     if (stager) {
-      const cpx<T> g0 = BPX ? f_sub(gsc0, gsi0) : gsc0;
-      const cpx<T> g1 = BPX ? f_sub(gsc1, gsi1) : gsc1;
+      const cpx<T> g0 = BPX ? f_sub(gsc0[G], gsi0[G]) : gsc0[G];
+      const cpx<T> g1 = BPX ? f_sub(gsc1[G], gsi1[G]) : gsc1[G];
       sm.Gz[slot][sr][sx] = TZ == 0 ? g0 : f_add(f_scale(w_lo<T>(TZ), g0), f_scale(w_hi<T>(TZ), g1));
-      if (BPX) sm.Sz[slot][sr][sx] = gsc0;   // used on c-points only (TZ == 0)
+      if (BPX) sm.Sz[slot][sr][sx] = gsc0[G];   // used on c-points only (TZ == 0)
     }
   };
   // u = w + P g on plane p (p mod 3 = PT) at row y (zero off the interior)
@@ -450,9 +453,12 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   if (MODE == kSweep) {
     const long long k0ofs = (long long)(mz0 - 1) * cstride;
     if (swave) {
-      load_g(std::integral_constant<int, 0>(), p0, k0ofs);
-      store_g(std::integral_constant<int, 0>(), 0);
-      load_g(std::integral_constant<int, 1>(), p0 + 1, k0ofs);
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, GF - 1>;
+      load_g(I0(), I0(), p0, k0ofs);
+      store_g(I0(), I0(), 0);
+      load_g(std::integral_constant<int, 1>(), I1(), p0 + 1, k0ofs);
+      if (GF == 2) load_g(std::integral_constant<int, 2>(), I0(), p0 + 2, k0ofs);
     }
   }
 #pragma unroll
@@ -503,7 +509,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
     // (2) refill w with plane p+PF; stage plane p+1's correction
     load_w(p + PF, pofs + PF * pstride, Wr[E], Wh[E]);
-    if (MODE == kSweep && swave) store_g(std::integral_constant<int, (K + 1) % 3>(), 1 - S);
+    if (MODE == kSweep && swave)
+      store_g(std::integral_constant<int, (K + 1) % 3>(), std::integral_constant<int, (K + 1) % GF>(), 1 - S);
     __syncthreads();
     // (3) neighbour rows across the wave edges
     cpx<T> ua = uh, ha = hh, ub = uh, hb = hh;
@@ -571,10 +578,12 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       nsum += s2;
       nmax = m2 > nmax ? m2 : nmax;
     }
-    // refill b with plane p+PF-1, the coarse registers with plane p+2
+    // refill b with plane p+PF-1, the coarse registers with plane p+1+GF
     load_b(p + PF - 1, pofs + (PF - 1) * pstride, Br[E]);
     if (MODE != kSweep) return;
-    if (swave) load_g(std::integral_constant<int, (K + 2) % 3>(), p + 2, kofs + ((K + 2) / 3) * cstride);
+    if (swave)
+      load_g(std::integral_constant<int, (K + 1 + GF) % 3>(), std::integral_constant<int, (K + 1) % GF>(), p + 1 + GF,
+             kofs + ((K + 1 + GF) / 3) * cstride);
     // (5) x part of R at the owned coarse columns (the boundary columns need
     // none): the wave's rows go to this wave's slot of the other UH buffer
     // (free during this half step: it is refilled by this wave only, at the
