@@ -46,6 +46,26 @@ __device__ inline void unravel(long long ii, int n, int j[3]) {
   }
 }
 
+// Division by a level's vertex count per axis n through a multiply-high:
+// floor(i / n) = umulhi(i, m) with m = ceil(2^32 / n) is exact for
+// i < 2^32 / n, so unravel_fast (two such divisions) covers levels with
+// n^4 < 2^32, i.e. n <= 255.
+__host__ __device__ inline unsigned fastdiv_magic(int n) { return 0xFFFFFFFFu / (unsigned)n + 1u; }
+template <int D>
+__device__ inline void unravel_fast(unsigned i, int n, unsigned magic, int j[3]) {
+  const unsigned t = __umulhi(i, magic);
+  j[0] = (int)(i - t * (unsigned)n);
+  if (D == 3) {
+    const unsigned z = __umulhi(t, magic);
+    j[1] = (int)(t - z * (unsigned)n);
+    j[2] = (int)z;
+  } else {
+    j[1] = (int)t;
+    j[2] = 0;
+  }
+}
+constexpr int kFastDivMaxN = 255;
+
 template <int D>
 __device__ inline long long ravel(const int j[3], int n) {
   return D == 3 ? ((long long)j[2] * n + j[1]) * n + j[0] : (long long)j[1] * n + j[0];

@@ -151,18 +151,15 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
 // the same vertex of the seam array (see f3_ytiles); one addition per vertex,
 // so the result does not depend on the order of the tiles.
 template <class T>
-__global__ __launch_bounds__(256) void k_seam3(cpx<T>* __restrict__ rhoc, const cpx<T>* __restrict__ spill, int nc,
+__global__ __launch_bounds__(128) void k_seam3(cpx<T>* __restrict__ rhoc, const cpx<T>* __restrict__ spill, int nc,
                                                int tyc) {
-  const int nseam = f3_ytiles(nc, tyc) - 1;
-  const long long total = (long long)nc * nseam * nc;
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
-    const int mx = (int)(i % nc);
-    const long long t = i / nc;
-    const int sidx = (int)(t % nseam), mz = (int)(t / nseam);
-    const int my = (sidx + 1) * tyc;
-    if (mx < 1 || mx > nc - 2 || mz < 1 || mz > nc - 2 || my > nc - 2) continue;
-    cpx<T>& d = rhoc[((long long)mz * nc + my) * nc + mx];
-    const cpx<T> e = spill[((long long)mz * nc + my) * nc + mx];
+  // block (s, mz): seam s of coarse plane mz, coarse row (s + 1) tyc
+  const int mz = blockIdx.y, my = (blockIdx.x + 1) * tyc;
+  if (mz < 1 || mz > nc - 2 || my > nc - 2) return;
+  const long long row = ((long long)mz * nc + my) * nc;
+  for (int mx = threadIdx.x + 1; mx <= nc - 2; mx += 128) {
+    cpx<T>& d = rhoc[row + mx];
+    const cpx<T> e = spill[row + mx];
     d = mk(d.re + e.re, d.im + e.im);
   }
 }
@@ -173,9 +170,7 @@ hipError_t launch_fused_seam(int dim, const FusedArgs<T>& a, hipStream_t s) {
   if (a.tile < 0 || a.tile >= kNumTiles3 || a.spill == nullptr || a.rhoc == nullptr) return hipErrorInvalidValue;
   const int tyc = kTiles3[a.tile].tyc, nseam = f3_ytiles(a.nc, tyc) - 1;
   if (nseam < 1) return hipSuccess;
-  const long long total = (long long)a.nc * nseam * a.nc;
-  const int blocks = (int)std::min<long long>((total + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_seam3<T>, dim3(blocks), dim3(256), 0, s, a.rhoc, a.spill, a.nc, tyc);
+  hipLaunchKernelGGL(k_seam3<T>, dim3(nseam, a.nc), dim3(128), 0, s, a.rhoc, a.spill, a.nc, tyc);
   return hipGetLastError();
 }
 

@@ -101,6 +101,20 @@ __global__ void k_pre(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc, co
   }
 }
 
+// The same over a flat index (one thread per vertex, every lane busy), for 3D
+// levels with n <= kFastDivMaxN whose rows do not fill whole wavefronts.
+template <class T>
+__global__ __launch_bounds__(256) void k_pre_flat3(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc,
+                                                   const cpx<T>* __restrict__ sf, const cpx<T>* __restrict__ scc,
+                                                   const cpx<T>* __restrict__ sic, int has_coarse, int bpx) {
+  const unsigned N = (unsigned)n * n * n, magic = fastdiv_magic(n);
+  for (unsigned i = blockIdx.x * 256u + threadIdx.x; i < N; i += gridDim.x * 256u) {
+    int j[3];
+    unravel_fast<3>(i, n, magic, j);
+    pre_vertex<T, 3>(n, j, i, u, sc, sf, scc, sic, has_coarse, bpx);
+  }
+}
+
 // Finest-level pre-phase on the folded iterate w = u + sc:
 //   u = w + P sc_c (- P si_c off c-points for BPX), written to a second buffer.
 template <class T, int D>
@@ -187,13 +201,8 @@ __global__ __launch_bounds__(256) void k_post_galerkin(OpData<T> op, const cpx<T
   int m[3] = {0, 0, 0};
   const bool valid = v < Nc;
   const long long vv = valid ? v : 0;
-  m[0] = (int)(vv % nc);
-  if (D == 3) {
-    m[1] = (int)((vv / nc) % nc);
-    m[2] = (int)(vv / ((long long)nc * nc));
-  } else {
-    m[1] = (int)(vv / nc);
-  }
+  if (nc <= kFastDivMaxN) unravel_fast<D>((unsigned)vv, nc, fastdiv_magic(nc), m);
+  else unravel<D>(vv, nc, m);
   cpx<T> p = czero<T>();
   if (valid && part < 5) p = post_galerkin_part<T, D>(op, m, vv, part - 2, rho, omega, mask_c, sc, sf, sfc, sic);
   T re = p.re, im = p.im;
@@ -242,13 +251,9 @@ __global__ __launch_bounds__(256) void k_restrict(int nc, const cpx<T>* __restri
   const int part = (int)(g & 7);
   const bool valid = v < Nc;
   const long long vv = valid ? v : 0;
-  int m[3] = {(int)(vv % nc), 0, 0};
-  if (D == 3) {
-    m[1] = (int)((vv / nc) % nc);
-    m[2] = (int)(vv / ((long long)nc * nc));
-  } else {
-    m[1] = (int)(vv / nc);
-  }
+  int m[3] = {0, 0, 0};
+  if (nc <= kFastDivMaxN) unravel_fast<D>((unsigned)vv, nc, fastdiv_magic(nc), m);
+  else unravel<D>(vv, nc, m);
   cpx<T> p = czero<T>();
   if (valid && part < 5) p = restrict_part<T, D>(vf, nf, m, part - 2);
   T re = p.re, im = p.im;
@@ -616,14 +621,7 @@ __global__ void k_finish(const double* __restrict__ partials, int count, double*
 // The smallest coarse levels in one block (see SmallArgs).
 template <class T, int D>
 __device__ inline void small_unravel(long long i, int n, int j[3]) {
-  j[0] = (int)(i % n);
-  if (D == 3) {
-    j[1] = (int)((i / n) % n);
-    j[2] = (int)(i / ((long long)n * n));
-  } else {
-    j[1] = (int)(i / n);
-    j[2] = 0;
-  }
+  unravel_fast<D>((unsigned)i, n, fastdiv_magic(n), j);   // small levels: n <= 16
 }
 
 template <class T, int D>
@@ -721,6 +719,12 @@ hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y
 template <class T>
 hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
                       const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s) {
+  if (dim == 3 && n <= kFastDivMaxN && n % 64 != 0) {
+    const long long N = (long long)n * n * n;
+    hipLaunchKernelGGL(k_pre_flat3<T>, dim3((unsigned)((N + 255) / 256)), 256, 0, s, n, u, sc, sf, scc, sic, has_coarse,
+                       bpx);
+    return hipGetLastError();
+  }
   MG_DISPATCH(dim, k_pre, row_grid(n, dim), n, u, sc, sf, scc, sic, has_coarse, bpx);
   return hipGetLastError();
 }
