@@ -106,29 +106,51 @@ __device__ inline void for_rows(int n, int tile, F f) {
   }
 }
 
-// The finest-sweep tiles run out of line so that their register allocation
-// does not add to that of the rest of the persistent loop.
+// Wave-uniform copies of values read from a problem descriptor.  The
+// descriptors are read with vector loads (the kernel also writes global
+// memory, so the scalar cache may not be used for them), which leaves every
+// field in vector registers; readfirstlane moves them to scalar registers,
+// where the sweep's per-plane address arithmetic and constants belong.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class P>
+__device__ inline P* uni(P* p) {
+  const unsigned long long b = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
+}
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline double uni(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <class T>
+__device__ inline cpx<T> uni(cpx<T> c) { return mk(uni(c.re), uni(c.im)); }
+
 template <class T>
 __device__ inline FusedArgs<T> batch_fused_args(const BProb<T>& P, int cyc) {
-  const int L = P.L;
-  const bool bpx = P.variant == MG_BPX, add = P.variant == MG_ADD;
-  const int pw = (P.parw + cyc) & 1, ps = (P.pars + cyc) & 1;
+  const int L = uni(P.L);
+  const int variant = uni(P.variant);
+  const bool bpx = variant == MG_BPX, add = variant == MG_ADD;
+  const int pw = (uni(P.parw) + cyc) & 1, ps = (uni(P.pars) + cyc) & 1;
   FusedArgs<T> f;
-  f.n = P.lv[L].n;
-  f.nc = P.lv[L - 1].n;
-  f.w = P.w[pw];
-  f.wout = P.w[1 - pw];
-  f.b = P.lv[L].b;
-  f.scc = P.lv[L - 1].sc;
-  f.sic = bpx ? P.si2[ps] : nullptr;
-  f.rhoc = P.lv[L - 1].b;
-  f.sfc = add ? P.lv[L - 1].sf : nullptr;
-  f.sic_out = bpx ? P.si2[1 - ps] : nullptr;
-  f.spill = P.spill;
-  for (int q = 0; q < 4; ++q) f.coef[q] = P.lv[L].op.coef[q];
-  f.ws = P.wsL;
+  f.n = uni(P.lv[L].n);
+  f.nc = uni(P.lv[L - 1].n);
+  f.w = uni(P.w[pw]);
+  f.wout = uni(P.w[1 - pw]);
+  f.b = uni(P.lv[L].b);
+  f.scc = uni(P.lv[L - 1].sc);
+  f.sic = bpx ? uni(P.si2[ps]) : nullptr;
+  f.rhoc = uni(P.lv[L - 1].b);
+  f.sfc = add ? uni(P.lv[L - 1].sf) : nullptr;
+  f.sic_out = bpx ? uni(P.si2[1 - ps]) : nullptr;
+  f.spill = uni(P.spill);
+  for (int q = 0; q < 4; ++q) f.coef[q] = uni(P.lv[L].op.coef[q]);
+  f.ws = uni(P.wsL);
   f.partials = nullptr;
-  f.variant = P.variant;
+  f.variant = variant;
   f.tile = 0;
   f.order = 0;
   return f;
