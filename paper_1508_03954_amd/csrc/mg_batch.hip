@@ -286,10 +286,10 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
   }
 }
 
-// Occupancy hints by precision, as measured on the compiler's output: with a
-// hint of 2 the complex128 kernel spilled about 90 registers to scratch, with 4
-// it uses 197 and spills none (2 waves per SIMD either way); complex64 fits 248
-// registers without spills at 2.
+// Occupancy hints by precision, chosen on the compiler's output: complex128
+// fits 164 registers without spills with a hint of 4 (3 waves per SIMD; hints
+// of 2 and 3 made it spill to scratch); complex64 fits 248 without spills at 2
+// (a hint of 3 spilled 14 registers and ran the batched cycle 4 % slower).
 template <class T>
 constexpr int kBatchWavesHint = sizeof(T) == 8 ? 4 : 2;
 
