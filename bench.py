@@ -49,6 +49,16 @@ def fused_bytes(dim, L, variant, word=16):
     return word * (3 * NL + coarse_words * Nc)
 
 
+def single_touch_bytes(dim, L, lmin=1, word=16):
+    """Bytes per cycle of the method's own single-touch form (Section 5's
+    pipelined traversal with constant phi): 5 words per finest vertex (read u,
+    sc, b; write u, sc) and 14 per coarse vertex (pre, post and the finer
+    level's transfers of u, sc, si, sf, b)."""
+    NL = (3 ** L + 1) ** dim
+    Nc = sum((3 ** l + 1) ** dim for l in range(lmin, L))
+    return word * (5 * NL + 14 * Nc)
+
+
 FUSED_SOURCES = ["mg_fused_ops.h", "mg_fused.hip", "mg_internal.h", "mg_common.h"]
 
 
@@ -316,7 +326,8 @@ def main():
             "algorithmic_bytes_per_launch": fb,
             "avg_launch_us": sweep_ms * 1e3,
             "launches_timed": nsw,
-            "cycle_effective_GBs": None,
+            # the whole cycle priced at the method's single-touch byte count
+            "cycle_effective_GBs": single_touch_bytes(dim, L) / (ms_step * 1e-3) / 1e9,
         },
     }
 
