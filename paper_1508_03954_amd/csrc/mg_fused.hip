@@ -57,7 +57,8 @@ struct TileShape3 { int tyc, rpt, zc, order, pf; };
 constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0, 1},  {2, 2, 14, 0, 1}, {2, 2, 21, 0, 1}, {2, 2, 27, 0, 1},
                                   {2, 2, 28, 0, 1}, {4, 2, 14, 0, 1}, {4, 2, 21, 0, 1}, {4, 2, 28, 0, 1},
                                   {2, 1, 14, 0, 1}, {2, 1, 21, 0, 1}, {2, 2, 9, 1, 1},  {2, 2, 21, 1, 1},
-                                  {4, 2, 28, 0, 2}, {4, 2, 28, 0, 3}, {2, 2, 28, 0, 2}, {2, 2, 28, 0, 3}};
+                                  {4, 2, 28, 0, 2}, {4, 2, 28, 0, 3}, {2, 2, 28, 0, 2}, {2, 2, 28, 0, 3},
+                                  {4, 2, 28, 1, 3}, {2, 2, 28, 1, 3}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -133,6 +134,8 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
       case 12: launch3<T, 4, 2, 28, 2>(a, g, s); break;
       case 13: launch3<T, 4, 2, 28, 3>(a, g, s); break;
       case 14: launch3<T, 2, 2, 28, 2>(a, g, s); break;
+      case 15: launch3<T, 2, 2, 28, 3>(a, g, s); break;
+      case 16: launch3<T, 4, 2, 28, 3>(a, g, s); break;
       default: launch3<T, 2, 2, 28, 3>(a, g, s); break;
     }
   } else {
