@@ -583,7 +583,12 @@ struct Engine {
     const int it = 1;
     for (int l = L; l > lmin; --l) {
       const cpx<T>* src = l == L ? rhoL : lv[l].pr;
-      MG_HIP(launch_restrict<T>(dim, lv[l - 1].n, src, lv[l - 1].pr, s));
+      // the finest restriction moves most of the bytes: in 3D it takes the
+      // sweep's march (the seam array is free outside the fused sweep)
+      if (l == L && dim == 3 && spill && lv[L].n >= 10)
+        MG_HIP(launch_restrict3<T>(lv[l - 1].n, src, lv[l - 1].pr, spill, s));
+      else
+        MG_HIP(launch_restrict<T>(dim, lv[l - 1].n, src, lv[l - 1].pr, s));
     }
     for (int l = lmin; l <= L; ++l) {
       const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, it);

@@ -183,6 +183,44 @@ size_t fused_spill_count(int dim, int n) {
   return nc * nc * nc;
 }
 
+// rho_c = R x (3D) with the sweep's march and restriction (no operator): the
+// 4 x 2 x 28 tile with prefetch depth 3 in the XCD-chunked block order; the
+// seam rows go through the seam array and k_seam3.
+constexpr int kRTyc = 4, kRRpt = 2, kRZc = 28;
+template <class T>
+__global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_restrict3(FusedArgs<T> a) {
+  __shared__ F3Lds<T, kRTyc, kRRpt, false, true> sm;
+  int bx, by, bz;
+  fused3_block_tile(1, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
+  fused3_tile<T, kRTyc, kRRpt, kRZc, 1, kRestrict, 3>(a, bx, by, bz, nullptr, sm);
+}
+
+template <class T>
+hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s) {
+  const int n = 3 * (nc - 1) + 1;
+  if (n < 10 || spill == nullptr) return hipErrorInvalidValue;
+  FusedArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nc = nc;
+  a.b = x;
+  a.rhoc = rhoc;
+  a.spill = spill;
+  a.variant = 1;
+  a.order = 1;
+  const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
+  constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
+  hipLaunchKernelGGL(k_restrict3<T>, g, NT, 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nseam = f3_ytiles(nc, kRTyc) - 1;
+  if (nseam >= 1) hipLaunchKernelGGL(k_seam3<T>, dim3(nseam, nc), dim3(128), 0, s, rhoc, spill, nc, kRTyc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_restrict3<double>(int, const cpx<double>*, cpx<double>*, cpx<double>*, hipStream_t);
+template hipError_t launch_restrict3<float>(int, const cpx<float>*, cpx<float>*, cpx<float>*, hipStream_t);
+
 // y = H x or r = b - H x (constant phi, 3D) with the sweep's march: 2 x 2
 // coarse-row tiles, z extent 21, no coarse levels.
 template <class T, int MODE>

@@ -261,14 +261,16 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // coarse rows each (one per half wave).
 // MODE kSweep: the fused sweep.  kResid / kApply: the same march without the
 // coarse levels, storing r = b - H w (with its partial norms) or y = H w.
-constexpr int kSweep = 0, kResid = 1, kApply = 2;
+// kRestrict: the restriction R x of the vector in b alone (rho_c and the seam
+// rows), with the sweep's R and no operator.
+constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3;
 
 // PF: prefetch depth of w and b in planes (1, 2 or 3).  With PF > 1 each wave
 // keeps the loads of PF planes in flight (PF register sets used in turn): for
 // grids whose tiles leave few waves per CU, latency is hidden per wave.
 template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep, int PF = 1>
 __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
-                                   F3Lds<T, TYC, RPT, VAR == 2, MODE == kSweep>& sm) {
+                                   F3Lds<T, TYC, RPT, VAR == 2, MODE == kSweep || MODE == kRestrict>& sm) {
   constexpr bool BPX = VAR == 2;
   using G = F3<T, TYC, RPT, ZC, BPX>;
   constexpr int TXR = G::TXR, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
@@ -461,15 +463,17 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       if (GF == 2) load_g(std::integral_constant<int, 2>(), I0(), p0 + 2, k0ofs);
     }
   }
+  if (MODE != kRestrict) {
 #pragma unroll
-  for (int i = 0; i < PF; ++i) load_w(p0 + i, (long long)(p0 + i) * pstride, Wr[i], Wh[i]);
+    for (int i = 0; i < PF; ++i) load_w(p0 + i, (long long)(p0 + i) * pstride, Wr[i], Wh[i]);
+  }
   if (MODE != kApply) {
 #pragma unroll
     for (int i = 0; i < PF; ++i) load_b(p0 - 1 + i, (long long)(p0 - 1 + i) * pstride, Br[i]);
   }
 #pragma unroll
   for (int j = 0; j < RPT; ++j) { A[j] = f_zero<T>(); Np[j] = f_zero<T>(); Cp[j] = f_zero<T>(); }
-  if (MODE == kSweep) {
+  if (MODE == kSweep || MODE == kRestrict) {
     // the zero rows of RX (both slots); nothing writes them later
     constexpr int NZ = 2 * 5 * TXR;
     for (int i = tid; i < NZ; i += G::NT) {
@@ -483,12 +487,45 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   // at its start Wr[E] holds w of plane p, Br[E] b of plane p-1 (the other
   // PF - 1 sets have the loads of the next planes in flight), and the coarse
   // registers the values of plane p+1
+  // R of the residual r of plane q = p - 1 of step K: (5) x part at the owned
+  // coarse columns (the boundary columns need none): the wave's rows go to
+  // this wave's slot of the other UH buffer (free during this half step: it
+  // is refilled by this wave only, at the next step), and lane l reads row
+  // l / TXR around coarse column l % TXR; (6) y and z parts of plane q-1 = p-2
+  // (its x part is in slot S)
+  auto restrict_r = [&](auto K_, const cpx<T>* r, int kb, long long kofs) {
+    constexpr int K = decltype(K_)::value;
+    constexpr int S = K & 1;
+    cpx<T>* rr = &sm.UH[1 - S][wv][0][0][0];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) rr[64 * j + lane] = r[j];
+    if (xr_ok) {
+      const cpx<T>* row = rr + xr_at;
+      const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
+      const cpx<T> rx = f_add(row[0], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
+      sm.RX[1 - S][2 + wv * RPT + xr_j][xr_c] = rx;
+    }
+    constexpr int KR = K < 2 ? -1 : (K < 5 ? 0 : 1);   // floor((K - 2) / 3)
+    if (rwave) rest_yz(std::integral_constant<int, (K + 1) % 3>(), kb + KR, kofs + KR * cstride, S);
+  };
+
   auto step = [&](auto K_, int p, int kb) {
     constexpr int K = decltype(K_)::value;
     constexpr int S = K & 1, PT = K % 3;
     constexpr int E = K % PF;   // register set of w(p) and b(p-1)
     const int q = p - 1;
     const long long pofs = (long long)p * pstride, kofs = (long long)kb * cstride;
+    if (MODE == kRestrict) {
+      // the input of plane q is in Br[E]; the barrier orders the LDS slots
+      __syncthreads();
+      cpx<T> r[RPT];
+#pragma unroll
+      for (int j = 0; j < RPT; ++j)
+        r[j] = f_sel(plane_ok(q) && row_ok(ybase + j) && xin && xcomp, Br[E][j], f_zero<T>());
+      load_b(p + PF - 1, pofs + (PF - 1) * pstride, Br[E]);
+      restrict_r(K_, r, kb, kofs);
+      return;
+    }
     cpx<T> u[RPT], h[RPT], uh = f_zero<T>(), hh = f_zero<T>();
     // (1) u and h on plane p
 #pragma unroll
@@ -584,22 +621,8 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     if (swave)
       load_g(std::integral_constant<int, (K + 1 + GF) % 3>(), std::integral_constant<int, (K + 1) % GF>(), p + 1 + GF,
              kofs + ((K + 1 + GF) / 3) * cstride);
-    // (5) x part of R at the owned coarse columns (the boundary columns need
-    // none): the wave's rows go to this wave's slot of the other UH buffer
-    // (free during this half step: it is refilled by this wave only, at the
-    // next step), and lane l reads row l / TXR around coarse column l % TXR
-    cpx<T>* rr = &sm.UH[1 - S][wv][0][0][0];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) rr[64 * j + lane] = r[j];
-    if (xr_ok) {
-      const cpx<T>* row = rr + xr_at;
-      const cpx<T> s1 = f_add(row[-1], row[1]), s2 = f_add(row[-2], row[2]);
-      const cpx<T> rx = f_add(row[0], f_add(f_scale(T(2.0 / 3.0), s1), f_scale(T(1.0 / 3.0), s2)));
-      sm.RX[1 - S][2 + wv * RPT + xr_j][xr_c] = rx;
-    }
-    // (6) y and z parts of R for plane q-1 = p-2 (its x part is in slot S)
-    constexpr int KR = K < 2 ? -1 : (K < 5 ? 0 : 1);   // floor((K - 2) / 3)
-    if (rwave) rest_yz(std::integral_constant<int, (K + 1) % 3>(), kb + KR, kofs + KR * cstride, S);
+    // (5), (6) the parts of R
+    restrict_r(K_, r, kb, kofs);
   };
   // six steps per iteration, so that plane phases, slots and register roles
   // are constants; the slot left holding the x part of R of plane plast-1
@@ -621,7 +644,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     if (p > plast) { last = 0; break; }
   }
   // R of the last plane plast - 1 = 3 (mz1 - 1) + 2
-  if (MODE == kSweep) {
+  if (MODE == kSweep || MODE == kRestrict) {
     __syncthreads();
     if (rwave) rest_yz(std::integral_constant<int, 2>(), mz1 - 1, (long long)(mz1 - 1) * cstride, last);
   }

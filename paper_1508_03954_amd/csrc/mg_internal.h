@@ -214,6 +214,10 @@ template <class T>
 hipError_t launch_stencil3(int apply, int n, const cpx<T>* coef, const cpx<T>* b, const cpx<T>* x, cpx<T>* out,
                            double* partials, int* nparts, hipStream_t s);
 int fused_partials_blocks(int dim, int n, int tile);  // -1 if unsupported
+// rho_c = R x in 3D (nc coarse vertices per axis, 3 (nc - 1) + 1 >= 10 fine)
+// with the sweep's march; spill: fused_spill_count(3, n) entries of scratch.
+template <class T>
+hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s);
 // Tile variant with the given shape (3D: coarse rows, rows per thread, coarse
 // planes; 2D: coarse rows zc only), or -1.
 int fused_tile_index(int dim, int tyc, int rpt, int zc);
