@@ -162,6 +162,13 @@ int mg_get_level(mg_ctx* ctx, int level, int field, mg_c128* out);
  * the variant's corrections; no operator application survives u = 0). */
 int mg_precondition(mg_ctx* ctx, const mg_c128* v, mg_c128* z);
 
+/* z = B v and y = H z in one call: the step of the Krylov driver.  In 3D with
+ * constant phi the finest level of B and the operator run as one pass over
+ * the finest grid (read v, write z and y).  v, z, y: device buffers of the
+ * finest size, not aliased; boundary entries of v are ignored, z and y get
+ * zero boundaries.  Complex128 contexts only (MG_EINVAL otherwise). */
+int mg_precondition_apply(mg_ctx* ctx, const mg_c128* v, mg_c128* z, mg_c128* y);
+
 /* Solves H u = b to relative residual rtol (|b - H u| / |b|, Euclidean over
  * interior vertices).  u holds the initial guess on entry and the result on
  * exit.  driver: MG_STATIONARY (cycles, then flush) or MG_BICGSTAB.  With

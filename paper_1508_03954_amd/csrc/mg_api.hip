@@ -199,6 +199,14 @@ int mg_precondition(mg_ctx* c, const mg_c128* v, mg_c128* z) {
   return MG_OK;
 }
 
+int mg_precondition_apply(mg_ctx* c, const mg_c128* v, mg_c128* z, mg_c128* y) {
+  if (!c || !v || !z || !y) return fail(MG_EINVAL, "NULL argument");
+  if ((const void*)v == (const void*)z || (const void*)v == (const void*)y || (const void*)z == (const void*)y)
+    return fail(MG_EINVAL, "v, z and y must not alias");
+  if (c->p.precision != MG_FP64) return fail(MG_EINVAL, "mg_precondition_apply: complex128 contexts only");
+  return c->e64->precondition_apply_any((const cpx<double>*)v, (cpx<double>*)z, (cpx<double>*)y);
+}
+
 int mg_residual_norm(mg_ctx* c, const mg_c128* u, const mg_c128* b, double* res_h) {
   if (!c || !u || !b || !res_h) return fail(MG_EINVAL, "NULL argument");
   return c->e64->resid_norm((const cpx<double>*)u, (const cpx<double>*)b, res_h, nullptr);

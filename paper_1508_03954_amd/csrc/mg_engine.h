@@ -573,13 +573,10 @@ struct Engine {
 
   // z = B v (zero-start cycle); v, z finest-size T buffers.  v's boundary is
   // ignored, unless `clean` promises it is zero already (then v is read in place).
-  int precondition(const cpx<T>* v, cpx<T>* z, bool clean = false) {
-    const cpx<T>* rhoL = v;
-    if (!clean) {
-      MG_TRY(ensure_scratch());
-      MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, v, tR, mk(T(1), T(0)), s));
-      rhoL = tR;
-    }
+  // Zero-start cycle below the finest level: the restriction chain of rhoL
+  // and the coarse levels l_min .. L-1; *gc receives the coarse correction
+  // the finest level prolongs (z_(L-1), or z_(L-1) - I s_L for BPX).
+  int precondition_coarse(const cpx<T>* rhoL, const cpx<T>** gc) {
     const int it = 1;
     for (int l = L; l > lmin; --l) {
       const cpx<T>* src = l == L ? rhoL : lv[l].pr;
@@ -590,22 +587,64 @@ struct Engine {
       else
         MG_HIP(launch_restrict<T>(dim, lv[l - 1].n, src, lv[l - 1].pr, s));
     }
+    *gc = nullptr;
     for (int l = lmin; l <= L; ++l) {
       const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, it);
       const cpx<T>* rho = l == L ? rhoL : lv[l].pr;
-      cpx<T>* out = l == L ? z : lv[l].pz;
-      const cpx<T>* gc = nullptr;
+      const cpx<T>* g = nullptr;
       if (l > lmin) {
-        gc = lv[l - 1].pz;
+        g = lv[l - 1].pz;
         if (variant == MG_BPX) {
           // rho_(l-1) (in pr) has been used by now: it holds g
           MG_HIP(launch_prec_g<T>(dim, lv[l].op, rho, to_c<T>(wl), lv[l - 1].pz, lv[l - 1].pr, s));
-          gc = lv[l - 1].pr;
+          g = lv[l - 1].pr;
         }
       }
-      MG_HIP(launch_prec_up<T>(dim, lv[l].op, rho, to_c<T>(wl), variant == MG_HB ? 1 : 0, l == lmin ? 1 : 0, gc, out,
-                               s));
+      if (l == L) {
+        *gc = g;
+        break;
+      }
+      MG_HIP(launch_prec_up<T>(dim, lv[l].op, rho, to_c<T>(wl), variant == MG_HB ? 1 : 0, l == lmin ? 1 : 0, g,
+                               lv[l].pz, s));
     }
+    return MG_OK;
+  }
+
+  int precondition(const cpx<T>* v, cpx<T>* z, bool clean = false) {
+    const cpx<T>* rhoL = v;
+    if (!clean) {
+      MG_TRY(ensure_scratch());
+      MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, v, tR, mk(T(1), T(0)), s));
+      rhoL = tR;
+    }
+    const cpx<T>* gc = nullptr;
+    MG_TRY(precondition_coarse(rhoL, &gc));
+    const complex<double> wL = omega_level(scheme, omega, omega_L, 0, 1);
+    MG_HIP(launch_prec_up<T>(dim, lv[L].op, rhoL, to_c<T>(wL), variant == MG_HB ? 1 : 0, L == lmin ? 1 : 0, gc, z, s));
+    return MG_OK;
+  }
+
+  // As precondition_apply for a v whose boundary entries may be nonzero.
+  int precondition_apply_any(const cpx<T>* v, cpx<T>* z, cpx<T>* y) {
+    MG_TRY(ensure_scratch());
+    MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, v, tR, mk(T(1), T(0)), s));
+    return precondition_apply(tR, z, y);
+  }
+
+  // z = M^-1 v (v with zero boundary) and y = H z.  In 3D with constant phi
+  // the finest level of M^-1 and the operator run as one march.
+  int precondition_apply(const cpx<T>* v, cpx<T>* z, cpx<T>* y) {
+    if (dim != 3 || varying || L == lmin || lv[L].n < 10 || !spill) {
+      MG_TRY(precondition(v, z, true));
+      MG_HIP(launch_apply<T>(dim, lv[L].op, z, y, s));
+      return MG_OK;
+    }
+    const cpx<T>* gc = nullptr;
+    MG_TRY(precondition_coarse(v, &gc));
+    const complex<double> wL = omega_level(scheme, omega, omega_L, 0, 1);
+    const Level<T>& f = lv[L];
+    const cpx<T> ws = to_c<T>(wL * complex<double>(f.op.invD.re, f.op.invD.im));
+    MG_HIP(launch_prec_apply3<T>(f.n, f.op.coef, ws, variant == MG_HB ? 1 : 0, v, gc, z, y, s));
     return MG_OK;
   }
 
@@ -675,8 +714,7 @@ struct Engine {
     for (it = 1; it <= maxit && status == MG_ENOTCONV; ++it) {
       const complex<double> beta = (rho_new / rho) * (alpha / om);
       MG_HIP(launch_bicg_p<T>(N, r, v, to_c<double>(beta), to_c<double>(om), p, s));
-      MG_TRY(precondition(p, y, true));
-      MG_HIP(launch_apply<T>(dim, op, y, v, s));
+      MG_TRY(precondition_apply(p, y, v));
       complex<double> rhv;
       MG_TRY(dot(rh, v, &rhv));
       alpha = rho_new / rhv;
@@ -690,8 +728,7 @@ struct Engine {
         status = MG_OK;
         break;
       }
-      MG_TRY(precondition(sv, z, true));
-      MG_HIP(launch_apply<T>(dim, op, z, t, s));
+      MG_TRY(precondition_apply(sv, z, t));
       MG_HIP(launch_bicg_ts<T>(N, t, sv, partials, s));
       MG_TRY(finish(3, h));
       om = complex<double>(h[0], h[1]) / h[2];

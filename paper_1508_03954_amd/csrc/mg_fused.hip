@@ -218,6 +218,42 @@ hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill
   return hipGetLastError();
 }
 
+template <class T, int VAR>
+__global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_prec_apply3(FusedArgs<T> a) {
+  __shared__ F3Lds<T, kRTyc, kRRpt, false, true> sm;
+  int bx, by, bz;
+  fused3_block_tile(1, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
+  fused3_tile<T, kRTyc, kRRpt, kRZc, VAR, kPrecApply, 3>(a, bx, by, bz, nullptr, sm);
+}
+
+template <class T>
+hipError_t launch_prec_apply3(int n, const cpx<T>* coef, cpx<T> ws, int mask_c, const cpx<T>* x, const cpx<T>* gc,
+                              cpx<T>* z, cpx<T>* y, hipStream_t s) {
+  if (n < 10 || (n - 1) % 3 != 0) return hipErrorInvalidValue;
+  const int nc = (n - 1) / 3 + 1;
+  FusedArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nc = nc;
+  a.w = x;
+  a.scc = gc;
+  a.wout = y;
+  a.zout = z;
+  for (int q = 0; q < 4; ++q) a.coef[q] = coef[q];
+  a.ws = ws;
+  a.variant = mask_c ? 1 : 0;
+  a.order = 1;
+  const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
+  constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
+  if (mask_c) hipLaunchKernelGGL((k_prec_apply3<T, 1>), g, NT, 0, s, a);
+  else hipLaunchKernelGGL((k_prec_apply3<T, 0>), g, NT, 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_prec_apply3<double>(int, const cpx<double>*, cpx<double>, int, const cpx<double>*,
+                                               const cpx<double>*, cpx<double>*, cpx<double>*, hipStream_t);
+template hipError_t launch_prec_apply3<float>(int, const cpx<float>*, cpx<float>, int, const cpx<float>*,
+                                              const cpx<float>*, cpx<float>*, cpx<float>*, hipStream_t);
 template hipError_t launch_restrict3<double>(int, const cpx<double>*, cpx<double>*, cpx<double>*, hipStream_t);
 template hipError_t launch_restrict3<float>(int, const cpx<float>*, cpx<float>*, cpx<float>*, hipStream_t);
 

@@ -262,15 +262,19 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // MODE kSweep: the fused sweep.  kResid / kApply: the same march without the
 // coarse levels, storing r = b - H w (with its partial norms) or y = H w.
 // kRestrict: the restriction R x of the vector in b alone (rho_c and the seam
-// rows), with the sweep's R and no operator.
-constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3;
+// rows), with the sweep's R and no operator.  kPrecApply: the finest level of
+// the zero-start cycle and the operator on its result in one pass: from x in
+// w and the coarse correction g in scc, z = s + P g with s = ws x (zero on
+// c-points for VAR 1), stored to zout, and y = H z, stored to wout.
+constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3, kPrecApply = 4;
+constexpr bool f3_full_lds(int mode) { return mode == kSweep || mode == kRestrict || mode == kPrecApply; }
 
 // PF: prefetch depth of w and b in planes (1, 2 or 3).  With PF > 1 each wave
 // keeps the loads of PF planes in flight (PF register sets used in turn): for
 // grids whose tiles leave few waves per CU, latency is hidden per wave.
 template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep, int PF = 1>
 __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
-                                   F3Lds<T, TYC, RPT, VAR == 2, MODE == kSweep || MODE == kRestrict>& sm) {
+                                   F3Lds<T, TYC, RPT, VAR == 2, f3_full_lds(MODE)>& sm) {
   constexpr bool BPX = VAR == 2;
   using G = F3<T, TYC, RPT, ZC, BPX>;
   constexpr int TXR = G::TXR, TY = G::TY, W = G::W, GX = G::GX, GY = G::GY;
@@ -408,11 +412,16 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       if (BPX) sm.Sz[slot][sr][sx] = gsc0[G];   // used on c-points only (TZ == 0)
     }
   };
-  // u = w + P g on plane p (p mod 3 = PT) at row y (zero off the interior)
+  // u = w + P g on plane p (p mod 3 = PT) at row y (zero off the interior);
+  // kPrecApply: u = s + P g with s = ws w, masked on c-points for VAR 1
   auto form_u = [&](auto PT_, int p, int slot, int y, cpx<T> w) {
     constexpr int PT = decltype(PT_)::value;
-    if (MODE != kSweep) return w;   // loads already vanish off the interior
+    if (MODE != kSweep && MODE != kPrecApply) return w;   // loads already vanish off the interior
     const int my = floor_div3(y), qy = y - 3 * my, gy = min(max(my - my0 + 1, 0), GY - 1);
+    if (MODE == kPrecApply) {
+      const cpx<T> sv = f_mul(ws, w);
+      w = VAR == 1 && PT == 0 ? f_sel(qy == 0 && ccol, f_zero<T>(), sv) : sv;
+    }
     cpx<T> g = f_add(f_scale(wx0, sm.Gz[slot][gy][gxl]), f_scale(wx1, sm.Gz[slot][gy][gxl1]));
     if (qy != 0) {
       const int gy1 = min(gy + 1, GY - 1);
@@ -452,7 +461,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
   };
 
-  if (MODE == kSweep) {
+  if (MODE == kSweep || MODE == kPrecApply) {
     const long long k0ofs = (long long)(mz0 - 1) * cstride;
     if (swave) {
       using I0 = std::integral_constant<int, 0>;
@@ -467,7 +476,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
 #pragma unroll
     for (int i = 0; i < PF; ++i) load_w(p0 + i, (long long)(p0 + i) * pstride, Wr[i], Wh[i]);
   }
-  if (MODE != kApply) {
+  if (MODE != kApply && MODE != kPrecApply) {
 #pragma unroll
     for (int i = 0; i < PF; ++i) load_b(p0 - 1 + i, (long long)(p0 - 1 + i) * pstride, Br[i]);
   }
@@ -538,6 +547,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       hh = hsum(uh);
     }
     constexpr int LE = RPT == 1 ? 0 : 1;   // slot of the last row (the first row when RPT == 1)
+    if (MODE == kPrecApply) {
+      const auto zo = frs(a.zout, pofs, p >= zown_lo && p <= zown_hi);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) bstore(u[j], zo, vst[j]);
+    }
     sm.UH[S][wv][0][0][lane] = u[0];
     sm.UH[S][wv][0][1][lane] = h[0];
     if (LE) {
@@ -546,7 +560,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
     // (2) refill w with plane p+PF; stage plane p+1's correction
     load_w(p + PF, pofs + PF * pstride, Wr[E], Wh[E]);
-    if (MODE == kSweep && swave)
+    if ((MODE == kSweep || MODE == kPrecApply) && swave)
       store_g(std::integral_constant<int, (K + 1) % 3>(), std::integral_constant<int, (K + 1) % GF>(), 1 - S);
     __syncthreads();
     // (3) neighbour rows across the wave edges
@@ -585,7 +599,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const cpx<T> M = f_mac(f_mac(f_mul(c0, C), c1, F2), c2, E2);
       const cpx<T> N = f_mac(f_mac(f_mul(c1, C), c2, F2), c3, E2);
       const bool in = plane_ok(q) && row_ok(y) && xin && xcomp;
-      if (MODE == kApply) {
+      if (MODE == kApply || MODE == kPrecApply) {
         bstore(f_sel(in, f_add(A[j], N), f_zero<T>()), wo, vst[j]);
         A[j] = f_add(M, Np[j]);
         Np[j] = N;
@@ -611,6 +625,12 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       Cp[j] = C;
     }
     if (MODE == kApply) return;
+    if (MODE == kPrecApply) {
+      if (swave)
+        load_g(std::integral_constant<int, (K + 1 + GF) % 3>(), std::integral_constant<int, (K + 1) % GF>(), p + 1 + GF,
+               kofs + ((K + 1 + GF) / 3) * cstride);
+      return;
+    }
     if (q_own) {
       nsum += s2;
       nmax = m2 > nmax ? m2 : nmax;

@@ -191,6 +191,7 @@ struct FusedArgs {
   cpx<T>* sfc;          // coarse sf <- I sc (ADD) or nullptr
   cpx<T>* sic_out;      // coarse si <- I s (BPX) or nullptr
   cpx<T>* spill;        // 3D: seam rows of R (fused_spill_count(3, n) entries), added by launch_fused_seam
+  cpx<T>* zout;         // preconditioner-apply march: z (its wout receives H z)
   cpx<T> coef[4];
   cpx<T> ws;            // omega * (1 / D)
   double* partials;     // per-block (sum |r|^2, max |r|) or nullptr
@@ -218,6 +219,11 @@ int fused_partials_blocks(int dim, int n, int tile);  // -1 if unsupported
 // with the sweep's march; spill: fused_spill_count(3, n) entries of scratch.
 template <class T>
 hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s);
+// Finest level of the zero-start cycle and the operator in one 3D pass (n >= 10):
+// z = s + P g with s = ws x (zero on c-points if mask_c), y = H z (constant phi).
+template <class T>
+hipError_t launch_prec_apply3(int n, const cpx<T>* coef, cpx<T> ws, int mask_c, const cpx<T>* x, const cpx<T>* gc,
+                              cpx<T>* z, cpx<T>* y, hipStream_t s);
 // Tile variant with the given shape (3D: coarse rows, rows per thread, coarse
 // planes; 2D: coarse rows zc only), or -1.
 int fused_tile_index(int dim, int tyc, int rpt, int zc);

@@ -28,7 +28,7 @@ FIELDS = {"u": 0, "b": 1, "sc": 2, "sf": 3, "si": 4}
 EXPORTED = [
     "mg_params_default", "mg_setup", "mg_destroy", "mg_last_error", "mg_level_size", "mg_apply",
     "mg_rhs_from_nodal", "mg_set_rhs", "mg_set_solution", "mg_cycle", "mg_flush", "mg_get_level",
-    "mg_precondition", "mg_solve", "mg_residual_norm", "mg_grad_potential", "mg_time_sweeps",
+    "mg_precondition", "mg_precondition_apply", "mg_solve", "mg_residual_norm", "mg_grad_potential", "mg_time_sweeps",
     "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
     "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
     "mg_batch_trace", "mg_batch_get_trace",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_flush.argtypes = [P, P]
     lib.mg_get_level.argtypes = [P, I, I, P]
     lib.mg_precondition.argtypes = [P, P, P]
+    lib.mg_precondition_apply.argtypes = [P, P, P, P]
     lib.mg_solve.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.mg_residual_norm.argtypes = [P, P, P, ctypes.POINTER(D)]
     lib.mg_grad_potential.argtypes = [P, P, P, P]
@@ -258,6 +259,14 @@ class Solver:
         z = self._new()
         _check(self._lib.mg_precondition(self._ctx, _ptr(v), _ptr(z)))
         return z
+
+    def precondition_apply(self, v):
+        """(z, y) with z = B v and y = H z (the Krylov driver's fused step)."""
+        v = self._as_dev(v)
+        z = self._new()
+        y = self._new()
+        _check(self._lib.mg_precondition_apply(self._ctx, _ptr(v), _ptr(z), _ptr(y)))
+        return z, y
 
     def solve(self, b, u0=None, rtol: float = 1e-10, maxit: int = 500, driver: str = "bicgstab"):
         """Returns (u, iterations, relative residual, status code)."""

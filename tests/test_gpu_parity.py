@@ -226,6 +226,22 @@ def test_precondition_matches_zero_start_cycle(dim, L, variant, phi_case):
     assert relerr(z, ref) <= TOL
 
 
+@pytest.mark.parametrize("dim,L,variant", [(3, 3, "bpx"), (3, 3, "hb"), (3, 4, "add"), (3, 4, "bpx"), (2, 4, "hb")])
+def test_precondition_apply_matches_oracle(dim, L, variant):
+    """The Krylov step z = B v, y = H z: in 3D one pass over the finest grid
+    (L = 4 spans several x, y and z tiles of the march; L = 3 a single one)."""
+    print(f"\n[case] precondition_apply dim={dim} L={L} {variant}", flush=True)
+    mg = mgmod()
+    theta, phi = 0.3, 200.0 * (1 + 0.5j)
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi, variant=variant, omega_scheme="exp", omega=0.7)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant=variant, omega_scheme="exp", omega=0.7)
+    v = rand_c((3 ** L + 1,) * dim, 19, zero_bnd=False)
+    z, y = s.precondition_apply(v)
+    zref = O.zero_start_cycle(p, O.zero_boundary(v))
+    assert relerr(to_np(z), zref) <= TOL
+    assert relerr(to_np(y), O.apply_H(zref, L, theta, phi)) <= TOL
+
+
 @pytest.mark.parametrize("dim,L", [(2, 3), (3, 2)])
 def test_bicgstab_reaches_dense_solution(dim, L):
     mg = mgmod()
