@@ -632,19 +632,36 @@ struct Engine {
   }
 
   // z = M^-1 v (v with zero boundary) and y = H z.  In 3D with constant phi
-  // the finest level of M^-1 and the operator run as one march.
-  int precondition_apply(const cpx<T>* v, cpx<T>* z, cpx<T>* y) {
+  // the finest level of M^-1 and the operator run as one march.  dot 1 also
+  // returns h[0..1] = conj(v2) y, dot 2 h[0..2] = conj(y) v2 and |y|^2 (both
+  // synchronise; in the march they are summed on the fly).
+  int precondition_apply(const cpx<T>* v, cpx<T>* z, cpx<T>* y, int dot = 0, const cpx<T>* v2 = nullptr,
+                         double* h = nullptr) {
     if (dim != 3 || varying || L == lmin || lv[L].n < 10 || !spill) {
       MG_TRY(precondition(v, z, true));
       MG_HIP(launch_apply<T>(dim, lv[L].op, z, y, s));
-      return MG_OK;
+      if (dot == 1) {
+        MG_HIP(launch_dot<T>(NL(), v2, y, partials, s));
+        MG_HIP(launch_finish_sum2(partials, kRedBlocks, red, s));
+      } else if (dot == 2) {
+        MG_HIP(launch_bicg_ts<T>(NL(), y, v2, partials, s));
+        MG_HIP(launch_finishN(3, partials, kRedBlocks, red, s));
+      }
+    } else {
+      const cpx<T>* gc = nullptr;
+      MG_TRY(precondition_coarse(v, &gc));
+      const complex<double> wL = omega_level(scheme, omega, omega_L, 0, 1);
+      const Level<T>& f = lv[L];
+      const cpx<T> ws = to_c<T>(wL * complex<double>(f.op.invD.re, f.op.invD.im));
+      MG_HIP(launch_prec_apply3<T>(f.n, f.op.coef, ws, variant == MG_HB ? 1 : 0, v, gc, z, y, dot, v2, partials, s));
+      const int nb = prec_apply3_blocks(f.n);
+      if (dot == 1) MG_HIP(launch_finish_sum2(partials, nb, red, s));
+      else if (dot == 2) MG_HIP(launch_finishN(3, partials, nb, red, s));
     }
-    const cpx<T>* gc = nullptr;
-    MG_TRY(precondition_coarse(v, &gc));
-    const complex<double> wL = omega_level(scheme, omega, omega_L, 0, 1);
-    const Level<T>& f = lv[L];
-    const cpx<T> ws = to_c<T>(wL * complex<double>(f.op.invD.re, f.op.invD.im));
-    MG_HIP(launch_prec_apply3<T>(f.n, f.op.coef, ws, variant == MG_HB ? 1 : 0, v, gc, z, y, s));
+    if (dot) {
+      MG_HIP(hipMemcpyAsync(h, red, (dot == 1 ? 2 : 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipStreamSynchronize(s));
+    }
     return MG_OK;
   }
 
@@ -714,10 +731,9 @@ struct Engine {
     for (it = 1; it <= maxit && status == MG_ENOTCONV; ++it) {
       const complex<double> beta = (rho_new / rho) * (alpha / om);
       MG_HIP(launch_bicg_p<T>(N, r, v, to_c<double>(beta), to_c<double>(om), p, s));
-      MG_TRY(precondition_apply(p, y, v));
-      complex<double> rhv;
-      MG_TRY(dot(rh, v, &rhv));
-      alpha = rho_new / rhv;
+      // y = M^-1 p, v = H y and (rh, v)
+      MG_TRY(precondition_apply(p, y, v, 1, rh, h));
+      alpha = rho_new / complex<double>(h[0], h[1]);
       // s = r - alpha v and |s|
       MG_HIP(launch_bicg_s<T>(N, r, v, to_c<double>(alpha), sv, partials, s));
       MG_TRY(finish(1, h));
@@ -728,9 +744,8 @@ struct Engine {
         status = MG_OK;
         break;
       }
-      MG_TRY(precondition_apply(sv, z, t));
-      MG_HIP(launch_bicg_ts<T>(N, t, sv, partials, s));
-      MG_TRY(finish(3, h));
+      // z = M^-1 s, t = H z, (t, s) and |t|^2
+      MG_TRY(precondition_apply(sv, z, t, 2, sv, h));
       om = complex<double>(h[0], h[1]) / h[2];
       // x += alpha y + om z; r = s - om t; |r| and (rh, r) for the next step
       MG_HIP(launch_bicg_xr2<T>(N, x, y, z, to_c<double>(alpha), to_c<double>(om), r, sv, t, rh, partials, s));

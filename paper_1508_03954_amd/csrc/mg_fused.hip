@@ -218,18 +218,36 @@ hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill
   return hipGetLastError();
 }
 
-template <class T, int VAR>
+template <class T, int VAR, int DOT>
 __global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_prec_apply3(FusedArgs<T> a) {
   __shared__ F3Lds<T, kRTyc, kRRpt, false, true> sm;
   int bx, by, bz;
   fused3_block_tile(1, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
-  fused3_tile<T, kRTyc, kRRpt, kRZc, VAR, kPrecApply, 3>(a, bx, by, bz, nullptr, sm);
+  // dot partials are indexed by tile, so their summation order does not depend on the block order
+  constexpr int ND = DOT == 1 ? 2 : 3;
+  double* part = DOT ? a.partials + ND * (bx + gridDim.x * (by + gridDim.y * bz)) : nullptr;
+  fused3_tile<T, kRTyc, kRRpt, kRZc, VAR, kPrecApply, 3, DOT>(a, bx, by, bz, part, sm);
+}
+
+int prec_apply3_blocks(int n) {
+  if (n < 10 || (n - 1) % 3 != 0) return -1;
+  const int nc = (n - 1) / 3 + 1;
+  return f3_xtiles(nc) * f3_ytiles(nc, kRTyc) * ((nc + kRZc - 1) / kRZc);
+}
+
+template <class T, int VAR>
+static void launch_pa3(int dot, dim3 g, const FusedArgs<T>& a, hipStream_t s) {
+  constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
+  if (dot == 1) hipLaunchKernelGGL((k_prec_apply3<T, VAR, 1>), g, NT, 0, s, a);
+  else if (dot == 2) hipLaunchKernelGGL((k_prec_apply3<T, VAR, 2>), g, NT, 0, s, a);
+  else hipLaunchKernelGGL((k_prec_apply3<T, VAR, 0>), g, NT, 0, s, a);
 }
 
 template <class T>
 hipError_t launch_prec_apply3(int n, const cpx<T>* coef, cpx<T> ws, int mask_c, const cpx<T>* x, const cpx<T>* gc,
-                              cpx<T>* z, cpx<T>* y, hipStream_t s) {
-  if (n < 10 || (n - 1) % 3 != 0) return hipErrorInvalidValue;
+                              cpx<T>* z, cpx<T>* y, int dot, const cpx<T>* v2, double* partials, hipStream_t s) {
+  if (n < 10 || (n - 1) % 3 != 0 || dot < 0 || dot > 2) return hipErrorInvalidValue;
+  if (dot && (v2 == nullptr || partials == nullptr)) return hipErrorInvalidValue;
   const int nc = (n - 1) / 3 + 1;
   FusedArgs<T> a;
   memset(&a, 0, sizeof(a));
@@ -239,21 +257,24 @@ hipError_t launch_prec_apply3(int n, const cpx<T>* coef, cpx<T> ws, int mask_c, 
   a.scc = gc;
   a.wout = y;
   a.zout = z;
+  a.b = v2;
+  a.partials = partials;
   for (int q = 0; q < 4; ++q) a.coef[q] = coef[q];
   a.ws = ws;
   a.variant = mask_c ? 1 : 0;
   a.order = 1;
   const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
-  constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
-  if (mask_c) hipLaunchKernelGGL((k_prec_apply3<T, 1>), g, NT, 0, s, a);
-  else hipLaunchKernelGGL((k_prec_apply3<T, 0>), g, NT, 0, s, a);
+  if (mask_c) launch_pa3<T, 1>(dot, g, a, s);
+  else launch_pa3<T, 0>(dot, g, a, s);
   return hipGetLastError();
 }
 
 template hipError_t launch_prec_apply3<double>(int, const cpx<double>*, cpx<double>, int, const cpx<double>*,
-                                               const cpx<double>*, cpx<double>*, cpx<double>*, hipStream_t);
+                                               const cpx<double>*, cpx<double>*, cpx<double>*, int,
+                                               const cpx<double>*, double*, hipStream_t);
 template hipError_t launch_prec_apply3<float>(int, const cpx<float>*, cpx<float>, int, const cpx<float>*,
-                                              const cpx<float>*, cpx<float>*, cpx<float>*, hipStream_t);
+                                              const cpx<float>*, cpx<float>*, cpx<float>*, int, const cpx<float>*,
+                                              double*, hipStream_t);
 template hipError_t launch_restrict3<double>(int, const cpx<double>*, cpx<double>*, cpx<double>*, hipStream_t);
 template hipError_t launch_restrict3<float>(int, const cpx<float>*, cpx<float>*, cpx<float>*, hipStream_t);
 

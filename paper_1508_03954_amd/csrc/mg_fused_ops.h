@@ -111,6 +111,28 @@ __device__ inline void block_reduce_store(double s, double m, double* part, int 
   __syncthreads();
 }
 
+// N sums over the block, in a fixed order (wave shuffles, then waves in order).
+template <int N>
+__device__ inline void block_reduce_sums(double (&v)[N], double* part, int nt) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  __shared__ double ss[N][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) ss[k][wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = 0;
+      for (int w = 0; w < (nt + 63) / 64; ++w) a += ss[k][w];
+      part[k] = a;
+    }
+  __syncthreads();
+}
+
 // Wavefront-local ordering of LDS traffic (the 2D sweep runs one tile per wave).
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -265,14 +287,17 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // rows), with the sweep's R and no operator.  kPrecApply: the finest level of
 // the zero-start cycle and the operator on its result in one pass: from x in
 // w and the coarse correction g in scc, z = s + P g with s = ws x (zero on
-// c-points for VAR 1), stored to zout, and y = H z, stored to wout.
+// c-points for VAR 1), stored to zout, and y = H z, stored to wout; with DOT
+// it also sums, over the owned vertices, conj(v2) y (DOT 1, 2 values) or
+// conj(y) v2 and |y|^2 (DOT 2, 3 values) for the vector v2 in b, into the
+// tile's slot of part.
 constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3, kPrecApply = 4;
 constexpr bool f3_full_lds(int mode) { return mode == kSweep || mode == kRestrict || mode == kPrecApply; }
 
 // PF: prefetch depth of w and b in planes (1, 2 or 3).  With PF > 1 each wave
 // keeps the loads of PF planes in flight (PF register sets used in turn): for
 // grids whose tiles leave few waves per CU, latency is hidden per wave.
-template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep, int PF = 1>
+template <class T, int TYC, int RPT, int ZC, int VAR, int MODE = kSweep, int PF = 1, int DOT = 0>
 __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz, double* part,
                                    F3Lds<T, TYC, RPT, VAR == 2, f3_full_lds(MODE)>& sm) {
   constexpr bool BPX = VAR == 2;
@@ -373,6 +398,16 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   cpx<T> gsc0[GF], gsc1[GF], gsi0[GF], gsi1[GF];
   cpx<T> acc0 = f_zero<T>(), acc1 = f_zero<T>();
   double nsum = 0.0, nmax = 0.0;
+  // dots of the preconditioner-apply march: v2 of plane P is loaded at step P
+  // (register set = parity of P relative to p0) and used one step later
+  static_assert(DOT == 0 || MODE == kPrecApply, "dots only in the preconditioner-apply march");
+  constexpr int ND = DOT == 0 ? 1 : (DOT == 1 ? 2 : 3);
+  double dacc[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) dacc[k] = 0.0;
+  cpx<T> Dv[2][RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) Dv[0][j] = Dv[1][j] = f_zero<T>();
 
   // The march runs over fine planes p = p0 .. plast with p0 = 3 (mz0 - 1), so
   // p mod 3 is known from the step's position in a group of six (which also
@@ -560,6 +595,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     }
     // (2) refill w with plane p+PF; stage plane p+1's correction
     load_w(p + PF, pofs + PF * pstride, Wr[E], Wh[E]);
+    if (DOT != 0) {
+      const auto rd = frs(a.b, pofs, p >= zown_lo && p <= zown_hi);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) Dv[K & 1][j] = bload(tagT, rd, vst[j]);
+    }
     if ((MODE == kSweep || MODE == kPrecApply) && swave)
       store_g(std::integral_constant<int, (K + 1) % 3>(), std::integral_constant<int, (K + 1) % GF>(), 1 - S);
     __syncthreads();
@@ -600,7 +640,20 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const cpx<T> N = f_mac(f_mac(f_mul(c1, C), c2, F2), c3, E2);
       const bool in = plane_ok(q) && row_ok(y) && xin && xcomp;
       if (MODE == kApply || MODE == kPrecApply) {
-        bstore(f_sel(in, f_add(A[j], N), f_zero<T>()), wo, vst[j]);
+        const cpx<T> yv = f_sel(in, f_add(A[j], N), f_zero<T>());
+        bstore(yv, wo, vst[j]);
+        if (DOT != 0) {
+          // owned vertices of plane q only (v2 of other vertices loads as zero)
+          const cpx<T> d = Dv[(K + 1) & 1][j];
+          if (DOT == 1) {
+            dacc[0] += (double)d.re * yv.re + (double)d.im * yv.im;
+            dacc[ND > 1 ? 1 : 0] += (double)d.re * yv.im - (double)d.im * yv.re;
+          } else {
+            dacc[0] += (double)yv.re * d.re + (double)yv.im * d.im;
+            dacc[ND > 1 ? 1 : 0] += (double)yv.re * d.im - (double)yv.im * d.re;
+            if (q_own && vst[j] != kOOB) dacc[ND - 1] += (double)yv.re * yv.re + (double)yv.im * yv.im;
+          }
+        }
         A[j] = f_add(M, Np[j]);
         Np[j] = N;
         continue;
@@ -668,7 +721,11 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     __syncthreads();
     if (rwave) rest_yz(std::integral_constant<int, 2>(), mz1 - 1, (long long)(mz1 - 1) * cstride, last);
   }
-  if (part) block_reduce_store(nsum, sqrt(nmax), part, G::NT);
+  if (DOT != 0) {
+    if (part) block_reduce_sums<ND>(dacc, part, G::NT);
+  } else if (part) {
+    block_reduce_store(nsum, sqrt(nmax), part, G::NT);
+  }
 }
 
 // ----------------------------------------------------------------------------

@@ -221,9 +221,12 @@ template <class T>
 hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s);
 // Finest level of the zero-start cycle and the operator in one 3D pass (n >= 10):
 // z = s + P g with s = ws x (zero on c-points if mask_c), y = H z (constant phi).
+// dot 1: partials[2 per block] of conj(v2) y; dot 2: partials[3 per block] of
+// conj(y) v2 and |y|^2 (prec_apply3_blocks(n) blocks); dot 0: none.
+int prec_apply3_blocks(int n);
 template <class T>
 hipError_t launch_prec_apply3(int n, const cpx<T>* coef, cpx<T> ws, int mask_c, const cpx<T>* x, const cpx<T>* gc,
-                              cpx<T>* z, cpx<T>* y, hipStream_t s);
+                              cpx<T>* z, cpx<T>* y, int dot, const cpx<T>* v2, double* partials, hipStream_t s);
 // Tile variant with the given shape (3D: coarse rows, rows per thread, coarse
 // planes; 2D: coarse rows zc only), or -1.
 int fused_tile_index(int dim, int tyc, int rpt, int zc);
