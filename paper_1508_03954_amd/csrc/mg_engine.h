@@ -132,12 +132,13 @@ struct Engine {
   cpx<T>* spill = nullptr;     // seam rows of the 3D fused sweep's restriction
   cpx<T>*tA = nullptr, *tR = nullptr, *tRh = nullptr;
   double* partials = nullptr;  // 2 * max(kRedBlocks, fused blocks)
-  double* red = nullptr;       // 2 doubles
+  double* red = nullptr;       // 4 doubles
   double* hist = nullptr;      // 2 * hist_cap
   int hist_cap = 0;
   int iter = 0;
   int fused_blocks = 0;
   int partials_cap = 0;        // capacity of `partials` in (sum, max) pairs
+  size_t partials_doubles = 0; // capacity of `partials` in doubles
   std::vector<cpx<T>*> kv;     // Krylov vectors
   std::vector<void*> owned;
   bool timing = false;
@@ -259,7 +260,8 @@ struct Engine {
     }
     // (sum, max) pairs per block, or up to four sums per block of the fused
     // Krylov kernels
-    MG_TRY(alloc_c(&partials, std::max<size_t>(2 * (size_t)max_blocks, 4 * (size_t)kRedBlocks)));
+    partials_doubles = std::max<size_t>(2 * (size_t)max_blocks, 4 * (size_t)kRedBlocks);
+    MG_TRY(alloc_c(&partials, partials_doubles));
     partials_cap = max_blocks;
     MG_TRY(alloc_c(&red, 4));
     MG_TRY(ensure_hist(64));
@@ -576,13 +578,20 @@ struct Engine {
   // Zero-start cycle below the finest level: the restriction chain of rhoL
   // and the coarse levels l_min .. L-1; *gc receives the coarse correction
   // the finest level prolongs (z_(L-1), or z_(L-1) - I s_L for BPX).
-  int precondition_coarse(const cpx<T>* rhoL, const cpx<T>** gc) {
+  // With s_r != nullptr (the restriction march only), rhoL is first formed as
+  // s_r - s_alpha s_v inside the finest restriction, and |rhoL|^2 per block
+  // goes to s_part.
+  int precondition_coarse(const cpx<T>* rhoL, const cpx<T>** gc, const cpx<T>* s_r = nullptr,
+                          const cpx<T>* s_v = nullptr, cpx<T> s_alpha = cpx<T>(), double* s_part = nullptr) {
     const int it = 1;
     for (int l = L; l > lmin; --l) {
       const cpx<T>* src = l == L ? rhoL : lv[l].pr;
       // the finest restriction moves most of the bytes: in 3D it takes the
       // sweep's march (the seam array is free outside the fused sweep)
-      if (l == L && dim == 3 && spill && lv[L].n >= 10)
+      if (l == L && s_r)
+        MG_HIP(launch_restrict3_s<T>(lv[l - 1].n, s_r, s_v, s_alpha, const_cast<cpx<T>*>(rhoL), lv[l - 1].pr, spill,
+                                     s_part, s));
+      else if (l == L && dim == 3 && spill && lv[L].n >= 10)
         MG_HIP(launch_restrict3<T>(lv[l - 1].n, src, lv[l - 1].pr, spill, s));
       else
         MG_HIP(launch_restrict<T>(dim, lv[l - 1].n, src, lv[l - 1].pr, s));
@@ -631,13 +640,23 @@ struct Engine {
     return precondition_apply(tR, z, y);
   }
 
+  // The Krylov step's finest passes run as marches in 3D with constant phi;
+  // their per-tile partials (3 per block of the preconditioner-apply march,
+  // then 1 per block of the restriction march) must fit the partials buffer.
+  bool krylov_marches() const {
+    if (dim != 3 || varying || L == lmin || lv[L].n < 10 || !spill) return false;
+    const size_t need = 3 * (size_t)prec_apply3_blocks(lv[L].n) + (size_t)restrict3_blocks(lv[L - 1].n);
+    return need <= partials_doubles;
+  }
+  size_t s_partials_offset() const { return 3 * (size_t)prec_apply3_blocks(lv[L].n); }
+
   // z = M^-1 v (v with zero boundary) and y = H z.  In 3D with constant phi
   // the finest level of M^-1 and the operator run as one march.  dot 1 also
   // returns h[0..1] = conj(v2) y, dot 2 h[0..2] = conj(y) v2 and |y|^2 (both
   // synchronise; in the march they are summed on the fly).
   int precondition_apply(const cpx<T>* v, cpx<T>* z, cpx<T>* y, int dot = 0, const cpx<T>* v2 = nullptr,
                          double* h = nullptr) {
-    if (dim != 3 || varying || L == lmin || lv[L].n < 10 || !spill) {
+    if (!krylov_marches()) {
       MG_TRY(precondition(v, z, true));
       MG_HIP(launch_apply<T>(dim, lv[L].op, z, y, s));
       if (dot == 1) {
@@ -650,18 +669,49 @@ struct Engine {
     } else {
       const cpx<T>* gc = nullptr;
       MG_TRY(precondition_coarse(v, &gc));
-      const complex<double> wL = omega_level(scheme, omega, omega_L, 0, 1);
-      const Level<T>& f = lv[L];
-      const cpx<T> ws = to_c<T>(wL * complex<double>(f.op.invD.re, f.op.invD.im));
-      MG_HIP(launch_prec_apply3<T>(f.n, f.op.coef, ws, variant == MG_HB ? 1 : 0, v, gc, z, y, dot, v2, partials, s));
-      const int nb = prec_apply3_blocks(f.n);
-      if (dot == 1) MG_HIP(launch_finish_sum2(partials, nb, red, s));
-      else if (dot == 2) MG_HIP(launch_finishN(3, partials, nb, red, s));
+      MG_TRY(finest_prec_apply(v, gc, z, y, dot, v2));
     }
     if (dot) {
       MG_HIP(hipMemcpyAsync(h, red, (dot == 1 ? 2 : 3) * sizeof(double), hipMemcpyDeviceToHost, s));
       MG_HIP(hipStreamSynchronize(s));
     }
+    return MG_OK;
+  }
+
+  int finest_prec_apply(const cpx<T>* v, const cpx<T>* gc, cpx<T>* z, cpx<T>* y, int dot, const cpx<T>* v2) {
+    const complex<double> wL = omega_level(scheme, omega, omega_L, 0, 1);
+    const Level<T>& f = lv[L];
+    const cpx<T> ws = to_c<T>(wL * complex<double>(f.op.invD.re, f.op.invD.im));
+    MG_HIP(launch_prec_apply3<T>(f.n, f.op.coef, ws, variant == MG_HB ? 1 : 0, v, gc, z, y, dot, v2, partials, s));
+    const int nb = prec_apply3_blocks(f.n);
+    if (dot == 1) MG_HIP(launch_finish_sum2(partials, nb, red, s));
+    else if (dot == 2) MG_HIP(launch_finishN(3, partials, nb, red, s));
+    return MG_OK;
+  }
+
+  // The second half-step of BiCGStab: sv = r - alpha v, z = M^-1 sv, t = H z;
+  // h[0] = |sv|^2, h[1..2] = conj(t) sv, h[3] = |t|^2 (synchronises).  With
+  // the marches, sv is formed inside the finest restriction.
+  int s_half_step(const cpx<T>* r, const cpx<T>* v, complex<double> alpha, cpx<T>* sv, cpx<T>* z, cpx<T>* t,
+                  double* h) {
+    if (!krylov_marches()) {
+      MG_HIP(launch_bicg_s<T>(NL(), r, v, to_c<double>(alpha), sv, partials, s));
+      MG_TRY(finish(1, h));
+      if (std::sqrt(h[0]) == 0.0) return MG_OK;   // the caller stops at s
+      return precondition_apply(sv, z, t, 2, sv, h + 1);
+    }
+    double* ps = partials + s_partials_offset();
+    const cpx<T>* gc = nullptr;
+    MG_TRY(precondition_coarse(sv, &gc, r, v, to_c<T>(alpha), ps));
+    MG_TRY(finest_prec_apply(sv, gc, z, t, 2, sv));
+    MG_HIP(launch_finishN(1, ps, restrict3_blocks(lv[L - 1].n), red + 3, s));
+    double q[4];
+    MG_HIP(hipMemcpyAsync(q, red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    h[0] = q[3];
+    h[1] = q[0];
+    h[2] = q[1];
+    h[3] = q[2];
     return MG_OK;
   }
 
@@ -734,19 +784,17 @@ struct Engine {
       // y = M^-1 p, v = H y and (rh, v)
       MG_TRY(precondition_apply(p, y, v, 1, rh, h));
       alpha = rho_new / complex<double>(h[0], h[1]);
-      // s = r - alpha v and |s|
-      MG_HIP(launch_bicg_s<T>(N, r, v, to_c<double>(alpha), sv, partials, s));
-      MG_TRY(finish(1, h));
-      const double sn = std::sqrt(h[0]);
+      // s = r - alpha v and |s|, z = M^-1 s, t = H z, (t, s) and |t|^2
+      double h4[4];
+      MG_TRY(s_half_step(r, v, alpha, sv, z, t, h4));
+      const double sn = std::sqrt(h4[0]);
       if (sn / bnorm <= rtol) {
         MG_HIP(launch_axpby<T>(N, to_c<double>(alpha), y, mk(1.0, 0.0), x, s));
         rel = sn / bnorm;
         status = MG_OK;
         break;
       }
-      // z = M^-1 s, t = H z, (t, s) and |t|^2
-      MG_TRY(precondition_apply(sv, z, t, 2, sv, h));
-      om = complex<double>(h[0], h[1]) / h[2];
+      om = complex<double>(h4[1], h4[2]) / h4[3];
       // x += alpha y + om z; r = s - om t; |r| and (rh, r) for the next step
       MG_HIP(launch_bicg_xr2<T>(N, x, y, z, to_c<double>(alpha), to_c<double>(om), r, sv, t, rh, partials, s));
       MG_TRY(finish(3, h));

@@ -187,13 +187,17 @@ size_t fused_spill_count(int dim, int n) {
 // 4 x 2 x 28 tile with prefetch depth 3 in the XCD-chunked block order; the
 // seam rows go through the seam array and k_seam3.
 constexpr int kRTyc = 4, kRRpt = 2, kRZc = 28;
-template <class T>
+template <class T, int DOT>
 __global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_restrict3(FusedArgs<T> a) {
   __shared__ F3Lds<T, kRTyc, kRRpt, false, true> sm;
   int bx, by, bz;
   fused3_block_tile(1, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
-  fused3_tile<T, kRTyc, kRRpt, kRZc, 1, kRestrict, 3>(a, bx, by, bz, nullptr, sm);
+  // |s|^2 partials are indexed by tile (summation order independent of the block order)
+  double* part = DOT ? a.partials + (bx + gridDim.x * (by + gridDim.y * bz)) : nullptr;
+  fused3_tile<T, kRTyc, kRRpt, kRZc, 1, kRestrict, 3, DOT>(a, bx, by, bz, part, sm);
 }
+
+int restrict3_blocks(int nc) { return f3_xtiles(nc) * f3_ytiles(nc, kRTyc) * ((nc + kRZc - 1) / kRZc); }
 
 template <class T>
 hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s) {
@@ -210,13 +214,46 @@ hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill
   a.order = 1;
   const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
   constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
-  hipLaunchKernelGGL(k_restrict3<T>, g, NT, 0, s, a);
+  hipLaunchKernelGGL((k_restrict3<T, 0>), g, NT, 0, s, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nseam = f3_ytiles(nc, kRTyc) - 1;
   if (nseam >= 1) hipLaunchKernelGGL(k_seam3<T>, dim3(nseam, nc), dim3(128), 0, s, rhoc, spill, nc, kRTyc);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<T> alpha, cpx<T>* sv, cpx<T>* rhoc,
+                              cpx<T>* spill, double* partials, hipStream_t s) {
+  const int n = 3 * (nc - 1) + 1;
+  if (n < 10 || spill == nullptr || partials == nullptr || sv == r || sv == v) return hipErrorInvalidValue;
+  FusedArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nc = nc;
+  a.b = r;
+  a.w2 = v;
+  a.ws = alpha;
+  a.zout = sv;
+  a.rhoc = rhoc;
+  a.spill = spill;
+  a.partials = partials;
+  a.variant = 1;
+  a.order = 1;
+  const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
+  constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
+  hipLaunchKernelGGL((k_restrict3<T, 3>), g, NT, 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nseam = f3_ytiles(nc, kRTyc) - 1;
+  if (nseam >= 1) hipLaunchKernelGGL(k_seam3<T>, dim3(nseam, nc), dim3(128), 0, s, rhoc, spill, nc, kRTyc);
+  return hipGetLastError();
+}
+
+template hipError_t launch_restrict3_s<double>(int, const cpx<double>*, const cpx<double>*, cpx<double>, cpx<double>*,
+                                               cpx<double>*, cpx<double>*, double*, hipStream_t);
+template hipError_t launch_restrict3_s<float>(int, const cpx<float>*, const cpx<float>*, cpx<float>, cpx<float>*,
+                                              cpx<float>*, cpx<float>*, double*, hipStream_t);
 
 template <class T, int VAR, int DOT>
 __global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_prec_apply3(FusedArgs<T> a) {

@@ -290,7 +290,9 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // c-points for VAR 1), stored to zout, and y = H z, stored to wout; with DOT
 // it also sums, over the owned vertices, conj(v2) y (DOT 1, 2 values) or
 // conj(y) v2 and |y|^2 (DOT 2, 3 values) for the vector v2 in b, into the
-// tile's slot of part.
+// tile's slot of part.  kRestrict with DOT 3 restricts s = b - ws w2 (the
+// BiCGStab update of its second half-step) instead of b, stores s to zout and
+// sums |s|^2 over the owned vertices into part.
 constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3, kPrecApply = 4;
 constexpr bool f3_full_lds(int mode) { return mode == kSweep || mode == kRestrict || mode == kPrecApply; }
 
@@ -400,8 +402,9 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   double nsum = 0.0, nmax = 0.0;
   // dots of the preconditioner-apply march: v2 of plane P is loaded at step P
   // (register set = parity of P relative to p0) and used one step later
-  static_assert(DOT == 0 || MODE == kPrecApply, "dots only in the preconditioner-apply march");
-  constexpr int ND = DOT == 0 ? 1 : (DOT == 1 ? 2 : 3);
+  static_assert(DOT == 0 || (MODE == kPrecApply && DOT <= 2) || (MODE == kRestrict && DOT == 3),
+                "dots of the preconditioner-apply march, or the s update of the restriction march");
+  constexpr int ND = DOT == 0 || DOT == 3 ? 1 : (DOT == 1 ? 2 : 3);
   double dacc[ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) dacc[k] = 0.0;
@@ -423,6 +426,13 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   // the first residual plane used is p0 + 1 (the lowest fine plane of R at coarse plane mz0)
   auto load_b = [&](int p, long long ofs, cpx<T>* dst) {
     const auto r = frs(a.b, ofs, plane_ok(p) && p > p0 && p < plast);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
+  };
+  // the second input of the s update (kRestrict, DOT 3), with the same planes
+  cpx<T> Vr[DOT == 3 ? PF : 1][RPT];
+  auto load_v2 = [&](int p, long long ofs, cpx<T>* dst) {
+    const auto r = frs(a.w2, ofs, plane_ok(p) && p > p0 && p < plast);
 #pragma unroll
     for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
   };
@@ -515,6 +525,10 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
 #pragma unroll
     for (int i = 0; i < PF; ++i) load_b(p0 - 1 + i, (long long)(p0 - 1 + i) * pstride, Br[i]);
   }
+  if (DOT == 3) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) load_v2(p0 - 1 + i, (long long)(p0 - 1 + i) * pstride, Vr[DOT == 3 ? i : 0]);
+  }
 #pragma unroll
   for (int j = 0; j < RPT; ++j) { A[j] = f_zero<T>(); Np[j] = f_zero<T>(); Cp[j] = f_zero<T>(); }
   if (MODE == kSweep || MODE == kRestrict) {
@@ -560,12 +574,29 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     const int q = p - 1;
     const long long pofs = (long long)p * pstride, kofs = (long long)kb * cstride;
     if (MODE == kRestrict) {
-      // the input of plane q is in Br[E]; the barrier orders the LDS slots
+      // the input of plane q is in Br[E] (and Vr[E]); the barrier orders the LDS slots
       __syncthreads();
       cpx<T> r[RPT];
 #pragma unroll
-      for (int j = 0; j < RPT; ++j)
-        r[j] = f_sel(plane_ok(q) && row_ok(ybase + j) && xin && xcomp, Br[E][j], f_zero<T>());
+      for (int j = 0; j < RPT; ++j) {
+        const bool in = plane_ok(q) && row_ok(ybase + j) && xin && xcomp;
+        if (DOT == 3) {
+          const cpx<T> sv = f_sel(in, f_sub(Br[E][j], f_mul(ws, Vr[DOT == 3 ? E : 0][j])), f_zero<T>());
+          r[j] = sv;
+        } else {
+          r[j] = f_sel(in, Br[E][j], f_zero<T>());
+        }
+      }
+      if (DOT == 3) {
+        const bool q_own = q >= zown_lo && q <= zown_hi;
+        const auto so = frs(a.zout, pofs - pstride, q_own);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          bstore(r[j], so, vst[j]);
+          if (q_own && vst[j] != kOOB) dacc[0] += (double)r[j].re * r[j].re + (double)r[j].im * r[j].im;
+        }
+        load_v2(p + PF - 1, pofs + (PF - 1) * pstride, Vr[DOT == 3 ? E : 0]);
+      }
       load_b(p + PF - 1, pofs + (PF - 1) * pstride, Br[E]);
       restrict_r(K_, r, kb, kofs);
       return;
