@@ -582,7 +582,7 @@ struct Engine {
   // s_r - s_alpha s_v inside the finest restriction, and |rhoL|^2 per block
   // goes to s_part.
   int precondition_coarse(const cpx<T>* rhoL, const cpx<T>** gc, const cpx<T>* s_r = nullptr,
-                          const cpx<T>* s_v = nullptr, cpx<T> s_alpha = cpx<T>(), double* s_part = nullptr) {
+                          const cpx<T>* s_v = nullptr, cpx<double> s_alpha = cpx<double>(), double* s_part = nullptr) {
     const int it = 1;
     for (int l = L; l > lmin; --l) {
       const cpx<T>* src = l == L ? rhoL : lv[l].pr;
@@ -702,7 +702,7 @@ struct Engine {
     }
     double* ps = partials + s_partials_offset();
     const cpx<T>* gc = nullptr;
-    MG_TRY(precondition_coarse(sv, &gc, r, v, to_c<T>(alpha), ps));
+    MG_TRY(precondition_coarse(sv, &gc, r, v, to_c<double>(alpha), ps));
     MG_TRY(finest_prec_apply(sv, gc, z, t, 2, sv));
     MG_HIP(launch_finishN(1, ps, restrict3_blocks(lv[L - 1].n), red + 3, s));
     double q[4];

@@ -223,7 +223,7 @@ hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill
 }
 
 template <class T>
-hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<T> alpha, cpx<T>* sv, cpx<T>* rhoc,
+hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<double> alpha, cpx<T>* sv, cpx<T>* rhoc,
                               cpx<T>* spill, double* partials, hipStream_t s) {
   const int n = 3 * (nc - 1) + 1;
   if (n < 10 || spill == nullptr || partials == nullptr || sv == r || sv == v) return hipErrorInvalidValue;
@@ -233,7 +233,7 @@ hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<T> a
   a.nc = nc;
   a.b = r;
   a.w2 = v;
-  a.ws = alpha;
+  a.alpha = alpha;
   a.zout = sv;
   a.rhoc = rhoc;
   a.spill = spill;
@@ -252,7 +252,7 @@ hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<T> a
 
 template hipError_t launch_restrict3_s<double>(int, const cpx<double>*, const cpx<double>*, cpx<double>, cpx<double>*,
                                                cpx<double>*, cpx<double>*, double*, hipStream_t);
-template hipError_t launch_restrict3_s<float>(int, const cpx<float>*, const cpx<float>*, cpx<float>, cpx<float>*,
+template hipError_t launch_restrict3_s<float>(int, const cpx<float>*, const cpx<float>*, cpx<double>, cpx<float>*,
                                               cpx<float>*, cpx<float>*, double*, hipStream_t);
 
 template <class T, int VAR, int DOT>

@@ -290,9 +290,10 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // c-points for VAR 1), stored to zout, and y = H z, stored to wout; with DOT
 // it also sums, over the owned vertices, conj(v2) y (DOT 1, 2 values) or
 // conj(y) v2 and |y|^2 (DOT 2, 3 values) for the vector v2 in b, into the
-// tile's slot of part.  kRestrict with DOT 3 restricts s = b - ws w2 (the
-// BiCGStab update of its second half-step) instead of b, stores s to zout and
-// sums |s|^2 over the owned vertices into part.
+// tile's slot of part.  kRestrict with DOT 3 restricts s = b - alpha w2 (the
+// BiCGStab update of its second half-step, formed in double precision, which
+// keeps the cancellation in s exact for complex64 vectors) instead of b,
+// stores s to zout and sums |s|^2 over the owned vertices into part.
 constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3, kPrecApply = 4;
 constexpr bool f3_full_lds(int mode) { return mode == kSweep || mode == kRestrict || mode == kPrecApply; }
 
@@ -581,8 +582,10 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       for (int j = 0; j < RPT; ++j) {
         const bool in = plane_ok(q) && row_ok(ybase + j) && xin && xcomp;
         if (DOT == 3) {
-          const cpx<T> sv = f_sel(in, f_sub(Br[E][j], f_mul(ws, Vr[DOT == 3 ? E : 0][j])), f_zero<T>());
-          r[j] = sv;
+          const cpx<T> bv = Br[E][j], vv = Vr[DOT == 3 ? E : 0][j];
+          const double sre = (double)bv.re - (a.alpha.re * (double)vv.re - a.alpha.im * (double)vv.im);
+          const double sim = (double)bv.im - (a.alpha.re * (double)vv.im + a.alpha.im * (double)vv.re);
+          r[j] = f_sel(in, mk(T(sre), T(sim)), f_zero<T>());
         } else {
           r[j] = f_sel(in, Br[E][j], f_zero<T>());
         }

@@ -192,7 +192,8 @@ struct FusedArgs {
   cpx<T>* sic_out;      // coarse si <- I s (BPX) or nullptr
   cpx<T>* spill;        // 3D: seam rows of R (fused_spill_count(3, n) entries), added by launch_fused_seam
   cpx<T>* zout;         // preconditioner-apply march: z (its wout receives H z); s update: s
-  const cpx<T>* w2;     // s update of the restriction march: the vector v of s = b - ws v
+  const cpx<T>* w2;     // s update of the restriction march: the vector v of s = b - alpha v
+  cpx<double> alpha;    // s update: alpha (the update is formed in double precision)
   cpx<T> coef[4];
   cpx<T> ws;            // omega * (1 / D)
   double* partials;     // per-block (sum |r|^2, max |r|) or nullptr
@@ -224,7 +225,7 @@ hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill
 // partials[one per block, restrict3_blocks(nc)] receive |s|^2 over the block.
 int restrict3_blocks(int nc);
 template <class T>
-hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<T> alpha, cpx<T>* sv, cpx<T>* rhoc,
+hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<double> alpha, cpx<T>* sv, cpx<T>* rhoc,
                               cpx<T>* spill, double* partials, hipStream_t s);
 // Finest level of the zero-start cycle and the operator in one 3D pass (n >= 10):
 // z = s + P g with s = ws x (zero on c-points if mask_c), y = H z (constant phi).
