@@ -209,8 +209,11 @@ int mg_autotune(mg_ctx* ctx, int reps, int* best_tile, double* best_us, double* 
 
 /* Measurement hook for the finest-level sweep (the kernel that moves most of
  * a cycle's bytes).  enable != 0: every following finest sweep launched by
- * mg_cycle is bracketed by a HIP event pair recorded on the context stream;
- * enable == 0 stops recording.  Enabling clears earlier records. */
+ * mg_cycle is timed by a HIP event pair on the context stream -- for the
+ * fused sweep the pair goes with the launch (hipExtLaunchKernel) and takes the
+ * kernel's own start and end; the unfused sweep's kernels are bracketed by
+ * two recorded events.  enable == 0 stops recording.  Enabling clears earlier
+ * records. */
 int mg_time_sweeps(mg_ctx* ctx, int enable);
 
 /* Synchronises and returns the summed event time (milliseconds) and the number

@@ -162,6 +162,21 @@ struct Engine {
     return MG_OK;
   }
 
+  // The next event pair of the record for a launch that takes its events
+  // itself (both nullptr when not timing).
+  int event_pair(hipEvent_t* t0, hipEvent_t* t1) {
+    *t0 = *t1 = nullptr;
+    if (!timing) return MG_OK;
+    while (ev.size() < ev_used + 2) {
+      hipEvent_t e;
+      MG_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    *t0 = ev[ev_used++];
+    *t1 = ev[ev_used++];
+    return MG_OK;
+  }
+
   int alloc(void** p, size_t bytes) {
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(p, bytes);
@@ -388,16 +403,18 @@ struct Engine {
     const complex<double> wL = omega_level(scheme, omega, omega_L, 0, iter);
     const int mask = (hc && variant != MG_ADD) ? 1 : 0;
     int nparts = kRedBlocks;
-    MG_TRY(mark(true));
     if (fused) {
+      // the event pair takes the sweep kernel's own start and end
+      hipEvent_t t0, t1;
+      MG_TRY(event_pair(&t0, &t1));
       FusedArgs<T> a = fused_args(w[1 - cur], c->b, c->sf, si_alt, wL.real(), wL.imag());
-      MG_HIP(launch_fused<T>(dim, a, s));
-      MG_TRY(mark(false));
+      MG_HIP(launch_fused<T>(dim, a, s, t0, t1));
       MG_HIP(launch_fused_seam<T>(dim, a, s));
       if (variant == MG_BPX) std::swap(c->si, si_alt);
       nparts = fused_blocks;
     } else {
       MG_TRY(ensure_scratch());
+      MG_TRY(mark(true));
       cpx<T>* U = w[1 - cur];
       MG_HIP(launch_fine_pre<T>(dim, f.n, w[cur], U, hc ? c->sc : nullptr, hc ? c->si : nullptr, hc ? 1 : 0,
                                 variant == MG_BPX ? 1 : 0, s));

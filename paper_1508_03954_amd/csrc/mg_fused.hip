@@ -1,4 +1,6 @@
 // Fused finest-level sweep: standalone kernels, tile table and launchers.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cstring>
 
@@ -94,24 +96,26 @@ int fused_partials_blocks(int dim, int n, int tile) {
   return (int)(g.x * g.y * g.z);
 }
 
+// The sweep is launched through hipExtLaunchKernel: the optional events t0 / t1
+// take the kernel's own start and end times (nullptr: no timing).
 template <class T, int TYC, int RPT, int ZC, int PF = 1>
-static void launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s) {
-  constexpr int NT = F3<T, TYC, RPT, ZC, false>::NT;
+static void launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  const dim3 b(F3<T, TYC, RPT, ZC, false>::NT);
   FusedArgs<T> a = a0;
   a.order = kTiles3[a0.tile].order;
-  if (a.variant == 2) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2, PF>), g, NT, 0, s, a);
-  else if (a.variant == 1) hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 1, PF>), g, NT, 0, s, a);
-  else hipLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 0, PF>), g, NT, 0, s, a);
+  if (a.variant == 2) hipExtLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2, PF>), g, b, 0, s, t0, t1, 0, a);
+  else if (a.variant == 1) hipExtLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 1, PF>), g, b, 0, s, t0, t1, 0, a);
+  else hipExtLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 0, PF>), g, b, 0, s, t0, t1, 0, a);
 }
 
 template <class T, int ZC>
-static void launch2(const FusedArgs<T>& a, dim3 g, hipStream_t s) {
-  if (a.variant == 2) hipLaunchKernelGGL((k_fused2<T, ZC, true>), g, 64, 0, s, a);
-  else hipLaunchKernelGGL((k_fused2<T, ZC, false>), g, 64, 0, s, a);
+static void launch2(const FusedArgs<T>& a, dim3 g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  if (a.variant == 2) hipExtLaunchKernelGGL((k_fused2<T, ZC, true>), g, dim3(64), 0, s, t0, t1, 0, a);
+  else hipExtLaunchKernelGGL((k_fused2<T, ZC, false>), g, dim3(64), 0, s, t0, t1, 0, a);
 }
 
 template <class T>
-hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
+hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   if (a.nc != (a.n - 1) / 3 + 1 || a.n < 10) return hipErrorInvalidValue;
   if (a.tile < 0 || a.tile >= fused_tile_count(dim)) return hipErrorInvalidValue;
   if (a.variant == 2 && (a.sic == nullptr || a.sic_out == nullptr || a.sic == a.sic_out)) return hipErrorInvalidValue;
@@ -119,31 +123,31 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s) {
   const dim3 g = fused_grid(dim, a.n, a.tile);
   if (dim == 3) {
     switch (a.tile) {
-      case 0: launch3<T, 2, 2, 9>(a, g, s); break;
-      case 1: launch3<T, 2, 2, 14>(a, g, s); break;
-      case 2: launch3<T, 2, 2, 21>(a, g, s); break;
-      case 3: launch3<T, 2, 2, 27>(a, g, s); break;
-      case 4: launch3<T, 2, 2, 28>(a, g, s); break;
-      case 5: launch3<T, 4, 2, 14>(a, g, s); break;
-      case 6: launch3<T, 4, 2, 21>(a, g, s); break;
-      case 7: launch3<T, 4, 2, 28>(a, g, s); break;
-      case 8: launch3<T, 2, 1, 14>(a, g, s); break;
-      case 9: launch3<T, 2, 1, 21>(a, g, s); break;
-      case 10: launch3<T, 2, 2, 9>(a, g, s); break;
-      case 11: launch3<T, 2, 2, 21>(a, g, s); break;
-      case 12: launch3<T, 4, 2, 28, 2>(a, g, s); break;
-      case 13: launch3<T, 4, 2, 28, 3>(a, g, s); break;
-      case 14: launch3<T, 2, 2, 28, 2>(a, g, s); break;
-      case 15: launch3<T, 2, 2, 28, 3>(a, g, s); break;
-      case 16: launch3<T, 4, 2, 28, 3>(a, g, s); break;
-      default: launch3<T, 2, 2, 28, 3>(a, g, s); break;
+      case 0: launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
+      case 1: launch3<T, 2, 2, 14>(a, g, s, t0, t1); break;
+      case 2: launch3<T, 2, 2, 21>(a, g, s, t0, t1); break;
+      case 3: launch3<T, 2, 2, 27>(a, g, s, t0, t1); break;
+      case 4: launch3<T, 2, 2, 28>(a, g, s, t0, t1); break;
+      case 5: launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
+      case 6: launch3<T, 4, 2, 21>(a, g, s, t0, t1); break;
+      case 7: launch3<T, 4, 2, 28>(a, g, s, t0, t1); break;
+      case 8: launch3<T, 2, 1, 14>(a, g, s, t0, t1); break;
+      case 9: launch3<T, 2, 1, 21>(a, g, s, t0, t1); break;
+      case 10: launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
+      case 11: launch3<T, 2, 2, 21>(a, g, s, t0, t1); break;
+      case 12: launch3<T, 4, 2, 28, 2>(a, g, s, t0, t1); break;
+      case 13: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 14: launch3<T, 2, 2, 28, 2>(a, g, s, t0, t1); break;
+      case 15: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 16: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
+      default: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
     }
   } else {
     switch (a.tile) {
-      case 0: launch2<T, 2>(a, g, s); break;
-      case 1: launch2<T, 1>(a, g, s); break;
-      case 2: launch2<T, 4>(a, g, s); break;
-      default: launch2<T, 8>(a, g, s); break;
+      case 0: launch2<T, 2>(a, g, s, t0, t1); break;
+      case 1: launch2<T, 1>(a, g, s, t0, t1); break;
+      case 2: launch2<T, 4>(a, g, s, t0, t1); break;
+      default: launch2<T, 8>(a, g, s, t0, t1); break;
     }
   }
   return hipGetLastError();
@@ -364,8 +368,8 @@ template hipError_t launch_stencil3<double>(int, int, const cpx<double>*, const 
 template hipError_t launch_stencil3<float>(int, int, const cpx<float>*, const cpx<float>*, const cpx<float>*,
                                            cpx<float>*, double*, int*, hipStream_t);
 
-template hipError_t launch_fused<double>(int, const FusedArgs<double>&, hipStream_t);
-template hipError_t launch_fused<float>(int, const FusedArgs<float>&, hipStream_t);
+template hipError_t launch_fused<double>(int, const FusedArgs<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_fused<float>(int, const FusedArgs<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_fused_seam<double>(int, const FusedArgs<double>&, hipStream_t);
 template hipError_t launch_fused_seam<float>(int, const FusedArgs<float>&, hipStream_t);
 

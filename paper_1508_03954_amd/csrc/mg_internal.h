@@ -201,8 +201,10 @@ struct FusedArgs {
   int tile;             // tile variant, 0 .. fused_tile_count(dim) - 1
   int order;            // block-to-tile order (set by the launcher from the tile table)
 };
+// t0 / t1 (or nullptr): events that receive the sweep kernel's start and end.
 template <class T>
-hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s);
+hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr);
 // Second pass of a 3D sweep: rho_c += the seam rows of R (no-op in 2D).
 template <class T>
 hipError_t launch_fused_seam(int dim, const FusedArgs<T>& a, hipStream_t s);

@@ -7,6 +7,7 @@ tiles with ragged tails.
 """
 
 import math
+import time
 
 import numpy as np
 import pytest
@@ -207,6 +208,39 @@ def test_autotune_keeps_state():
     after["w"] = to_np(s.get_level(L, "u"))
     for k in before:
         np.testing.assert_array_equal(before[k], after[k])
+
+
+@pytest.mark.parametrize("dim,L,sweep", [(3, 4, "fused"), (2, 4, "fused"), (3, 3, "generic")])
+def test_sweep_timing_hook(dim, L, sweep):
+    """mg_time_sweeps records one event pair per finest sweep (the fused
+    sweep's pair takes the kernel's own start and end); the recorded time is
+    positive and below the cycles' wall time, recording stops when disabled,
+    and the cycles' results do not depend on whether timing is on."""
+    mg = mgmod()
+    n = 3 ** L + 1
+    b, u0 = rand_c((n,) * dim, 1), rand_c((n,) * dim, 2)
+    finals = []
+    for timed in (False, True):
+        print(f"\n[case] sweep timing dim={dim} L={L} {sweep} timed={timed}", flush=True)
+        s = mg.Solver(dim, L, theta=0.3, phi=200.0, variant="bpx", sweep=sweep)
+        s.set_rhs(b)
+        s.set_solution(u0)
+        if timed:
+            s.time_sweeps(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.cycle(5)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        finals.append(to_np(s.get_level(L, "u")))
+        if timed:
+            ms, cnt = s.sweep_time()
+            assert cnt == 5
+            assert 0 < ms < 1e3 * wall, (ms, wall)
+            s.time_sweeps(False)
+            s.cycle(1)
+            assert s.sweep_time()[1] == 5
+    np.testing.assert_array_equal(finals[0], finals[1])
 
 
 @pytest.mark.parametrize("dim,L,variant", [(2, 4, "bpx"), (3, 3, "hb"), (3, 3, "add")])
