@@ -11,9 +11,10 @@
 // after the items it waits for, so the waits always end: a waiting workgroup
 // only waits for items claimed earlier by workgroups that are resident and
 // whose own waits point further back.  Completion is published per
-// (problem, phase) with an agent-scope release; waiters acquire at agent scope
-// (each XCD has its own L2).  Every wait is bounded; a timeout sets an error
-// flag and the kernel still drains.
+// (problem, phase) with an agent-scope release, one write-back of the XCD's L2
+// per item; waiters poll with relaxed loads and acquire at agent scope (each
+// XCD has its own L2) once per dependency and workgroup.  Every wait is
+// bounded; a timeout sets an error flag and the kernel still drains.
 //
 // The per-vertex and per-tile code is the same as in the single-problem
 // kernels (mg_level_ops.h, mg_fused_ops.h), so a problem advanced in a batch
@@ -205,8 +206,12 @@ __device__ inline void batch_fused2(const BProb<T>* Pp, int cyc, int id, cpx<T> 
   }
 }
 
+// Inlined on purpose: as a called function (its default for the 3D instance)
+// it received the kernel arguments through scratch memory and saved registers
+// there, and its items ran 2-5x slower.
 template <class T, int D>
-__device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, int phase, int tile,
+__device__ __attribute__((always_inline)) inline void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob,
+                                                                 int phase, int tile,
                            cpx<T> (*Gz2)[2][F2_GX], cpx<T> (*Sz2)[2][F2_GX], F3Lds<T, 2, 2, true>* f3lds) {
   const int kind = P.phase_kind[phase], lev = P.phase_level[phase];
   const bool bpx = P.variant == MG_BPX, add = P.variant == MG_ADD;
@@ -286,16 +291,17 @@ __device__ void batch_item(const BatchArgs<T>& A, const BProb<T>& P, int prob, i
   }
 }
 
-// Occupancy hints by precision, chosen on the compiler's output: complex128
-// fits 164 registers without spills with a hint of 4 (3 waves per SIMD; hints
-// of 2 and 3 made it spill to scratch); complex64 fits 248 without spills at 2
-// (a hint of 3 spilled 14 registers and ran the batched cycle 4 % slower).
+// Occupancy hints by precision, chosen on the compiler's output with every
+// item type inlined into the kernel: complex128 takes 224 registers (2 waves
+// per SIMD; a hint of 3 fitted 168 but spilled 352 bytes per lane to
+// scratch), complex64 161 (3 waves per SIMD).
 template <class T>
-constexpr int kBatchWavesHint = sizeof(T) == 8 ? 4 : 2;
+constexpr int kBatchWavesHint = 2;
 
 template <class T>
 __global__ __launch_bounds__(kBThreads, kBatchWavesHint<T>) void k_batch_cycle(BatchArgs<T> A) {
-  __shared__ int s_item, s_ok;
+  __shared__ int s_item, s_ok, s_acq;
+  int acq_prob = -1, acq_phase = -1;  // thread 0: the dependency this workgroup last acquired
   __shared__ cpx<T> Gz2[kBWaves][2][F2_GX];
   __shared__ cpx<T> Sz2[kBWaves][2][F2_GX];
   __shared__ F3Lds<T, 2, 2, true> f3lds;
@@ -319,12 +325,20 @@ __global__ __launch_bounds__(kBThreads, kBatchWavesHint<T>) void k_batch_cycle(B
     unsigned long long t_wait = 0, t_ready = 0;
     if (threadIdx.x == 0) {
       if (A.trace) t_wait = wall_clock64();
-      int ok = 1;
-      if (w.phase > 0) {
+      int ok = 1, acq = 0;
+      // phase 0 depends on the previous launch only; a dependency this
+      // workgroup has already waited for and acquired needs neither again
+      // (completion counts only grow, and an acquire invalidates caches
+      // under every item running on the XCD)
+      if (w.phase > 0 && (w.prob != acq_prob || w.phase != acq_phase)) {
+        acq = 1;
         const int need = P.phase_items[w.phase - 1];
         int* cnt = A.done + w.prob * kBMaxPhases + w.phase - 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        // relaxed polling: an acquiring load would invalidate caches on every
+        // poll, under the items other workgroups are running; the acquire is
+        // the fence after the barrier below
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
           if (++spins > A.spin_limit) {
             ok = 0;
             atomicOr(A.err, 1);
@@ -332,17 +346,26 @@ __global__ __launch_bounds__(kBThreads, kBatchWavesHint<T>) void k_batch_cycle(B
           }
           __builtin_amdgcn_s_sleep(2);
         }
+        if (ok) {
+          acq_prob = w.prob;
+          acq_phase = w.phase;
+        }
       }
       s_ok = ok;
+      s_acq = acq;
       if (A.trace) t_ready = wall_clock64();
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (s_acq) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (s_ok) {
       if (P.dim == 3) batch_item<T, 3>(A, P, w.prob, w.phase, w.tile, Gz2, Sz2, &f3lds);
       else batch_item<T, 2>(A, P, w.prob, w.phase, w.tile, Gz2, Sz2, &f3lds);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Publication: every wave waits until its stores have reached the L2,
+    // then thread 0's releasing add writes the XCD's L2 back once for the
+    // whole workgroup (a release fence in every wave would write it back once
+    // per wave).
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
       if (A.trace) {
