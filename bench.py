@@ -242,6 +242,9 @@ def main():
                     help="also solve the 3D k=40 problem at this level with complex64 refinement vs FP64 (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy three times (calibrates hardware byte counters)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 96-problem batched measurement (and the copy probe if asked) and print "
+                         "its record; for counter runs of the batched kernel")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -258,6 +261,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     mg.load_library()
+    if args.batched_only:
+        out = {"batched": batched_extra(torch)}
+        if args.copy_probe:
+            copy_probe(torch, out)
+        print(json.dumps(out))
+        return
     L, dim = args.level, 3
     prob = config_3d_csg(level_max=L, variant=args.variant)
     chi = torch.from_numpy(prob.chi).cuda()
@@ -364,15 +373,19 @@ def main():
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} vertex-updates/s")
 
     if args.copy_probe:
-        src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda")   # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_probe_bytes"] = 2 * src.numel() * 16
-        del src, dst
+        copy_probe(torch, out)
 
     print(json.dumps(out))
+
+
+def copy_probe(torch, out):
+    """A plain 1 GiB device copy, three times: the reference for the byte counters."""
+    src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda")   # 1 GiB
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_probe_bytes"] = 2 * src.numel() * 16
 
 
 if __name__ == "__main__":
