@@ -130,6 +130,7 @@ struct Engine {
   cpx<T>* si_alt = nullptr;    // second si buffer of level L-1 (fused BPX sweep reads old, writes new)
   cpx<T>* tune_c = nullptr;    // coarse scratch for the autotuner
   cpx<T>* spill = nullptr;     // seam rows of the 3D fused sweep's restriction
+  bool small_pre_done = false; // the small levels' pre-phase of the next cycle has run
   cpx<T>*tA = nullptr, *tR = nullptr, *tRh = nullptr;
   double* partials = nullptr;  // 2 * max(kRedBlocks, fused blocks)
   double* red = nullptr;       // 4 doubles
@@ -321,6 +322,7 @@ struct Engine {
   }
 
   int zero_helpers() {
+    small_pre_done = false;
     for (int l = lmin; l < L; ++l) {
       MG_HIP(launch_fill(lv[l].sc, lv[l].N * sizeof(cpx<T>), s));
       MG_HIP(launch_fill(lv[l].sf, lv[l].N * sizeof(cpx<T>), s));
@@ -381,7 +383,8 @@ struct Engine {
     int l0 = lmin;
     const int ns = small_levels();
     if (ns) {
-      MG_HIP(launch_small_pre<T>(small_args(ns), s));
+      if (!small_pre_done) MG_HIP(launch_small_pre<T>(small_args(ns), s));
+      small_pre_done = false;
       l0 = lmin + ns;
     }
     for (int l = l0; l < L; ++l) {
@@ -393,7 +396,9 @@ struct Engine {
     return MG_OK;
   }
 
-  int cycle_once(int k) {
+  // more: another cycle follows in the same call (its small-level pre-phase
+  // then runs in this cycle's last launch)
+  int cycle_once(int k, bool more = false) {
     ++iter;
     MG_TRY(ensure_hist(k + 1));
     MG_TRY(pre_coarse());
@@ -438,7 +443,9 @@ struct Engine {
         a.partials = partials;
         a.nparts = nparts;
         a.out = hist + 2 * k;
+        a.then_pre = more ? 1 : 0;
         MG_HIP(launch_small_post<T>(a, s));
+        small_pre_done = more;
         break;
       }
       Level<T>& v = lv[l];
@@ -549,7 +556,7 @@ struct Engine {
 
   int cycles(int ncycles, double* res_h, double* res_max) {
     MG_TRY(ensure_hist(ncycles));
-    for (int k = 0; k < ncycles; ++k) MG_TRY(cycle_once(k));
+    for (int k = 0; k < ncycles; ++k) MG_TRY(cycle_once(k, k + 1 < ncycles));
     if (res_h || res_max) {
       std::vector<double> h(2 * (size_t)ncycles);
       MG_HIP(hipMemcpyAsync(h.data(), hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));

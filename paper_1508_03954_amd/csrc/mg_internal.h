@@ -172,6 +172,7 @@ struct SmallArgs {
   const double* partials;   // post: block partials of the finest sweep, or nullptr
   int nparts;
   double* out;              // post: (sum |r|^2, max |r|)
+  int then_pre;             // post: then also the next cycle's pre-phase of these levels
 };
 template <class T>
 hipError_t launch_small_pre(const SmallArgs<T>& a, hipStream_t s);

@@ -625,7 +625,7 @@ __device__ inline void small_unravel(long long i, int n, int j[3]) {
 }
 
 template <class T, int D>
-__global__ __launch_bounds__(kSmallThreads) void k_small_pre(SmallArgs<T> a) {
+__device__ inline void small_pre_levels(const SmallArgs<T>& a) {
   for (int k = 0; k < a.nl; ++k) {
     const SmallLevel<T>& v = a.lv[k];
     const long long N = D == 3 ? (long long)v.n * v.n * v.n : (long long)v.n * v.n;
@@ -638,6 +638,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_pre(SmallArgs<T> a) {
     }
     __syncthreads();
   }
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(kSmallThreads) void k_small_pre(SmallArgs<T> a) {
+  small_pre_levels<T, D>(a);
 }
 
 template <class T, int D>
@@ -679,6 +684,11 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_post(SmallArgs<T> a) {
     }
   }
   if (a.partials) finish_block<true>(a.partials, a.nparts, a.out);
+  // the next cycle starts with the pre-phase of these levels: one launch fewer
+  if (a.then_pre) {
+    __syncthreads();
+    small_pre_levels<T, D>(a);
+  }
 }
 
 

@@ -210,6 +210,39 @@ def test_autotune_keeps_state():
         np.testing.assert_array_equal(before[k], after[k])
 
 
+@pytest.mark.parametrize("dim,L,variant,sweep", [(3, 4, "bpx", "fused"), (3, 3, "bpx", "fused"),
+                                                  (2, 5, "hb", "fused"), (3, 3, "add", "generic")])
+def test_cycles_in_one_call_match_single_calls(dim, L, variant, sweep):
+    """mg_cycle(ctx, 4) runs the next cycle's small-level pre-phase inside the
+    previous cycle's last launch; the state and the residual history equal
+    those of four mg_cycle(ctx, 1) calls bit for bit."""
+    print(f"\n[case] cycles in one call dim={dim} L={L} {variant} {sweep}", flush=True)
+    mg = mgmod()
+    n = 3 ** L + 1
+    b, u0 = rand_c((n,) * dim, 1), rand_c((n,) * dim, 2)
+    solvers, hist = [], []
+    for one_call in (True, False):
+        s = mg.Solver(dim, L, theta=0.4, phi=90 * (1 + 0.5j), variant=variant, sweep=sweep, omega=0.6)
+        s.set_rhs(b)
+        s.set_solution(u0)
+        if one_call:
+            rh, rm = s.cycle(4)
+        else:
+            rh, rm = [], []
+            for _ in range(4):
+                a, m = s.cycle(1)
+                rh += list(a)
+                rm += list(m)
+        solvers.append(s)
+        hist.append((list(rh), list(rm)))
+    assert hist[0] == hist[1]
+    for lev in range(1, L + 1):
+        for field in ("u", "b", "sc", "sf", "si"):
+            np.testing.assert_array_equal(to_np(solvers[0].get_level(lev, field)),
+                                          to_np(solvers[1].get_level(lev, field)), err_msg=f"{lev} {field}")
+    np.testing.assert_array_equal(to_np(solvers[0].flush()), to_np(solvers[1].flush()))
+
+
 @pytest.mark.parametrize("dim,L,sweep", [(3, 4, "fused"), (2, 4, "fused"), (3, 3, "generic")])
 def test_sweep_timing_hook(dim, L, sweep):
     """mg_time_sweeps records one event pair per finest sweep (the fused
