@@ -229,27 +229,33 @@ __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned b
   void* p = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), kRawBufferWord3);
 }
+// CP: the access's cache policy bits (0, or kStream for data used once).
+constexpr int kStream = 2;   // non-temporal
+template <int CP = 0>
 __device__ inline cpx<double> bload(cpx<double>*, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, CP);
   cpx<double> c;
   __builtin_memcpy(&c, &v, sizeof(c));
   return c;
 }
+template <int CP = 0>
 __device__ inline cpx<float> bload(cpx<float>*, __amdgpu_buffer_rsrc_t r, unsigned off) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, CP);
   cpx<float> c;
   __builtin_memcpy(&c, &v, sizeof(c));
   return c;
 }
+template <int CP = 0>
 __device__ inline void bstore(cpx<double> c, __amdgpu_buffer_rsrc_t r, unsigned off) {
   __attribute__((ext_vector_type(4))) unsigned v;
   __builtin_memcpy(&v, &c, sizeof(c));
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, CP);
 }
+template <int CP = 0>
 __device__ inline void bstore(cpx<float> c, __amdgpu_buffer_rsrc_t r, unsigned off) {
   __attribute__((ext_vector_type(2))) unsigned v;
   __builtin_memcpy(&v, &c, sizeof(c));
-  __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, CP);
 }
 
 // Seam array of the 3D sweep's restriction.  A tile computes r on its own
@@ -428,7 +434,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   auto load_b = [&](int p, long long ofs, cpx<T>* dst) {
     const auto r = frs(a.b, ofs, plane_ok(p) && p > p0 && p < plast);
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) dst[j] = bload(tagT, r, vld[j]);
+    for (int j = 0; j < RPT; ++j) dst[j] = bload<kStream>(tagT, r, vld[j]);
   };
   // the second input of the s update (kRestrict, DOT 3), with the same planes
   cpx<T> Vr[DOT == 3 ? PF : 1][RPT];
@@ -595,7 +601,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
         const auto so = frs(a.zout, pofs - pstride, q_own);
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
-          bstore(r[j], so, vst[j]);
+          bstore<kStream>(r[j], so, vst[j]);
           if (q_own && vst[j] != kOOB) dacc[0] += (double)r[j].re * r[j].re + (double)r[j].im * r[j].im;
         }
         load_v2(p + PF - 1, pofs + (PF - 1) * pstride, Vr[DOT == 3 ? E : 0]);
@@ -619,7 +625,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
     if (MODE == kPrecApply) {
       const auto zo = frs(a.zout, pofs, p >= zown_lo && p <= zown_hi);
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) bstore(u[j], zo, vst[j]);
+      for (int j = 0; j < RPT; ++j) bstore<kStream>(u[j], zo, vst[j]);
     }
     sm.UH[S][wv][0][0][lane] = u[0];
     sm.UH[S][wv][0][1][lane] = h[0];
@@ -675,7 +681,7 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
       const bool in = plane_ok(q) && row_ok(y) && xin && xcomp;
       if (MODE == kApply || MODE == kPrecApply) {
         const cpx<T> yv = f_sel(in, f_add(A[j], N), f_zero<T>());
-        bstore(yv, wo, vst[j]);
+        bstore<kStream>(yv, wo, vst[j]);
         if (DOT != 0) {
           // owned vertices of plane q only (v2 of other vertices loads as zero)
           const cpx<T> d = Dv[(K + 1) & 1][j];
@@ -698,10 +704,10 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
         const bool cp = q_c && q >= 0 && ccol && x >= 0 && (y % 3) == 0;
         const cpx<T> scm = f_sel(VAR != 0 && cp, f_zero<T>(), s);
         // off the interior u, r and s vanish, so the stored value is zero there
-        bstore(f_add(Cp[j], scm), wo, vst[j]);
+        bstore<kStream>(f_add(Cp[j], scm), wo, vst[j]);
         if (VAR != 1 && q_c) bstore(VAR == 0 ? scm : s, co, vcp[j]);
       } else {
-        bstore(rv, wo, vst[j]);
+        bstore<kStream>(rv, wo, vst[j]);
       }
       const double r2 = vst[j] != kOOB ? (double)rv.re * rv.re + (double)rv.im * rv.im : 0.0;
       s2 += r2;
