@@ -295,9 +295,9 @@ __device__ __attribute__((always_inline)) inline void batch_item(const BatchArgs
 }
 
 // Occupancy hints by precision, chosen on the compiler's output with every
-// item type inlined into the kernel: complex128 takes 224 registers (2 waves
+// item type inlined into the kernel: complex128 takes 227 registers (2 waves
 // per SIMD; a hint of 3 fitted 168 but spilled 352 bytes per lane to
-// scratch), complex64 161 (3 waves per SIMD).
+// scratch), complex64 165 (3 waves per SIMD).
 template <class T>
 constexpr int kBatchWavesHint = 2;
 
