@@ -182,6 +182,31 @@ int mg_solve(mg_ctx* ctx, const mg_c128* b, mg_c128* u, double rtol, int maxit,
 /* res_h = |b - H u|_h (FP64). */
 int mg_residual_norm(mg_ctx* ctx, const mg_c128* u, const mg_c128* b, double* res_h);
 
+/* uf = P uc: d-linear prolongation (factor 3) from level - 1 to level, the
+ * paper's P of Section 4.  uc: device buffer of (3^(level-1)+1)^dim entries,
+ * uf: (3^level+1)^dim entries (C order, x fastest), not aliased; uf is zero
+ * on the boundary.  2 <= level <= level_max (MG_EINVAL otherwise).  Enqueued
+ * on the context stream. */
+int mg_prolong(mg_ctx* ctx, int level, const mg_c128* uc, mg_c128* uf);
+
+/* Nested (FMG-like) solve, the regular-grid form of the paper's remark on
+ * FMG-like cycles (Section 5): coarse solution approximations serve as
+ * initial guesses on finer grids.  chi: the nodal load on the finest grid
+ * (device, (3^level_max+1)^dim entries; b = eta_L^dim chi at interior
+ * vertices, as mg_rhs_from_nodal).  For l = level_start .. level_max - 1 the
+ * load is sampled at the vertices of level l, H_l u_l = b_l is solved to
+ * relative residual coarse_rtol (driver, maxit as mg_solve; MG_ENOTCONV on a
+ * coarse level is accepted) starting from P u_(l-1) (zero on level_start),
+ * each on a context with the parameters of ctx and level_max = l.
+ * Then u = P u_(level_max - 1) is the initial guess of mg_solve on ctx with
+ * rtol (u's entry value is ignored; level_start == level_max starts from
+ * zero).  iters_out / relres_out: those of the finest solve (may be NULL).
+ * Constant phi only (MG_EINVAL otherwise).  chi and u must not alias.  The
+ * coarser levels' contexts and buffers are made on the first call and kept
+ * with ctx (mg_destroy frees them).  Synchronises. */
+int mg_solve_nested(mg_ctx* ctx, const mg_c128* chi, mg_c128* u, int level_start, double coarse_rtol,
+                    double rtol, int maxit, int driver, int* iters_out, double* relres_out);
+
 /* Gradient of J = sum_S |u|^2 with respect to a nodal potential V entering
  * phi = phi0 - V (cell-averaged mass weight):
  *   dJdV_j = -2 Re sum_{cells c containing j} 2^-d eta^d lam_c^H M u_c,

@@ -27,5 +27,5 @@ from .cycle import (  # noqa: F401
     Params, omega_levels, semantic_cycle, textbook_additive, bottom_up_fas,
     Pipelined, zero_start_cycle,
 )
-from .solve import stationary_solve, bicgstab, dense_solve  # noqa: F401
+from .solve import stationary_solve, bicgstab, dense_solve, nested_initial_guess  # noqa: F401
 from .adjoint import shell_functional, potential_gradient  # noqa: F401

@@ -10,15 +10,20 @@ Test infrastructure only (see the package header).
   Sections 2 and 4); an addition beyond the paper, needed because the
   stationary cycle diverges on indefinite 3D problems;
 * `dense_solve`      -- LU on the dense interior matrix (tiny grids only), the
-  fixed point both drivers must reach.
+  fixed point both drivers must reach;
+* `nested_initial_guess` -- the finest level's starting point of a nested
+  solve: the level below solved with the load sampled there, prolonged.
 """
 
 from __future__ import annotations
 
 import numpy as np
 
+import dataclasses
+
 from .cycle import Params, Pipelined, zero_start_cycle
-from .discretisation import dense_H, interior_mask, zero_boundary
+from .discretisation import dense_H, interior_mask, lumped_rhs, zero_boundary
+from .transfer import prolong
 
 
 def stationary_solve(p: Params, b: np.ndarray, rtol: float, maxit: int, u0=None):
@@ -87,3 +92,19 @@ def dense_solve(p: Params, b: np.ndarray) -> np.ndarray:
     u = np.zeros((n,) * p.dim, dtype=np.complex128)
     u[m] = np.linalg.solve(A, np.asarray(b)[m])
     return u
+
+
+def nested_initial_guess(p: Params, chi: np.ndarray) -> np.ndarray:
+    """Initial guess of the finest level L in a nested solve, the regular-grid
+    form of the remark on FMG-like cycles (Section 5): coarse solutions act as
+    initial guesses on finer grids.  The load chi (nodal, finest grid) is
+    sampled at the vertices of level L - 1, that level is solved exactly
+    (dense_solve) and its solution prolonged d-linearly to level L.
+
+    Pinned: for a Poisson problem with a smooth manufactured solution the
+    guess converges to it at O(h^2) (tests/test_oracle_solve.py)."""
+    L = p.level_max
+    q = dataclasses.replace(p, level_max=L - 1, level_min=min(p.level_min, L - 1))
+    chic = np.asarray(chi)[(slice(None, None, 3),) * p.dim]
+    uc = dense_solve(q, lumped_rhs(chic, L - 1, p.theta))
+    return prolong(uc)

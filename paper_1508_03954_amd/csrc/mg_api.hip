@@ -294,6 +294,74 @@ int mg_solve(mg_ctx* c, const mg_c128* b, mg_c128* u, double rtol, int maxit, in
   return E.stationary((const cpx<double>*)b, (cpx<double>*)u, rtol, maxit, iters_out, relres_out);
 }
 
+int mg_prolong(mg_ctx* c, int level, const mg_c128* uc, mg_c128* uf) {
+  if (!c || !uc || !uf) return fail(MG_EINVAL, "NULL argument");
+  if ((const void*)uc == (const void*)uf) return fail(MG_EINVAL, "uc and uf must not alias");
+  if (level < 2 || level > c->p.level_max) return fail(MG_EINVAL, "need 2 <= level <= level_max");
+  MG_HIP(launch_prolong<double>(c->p.dim, (int)ipow(3, level) + 1, (const cpx<double>*)uc, (cpx<double>*)uf, c->s));
+  return MG_OK;
+}
+
+mg_ctx::~mg_ctx() {
+  for (Nested& q : nested) mg_destroy(q.ctx);
+  delete e64;
+  delete e32;
+  for (void* q : owned) (void)hipFree(q);
+}
+
+static int alloc_c128(mg_ctx* c, mg_c128** out, size_t count) {
+  void* q = nullptr;
+  const hipError_t e = hipMalloc(&q, count * sizeof(mg_c128));
+  if (e != hipSuccess) return fail(MG_ENOMEM, std::string("nested solve: ") + hipGetErrorString(e));
+  c->owned.push_back(q);
+  *out = (mg_c128*)q;
+  return MG_OK;
+}
+
+int mg_solve_nested(mg_ctx* c, const mg_c128* chi, mg_c128* u, int level_start, double coarse_rtol, double rtol,
+                    int maxit, int driver, int* iters_out, double* relres_out) {
+  if (!c || !chi || !u) return fail(MG_EINVAL, "NULL argument");
+  if ((const void*)chi == (const void*)u) return fail(MG_EINVAL, "chi and u must not alias");
+  const int L = c->p.level_max, dim = c->p.dim;
+  if (level_start < c->p.level_min || level_start > L) return fail(MG_EINVAL, "need level_min <= level_start <= level_max");
+  if (!(coarse_rtol > 0) || !(rtol > 0) || maxit < 1) return fail(MG_EINVAL, "need rtol, coarse_rtol > 0 and maxit >= 1");
+  if (driver != MG_STATIONARY && driver != MG_BICGSTAB) return fail(MG_EINVAL, "bad driver");
+  const bool varying = c->p.precision == MG_FP64 ? c->e64->varying : c->e32->varying;
+  if (varying) return fail(MG_EINVAL, "nested solves need a constant phi");
+  if (c->nested.size() < (size_t)L) c->nested.resize(L);
+  const mg_c128* uprev = nullptr;
+  // levels level_start .. L-1: solve with the load sampled there, from the
+  // prolonged solution of the level below (zero on the first)
+  for (int l = level_start; l < L; ++l) {
+    mg_ctx::Nested& q = c->nested[l];
+    const size_t Nl = (size_t)ipow(ipow(3, l) + 1, dim);
+    if (!q.ctx) {
+      mg_params pl = c->p;
+      pl.level_max = l;
+      pl.phi_field = nullptr;
+      MG_TRY(mg_setup(&pl, c->s, &q.ctx));
+      MG_TRY(alloc_c128(c, &q.chi, Nl));
+      MG_TRY(alloc_c128(c, &q.b, Nl));
+      MG_TRY(alloc_c128(c, &q.u, Nl));
+    }
+    MG_HIP(launch_sample<double>(dim, (int)ipow(3, l) + 1, (int)ipow(3, L - l), (const cpx<double>*)chi,
+                                 (cpx<double>*)q.chi, c->s));
+    MG_TRY(mg_rhs_from_nodal(q.ctx, q.chi, q.b));
+    if (uprev) MG_TRY(mg_prolong(q.ctx, l, uprev, q.u));
+    else MG_HIP(launch_fill(q.u, Nl * sizeof(mg_c128), c->s));
+    int its = 0;
+    double rel = 0;
+    const int rc = mg_solve(q.ctx, q.b, q.u, coarse_rtol, maxit, driver, &its, &rel);
+    if (rc != MG_OK && rc != MG_ENOTCONV) return rc;
+    uprev = q.u;
+  }
+  if (!c->nested_b) MG_TRY(alloc_c128(c, &c->nested_b, finest_N(c)));
+  MG_TRY(mg_rhs_from_nodal(c, chi, c->nested_b));
+  if (uprev) MG_TRY(mg_prolong(c, L, uprev, u));
+  else MG_HIP(launch_fill(u, finest_N(c) * sizeof(mg_c128), c->s));
+  return mg_solve(c, c->nested_b, u, rtol, maxit, driver, iters_out, relres_out);
+}
+
 int mg_tiles(const mg_ctx* c, int* current, int* count) {
   if (!c) return fail(MG_EINVAL, "NULL ctx");
   const bool f = c->p.precision == MG_FP64 ? c->e64->fused : c->e32->fused;

@@ -801,6 +801,7 @@ struct Engine {
     int it = 0;
     int status = MG_ENOTCONV;
     if (rel <= rtol) status = MG_OK;
+    const bool met_at_start = status == MG_OK;
     double h[3];
     for (it = 1; it <= maxit && status == MG_ENOTCONV; ++it) {
       const complex<double> beta = (rho_new / rho) * (alpha / om);
@@ -835,7 +836,7 @@ struct Engine {
         break;
       }
     }
-    if (its) *its = std::min(it, maxit);
+    if (its) *its = met_at_start ? 0 : std::min(it, maxit);
     if (relres) *relres = rel;
     return status;
   }
@@ -917,10 +918,14 @@ struct mg_ctx {
   OpData<double> op64;
   cpx<double>*r64 = nullptr, *b64 = nullptr;
   cpx<float>*r32 = nullptr, *e32v = nullptr;
-  ~mg_ctx() {
-    delete e64;
-    delete e32;
-    for (void* q : owned) (void)hipFree(q);
-  }
+  // nested solves: a context per coarser level (level_max = l) with its load,
+  // rhs and solution buffers, made on first use and kept
+  struct Nested {
+    mg_ctx* ctx = nullptr;
+    mg_c128 *chi = nullptr, *b = nullptr, *u = nullptr;
+  };
+  std::vector<Nested> nested;
+  mg_c128* nested_b = nullptr;    // finest rhs of a nested solve
+  ~mg_ctx();
 };
 

@@ -79,6 +79,12 @@ hipError_t launch_restrict(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStr
 
 template <class T>
 hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStream_t s);
+// vc(m) = vf(stride m) on a level with nc vertices per axis (every vertex).
+template <class T>
+hipError_t launch_sample(int dim, int nc, int stride, const cpx<T>* vf, cpx<T>* vc, hipStream_t s);
+// uf = P uc on the interior of the level with n vertices per axis, 0 on its boundary.
+template <class T>
+hipError_t launch_prolong(int dim, int n, const cpx<T>* uc, cpx<T>* uf, hipStream_t s);
 
 // Zero-start cycle pieces: z_l = Lop(omega D^-1 rho_l) + P z_(l-1), written
 // as z_l = s_l (masked on c-points for hb) + P g with g = z_(l-1), or for BPX

@@ -277,6 +277,31 @@ __global__ void k_inject(int nc, const cpx<T>* __restrict__ vf, cpx<T>* __restri
   }
 }
 
+// Nested iteration: vc(m) = vf(stride m) (the load sampled on a coarser level)
+// and uf = P uc on the interior of the finer level, zero on its boundary.
+template <class T, int D>
+__global__ void k_sample(int nc, int stride, const cpx<T>* __restrict__ vf, cpx<T>* __restrict__ vc) {
+  const int nf = stride * (nc - 1) + 1;
+  MG_ROWS(D, nc) {
+    int m[3];
+    long long i;
+    if (!row_vertex<D>(row_, x_, nc, m, i)) continue;
+    int j[3] = {stride * m[0], stride * m[1], stride * m[2]};
+    vc[i] = vf[ravel<D>(j, nf)];
+  }
+}
+
+template <class T, int D>
+__global__ void k_prolong(int n, const cpx<T>* __restrict__ uc, cpx<T>* __restrict__ uf) {
+  const int nc = (n - 1) / 3 + 1;
+  MG_ROWS(D, n) {
+    int j[3];
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
+    uf[i] = is_interior<D>(j, n) ? prolong_at<T, D>(uc, nc, j) : czero<T>();
+  }
+}
+
 // Zero-start cycle, upward part on one level:
 //   s = omega rho / D;  z = Lop(s) + P z_c, Lop = id (add), c-point mask (hb),
 //   s - P I s (BPX); on the coarsest level z = s.
@@ -799,6 +824,20 @@ hipError_t launch_inject(int dim, int nc, const cpx<T>* vf, cpx<T>* vc, hipStrea
 }
 
 template <class T>
+hipError_t launch_sample(int dim, int nc, int stride, const cpx<T>* vf, cpx<T>* vc, hipStream_t s) {
+  if (nc < 2 || stride < 1) return hipErrorInvalidValue;
+  MG_DISPATCH(dim, k_sample, row_grid(nc, dim), nc, stride, vf, vc);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_prolong(int dim, int n, const cpx<T>* uc, cpx<T>* uf, hipStream_t s) {
+  if (n < 4 || (n - 1) % 3 != 0) return hipErrorInvalidValue;
+  MG_DISPATCH(dim, k_prolong, row_grid(n, dim), n, uc, uf);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_prec_up(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, int mask_c, int is_lmin,
                           const cpx<T>* gc, cpx<T>* z, hipStream_t s) {
   MG_DISPATCH(dim, k_prec_up, row_grid(op.n, dim), op, rho, omega, mask_c, is_lmin, gc, z);
@@ -965,6 +1004,8 @@ hipError_t launch_finish_sum2(const double* partials, int count, double* out, hi
                                        const cpx<T>*, cpx<T>*, cpx<T>*, hipStream_t);                            \
   template hipError_t launch_restrict<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                        \
   template hipError_t launch_inject<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                          \
+  template hipError_t launch_sample<T>(int, int, int, const cpx<T>*, cpx<T>*, hipStream_t);                     \
+  template hipError_t launch_prolong<T>(int, int, const cpx<T>*, cpx<T>*, hipStream_t);                         \
   template hipError_t launch_prec_up<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, int, int, const cpx<T>*,   \
                                         cpx<T>*, hipStream_t);                                                  \
   template hipError_t launch_prec_g<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, const cpx<T>*, cpx<T>*,     \

@@ -31,7 +31,7 @@ EXPORTED = [
     "mg_precondition", "mg_precondition_apply", "mg_solve", "mg_residual_norm", "mg_grad_potential", "mg_time_sweeps",
     "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
     "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
-    "mg_batch_trace", "mg_batch_get_trace",
+    "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested",
 ]
 
 
@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_solve.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.mg_residual_norm.argtypes = [P, P, P, ctypes.POINTER(D)]
     lib.mg_grad_potential.argtypes = [P, P, P, P]
+    lib.mg_prolong.argtypes = [P, I, P, P]
+    lib.mg_solve_nested.argtypes = [P, P, P, I, D, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.mg_time_sweeps.argtypes = [P, I]
     lib.mg_tiles.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.mg_set_tile.argtypes = [P, I]
@@ -276,6 +278,32 @@ class Solver:
         rel = ctypes.c_double(0.0)
         rc = self._lib.mg_solve(self._ctx, _ptr(b), _ptr(u), rtol, maxit, DRIVERS[driver],
                                 ctypes.byref(its), ctypes.byref(rel))
+        _check(rc, allow=(MG_ENOTCONV, MG_EDIVERGED))
+        return u, its.value, rel.value, rc
+
+    def prolong(self, uc, level: int):
+        """P uc from level - 1 to `level` (a new complex128 tensor of that level's size)."""
+        t = self._torch
+        if not isinstance(uc, t.Tensor):
+            uc = t.from_numpy(np.ascontiguousarray(uc))
+        uc = uc.to(device="cuda", dtype=t.complex128).contiguous()
+        if tuple(uc.shape) != (3 ** (level - 1) + 1,) * self.dim:
+            raise ValueError(f"expected level {level - 1} shape, got {tuple(uc.shape)}")
+        uf = self._new((3 ** level + 1,) * self.dim)
+        _check(self._lib.mg_prolong(self._ctx, level, _ptr(uc), _ptr(uf)))
+        return uf
+
+    def solve_nested(self, chi, level_start: int, coarse_rtol: float = 1e-2, rtol: float = 1e-10,
+                     maxit: int = 500, driver: str = "bicgstab"):
+        """Nested solve from the nodal load chi (finest size): levels level_start ..
+        level_max - 1 to coarse_rtol, each from the prolonged solution below, then
+        the finest level to rtol.  Returns (u, finest iterations, relative residual, status)."""
+        chi = self._as_dev(chi)
+        u = self._new()
+        its = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        rc = self._lib.mg_solve_nested(self._ctx, _ptr(chi), _ptr(u), level_start, coarse_rtol, rtol, maxit,
+                                       DRIVERS[driver], ctypes.byref(its), ctypes.byref(rel))
         _check(rc, allow=(MG_ENOTCONV, MG_EDIVERGED))
         return u, its.value, rel.value, rc
 

@@ -322,6 +322,56 @@ def test_bicgstab_reaches_dense_solution(dim, L):
     assert relerr(to_np(u), ref) <= 1e-9
 
 
+@pytest.mark.parametrize("dim,level", [(2, 2), (2, 4), (3, 3), (3, 4)])
+def test_prolong_matches_oracle(dim, level):
+    """mg_prolong against the oracle's tensor-product P (interior; zero boundary)."""
+    print(f"\n[case] prolong dim={dim} level={level}", flush=True)
+    mg = mgmod()
+    s = mg.Solver(dim, level, theta=0.3, phi=100.0)
+    uc = rand_c((3 ** (level - 1) + 1,) * dim, 21, zero_bnd=False)
+    got = to_np(s.prolong(torch.from_numpy(uc), level))
+    ref = O.zero_boundary(O.prolong(uc))
+    assert relerr(got, ref) <= 1e-14
+
+
+NESTED_CASES = [(2, 4, 90 * (1 + 0.5j), 0.3), (3, 3, 400.0, math.pi / 6)]
+
+
+@pytest.mark.parametrize("dim,L,phi,theta", NESTED_CASES)
+def test_nested_initial_guess_matches_oracle(dim, L, phi, theta):
+    """With a finest-level target the start already meets (rtol 10), the
+    nested solve returns its initial guess: level L - 1 solved (to 1e-13 here)
+    with the sampled load and prolonged.  Oracle: the dense solution of level
+    L - 1, prolonged."""
+    print(f"\n[case] nested guess dim={dim} L={L}", flush=True)
+    mg = mgmod()
+    n = 3 ** L + 1
+    chi = rand_c((n,) * dim, 31, zero_bnd=False)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant="bpx")
+    u, its, rel, rc = s.solve_nested(torch.from_numpy(chi), level_start=1, coarse_rtol=1e-13, rtol=10.0,
+                                     maxit=500, driver="bicgstab")
+    assert rc == 0 and its == 0
+    ref = O.nested_initial_guess(Params(dim=dim, level_max=L, theta=theta, phi=phi), chi)
+    assert relerr(to_np(u), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("dim,L,phi,driver", [(2, 3, 400.0, "bicgstab"), (3, 2, 400.0, "bicgstab"),
+                                              (2, 3, -100.0, "stationary")])
+def test_nested_solve_reaches_dense_solution(dim, L, phi, driver):
+    print(f"\n[case] nested solve dim={dim} L={L} {driver}", flush=True)
+    mg = mgmod()
+    theta = math.pi / 6 if phi > 0 else 0.0
+    n = 3 ** L + 1
+    chi = rand_c((n,) * dim, 41, zero_bnd=False)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant="bpx", omega=0.6)
+    u, its, rel, rc = s.solve_nested(torch.from_numpy(chi), level_start=1, coarse_rtol=1e-6, rtol=1e-12,
+                                     maxit=500, driver=driver)
+    assert rc == 0 and rel <= 1e-12
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi)
+    ref = O.dense_solve(p, O.lumped_rhs(chi, L, theta))
+    assert relerr(to_np(u), ref) <= 1e-9
+
+
 def test_stationary_solve_poisson():
     mg = mgmod()
     from paper_1508_03954_amd.inputs import sine_load

@@ -56,3 +56,32 @@ def test_manufactured_solution_second_order(dim, levels, phi):
     ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
     for r in ratios:
         assert 7.0 < r < 11.0, (errs, ratios)
+
+
+def test_nested_initial_guess_converges_at_second_order():
+    """The nested guess (level L - 1 solved with the sampled load, prolonged)
+    approaches the manufactured Poisson solution prod sin(pi x) at O(h^2):
+    its max error drops by about 9 from L = 3 to L = 4 (2D), and it beats the
+    zero guess by far."""
+    errs = []
+    for L in (3, 4):
+        p = Params(dim=2, level_max=L, theta=0.0, phi=0.0)
+        guess = O.nested_initial_guess(p, sine_load(L, 2))
+        exact = sine_solution(L, 2)
+        # the guess is zero on the boundary, where the solution vanishes too
+        assert np.all(guess[0, :] == 0) and np.all(guess[:, -1] == 0)
+        errs.append(np.abs(guess - exact).max())
+        assert errs[-1] < 0.1 * np.abs(exact).max()
+    assert 6.0 < errs[0] / errs[1] < 12.0, errs
+
+
+def test_nested_initial_guess_on_coarse_vertices_is_the_coarse_solution():
+    """At the vertices the two levels share, the guess equals the level L - 1
+    discrete solution (P reproduces coarse values at c-points)."""
+    p = Params(dim=2, level_max=3, theta=np.pi / 6, phi=90 * (1 + 0.5j))
+    rng = np.random.default_rng(11)
+    chi = rng.standard_normal((28, 28)) + 1j * rng.standard_normal((28, 28))
+    guess = O.nested_initial_guess(p, chi)
+    q = Params(dim=2, level_max=2, theta=np.pi / 6, phi=90 * (1 + 0.5j))
+    uc = O.dense_solve(q, O.lumped_rhs(chi[::3, ::3], 2, np.pi / 6))
+    np.testing.assert_allclose(guess[::3, ::3], uc, rtol=0, atol=1e-13 * np.abs(uc).max())
