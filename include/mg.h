@@ -46,9 +46,13 @@ enum { MG_ADD = 0, MG_HB = 1, MG_BPX = 2 };
 
 /* Relaxation schemes omega_l (table of Section 5.1), succ = l_max - l:
  * CONST omega; JACOBI omega on l_max only; LGRID omega where succ <= omega_L;
- * EXP omega^(succ+1); TRANSITION omega^((1-1/n)(succ+1)), n = cycle counter. */
+ * EXP omega^(succ+1); TRANSITION omega^((1-1/n)(succ+1)), n = cycle counter.
+ * TWO_PHASE: the two-phase relaxation of Section 7.4 (used there with plain
+ * Jacobi, level_min = level_max): omega on odd cycles n and -conj(omega) on
+ * even ones, on every level.  The zero-start cycle of the Krylov driver uses
+ * n = 1 for every scheme. */
 enum { MG_OMEGA_CONST = 0, MG_OMEGA_JACOBI = 1, MG_OMEGA_LGRID = 2,
-       MG_OMEGA_EXP = 3, MG_OMEGA_TRANSITION = 4 };
+       MG_OMEGA_EXP = 3, MG_OMEGA_TRANSITION = 4, MG_OMEGA_TWO_PHASE = 5 };
 
 /* Arithmetic of the cycle: complex128 throughout, or complex64 level
  * corrections inside an FP64 residual-refinement loop (mg_solve only; the

@@ -35,7 +35,7 @@ from .discretisation import (apply_H, coarse_fields, diag_H, interior_mask, norm
 from .transfer import cpoint_mask, inject, prolong, restrict
 
 VARIANTS = ("add", "hb", "bpx")
-OMEGA_SCHEMES = ("const", "jacobi", "lgrid", "exp", "transition")
+OMEGA_SCHEMES = ("const", "jacobi", "lgrid", "exp", "transition", "two_phase")
 
 
 @dataclasses.dataclass
@@ -96,6 +96,9 @@ def omega_levels(p: Params, iteration: int = 1) -> Dict[int, complex]:
     lgrid       omega where succ <= omega_L, 0 elsewhere
     exp         omega^(succ + 1)                      (exponential damping)
     transition  omega^((1 - 1/n)(succ + 1)), n the iteration counter (n >= 1)
+    two_phase   omega on odd n, -conj(omega) on even n, every level (the
+                two-phase relaxation of Section 7.4; pinned against explicit
+                Jacobi steps with a dense matrix in tests/test_oracle_cycle.py)
     """
     out = {}
     for lev in p.levels:
@@ -109,6 +112,8 @@ def omega_levels(p: Params, iteration: int = 1) -> Dict[int, complex]:
             out[lev] = w if succ <= p.omega_L else 0j
         elif p.omega_scheme == "exp":
             out[lev] = w ** (succ + 1)
+        elif p.omega_scheme == "two_phase":
+            out[lev] = w if iteration % 2 == 1 else -np.conj(w)
         else:
             out[lev] = w ** ((1.0 - 1.0 / iteration) * (succ + 1))
     return out

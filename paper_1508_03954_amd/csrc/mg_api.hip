@@ -8,7 +8,7 @@ static int check_params(const mg_params* p) {
   const int maxL = p->dim == 3 ? 6 : 9;   // every vertex index fits 32 bits
   if (p->level_max > maxL) return fail(MG_EINVAL, "level_max too large (3D: <= 6, 2D: <= 9)");
   if (p->variant < MG_ADD || p->variant > MG_BPX) return fail(MG_EINVAL, "bad variant");
-  if (p->omega_scheme < MG_OMEGA_CONST || p->omega_scheme > MG_OMEGA_TRANSITION) return fail(MG_EINVAL, "bad omega scheme");
+  if (p->omega_scheme < MG_OMEGA_CONST || p->omega_scheme > MG_OMEGA_TWO_PHASE) return fail(MG_EINVAL, "bad omega scheme");
   if (p->precision != MG_FP64 && p->precision != MG_FP32_REFINE) return fail(MG_EINVAL, "bad precision");
   if (p->restrict_form < MG_RESTRICT_AUTO || p->restrict_form > MG_RESTRICT_GALERKIN) return fail(MG_EINVAL, "bad restrict_form");
   if (p->sweep < MG_SWEEP_AUTO || p->sweep > MG_SWEEP_FUSED) return fail(MG_EINVAL, "bad sweep");

@@ -443,7 +443,8 @@ struct Batch : BatchBase {
     P.lmin = E.lmin;
     P.variant = E.variant;
     if (!E.fused) return fail(MG_EINVAL, "batched problems need the fused finest sweep (constant phi, level_max > level_min)");
-    if (E.scheme == MG_OMEGA_TRANSITION) return fail(MG_EINVAL, "batched cycles need an iteration-independent omega scheme");
+    if (E.scheme == MG_OMEGA_TRANSITION || E.scheme == MG_OMEGA_TWO_PHASE)
+      return fail(MG_EINVAL, "batched cycles need an iteration-independent omega scheme");
     if (E.L >= kBMaxLevels) return fail(MG_EINVAL, "level_max too large for a batch");
     for (int l = E.lmin; l <= E.L; ++l) {
       BLevel<T>& v = P.lv[l];

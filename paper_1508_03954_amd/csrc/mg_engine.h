@@ -104,6 +104,7 @@ inline complex<double> omega_level(int scheme, complex<double> w, int omega_L, i
     case MG_OMEGA_JACOBI: return succ == 0 ? w : 0.0;
     case MG_OMEGA_LGRID: return succ <= omega_L ? w : 0.0;
     case MG_OMEGA_EXP: return std::pow(w, (double)(succ + 1));
+    case MG_OMEGA_TWO_PHASE: return std::max(iteration, 1) % 2 == 1 ? w : -std::conj(w);
     default: return std::pow(w, (1.0 - 1.0 / std::max(iteration, 1)) * (succ + 1));
   }
 }

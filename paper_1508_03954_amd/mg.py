@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libmg.so")
 
 MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ENOTCONV, MG_EDIVERGED = 0, -1, -2, -3, -4, -5
 VARIANTS = {"add": 0, "hb": 1, "bpx": 2}
-OMEGA_SCHEMES = {"const": 0, "jacobi": 1, "lgrid": 2, "exp": 3, "transition": 4}
+OMEGA_SCHEMES = {"const": 0, "jacobi": 1, "lgrid": 2, "exp": 3, "transition": 4, "two_phase": 5}
 PRECISIONS = {"fp64": 0, "fp32_refine": 1}
 DRIVERS = {"stationary": 0, "bicgstab": 1}
 RESTRICT_FORMS = {"auto": 0, "fas": 1, "galerkin": 2}

@@ -123,6 +123,10 @@ CYCLE_CASES = [
     (3, 4, 1, "bpx", "galerkin", "fused", "const", "const"),
     (3, 4, 1, "add", "galerkin", "fused", "const", "exp"),
     (3, 2, 1, "bpx", "galerkin", "fused", "const", "const"),
+    # two-phase relaxation: plain Jacobi (one level) and multilevel, fused and not
+    (2, 3, 3, "add", "galerkin", "generic", "const", "two_phase"),
+    (2, 4, 1, "hb", "galerkin", "generic", "const", "two_phase"),
+    (3, 3, 1, "bpx", "galerkin", "fused", "const", "two_phase"),
 ]
 
 

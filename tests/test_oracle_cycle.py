@@ -195,3 +195,31 @@ def test_omega_table():
     assert omega_levels(p, 1) == {4: 1, 3: 1, 2: 1, 1: 1}
     w = omega_levels(p, 2)
     assert abs(w[3] - 0.5 ** 1.0) < 1e-15 and abs(w[1] - 0.5 ** 2.0) < 1e-15
+
+
+def test_two_phase_relaxation_is_alternating_jacobi():
+    """Single level, two-phase scheme (Section 7.4): four pipelined cycles and
+    a flush equal four explicit Jacobi steps on the dense interior matrix with
+    omega_1 = 0.01 (sqrt 3 - i) and omega_2 = -conj(omega_1) in turn."""
+    dim, level, theta, phi = 2, 2, 0.5, 90 * (1 + 0.5j)
+    w1 = 0.01 * (math.sqrt(3) - 1j)
+    p = Params(dim=dim, level_max=level, level_min=level, theta=theta, phi=phi, omega=w1,
+               omega_scheme="two_phase")
+    assert omega_levels(p, 1)[level] == w1 and omega_levels(p, 2)[level] == -np.conj(w1)
+    rng = np.random.default_rng(7)
+    n = 3 ** level + 1
+    b = rand_c((n,) * dim, rng)
+    u0 = rand_c((n,) * dim, rng)
+    pipe = O.Pipelined(p, b, u0)
+    for _ in range(4):
+        pipe.cycle()
+    got = pipe.flush()
+    A = O.dense_H(n, dim, level, theta, phi)
+    m = interior_mask(n, dim)
+    d = np.diag(A)
+    x = u0[m].copy()
+    for k in range(4):
+        w = w1 if k % 2 == 0 else -np.conj(w1)
+        x = x + w * (b[m] - A @ x) / d
+    np.testing.assert_allclose(got[m], x, rtol=0, atol=1e-13 * np.abs(x).max())
+    assert np.all(got[~m] == 0)
