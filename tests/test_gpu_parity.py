@@ -359,15 +359,17 @@ def test_nested_initial_guess_matches_oracle(dim, L, phi, theta):
     assert relerr(to_np(u), ref) <= 1e-9
 
 
-@pytest.mark.parametrize("dim,L,phi,driver", [(2, 3, 400.0, "bicgstab"), (3, 2, 400.0, "bicgstab"),
-                                              (2, 3, -100.0, "stationary")])
-def test_nested_solve_reaches_dense_solution(dim, L, phi, driver):
-    print(f"\n[case] nested solve dim={dim} L={L} {driver}", flush=True)
+@pytest.mark.parametrize("dim,L,phi,driver,precision", [(2, 3, 400.0, "bicgstab", "fp64"),
+                                                        (3, 2, 400.0, "bicgstab", "fp64"),
+                                                        (2, 3, -100.0, "stationary", "fp64"),
+                                                        (2, 3, 400.0, "bicgstab", "fp32_refine")])
+def test_nested_solve_reaches_dense_solution(dim, L, phi, driver, precision):
+    print(f"\n[case] nested solve dim={dim} L={L} {driver} {precision}", flush=True)
     mg = mgmod()
     theta = math.pi / 6 if phi > 0 else 0.0
     n = 3 ** L + 1
     chi = rand_c((n,) * dim, 41, zero_bnd=False)
-    s = mg.Solver(dim, L, theta=theta, phi=phi, variant="bpx", omega=0.6)
+    s = mg.Solver(dim, L, theta=theta, phi=phi, variant="bpx", omega=0.6, precision=precision)
     u, its, rel, rc = s.solve_nested(torch.from_numpy(chi), level_start=1, coarse_rtol=1e-6, rtol=1e-12,
                                      maxit=500, driver=driver)
     assert rc == 0 and rel <= 1e-12
