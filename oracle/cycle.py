@@ -285,6 +285,48 @@ class Pipelined:
             self.si[lev][...] = 0
         return self.u[self.p.level_max].copy()
 
+    def restricted_residual_state(self) -> dict:
+        """The coarse fields the last cycle's post-phase wrote, formed from the
+        finest residual instead of from each level's own FAS residual.
+
+        With constant phi and a uniform rotation, Lemma 2 and the Galerkin
+        identity R H_l P = H_(l-1) give b_(l-1) - H_(l-1) I u_l = R r_l, and
+        Lemma 1 (u_(l-1) = I u_l when residuals are evaluated) turns this into
+        r_(l-1) = R r_l on every coarse level, so r_l = R^(L-l) r_L.  The
+        post-phase then forms s_l = omega_l r_l / D_l, sc_l (s_l, or 0 on
+        c-points for hb / BPX), si_(l-1) = I s_l (BPX) and sf_(l-1) =
+        I(sf_l + sc_l), from the finest level down.
+
+        Returns {level: {"b": r_l, "sc", "sf", "si"}} for the coarse levels l < L
+        ("b" holds the residual r_l = b_l - H_l u_l).  Unlike b_l - H_l u_l,
+        whose two terms grow with the iterate while their difference shrinks,
+        nothing here is formed by cancellation: the values carry rounding
+        relative to their own size.  Valid for the Galerkin case only; pinned
+        against the pipeline's own post-phase in tests/test_oracle_cycle.py.
+        """
+        p = self.p
+        L, lmin = p.level_max, p.level_min
+        assert p.phi_nodal is None, "the restricted-residual form needs a constant phi"
+        om = omega_levels(p, self.iteration)
+        r = {L: zero_boundary(self.residual)}
+        for lev in range(L, lmin, -1):
+            r[lev - 1] = restrict(r[lev])
+        out = {lev: {"b": r[lev]} for lev in p.levels if lev < L}
+        sf_l = self.sf[L]
+        for lev in range(L, lmin - 1, -1):
+            s = _smooth(p, lev, r[lev], om[lev])
+            sc = np.where(p.cpoints(lev), 0, s) if p.variant in ("hb", "bpx") else s
+            if lev < L:
+                out[lev]["sc"] = sc
+            if lev > lmin:
+                out[lev - 1]["si"] = inject(s) if p.variant == "bpx" else self.si[lev - 1].copy()
+                out[lev - 1]["sf"] = inject(sf_l + sc)
+                sf_l = out[lev - 1]["sf"]
+        for lev in range(lmin, L):
+            out[lev].setdefault("sf", self.sf[lev].copy())
+            out[lev].setdefault("si", self.si[lev].copy())
+        return out
+
     def state(self) -> dict:
         return {"u": {k: v.copy() for k, v in self.u.items()},
                 "b": {k: v.copy() for k, v in self.b.items()},

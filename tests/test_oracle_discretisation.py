@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle.cycle import Params
 from oracle.discretisation import element_matrices, interior_mask
 
 GAUSS_X, GAUSS_W = np.polynomial.legendre.leggauss(3)
@@ -192,3 +193,29 @@ def test_paper_regular_grid_vertex_count():
     for dim, level, count in ((int(a), int(b), int(c)) for a, b, c in rows):
         n = 3 ** level + 1
         assert interior_mask(n, dim).sum() == count
+
+
+@pytest.mark.parametrize("dim,L,lmin", [(2, 4, 1), (2, 4, 3), (3, 3, 1)])
+def test_coarse_fields_sample_the_analytic_field(dim, L, lmin):
+    """Rediscretisation (Section 4): the nodal phi of every coarse level is the
+    function phi(x) itself at that level's vertices x_j = j 3^-l.  The field
+    is smooth, complex, nonlinear and not symmetric in the axes, so a wrong
+    stride, an offset, a transposed axis or an average instead of a sample
+    would all change it."""
+    from paper_1508_03954_amd.inputs import vertex_coords
+
+    def phi_fn(xs):
+        a = xs[0]
+        c = xs[-1]
+        mid = xs[1] if len(xs) == 3 else 0.25
+        return (50 + 30 * np.sin(2.1 * a + 0.7 * c) + 17 * a * c ** 2 + 5 * mid) * (1 + 0.3j) + 3j * c
+
+    shape = lambda l: (3 ** l + 1,) * dim
+    fine = np.broadcast_to(phi_fn(vertex_coords(L, dim)), shape(L)).astype(np.complex128)
+    fields = O.coarse_fields(fine, L, lmin)
+    assert sorted(fields) == list(range(lmin, L + 1))
+    p = Params(dim=dim, level_max=L, level_min=lmin, phi=0, phi_nodal=fine)
+    for lev in range(lmin, L + 1):
+        ref = np.broadcast_to(phi_fn(vertex_coords(lev, dim)), shape(lev))
+        np.testing.assert_allclose(fields[lev], ref, rtol=1e-14, atol=0)
+        np.testing.assert_allclose(p.phi_at(lev), ref, rtol=1e-14, atol=0)

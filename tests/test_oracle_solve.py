@@ -85,3 +85,34 @@ def test_nested_initial_guess_on_coarse_vertices_is_the_coarse_solution():
     q = Params(dim=2, level_max=2, theta=np.pi / 6, phi=90 * (1 + 0.5j))
     uc = O.dense_solve(q, O.lumped_rhs(chi[::3, ::3], 2, np.pi / 6))
     np.testing.assert_allclose(guess[::3, ::3], uc, rtol=0, atol=1e-13 * np.abs(uc).max())
+
+
+def _rotated_mms_error(dim, L, theta, phi, weight_theta):
+    """Max error of the discrete solution against prod sin(pi x) for the load
+    chi = (d pi^2 e^(-2 i theta) - phi) prod sin(pi x), lumped with the weight
+    of `weight_theta` (the correct weight is eta_L^d = (3^-L e^(i theta))^d)."""
+    p = Params(dim=dim, level_max=L, theta=theta, phi=phi, variant="bpx", omega=0.6)
+    exact = sine_solution(L, dim)
+    chi = (dim * np.pi ** 2 * np.exp(-2j * theta) - phi) * exact
+    b = O.lumped_rhs(chi, L, weight_theta)
+    if (3 ** L - 1) ** dim <= 700:
+        u = O.dense_solve(p, b)
+    else:
+        u, its, hist, ok = O.bicgstab(p, b, 1e-13, 400)
+        assert ok
+    return np.abs(u - exact).max()
+
+
+@pytest.mark.parametrize("dim,levels", [(2, (2, 3, 4)), (3, (2, 3))])
+def test_rotated_grid_manufactured_solution(dim, levels):
+    """Complex grid rotation (Section 2, CSG) with the lumped load weight
+    eta_L^d: on the grid x -> x e^(i theta) the discrete operator approximates
+    e^(-2 i theta) (-Lap) - phi, so the load (d pi^2 e^(-2 i theta) - phi)
+    prod sin(pi x) has the solution prod sin(pi x), reached at O(h^2).  The
+    weights h^d or eta^(d-2) in place of eta^d leave an O(1) error."""
+    theta, phi = np.pi / 6, 30 * (1 + 0.2j)
+    errs = [_rotated_mms_error(dim, L, theta, phi, theta) for L in levels]
+    for a, c in zip(errs, errs[1:]):
+        assert 7.0 < a / c < 11.0, errs
+    # a planted mistake in the weight (h^d: the unrotated weight) fails the pin
+    assert _rotated_mms_error(dim, levels[-1], theta, phi, 0.0) > 0.3
