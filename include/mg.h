@@ -133,8 +133,10 @@ int mg_apply(mg_ctx* ctx, const mg_c128* x, mg_c128* y);
 int mg_rhs_from_nodal(mg_ctx* ctx, const mg_c128* chi, mg_c128* b);
 
 /* Sets the finest right-hand side and resets the pipeline helpers
- * (sc = sf = si = 0) and the cycle counter; a pending update is discarded
- * (call mg_flush first to keep it). */
+ * (sc = sf = si = 0, the start of the single-sweep iteration of Section 5.1)
+ * and the cycle counter of the iteration-dependent relaxation schemes; a
+ * pending update is discarded (call mg_flush first to keep it).  b: device,
+ * finest size; boundary entries ignored. */
 int mg_set_rhs(mg_ctx* ctx, const mg_c128* b);
 
 /* Sets the finest iterate, injects it into every coarser level (the FAS
@@ -150,8 +152,11 @@ int mg_set_solution(mg_ctx* ctx, const mg_c128* u);
  * synchronises. */
 int mg_cycle(mg_ctx* ctx, int ncycles, double* res_h, double* res_max);
 
-/* Applies the pending update (pre-phase only), clears the helpers and, if
- * u_out != NULL, copies the finest iterate into it. */
+/* Applies the pending update (the descent of Algorithms tdAdd / tdBPX alone,
+ * which completes the half-shifted iteration of Section 5.1), clears the
+ * helpers and, if u_out != NULL, copies the finest iterate into it (device,
+ * finest size).  The cycle counter is kept: the transition and two-phase
+ * schemes continue with the next cycle number after a flush. */
 int mg_flush(mg_ctx* ctx, mg_c128* u_out);
 
 /* Copies one level field into a device buffer of (3^level+1)^d complex128.
@@ -175,11 +180,20 @@ int mg_precondition_apply(mg_ctx* ctx, const mg_c128* v, mg_c128* z, mg_c128* y)
 
 /* Solves H u = b to relative residual rtol (|b - H u| / |b|, Euclidean over
  * interior vertices).  u holds the initial guess on entry and the result on
- * exit.  driver: MG_STATIONARY (cycles, then flush) or MG_BICGSTAB.  With
- * MG_FP32_REFINE the inner corrections run in complex64 inside an FP64
- * residual-refinement loop.  iters_out / relres_out may be NULL.  Returns
- * MG_ENOTCONV or MG_EDIVERGED (u valid) when the target is missed.  Resets
- * the cycle state. */
+ * exit; b, u: device, finest size.  driver:
+ *   MG_STATIONARY  the paper's iteration (Section 5.1): pipelined cycles until
+ *                  the residual a cycle reports (that of the iterate before
+ *                  it) meets rtol, then a flush; *iters_out = cycles run, u =
+ *                  the iterate after them.  MG_ENOTCONV also when the returned
+ *                  iterate itself misses rtol;
+ *   MG_BICGSTAB    BiCGStab preconditioned by one cycle from a zero start (the
+ *                  cycle used as a preconditioner, Sections 2 and 4; the Krylov
+ *                  method is an addition to the paper).
+ * With MG_FP32_REFINE the inner corrections run in complex64 inside an FP64
+ * residual-refinement loop.  iters_out / relres_out may be NULL; *relres_out
+ * is the returned iterate's relative residual.  Returns MG_ENOTCONV or
+ * MG_EDIVERGED (non-finite residual or one above 1e8 times the first; u
+ * valid) when the target is missed.  Resets the cycle state. */
 int mg_solve(mg_ctx* ctx, const mg_c128* b, mg_c128* u, double rtol, int maxit,
              int driver, int* iters_out, double* relres_out);
 
@@ -261,7 +275,8 @@ int mg_sweep_time(mg_ctx* ctx, double* total_ms, int* count);
  * cycle and leaves each context in the state mg_cycle(ctx, 1, ...) would, with
  * the fused sweep in the batch's tiling.  Requirements per problem: constant
  * phi, level_max > level_min, level_max <= 7, an iteration-independent omega
- * scheme (not MG_OMEGA_TRANSITION); all problems share one precision.
+ * scheme (not MG_OMEGA_TRANSITION or MG_OMEGA_TWO_PHASE); all problems share
+ * one precision.
  * Problems are advanced concurrently: a call overlaps the coarse levels of
  * small problems with the finest sweeps of large ones. */
 typedef struct mg_batch mg_batch;
@@ -293,6 +308,14 @@ int mg_batch_autotune(mg_batch* batch, int reps, int* config, double* us_per_cyc
 
 /* Number of batch configurations the autotuner tries. */
 int mg_batch_configs(void);
+
+/* Bound of every dependency wait inside the batched kernel, in polls (default
+ * 2^20, about a second; 0 <= polls <= 2^26, MG_EINVAL otherwise).  A wait
+ * that reaches it gives up: the item is skipped, the launch still drains, and
+ * the mg_batch_cycle call returns MG_EDEVICE with the state undefined.  For
+ * tests of that error path (a bound of 0 makes every wait that finds its
+ * dependency unfinished give up at once). */
+int mg_batch_set_spin_limit(mg_batch* batch, long long polls);
 
 /* Scheduler trace.  mg_batch_trace(b, 1) makes every following batched cycle
  * record, per work item, the device wall clock (100 MHz) when its workgroup

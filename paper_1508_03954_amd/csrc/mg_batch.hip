@@ -395,8 +395,14 @@ Engine<double>* engine_of<double>(mg_ctx* c) { return c->e64; }
 template <>
 Engine<float>* engine_of<float>(mg_ctx* c) { return c->e32; }
 
+// Polls of one dependency wait before it gives up: the default bounds a wait
+// to about a second; the settable maximum to about a minute.
+constexpr unsigned kDefaultSpinLimit = 1u << 20;
+constexpr long long kMaxSpinLimit = 1ll << 26;
+
 struct BatchBase {
   virtual ~BatchBase() {}
+  virtual void set_spin_limit(unsigned v) = 0;
   virtual int cycle(int ncycles, double* res) = 0;
   virtual int autotune(int reps, int* best, double* best_us, double* times) = 0;
   virtual int set_trace(bool on) = 0;
@@ -417,6 +423,7 @@ struct Batch : BatchBase {
   double* dhist = nullptr;
   int hist_cap = 0;
   int grid = 0;
+  unsigned spin_limit = kDefaultSpinLimit;
   std::vector<void*> owned;
 
   ~Batch() override {
@@ -563,6 +570,8 @@ struct Batch : BatchBase {
     return MG_OK;
   }
 
+  void set_spin_limit(unsigned v) override { spin_limit = v; }
+
   int set_trace(bool on) override {
     tracing = on;
     return on ? ensure_trace() : MG_OK;
@@ -623,6 +632,9 @@ struct Batch : BatchBase {
   int cycle(int ncycles, double* res) override {
     if (ncycles <= 0) return MG_OK;
     MG_TRY(ensure_hist(ncycles));
+    // the error word collects the waits that gave up in any launch of this
+    // call: cleared once here, not with the per-launch counters below
+    MG_HIP(launch_fill(dq + 1, sizeof(int), s));
     // parities of the ping-pong buffers at this call
     for (int i = 0; i < np; ++i) {
       Engine<T>& E = *engine_of<T>(ctx[i]);
@@ -633,7 +645,8 @@ struct Batch : BatchBase {
     }
     MG_HIP(hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(BProb<T>), hipMemcpyHostToDevice, s));
     for (int k = 0; k < ncycles; ++k) {
-      MG_HIP(launch_fill(ddone, ((size_t)np * kBMaxPhases + 2) * sizeof(int), s));
+      // completion counters and the queue head (not the error word after them)
+      MG_HIP(launch_fill(ddone, ((size_t)np * kBMaxPhases + 1) * sizeof(int), s));
       BatchArgs<T> A;
       A.items = ditems;
       A.nitems = nitems;
@@ -643,7 +656,7 @@ struct Batch : BatchBase {
       A.err = dq + 1;
       A.hist = dhist + (size_t)2 * np * k;
       A.cyc = k;
-      A.spin_limit = 1u << 20;
+      A.spin_limit = spin_limit;
       A.trace = tracing ? dtrace : nullptr;
       hipLaunchKernelGGL(k_batch_cycle<T>, dim3(grid), dim3(kBThreads), 0, s, A);
       MG_HIP(hipGetLastError());
@@ -776,6 +789,12 @@ int mg_batch_autotune(mg_batch* b, int reps, int* config, double* us_per_cycle, 
 }
 
 int mg_batch_configs(void) { return kBatchConfigs; }
+
+int mg_batch_set_spin_limit(mg_batch* b, long long polls) {
+  if (!b || polls < 0 || polls > kMaxSpinLimit) return fail(MG_EINVAL, "spin limit out of range");
+  b->impl->set_spin_limit((unsigned)polls);
+  return MG_OK;
+}
 
 int mg_batch_trace(mg_batch* b, int enable) {
   if (!b) return fail(MG_EINVAL, "NULL batch");

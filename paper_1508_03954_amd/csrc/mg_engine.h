@@ -330,12 +330,15 @@ struct Engine {
       MG_HIP(launch_fill(lv[l].si, lv[l].N * sizeof(cpx<T>), s));
     }
     if (si_alt) MG_HIP(launch_fill(si_alt, lv[L - 1].N * sizeof(cpx<T>), s));
-    iter = 0;
     return MG_OK;
   }
 
+  // A new right-hand side or iterate starts the iteration afresh: helpers
+  // and the cycle counter of the iteration-dependent relaxation schemes.  A
+  // flush clears the helpers only, so the schemes continue where they were.
   int set_rhs(const cpx<T>* b) {
     MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, b, lv[L].b, mk(T(1), T(0)), s));
+    iter = 0;
     return zero_helpers();
   }
 
@@ -345,6 +348,7 @@ struct Engine {
       const cpx<T>* src = l == L ? w[cur] : lv[l].u;
       MG_HIP(launch_inject<T>(dim, lv[l - 1].n, src, lv[l - 1].u, s));
     }
+    iter = 0;
     return zero_helpers();
   }
 
@@ -856,7 +860,14 @@ struct Engine {
     return MG_OK;
   }
 
-  // Stationary driver: cycles until ||r_n||_h <= rtol ||b||_h, then flush.
+  // Stationary driver (the paper's iteration, one cycle per traversal).  Cycle
+  // n reports the residual of iterate n - 1; the driver stops after the first
+  // cycle whose reported residual meets ||r||_h <= rtol ||b||_h, or at maxit,
+  // then flushes, so u holds the iterate after the cycles run (one beyond the
+  // one that met the target) and *its their count.  Status: MG_EDIVERGED on a
+  // non-finite residual or one above 1e8 times the first; otherwise MG_OK
+  // when the returned iterate's own residual meets rtol, MG_ENOTCONV when it
+  // does not (maxit reached, or the last cycle moved away from the target).
   int stationary(const cpx<T>* b, cpx<T>* u, double rtol, int maxit, int* its, double* relres) {
     MG_TRY(set_rhs(b));
     MG_TRY(set_solution(u));
@@ -872,35 +883,27 @@ struct Engine {
       if (relres) *relres = 0;
       return MG_OK;
     }
-    const int chunk = 4;
-    int done = 0, status = MG_ENOTCONV;
+    int done = 0;
+    bool diverged = false;
     double r0 = -1;
-    std::vector<double> rh(chunk);
     while (done < maxit) {
-      const int m = std::min(chunk, maxit - done);
-      MG_TRY(cycles(m, rh.data(), nullptr));
-      for (int k = 0; k < m; ++k) {
-        if (r0 < 0) r0 = rh[k];
-        const double rel = rh[k] / bh;
-        if (!std::isfinite(rel) || rh[k] > 1e8 * r0) {
-          status = MG_EDIVERGED;
-          break;
-        }
-        if (rel <= rtol) {
-          status = MG_OK;
-          break;
-        }
+      double rh;
+      MG_TRY(cycles(1, &rh, nullptr));
+      ++done;
+      if (r0 < 0) r0 = rh;
+      if (!std::isfinite(rh) || rh > 1e8 * r0) {
+        diverged = true;
+        break;
       }
-      done += m;
-      if (status != MG_ENOTCONV) break;
+      if (rh / bh <= rtol) break;
     }
     MG_TRY(flush(u));
     double fin;
     MG_TRY(resid_norm(u, lv[L].b, &fin, nullptr));
     if (its) *its = done;
     if (relres) *relres = fin / bh;
-    if (status == MG_OK && fin / bh > rtol) status = MG_OK;  // the flushed iterate is one cycle further
-    return status;
+    if (diverged || !std::isfinite(fin)) return MG_EDIVERGED;
+    return fin / bh <= rtol ? MG_OK : MG_ENOTCONV;
   }
 };
 

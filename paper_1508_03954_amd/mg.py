@@ -31,7 +31,7 @@ EXPORTED = [
     "mg_precondition", "mg_precondition_apply", "mg_solve", "mg_residual_norm", "mg_grad_potential", "mg_time_sweeps",
     "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
     "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
-    "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested",
+    "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested", "mg_batch_set_spin_limit",
 ]
 
 
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_batch_cycle.argtypes = [P, I, ctypes.POINTER(D)]
     lib.mg_batch_autotune.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.mg_batch_configs.argtypes = []
+    lib.mg_batch_set_spin_limit.argtypes = [P, ctypes.c_longlong]
     lib.mg_batch_trace.argtypes = [P, I]
     lib.mg_batch_get_trace.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]
     lib.mg_batch_solve.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, I, ctypes.POINTER(I),
@@ -410,6 +411,15 @@ class Batch:
 
     def trace(self, enable: bool = True):
         _check(self._lib.mg_batch_trace(self._b, 1 if enable else 0))
+
+    def set_spin_limit(self, polls: int):
+        """Bound of the kernel's dependency waits (tests of the error path)."""
+        _check(self._lib.mg_batch_set_spin_limit(self._b, polls))
+
+    def cycle_status(self, ncycles: int = 1) -> int:
+        """ncycles batched cycles without norms; returns the status code
+        (MG_OK or MG_EDEVICE when a dependency wait gave up)."""
+        return _check(self._lib.mg_batch_cycle(self._b, ncycles, None), allow=(MG_EDEVICE,))
 
     def get_trace(self):
         """Last cycle's per-item record as an (items, 8) int64 array: problem,

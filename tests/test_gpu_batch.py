@@ -145,3 +145,67 @@ def test_batched_solve_fp32_refinement():
         # relative residual 1e-10 bounds the error by cond(H) * 1e-10
         assert err <= 1e-6, (p.name, err)
     batch.close()
+
+
+def test_batched_wait_bound_reports_device_error():
+    """A host-set bound of 0 polls makes every dependency wait that finds its
+    dependency unfinished give up: the kernel still drains, the two-cycle call
+    returns MG_EDEVICE (the flag is kept across the launches of a call), and
+    with the default bound restored the next call is clean and exact."""
+    from paper_1508_03954_amd import mg
+    probs, kws = small_batch("fp64")
+    batch = mg.Batch(kws)
+    for s, p in zip(batch.solvers, probs):
+        start(s, p.chi)
+    batch.set_spin_limit(0)
+    print("\n[case] batch with a wait bound of 0 polls, 2 cycles", flush=True)
+    assert batch.cycle_status(2) == mg.MG_EDEVICE
+    batch.set_spin_limit(1 << 20)
+    with pytest.raises(mg.MGError):
+        batch.set_spin_limit(1 << 40)
+    check_equal_to_standalone(batch, probs, kws, 2)
+    batch.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batched_full_depth_members_match_oracle(precision):
+    """The deepest members of the 96-problem workload -- its first 3D level-5
+    and first 2D level-6 problem -- with a 2D and a 3D level-3 member, in one
+    batch in the autotuned configuration: two batched cycles against the FP64
+    oracle's pipeline, residual history and flushed iterate.  FP64: 1e-12.
+    complex64 corrections (the workload's precision): 2e-5, a bound on the
+    complex64 rounding (unit roundoff 6e-8) accumulated over two cycles."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_batched
+    probs = config_batched()
+    pick = [next(i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 5),
+            next(i for i, p in enumerate(probs) if p.dim == 2 and p.level_max == 6),
+            next(i for i, p in enumerate(probs) if p.dim == 2 and p.level_max == 3),
+            next(i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 3)]
+    sub = [probs[i] for i in pick]
+    kws = [dict(dim=p.dim, level_max=p.level_max, phi=p.phi, variant="bpx", omega=0.6, precision=precision)
+           for p in sub]
+    batch = mg.Batch(kws)
+    for s, p in zip(batch.solvers, sub):
+        start(s, p.chi)
+    cfg, us, _ = batch.autotune(reps=1)
+    for s, p in zip(batch.solvers, sub):
+        start(s, p.chi)
+    print(f"\n[case] full-depth batch {pick} ({precision}), configuration {cfg}", flush=True)
+    ncyc = 2
+    res = batch.cycle(ncyc)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    for i, (s, p) in enumerate(zip(batch.solvers, sub)):
+        op = Params(dim=p.dim, level_max=p.level_max, theta=0.0, phi=p.phi, variant="bpx", omega=0.6)
+        pipe = O.Pipelined(op, O.lumped_rhs(p.chi, p.level_max, 0.0))
+        for k in range(ncyc):
+            rh_ref, _ = pipe.cycle()
+            assert abs(res[k, i] - rh_ref) <= tol * rh_ref, (p.name, k, res[k, i], rh_ref)
+        u_ref = pipe.flush()
+        u = s.flush().cpu().numpy()
+        err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+        print(f"[full-depth batch] {p.name}: flushed iterate relative error {err:.2e}", flush=True)
+        assert err <= tol, (p.name, err)
+        del pipe
+    batch.close()

@@ -128,3 +128,104 @@ def test_3d_level6_operator_sampled():
         worst = max(worst, abs(yv[t] - ref) / max(abs(ref), 1e-300))
     print(f"\n[level 6 apply] worst relative deviation over 2000 vertices: {worst:.2e}")
     assert worst <= 1e-11
+
+
+def _win(a, lo, size):
+    """a[lo : lo + size] per axis (numpy or torch, 3D), zero-padded past the
+    array's ends, as a complex128 numpy array."""
+    n = a.shape[0]
+    out = np.zeros((size,) * 3, dtype=np.complex128)
+    src = tuple(slice(max(l, 0), min(l + size, n)) for l in lo)
+    dst = tuple(slice(s.start - l, s.stop - l) for s, l in zip(src, lo))
+    piece = a[src]
+    if hasattr(piece, "cpu"):
+        piece = piece.cpu().numpy()
+    out[dst] = piece
+    return out
+
+
+def _true_interior(lo, size, n):
+    """Mask of the window positions that are interior vertices of the level."""
+    idx = [np.arange(l, l + size) for l in lo]
+    ok = [(i > 0) & (i < n - 1) for i in idx]
+    return ok[0][:, None, None] & ok[1][None, :, None] & ok[2][None, None, :]
+
+
+@pytest.mark.timeout(600)
+def test_3d_level6_fused_sweep_sampled():
+    """The 730^3 fused sweep (levels 1..6, k = 40, shift (1 + 0.5i) k^2, BPX,
+    autotuned tile, as the benchmark runs it), two cycles, checked at sampled
+    vertices against the oracle evaluated on local windows of the GPU's state
+    before each cycle:
+      cycle 1 starts from zero helpers, so its finest sweep is a function of
+        u0 and b alone;
+      cycle 2: the oracle runs the descent of every coarse level from the
+        GPU's coarse state (P of sc and si down the hierarchy), then the
+        finest pre-phase u = w + P sc_5 - P si_5 (off c-points).
+    Per sampled coarse vertex m (13^3 fine window around 3m): r = b - H u,
+    s = omega r / D, w' = u + s (0 on c-points) on the 5^3 fine vertices
+    around 3m, rho_5(m) = (R r)(m) and si_5(m) = s(3m).  Sample set 2-norm
+    relative error <= 1e-12 per field."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_3d_large, random_complex, sample_vertices
+    prob = config_3d_large(level_max=6)
+    L, dim, n = 6, 3, 730
+    p5 = Params(dim=3, level_max=L - 1, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
+    D = O.diag_H(4, 3, L, prob.theta, prob.phi)[1, 1, 1]
+    s = mg.Solver(dim, L, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
+    tile, us, _ = s.autotune(reps=2)
+    print(f"\n[case] level 6 fused sweep, tile {tile} ({us:.0f} us)", flush=True)
+    s.set_rhs(s.rhs_from_nodal(torch.from_numpy(prob.chi).cuda()))
+    u0 = random_complex((n,) * 3, seed=606)
+    s.set_solution(torch.from_numpy(u0).cuda())
+    ms = sample_vertices(L - 1, 3, 250, seed=66)
+    prev_w = u0                                   # the finest iterate before cycle 1
+    g_sc = g_si = None                            # level-5 correction fields before cycle 2
+    for cyc in (1, 2):
+        if cyc == 2:
+            # the oracle's descent of every coarse level from the GPU's state
+            pipe = O.Pipelined(p5, np.zeros((3 ** (L - 1) + 1,) * 3))
+            for lev in range(1, L):
+                for f in ("u", "sc", "sf", "si"):
+                    getattr(pipe, f)[lev] = to_np(s.get_level(lev, f))
+            for lev in range(1, L):
+                pipe.pre(lev)
+            g_sc, g_si = pipe.sc[L - 1], pipe.si[L - 1]
+            del pipe
+            prev_w = s.get_level(L, "u")
+        s.cycle(1)
+        W, RHO, SI = s.get_level(L, "u"), s.get_level(L - 1, "b"), s.get_level(L - 1, "si")
+        got = {"w": [], "rho": [], "si": []}
+        ref = {"w": [], "rho": [], "si": []}
+        for m in ms:
+            lo = [3 * int(c) - 6 for c in m]
+            inner = _true_interior(lo, 13, n)
+            u = _win(prev_w, lo, 13)
+            if cyc == 2:
+                clo = [int(c) - 2 for c in m]
+                pc = O.prolong(_win(g_sc, clo, 5))
+                pi = O.prolong(_win(g_si, clo, 5))
+                cp = np.zeros((13,) * 3, bool)
+                cp[::3, ::3, ::3] = True
+                u = u + pc - np.where(cp, 0, pi)
+            u = np.where(inner, u, 0)
+            chi = _win(prob.chi, lo, 13)
+            b = np.where(inner, O.lumped_rhs(chi, L, prob.theta), 0)
+            r = np.where(inner, b - O.apply_H(u, L, prob.theta, prob.phi), 0)
+            sm = 0.6 * r / D
+            cpm = np.zeros((13,) * 3, bool)
+            cpm[::3, ::3, ::3] = True
+            wn = u + np.where(cpm, 0, sm)
+            ref["w"].append(wn[4:9, 4:9, 4:9].ravel())
+            got["w"].append(_win(W, [x + 4 for x in lo], 5).ravel())
+            ref["rho"].append(O.restrict(r)[2, 2, 2])
+            ref["si"].append(sm[6, 6, 6])
+            got["rho"].append(RHO[tuple(int(c) for c in m)].item())
+            got["si"].append(SI[tuple(int(c) for c in m)].item())
+        for f in ("w", "rho", "si"):
+            g, rf = np.hstack(got[f]), np.hstack(ref[f])
+            err = np.linalg.norm(g - rf) / np.linalg.norm(rf)
+            print(f"[level 6] cycle {cyc} {f}: {g.size} samples, relative error {err:.2e}", flush=True)
+            assert err <= 1e-12, (cyc, f, err)
+        del W, RHO, SI
+        torch.cuda.empty_cache()

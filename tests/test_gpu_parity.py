@@ -438,3 +438,66 @@ def test_invalid_arguments_raise():
     s = mg.Solver(2, 2)
     with pytest.raises(ValueError):
         s.apply(np.zeros((5, 5), dtype=np.complex128))
+
+
+@pytest.mark.parametrize("dim,L,lmin,variant,sweep,scheme", [(2, 4, 1, "add", "generic", "transition"),
+                                                             (2, 3, 3, "add", "generic", "two_phase"),
+                                                             (3, 3, 1, "bpx", "fused", "two_phase")])
+def test_cycle_flush_cycle_keeps_the_cycle_counter(dim, L, lmin, variant, sweep, scheme):
+    """A flush applies the pending update without restarting the cycle count:
+    the transition scheme (Section 5.1) and the two-phase relaxation (Section
+    7.4) continue with the next cycle number, as the oracle's pipeline does."""
+    print(f"\n[case] cycle-flush-cycle dim={dim} L={L} {variant} {scheme}", flush=True)
+    mg = mgmod()
+    theta, phi = 0.4, 90 * (1 + 0.5j)
+    n = 3 ** L + 1
+    w = 0.6 if scheme == "transition" else 0.3 * (math.sqrt(3) - 1j)
+    p = Params(dim=dim, level_max=L, level_min=lmin, theta=theta, phi=phi, variant=variant, omega_scheme=scheme,
+               omega=w)
+    b, u0 = rand_c((n,) * dim, 1), rand_c((n,) * dim, 2)
+    s = mg.Solver(dim, L, level_min=lmin, theta=theta, phi=phi, variant=variant, omega_scheme=scheme, omega=w,
+                  sweep=sweep)
+    s.set_rhs(b)
+    s.set_solution(u0)
+    pipe = O.Pipelined(p, b, u0)
+    for ncyc in (3, 2):
+        rh, _ = s.cycle(ncyc)
+        ref = [pipe.cycle()[0] for _ in range(ncyc)]
+        for a, c in zip(rh, ref):
+            assert abs(a - c) <= TOL * c, (a, c)
+        u = to_np(s.flush())
+        assert relerr(u, pipe.flush()) <= TOL
+
+
+def test_stationary_driver_status_and_count():
+    """The stationary driver against the oracle's: the cycle count at which it
+    stops, MG_EDIVERGED for the indefinite 3D cycle with omega 0.6 on every
+    level (it grows by 1e8 within 14 cycles), MG_ENOTCONV at maxit with the
+    iterate of that many cycles, MG_OK and the returned iterate's residual
+    when it converges."""
+    mg = mgmod()
+    rng = np.random.default_rng(3)
+    # diverging: k = 30 without shift or rotation
+    p = Params(dim=3, level_max=3, theta=0.0, phi=900.0, variant="bpx", omega=0.6)
+    b = O.zero_boundary(rng.standard_normal((28,) * 3) + 0j)
+    _, its_ref, hist, ok = O.stationary_solve(p, b, 1e-10, 300)
+    assert not ok and hist[-1] > 1e8 * hist[0]
+    s = mg.Solver(3, 3, theta=0.0, phi=900.0, variant="bpx", omega=0.6)
+    u, its, rel, rc = s.solve(b, rtol=1e-10, maxit=300, driver="stationary")
+    print(f"\n[stationary] diverging: rc={rc}, cycles {its} (oracle {its_ref})", flush=True)
+    assert rc == mg.MG_EDIVERGED and its == its_ref
+    # Poisson: converges; stopped after maxit = 5 first
+    from paper_1508_03954_amd.inputs import sine_load
+    q = Params(dim=2, level_max=4, theta=0.0, phi=0.0, variant="add", omega_scheme="exp", omega=0.6)
+    bq = O.lumped_rhs(sine_load(4, 2), 4, 0.0)
+    sq = mg.Solver(2, 4, theta=0.0, phi=0.0, variant="add", omega_scheme="exp", omega=0.6)
+    u5, its5, rel5, rc5 = sq.solve(bq, rtol=1e-12, maxit=5, driver="stationary")
+    u5_ref, its5_ref, _, ok5 = O.stationary_solve(q, bq, 1e-12, 5)
+    assert rc5 == mg.MG_ENOTCONV and its5 == 5 == its5_ref and not ok5
+    assert relerr(to_np(u5), u5_ref) <= TOL
+    true5 = np.linalg.norm(O.zero_boundary(bq - O.apply_H(u5_ref, 4, 0.0, 0.0))) / np.linalg.norm(bq)
+    assert abs(rel5 - true5) <= 1e-10 * true5
+    uc, itsc, relc, rcc = sq.solve(bq, rtol=1e-8, maxit=400, driver="stationary")
+    uc_ref, itsc_ref, _, okc = O.stationary_solve(q, bq, 1e-8, 400)
+    assert okc and rcc == mg.MG_OK and itsc == itsc_ref and relc <= 1e-8
+    assert relerr(to_np(uc), uc_ref) <= 1e-10
