@@ -98,6 +98,16 @@ typedef struct {
   double inner_rtol;         /* MG_FP32_REFINE: relative residual each complex64   */
                              /* inner solve aims for (0: 1e-4); an outer step      */
                              /* then reduces the FP64 residual by about this much  */
+  /* Absorbing layer (Section 7.4): on every level, a cell whose centre lies   */
+  /* closer than layer_width to one of the faces in layer_faces is rotated by  */
+  /* layer_theta instead of theta (stiffness eta_c^(d-2), mass eta_c^d of that */
+  /* cell; diagonal accumulated cell by cell).  Faces: bit 2a is x_a = 0, bit  */
+  /* 2a+1 is x_a = 1, with x_0 = x the fastest-varying coordinate.  A layer    */
+  /* (layer_width > 0) takes the nodal-coefficient path (FAS form, no fused    */
+  /* sweep); it is not available with batches, nested solves or gradients.    */
+  double layer_theta;
+  double layer_width;        /* 0: no layer                                        */
+  int layer_faces;
 } mg_params;
 
 /* Fills *p with: dim 3, levels 1..3, theta 0, phi 0, constant, BPX, CONST,
@@ -129,7 +139,8 @@ int mg_apply(mg_ctx* ctx, const mg_c128* x, mg_c128* y);
 
 /* Lumped discrete load: b = eta_L^d chi at interior vertices, 0 on the
  * boundary, eta_L = 3^-L exp(i theta) (the weight of the discretised
- * right-hand side, Section 4).  chi and b may alias. */
+ * right-hand side, Section 4).  With an absorbing layer the weight of a vertex
+ * is the mean of eta_c^d over its 2^d cells.  chi and b may alias. */
 int mg_rhs_from_nodal(mg_ctx* ctx, const mg_c128* chi, mg_c128* b);
 
 /* Sets the finest right-hand side and resets the pipeline helpers

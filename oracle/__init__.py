@@ -19,7 +19,7 @@ independent test that fixes it (closed form, textbook routine, brute force).
 """
 
 from .discretisation import (  # noqa: F401
-    element_matrices, level_eta, apply_H, diag_H, cell_average, coarse_fields,
+    element_matrices, level_eta, cell_theta, cell_eta, apply_H, diag_H, cell_average, coarse_fields,
     lumped_rhs, dense_H, norm_h, norm_max, zero_boundary, interior_mask,
 )
 from .transfer import prolong, restrict, inject, cpoint_mask, prolong_matrix_1d  # noqa: F401
@@ -27,5 +27,5 @@ from .cycle import (  # noqa: F401
     Params, omega_levels, semantic_cycle, textbook_additive, bottom_up_fas,
     Pipelined, zero_start_cycle,
 )
-from .solve import stationary_solve, bicgstab, dense_solve, nested_initial_guess  # noqa: F401
+from .solve import stationary_solve, bicgstab, dense_solve, nested_initial_guess, max_norm_reduction  # noqa: F401
 from .adjoint import shell_functional, potential_gradient  # noqa: F401

@@ -30,8 +30,8 @@ from typing import Dict, Optional
 
 import numpy as np
 
-from .discretisation import (apply_H, coarse_fields, diag_H, interior_mask, norm_h,
-                             norm_max, zero_boundary)
+from .discretisation import (apply_H, cell_theta, coarse_fields, diag_H, interior_mask,
+                             norm_h, norm_max, zero_boundary)
 from .transfer import cpoint_mask, inject, prolong, restrict
 
 VARIANTS = ("add", "hb", "bpx")
@@ -51,6 +51,7 @@ class Params:
     omega: complex = 0.6
     omega_L: int = 1                          # grid count bound of the L-grid scheme
     conjugate: bool = False
+    layer: Optional[tuple] = None             # absorbing layer (angle, width, faces), Section 7.4
 
     def __post_init__(self):
         assert self.variant in VARIANTS
@@ -74,12 +75,17 @@ class Params:
             self._phi = coarse_fields(self.phi_nodal, self.level_max, self.level_min)
         return self._phi[level]
 
+    def theta_at(self, level: int):
+        """Rotation of the level's cells: theta, or per cell with the layer
+        (each level's cells are classified by their own centres)."""
+        return cell_theta(level, self.dim, self.theta, self.layer)
+
     def H(self, v: np.ndarray, level: int) -> np.ndarray:
-        return apply_H(v, level, self.theta, self.phi_at(level), self.conjugate)
+        return apply_H(v, level, self.theta_at(level), self.phi_at(level), self.conjugate)
 
     def D(self, level: int) -> np.ndarray:
         if level not in self._diag:
-            self._diag[level] = diag_H(self.n(level), self.dim, level, self.theta,
+            self._diag[level] = diag_H(self.n(level), self.dim, level, self.theta_at(level),
                                        self.phi_at(level), self.conjugate)
         return self._diag[level]
 
@@ -306,7 +312,8 @@ class Pipelined:
         """
         p = self.p
         L, lmin = p.level_max, p.level_min
-        assert p.phi_nodal is None, "the restricted-residual form needs a constant phi"
+        assert p.phi_nodal is None and p.layer is None, \
+            "the restricted-residual form needs a constant phi and a uniform rotation"
         om = omega_levels(p, self.iteration)
         r = {L: zero_boundary(self.residual)}
         for lev in range(L, lmin, -1):

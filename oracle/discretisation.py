@@ -16,7 +16,12 @@ Readings of points the paper leaves open (each listed in the design notes):
     their own vertices (rediscretisation, not Galerkin);
   * the discrete load is lumped: b_j = eta_L^d chi(x_j) at interior vertices;
   * rows of boundary vertices are dropped (zero Dirichlet): operator results
-    are zero on the boundary and boundary input entries are ignored.
+    are zero on the boundary and boundary input entries are ignored;
+  * the absorbing layer of Section 7.4 rotates single cells: a cell whose
+    centre lies within the layer width of one of the layer's faces takes the
+    layer's angle, every other cell the global theta.  Rotation angles may
+    therefore be given per cell; the lumped load weight of a vertex is then the
+    mean of eta_c^d over its 2^d cells (the row sum of the lumped mass matrix).
 """
 
 from __future__ import annotations
@@ -57,6 +62,39 @@ def level_eta(level: int, theta: float, conjugate: bool = False) -> complex:
     """Complex cell side eta_l = 3^-l exp(i theta) (conjugated for H^H)."""
     eta = 3.0 ** (-level) * np.exp(1j * theta)
     return np.conj(eta) if conjugate else eta
+
+
+def cell_theta(level: int, dim: int, theta: float, layer=None):
+    """Rotation angle of every cell of a level (Section 7.4 absorbing layer).
+
+    layer = None gives the uniform angle theta (a scalar).  Otherwise layer is
+    (layer_theta, width, faces): faces is a bit set, bit 2a for the face
+    x_a = 0 and bit 2a + 1 for the face x_a = 1, coordinate x_0 being the
+    fastest-varying one (numpy's last axis); a cell whose centre lies closer
+    than `width` to a selected face is rotated by layer_theta, every other cell
+    by theta.  Returns an array of shape (3^level,)*dim.
+    """
+    if layer is None:
+        return theta
+    lt, width, faces = layer
+    m = 3 ** level
+    centre = (np.arange(m) + 0.5) / m
+    inside = np.zeros((m,) * dim, dtype=bool)
+    for a in range(dim):
+        shape = [1] * dim
+        shape[dim - 1 - a] = m
+        if faces & (1 << (2 * a)):
+            inside |= (centre < width).reshape(shape)
+        if faces & (1 << (2 * a + 1)):
+            inside |= (1.0 - centre < width).reshape(shape)
+    return np.where(inside, float(lt), float(theta))
+
+
+def cell_eta(level: int, theta, conjugate: bool = False):
+    """Complex cell sides 3^-l exp(i theta_c) for a scalar or per-cell theta."""
+    eta = 3.0 ** (-level) * np.exp(1j * np.asarray(theta, dtype=np.float64))
+    eta = np.conj(eta) if conjugate else eta
+    return complex(eta) if np.ndim(eta) == 0 else eta
 
 
 def corners(dim: int):
@@ -107,7 +145,8 @@ def apply_H(u: np.ndarray, level: int, theta: float, phi, conjugate: bool = Fals
     """(H_l u)_j = sum over cells c containing j of (H_c u_c)_loc(j),
     H_c = eta^(d-2) K - phibar_c eta^d M, evaluated element by element.
 
-    `phi` is a complex scalar or a nodal array of shape (n,)*d (cell-averaged).
+    `phi` is a complex scalar or a nodal array of shape (n,)*d (cell-averaged);
+    `theta` a scalar or one angle per cell (shape (n-1,)*d, see cell_theta).
     Boundary entries of u are ignored; boundary rows of the result are zero.
     Conjugate mode builds conj(H) = H^H (H is complex symmetric).
     Pinned by: the sine-mode symbol, the Kronecker assembly of 1D FE matrices,
@@ -115,7 +154,7 @@ def apply_H(u: np.ndarray, level: int, theta: float, phi, conjugate: bool = Fals
     """
     dim = u.ndim
     K, M = element_matrices(dim)
-    eta = level_eta(level, theta, conjugate)
+    eta = cell_eta(level, theta, conjugate)
     if np.ndim(phi) == 0:
         phibar = complex(phi)
     else:
@@ -140,7 +179,7 @@ def diag_H(n: int, dim: int, level: int, theta: float, phi, conjugate: bool = Fa
     that a division leaves the (zero) boundary residual untouched.
     Pinned by the closed form  eta^(d-2) 2d (2/3)^(d-1) - phi eta^d (2/3)^d."""
     K, M = element_matrices(dim)
-    eta = level_eta(level, theta, conjugate)
+    eta = cell_eta(level, theta, conjugate)
     if np.ndim(phi) == 0:
         phibar = complex(phi) * np.ones((n - 1,) * dim)
     else:
@@ -154,9 +193,19 @@ def diag_H(n: int, dim: int, level: int, theta: float, phi, conjugate: bool = Fa
     return out
 
 
-def lumped_rhs(chi: np.ndarray, level: int, theta: float) -> np.ndarray:
-    """b_j = eta_L^d chi(x_j) on interior vertices, zero on the boundary."""
-    return zero_boundary(level_eta(level, theta) ** chi.ndim * np.asarray(chi))
+def lumped_rhs(chi: np.ndarray, level: int, theta) -> np.ndarray:
+    """b_j = eta_L^d chi(x_j) on interior vertices, zero on the boundary.  With
+    one angle per cell the weight is the mean of eta_c^d over the vertex's 2^d
+    cells."""
+    chi = np.asarray(chi)
+    dim = chi.ndim
+    if np.ndim(theta) == 0:
+        return zero_boundary(level_eta(level, theta) ** dim * chi)
+    etad = cell_eta(level, theta) ** dim
+    wgt = np.zeros(chi.shape, dtype=np.complex128)
+    for k in corners(dim):
+        wgt[_cell_view(wgt, k)] += etad
+    return zero_boundary(wgt / 2 ** dim * chi)
 
 
 def dense_H(n: int, dim: int, level: int, theta: float, phi, conjugate: bool = False) -> np.ndarray:

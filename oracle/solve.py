@@ -12,7 +12,10 @@ Test infrastructure only (see the package header).
 * `dense_solve`      -- LU on the dense interior matrix (tiny grids only), the
   fixed point both drivers must reach;
 * `nested_initial_guess` -- the finest level's starting point of a nested
-  solve: the level below solved with the load sampled there, prolonged.
+  solve: the level below solved with the load sampled there, prolonged;
+* `max_norm_reduction` -- the measure of the Section 7.4 study: the maximum
+  norm of the residual after a number of iterations from u = 0, relative to
+  that of the start.
 """
 
 from __future__ import annotations
@@ -87,7 +90,7 @@ def dense_solve(p: Params, b: np.ndarray) -> np.ndarray:
     """u with H u = b on interior vertices, zero boundary (np.linalg.solve)."""
     L = p.level_max
     n = p.n(L)
-    A = dense_H(n, p.dim, L, p.theta, p.phi_at(L), p.conjugate)
+    A = dense_H(n, p.dim, L, p.theta_at(L), p.phi_at(L), p.conjugate)
     m = interior_mask(n, p.dim)
     u = np.zeros((n,) * p.dim, dtype=np.complex128)
     u[m] = np.linalg.solve(A, np.asarray(b)[m])
@@ -106,5 +109,19 @@ def nested_initial_guess(p: Params, chi: np.ndarray) -> np.ndarray:
     L = p.level_max
     q = dataclasses.replace(p, level_max=L - 1, level_min=min(p.level_min, L - 1))
     chic = np.asarray(chi)[(slice(None, None, 3),) * p.dim]
-    uc = dense_solve(q, lumped_rhs(chic, L - 1, p.theta))
+    uc = dense_solve(q, lumped_rhs(chic, L - 1, p.theta_at(L - 1)))
     return prolong(uc)
+
+
+def max_norm_reduction(p: Params, b: np.ndarray, iterations: int):
+    """max|b - H u_n| / max|b| after n pipelined cycles from u_0 = 0 and a
+    flush (u_n the n-th iterate), with the flushed iterate (Section 7.4,
+    Table 08gaussian measures this after 50 iterations)."""
+    pipe = Pipelined(p, b)
+    for _ in range(iterations):
+        pipe.cycle()
+    u = pipe.flush()
+    L = p.level_max
+    r = zero_boundary(np.asarray(b) - p.H(u, L))
+    m = interior_mask(p.n(L), p.dim)
+    return float(np.abs(r[m]).max() / np.abs(np.asarray(b)[m]).max()), u

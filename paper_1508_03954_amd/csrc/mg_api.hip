@@ -12,6 +12,10 @@ static int check_params(const mg_params* p) {
   if (p->precision != MG_FP64 && p->precision != MG_FP32_REFINE) return fail(MG_EINVAL, "bad precision");
   if (p->restrict_form < MG_RESTRICT_AUTO || p->restrict_form > MG_RESTRICT_GALERKIN) return fail(MG_EINVAL, "bad restrict_form");
   if (p->sweep < MG_SWEEP_AUTO || p->sweep > MG_SWEEP_FUSED) return fail(MG_EINVAL, "bad sweep");
+  if (!(p->layer_width >= 0) || p->layer_width > 1 || !std::isfinite(p->layer_theta))
+    return fail(MG_EINVAL, "layer_width must lie in [0, 1] and layer_theta be finite");
+  if (p->layer_width > 0 && (p->layer_faces <= 0 || p->layer_faces >= (1 << (2 * p->dim))))
+    return fail(MG_EINVAL, "layer_faces must select at least one face of the domain and no other bits");
   return MG_OK;
 }
 
@@ -109,6 +113,13 @@ int mg_apply(mg_ctx* c, const mg_c128* x, mg_c128* y) {
 
 int mg_rhs_from_nodal(mg_ctx* c, const mg_c128* chi, mg_c128* b) {
   if (!c || !chi || !b) return fail(MG_EINVAL, "NULL argument");
+  if (c->p.layer_width > 0) {
+    mg_params q = c->p;
+    q.conjugate = 0;   // the load weight is that of the forward problem
+    MG_HIP(launch_rhs_cells(c->p.dim, (int)ipow(3, c->p.level_max) + 1, (const cpx<double>*)chi, (cpx<double>*)b,
+                            rotation(q, c->p.level_max), c->s));
+    return MG_OK;
+  }
   const LevelScalars ls = level_scalars(c->p.dim, c->p.level_max, c->p.theta, false);
   MG_HIP(launch_zero_boundary_copy<double>(c->p.dim, (int)ipow(3, c->p.level_max) + 1, (const cpx<double>*)chi,
                                            (cpx<double>*)b, to_c<double>(ls.etad), c->s));
@@ -406,6 +417,7 @@ int mg_sweep_time(mg_ctx* c, double* total_ms, int* count) {
 
 int mg_grad_potential(mg_ctx* c, const mg_c128* u, const mg_c128* lam, double* dJdV) {
   if (!c || !u || !lam || !dJdV) return fail(MG_EINVAL, "NULL argument");
+  if (c->p.layer_width > 0) return fail(MG_EINVAL, "the potential gradient needs a uniform rotation (no absorbing layer)");
   const LevelScalars ls = level_scalars(c->p.dim, c->p.level_max, c->p.theta, false);
   MG_HIP(launch_grad_potential(c->p.dim, (int)ipow(3, c->p.level_max) + 1, to_c<double>(ls.etad),
                                (const cpx<double>*)u, (const cpx<double>*)lam, dJdV, c->s));

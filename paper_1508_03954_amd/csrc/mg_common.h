@@ -172,7 +172,8 @@ __device__ cpx<T> stencil_const(const cpx<T>* __restrict__ x, int n, const int j
   return r;
 }
 
-// Stiffness-only stencil weights S_K by class (real), used with a nodal phi.
+// Stiffness-only stencil weights S_K by class (real), used with per-cell
+// mass coefficients and a uniform stiffness.
 template <class T, int D>
 __device__ inline T stiff_weight(int cls) {
   if (D == 3) {
@@ -184,52 +185,103 @@ __device__ inline T stiff_weight(int cls) {
   }
 }
 
-// Nodal-phi operator row: alpha * (S_K x)_j - etad * sum_{c contains j} phibar_c (M x_c)_loc(j),
-// with M_kk' = 3^-d 2^-(number of axes where k and k' differ).
+// Entries of the reference-cell element matrices between local vertices a
+// and b (bit k of a local index: offset along axis k):
+//   mass      M_ab = prod_k (1/3 if a_k == b_k else 1/6),
+//   stiffness K_ab = sum_k (+-1 along k) prod_(k' != k) (1/3 or 1/6),
+// the tensor products of the 1D hat-function matrices [[1,-1],[-1,1]] and
+// [[1/3,1/6],[1/6,1/3]].
+template <class T, int D>
+__device__ inline T elem_mass(int a, int b) {
+  const int diff = __builtin_popcount((unsigned)(a ^ b));
+  return T(1.0 / (D == 3 ? 27.0 : 9.0)) * T(1.0 / (1 << diff));
+}
+template <class T, int D>
+__device__ inline T elem_stiff(int a, int b) {
+  T acc = T(0);
+  for (int k = 0; k < D; ++k) {
+    T t = ((a ^ b) >> k) & 1 ? T(-1) : T(1);
+    for (int q = 0; q < D; ++q)
+      if (q != k) t *= ((a ^ b) >> q) & 1 ? T(1.0 / 6.0) : T(1.0 / 3.0);
+    acc += t;
+  }
+  return acc;
+}
+
+// Operator row with per-cell coefficients:
+//   (H x)_j = sum_{cells c containing j} (kappa_c (K x_c)_loc(j) - mu_c (M x_c)_loc(j)),
+// with kappa_c = alpha for every cell unless op.cstiff is given (then the
+// assembled S_K stencil is replaced by the cell loop).
 template <class T, int D>
 __device__ cpx<T> stencil_var(const cpx<T>* __restrict__ x, int n, const int j[3], const OpData<T>& op) {
   cpx<T> st = czero<T>();
-  const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-  for (int oz = zlo; oz <= zhi; ++oz)
-    for (int oy = -1; oy <= 1; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
-        if (!is_interior<D>(k, n)) continue;
-        const int cls = (ox != 0) + (oy != 0) + (oz != 0);
-        st = st + stiff_weight<T, D>(cls) * x[ravel<D>(k, n)];
-      }
-  const T m0 = D == 3 ? T(1.0 / 27.0) : T(1.0 / 9.0);
+  if (!op.cstiff) {
+    const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
+    for (int oz = zlo; oz <= zhi; ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
+          if (!is_interior<D>(k, n)) continue;
+          const int cls = (ox != 0) + (oy != 0) + (oz != 0);
+          st = st + stiff_weight<T, D>(cls) * x[ravel<D>(k, n)];
+        }
+    st = cmul(op.alpha, st);
+  }
   cpx<T> ms = czero<T>();
   const int nc = n - 1;
   for (int c = 0; c < (1 << D); ++c) {
-    int loc[3] = {0, 0, 0}, cell[3] = {0, 0, 0};
+    int loc = 0, cell[3] = {0, 0, 0};
     bool ok = true;
     for (int a = 0; a < D; ++a) {
-      loc[a] = (c >> a) & 1;          // position of j inside the cell
-      cell[a] = j[a] - loc[a];
+      const int bit = (c >> a) & 1;   // position of j inside the cell along a
+      loc |= bit << a;
+      cell[a] = j[a] - bit;
       if (cell[a] < 0 || cell[a] >= nc) ok = false;
     }
     if (!ok) continue;
-    cpx<T> acc = czero<T>();
+    cpx<T> am = czero<T>(), ak = czero<T>();
     for (int kk = 0; kk < (1 << D); ++kk) {
       int v[3] = {0, 0, 0};
-      T w = m0;
-      for (int a = 0; a < D; ++a) {
-        const int b = (kk >> a) & 1;
-        v[a] = cell[a] + b;
-        if (b != loc[a]) w *= T(0.5);
-      }
+      for (int a = 0; a < D; ++a) v[a] = cell[a] + ((kk >> a) & 1);
       if (!is_interior<D>(v, n)) continue;
-      acc = acc + w * x[ravel<D>(v, n)];
+      const cpx<T> xv = x[ravel<D>(v, n)];
+      am = am + elem_mass<T, D>(loc, kk) * xv;
+      if (op.cstiff) ak = ak + elem_stiff<T, D>(loc, kk) * xv;
     }
-    ms = ms + cmul(op.phibar[ravel<D>(cell, nc)], acc);
+    const long long ci = ravel<D>(cell, nc);
+    ms = ms + cmul(op.cmass[ci], am);
+    if (op.cstiff) st = st + cmul(op.cstiff[ci], ak);
   }
-  return cmul(op.alpha, st) - cmul(op.etad, ms);
+  return st - ms;
+}
+
+// Rotation angle of cell c on a level with m cells per axis.
+template <int D>
+__device__ inline double cell_angle(const CellRotation& r, const int c[3], int m) {
+  if (r.width > 0) {
+    for (int a = 0; a < D; ++a) {
+      const double centre = (c[a] + 0.5) / m;
+      if (((r.faces >> (2 * a)) & 1) && centre < r.width) return r.layer_theta;
+      if (((r.faces >> (2 * a + 1)) & 1) && 1.0 - centre < r.width) return r.layer_theta;
+    }
+  }
+  return r.theta;
+}
+
+// eta_c^p (p = 0 .. 3) of cell c: (h exp(i theta_c))^p, conjugated in
+// conjugate mode.
+template <int D>
+__device__ inline cpx<double> cell_eta_pow(const CellRotation& r, const int c[3], int m, int p) {
+  const double t = cell_angle<D>(r, c, m);
+  const cpx<double> eta = mk(r.h * cos(t), r.conj ? -r.h * sin(t) : r.h * sin(t));
+  cpx<double> out = mk(1.0, 0.0);
+  for (int k = 0; k < p; ++k) out = cmul(out, eta);
+  return out;
 }
 
 template <class T, int D>
 __device__ inline cpx<T> apply_row(const cpx<T>* x, int n, const int j[3], const OpData<T>& op) {
-  return op.phibar ? stencil_var<T, D>(x, n, j, op) : stencil_const<T, D>(x, n, j, op);
+  return op.cmass ? stencil_var<T, D>(x, n, j, op) : stencil_const<T, D>(x, n, j, op);
 }
 
 

@@ -93,7 +93,8 @@ inline OpData<T> make_const_op(int dim, int lev, double theta, complex<double> p
   const complex<double> D = ls.alpha * (2.0 * dim * std::pow(2.0 / 3.0, dim - 1)) -
                             phi * ls.etad * std::pow(2.0 / 3.0, dim);
   op.invD = to_c<T>(1.0 / D);
-  op.phibar = nullptr;
+  op.cmass = nullptr;
+  op.cstiff = nullptr;
   op.invDv = nullptr;
   return op;
 }
@@ -109,12 +110,24 @@ inline complex<double> omega_level(int scheme, complex<double> w, int omega_L, i
   }
 }
 
+// Cell rotations of level l (the absorbing layer only when its width is set).
+inline CellRotation rotation(const mg_params& p, int l) {
+  CellRotation r;
+  r.h = std::pow(3.0, -l);
+  r.theta = p.theta;
+  r.layer_theta = p.layer_theta;
+  r.width = p.layer_width > 0 ? p.layer_width : 0.0;
+  r.faces = p.layer_faces;
+  r.conj = p.conjugate != 0;
+  return r;
+}
+
 template <class T>
 struct Level {
   int lev = 0, n = 0;
   size_t N = 0;
   cpx<T>*u = nullptr, *b = nullptr, *sc = nullptr, *sf = nullptr, *si = nullptr;
-  cpx<T>*phi = nullptr, *phibar = nullptr, *invDv = nullptr;
+  cpx<T>*phi = nullptr, *cmass = nullptr, *cstiff = nullptr, *invDv = nullptr;
   cpx<T>*pr = nullptr, *pz = nullptr;  // zero-start cycle scratch (coarse levels)
   OpData<T> op;
 };
@@ -123,7 +136,7 @@ template <class T>
 struct Engine {
   int dim = 3, lmin = 1, L = 1, variant = MG_BPX, scheme = MG_OMEGA_CONST, omega_L = 1;
   complex<double> omega = 0.6;
-  bool galerkin = true, fused = false, varying = false;
+  bool galerkin = true, fused = false, varying = false, layered = false;
   hipStream_t s = nullptr;
   std::vector<Level<T>> lv;
   cpx<T>* w[2] = {nullptr, nullptr};
@@ -211,12 +224,14 @@ struct Engine {
     scheme = p.omega_scheme;
     omega_L = p.omega_L;
     omega = complex<double>(p.omega.re, p.omega.im);
-    varying = phi_field != nullptr;
+    // per-cell coefficients for a nodal phi or an absorbing layer
+    layered = p.layer_width > 0;
+    varying = phi_field != nullptr || layered;
     const bool conj = p.conjugate != 0;
     galerkin = !varying;
     if (p.restrict_form == MG_RESTRICT_FAS) galerkin = false;
     if (p.restrict_form == MG_RESTRICT_GALERKIN) {
-      if (varying) return fail(MG_EINVAL, "GALERKIN restriction needs a constant phi");
+      if (varying) return fail(MG_EINVAL, "GALERKIN restriction needs a constant phi and no absorbing layer");
       galerkin = true;
     }
     if (op_only) lmin = L;
@@ -247,11 +262,15 @@ struct Engine {
       }
     }
     if (varying) {
-      // nodal phi on every level by injection, cell averages, accumulated diagonal
+      // nodal phi on every level by injection (a constant phi with a layer:
+      // the constant on every vertex), per-cell coefficients with each level's
+      // own cell rotations, accumulated diagonal
       for (int l = L; l >= lmin; --l) {
         Level<T>& v = lv[l];
         MG_TRY(alloc_c(&v.phi, v.N));
-        if (l == L) {
+        if (!phi_field) {
+          MG_HIP(launch_set_value<T>(v.N, v.phi, mk(p.phi.re, p.phi.im), s));
+        } else if (l == L) {
           MG_HIP((launch_convert<double, T>(v.N, phi_field, v.phi, 1.0, s)));
         } else {
           MG_HIP(launch_inject<T>(dim, v.n, lv[l + 1].phi, v.phi, s));
@@ -259,10 +278,14 @@ struct Engine {
       }
       for (int l = lmin; l <= L; ++l) {
         Level<T>& v = lv[l];
-        MG_TRY(alloc_c(&v.phibar, (size_t)ipow(v.n - 1, dim)));
+        const size_t cells = (size_t)ipow(v.n - 1, dim);
+        MG_TRY(alloc_c(&v.cmass, cells));
+        // the stiffness scale eta_c^(d-2) varies over the cells only in 3D
+        if (layered && dim == 3) MG_TRY(alloc_c(&v.cstiff, cells));
         MG_TRY(alloc_c(&v.invDv, v.N));
-        MG_HIP(launch_cellavg<T>(dim, v.n, v.phi, v.phibar, conj ? 1 : 0, s));
-        v.op.phibar = v.phibar;
+        MG_HIP(launch_cellcoef<T>(dim, v.n, v.phi, v.cmass, v.cstiff, rotation(p, l), s));
+        v.op.cmass = v.cmass;
+        v.op.cstiff = v.cstiff;
         MG_HIP(launch_invdiag<T>(dim, v.op, v.invDv, s));
         v.op.invDv = v.invDv;
       }

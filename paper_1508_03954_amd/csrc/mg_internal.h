@@ -22,7 +22,10 @@ __host__ __device__ inline cpx<T> mk(T a, T b) {
 
 // Per-level operator data, passed by value to kernels.
 //   H = alpha * S_K - etad * phi * S_M (constant phi: coef[] by neighbour class),
-//   or, for a nodal phi, stiffness alpha * S_K plus the cell-averaged mass.
+//   or, cell by cell, H_c = kappa_c K - mu_c M with per-cell coefficients:
+//   mass mu_c = phibar_c eta_c^d (phibar_c the mean of the nodal phi over the
+//   cell's vertices) and stiffness kappa_c = eta_c^(d-2) (uniform alpha unless
+//   cells are rotated individually).
 template <class T>
 struct OpData {
   int n;                  // vertices per axis
@@ -30,8 +33,21 @@ struct OpData {
   cpx<T> alpha;           // eta^(d-2)
   cpx<T> etad;            // eta^d
   cpx<T> invD;            // constant phi: 1 / diag
-  const cpx<T>* phibar;   // nodal phi: per-cell averages ((n-1)^d), else nullptr
-  const cpx<T>* invDv;    // nodal phi: per-vertex 1 / diag (n^d), else nullptr
+  const cpx<T>* cmass;    // per-cell mass coefficients mu_c ((n-1)^d), else nullptr
+  const cpx<T>* cstiff;   // per-cell stiffness coefficients kappa_c, or nullptr (alpha)
+  const cpx<T>* invDv;    // per-cell path: per-vertex 1 / diag (n^d), else nullptr
+};
+
+// Rotation of the cells of one level: the complex grid scaling h -> h
+// exp(i theta) of Section 2, with the absorbing layer of Section 7.4 rotating
+// the cells near selected faces by their own angle.
+struct CellRotation {
+  double h;             // real cell side of the level, 3^-l
+  double theta;         // angle of the cells outside the layer
+  double layer_theta;   // angle of the layer's cells
+  double width;         // layer width; 0: no layer
+  int faces;            // bit 2a: face x_a = 0, bit 2a + 1: face x_a = 1 (a = 0: x, fastest)
+  int conj;             // conjugate mode: every eta_c conjugated
 };
 
 // Number of blocks of every kernel that writes reduction partials; the second
@@ -96,8 +112,20 @@ template <class T>
 hipError_t launch_prec_g(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T> omega, const cpx<T>* zc, cpx<T>* g,
                          hipStream_t s);
 
+// Per-cell coefficients of a level with n vertices per axis from its nodal
+// phi: mass mu_c = phibar_c eta_c^d and, when stiff != nullptr, stiffness
+// kappa_c = eta_c^(d-2), with eta_c = h exp(i theta_c) from rot (conjugated,
+// with phibar, in conjugate mode).
 template <class T>
-hipError_t launch_cellavg(int dim, int n, const cpx<T>* phi, cpx<T>* phibar, int conj, hipStream_t s);
+hipError_t launch_cellcoef(int dim, int n, const cpx<T>* phi, cpx<T>* mass, cpx<T>* stiff, CellRotation rot,
+                           hipStream_t s);
+// v = value on all `count` entries.
+template <class T>
+hipError_t launch_set_value(size_t count, cpx<T>* v, cpx<double> value, hipStream_t s);
+// Lumped load with per-cell rotation: b_j = chi_j 2^-d sum_{c contains j} eta_c^d
+// on interior vertices, 0 on the boundary (FP64).
+hipError_t launch_rhs_cells(int dim, int n, const cpx<double>* chi, cpx<double>* b, CellRotation rot,
+                            hipStream_t s);
 
 template <class T>
 hipError_t launch_invdiag(int dim, const OpData<T>& op, cpx<T>* invDv, hipStream_t s);

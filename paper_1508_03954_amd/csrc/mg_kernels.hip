@@ -355,45 +355,84 @@ __global__ void k_prec_g(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> om
   }
 }
 
+// Per-cell coefficients: mu_c = phibar_c eta_c^d and (stiff != nullptr)
+// kappa_c = eta_c^(d-2), formed in double precision.
 template <class T, int D>
-__global__ void k_cellavg(int n, const cpx<T>* __restrict__ phi, cpx<T>* __restrict__ phibar, int conj) {
+__global__ void k_cellcoef(int n, const cpx<T>* __restrict__ phi, cpx<T>* __restrict__ mass,
+                           cpx<T>* __restrict__ stiff, CellRotation rot) {
   const int nc = n - 1;
   const long long N = total<D>(nc);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     int c[3];
     unravel<D>(i, nc, c);
-    cpx<T> acc = czero<T>();
+    cpx<double> acc = mk(0.0, 0.0);
     for (int k = 0; k < (1 << D); ++k) {
       int v[3] = {c[0] + (k & 1), c[1] + ((k >> 1) & 1), c[2] + ((k >> 2) & 1)};
-      acc = acc + phi[ravel<D>(v, n)];
+      const cpx<T> p = phi[ravel<D>(v, n)];
+      acc = acc + mk((double)p.re, (double)p.im);
     }
-    acc = T(1.0 / (1 << D)) * acc;
-    if (conj) acc.im = -acc.im;
-    phibar[i] = acc;
+    acc = (1.0 / (1 << D)) * acc;
+    if (rot.conj) acc.im = -acc.im;
+    const cpx<double> mu = cmul(acc, cell_eta_pow<D>(rot, c, nc, D));
+    mass[i] = mk(T(mu.re), T(mu.im));
+    if (stiff) {
+      const cpx<double> ka = cell_eta_pow<D>(rot, c, nc, D - 2);
+      stiff[i] = mk(T(ka.re), T(ka.im));
+    }
   }
 }
 
-// 1 / D_j with D_j = alpha 2d (2/3)^(d-1) - etad 3^-d sum_{c contains j} phibar_c.
+// 1 / D_j with D_j = sum_{c contains j} (kappa_c K_jj - mu_c M_jj), K_jj =
+// d 3^(1-d) and M_jj = 3^-d on every cell (kappa_c = alpha unless per cell).
 template <class T, int D>
 __global__ void k_invdiag(OpData<T> op, cpx<T>* __restrict__ invDv) {
   const int n = op.n, nc = n - 1;
-  const T kd = D == 3 ? T(6.0 * 4.0 / 9.0) : T(4.0 * 2.0 / 3.0);
+  const T kd = D == 3 ? T(1.0 / 3.0) : T(2.0 / 3.0);
   const T m0 = D == 3 ? T(1.0 / 27.0) : T(1.0 / 9.0);
   MG_ROWS(D, n) {
     int j[3];
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     if (!is_interior<D>(j, n)) { invDv[i] = mk(T(1), T(0)); continue; }
-    cpx<T> ps = czero<T>();
+    cpx<T> ms = czero<T>(), ks = czero<T>();
     for (int k = 0; k < (1 << D); ++k) {
       int c[3] = {j[0] - (k & 1), j[1] - ((k >> 1) & 1), j[2] - ((k >> 2) & 1)};
-      ps = ps + op.phibar[ravel<D>(c, nc)];
+      const long long ci = ravel<D>(c, nc);
+      ms = ms + op.cmass[ci];
+      ks = ks + (op.cstiff ? op.cstiff[ci] : op.alpha);
     }
-    const cpx<T> d = kd * op.alpha - cmul(op.etad, m0 * ps);
+    const cpx<T> d = kd * ks - m0 * ms;
     // 1/d computed in double for both precisions
     const double dr = d.re, di = d.im, den = dr * dr + di * di;
     invDv[i] = mk(T(dr / den), T(-di / den));
+  }
+}
+
+template <class T>
+__global__ void k_set_value(size_t count, cpx<T>* __restrict__ v, cpx<T> value) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = value;
+}
+
+template <int D>
+__global__ void k_rhs_cells(int n, const cpx<double>* __restrict__ chi, cpx<double>* __restrict__ b,
+                            CellRotation rot) {
+  const int nc = n - 1;
+  MG_ROWS(D, n) {
+    int j[3];
+    long long i;
+    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
+    cpx<double> out = mk(0.0, 0.0);
+    if (is_interior<D>(j, n)) {
+      cpx<double> w = mk(0.0, 0.0);
+      for (int k = 0; k < (1 << D); ++k) {
+        int c[3] = {j[0] - (k & 1), j[1] - ((k >> 1) & 1), j[2] - ((k >> 2) & 1)};
+        w = w + cell_eta_pow<D>(rot, c, nc, D);
+      }
+      out = cmul((1.0 / (1 << D)) * w, chi[i]);
+    }
+    b[i] = out;
   }
 }
 
@@ -745,7 +784,7 @@ static inline dim3 row_grid(int n, int dim, int max_row_blocks = 65535) {
 
 template <class T>
 hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y, hipStream_t s) {
-  if (dim == 3 && !op.phibar && stencil3_blocks(op.n) > 0)
+  if (dim == 3 && !op.cmass && stencil3_blocks(op.n) > 0)
     return launch_stencil3<T>(1, op.n, op.coef, nullptr, x, y, nullptr, nullptr, s);
   MG_DISPATCH(dim, k_apply, row_grid(op.n, dim), op, x, y);
   return hipGetLastError();
@@ -780,7 +819,7 @@ hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>
 template <class T>
 hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
                         double* partials, int* nparts, hipStream_t s) {
-  const int sb = dim == 3 && !op.phibar ? stencil3_blocks(op.n) : -1;
+  const int sb = dim == 3 && !op.cmass ? stencil3_blocks(op.n) : -1;
   if (sb > 0 && (!partials || sb <= kRedBlocks))
     return launch_stencil3<T>(0, op.n, op.coef, b, x, r, partials, nparts, s);
   dim3 g = row_grid(op.n, dim);
@@ -853,8 +892,9 @@ hipError_t launch_prec_g(int dim, const OpData<T>& op, const cpx<T>* rho, cpx<T>
 }
 
 template <class T>
-hipError_t launch_cellavg(int dim, int n, const cpx<T>* phi, cpx<T>* phibar, int conj, hipStream_t s) {
-  MG_DISPATCH(dim, k_cellavg, dim3(grid_for(pow_n(n - 1, dim))), n, phi, phibar, conj);
+hipError_t launch_cellcoef(int dim, int n, const cpx<T>* phi, cpx<T>* mass, cpx<T>* stiff, CellRotation rot,
+                           hipStream_t s) {
+  MG_DISPATCH(dim, k_cellcoef, dim3(grid_for(pow_n(n - 1, dim))), n, phi, mass, stiff, rot);
   return hipGetLastError();
 }
 
@@ -867,6 +907,19 @@ hipError_t launch_invdiag(int dim, const OpData<T>& op, cpx<T>* invDv, hipStream
 template <class T>
 hipError_t launch_zero_boundary_copy(int dim, int n, const cpx<T>* in, cpx<T>* out, cpx<T> scale, hipStream_t s) {
   MG_DISPATCH(dim, k_zero_boundary_copy, row_grid(n, dim), n, in, out, scale);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_set_value(size_t count, cpx<T>* v, cpx<double> value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_value<T>, dim3(grid_for((long long)count)), 256, 0, s, count, v,
+                     mk(T(value.re), T(value.im)));
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_cells(int dim, int n, const cpx<double>* chi, cpx<double>* b, CellRotation rot, hipStream_t s) {
+  if (dim == 3) hipLaunchKernelGGL(k_rhs_cells<3>, row_grid(n, 3), 256, 0, s, n, chi, b, rot);
+  else hipLaunchKernelGGL(k_rhs_cells<2>, row_grid(n, 2), 256, 0, s, n, chi, b, rot);
   return hipGetLastError();
 }
 
@@ -1010,7 +1063,8 @@ hipError_t launch_finish_sum2(const double* partials, int count, double* out, hi
                                         cpx<T>*, hipStream_t);                                                  \
   template hipError_t launch_prec_g<T>(int, const OpData<T>&, const cpx<T>*, cpx<T>, const cpx<T>*, cpx<T>*,     \
                                        hipStream_t);                                                            \
-  template hipError_t launch_cellavg<T>(int, int, const cpx<T>*, cpx<T>*, int, hipStream_t);                    \
+  template hipError_t launch_cellcoef<T>(int, int, const cpx<T>*, cpx<T>*, cpx<T>*, CellRotation, hipStream_t);  \
+  template hipError_t launch_set_value<T>(size_t, cpx<T>*, cpx<double>, hipStream_t);                           \
   template hipError_t launch_invdiag<T>(int, const OpData<T>&, cpx<T>*, hipStream_t);                           \
   template hipError_t launch_zero_boundary_copy<T>(int, int, const cpx<T>*, cpx<T>*, cpx<T>, hipStream_t);      \
   template hipError_t launch_dot<T>(size_t, const cpx<T>*, const cpx<T>*, double*, hipStream_t);                \

@@ -93,12 +93,16 @@ class Problem:
     variant: str = "bpx"
     omega: complex = 0.6
     cycles: int = 30
+    phi_nodal: Optional[np.ndarray] = None   # nodal phi(x) on the finest level (replaces phi)
+    layer: Optional[Tuple[float, float, int]] = None   # absorbing layer: angle, width, face bits
 
     @property
     def n(self) -> int:
         return n_vertices(self.level_max)
 
     def phi_field(self) -> Optional[np.ndarray]:
+        if self.phi_nodal is not None:
+            return np.asarray(self.phi_nodal, dtype=np.complex128)
         if self.potential is None:
             return None
         return (self.phi - self.potential).astype(np.complex128)
@@ -174,6 +178,27 @@ def config_potential(level_max: int = 5, seed: int = 5) -> Problem:
     chi = gaussian(level_max, 3, c, 0.05).astype(np.complex128)
     return Problem("3d_potential_k15", 3, level_max, 1, 0.0, 225.0 * (1 + 0.3j), chi,
                    potential=V, variant="bpx", omega=0.6, cycles=50)
+
+
+def config_gaussian08(theta_deg: float, level_max: int = 4) -> Problem:
+    """The p = 2 application problem of Section 7.4 (eq. 08-gaussian) on the
+    regular grid h = 3^-level_max (1/81 by default):
+        chi(x, y) = exp(-(125 x)^2 - (125 y)^2),
+        phi(x, y) = 45^2 + 135^2 (exp(-(15 x)^2) + exp(-(15 y)^2)),
+    x and y measured from the corner at the origin (the centre of mass).  The
+    faces x = 1 and y = 1 are open: the cells within 1/3 of them form an
+    absorbing layer rotated by 30 degrees; every other cell is rotated by
+    theta_deg.  The faces are bits 1 (x = 1) and 3 (y = 1) of the layer's
+    face set, x being the fastest-varying coordinate."""
+    xs = vertex_coords(level_max, 2)
+    y, x = xs[0], xs[1]
+    chi = np.exp(-(125.0 * x) ** 2 - (125.0 * y) ** 2) * np.ones((n_vertices(level_max),) * 2)
+    phi = 45.0 ** 2 + 135.0 ** 2 * (np.exp(-(15.0 * x) ** 2) + np.exp(-(15.0 * y) ** 2))
+    phi = np.broadcast_to(phi, chi.shape)
+    return Problem(f"gaussian08_theta{theta_deg:g}", 2, level_max, 1, math.radians(theta_deg), 0j,
+                   chi.astype(np.complex128), variant="bpx", omega=0.4, cycles=50,
+                   phi_nodal=phi.astype(np.complex128),
+                   layer=(math.radians(30.0), 1.0 / 3.0, (1 << 1) | (1 << 3)))
 
 
 def shell_mask(level: int, dim: int, r_in: float = 0.9, r_out: float = 0.95) -> np.ndarray:

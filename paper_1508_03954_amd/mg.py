@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("variant", ctypes.c_int), ("omega_scheme", ctypes.c_int), ("omega", c128),
         ("omega_L", ctypes.c_int), ("precision", ctypes.c_int), ("conjugate", ctypes.c_int),
         ("restrict_form", ctypes.c_int), ("sweep", ctypes.c_int), ("inner_rtol", ctypes.c_double),
+        ("layer_theta", ctypes.c_double), ("layer_width", ctypes.c_double), ("layer_faces", ctypes.c_int),
     ]
 
 
@@ -127,8 +128,9 @@ def _ptr(t) -> int:
 def make_params(dim: int, level_max: int, level_min: int = 1, theta: float = 0.0, phi: complex = 0.0,
                 phi_field=None, variant: str = "bpx", omega_scheme: str = "const", omega: complex = 0.6,
                 omega_L: int = 1, precision: str = "fp64", conjugate: bool = False, restrict_form: str = "auto",
-                sweep: str = "auto", inner_rtol: float = 0.0):
-    """mg_params from keyword values; returns (params, device phi field kept alive or None)."""
+                sweep: str = "auto", inner_rtol: float = 0.0, layer=None):
+    """mg_params from keyword values; returns (params, device phi field kept alive or None).
+    layer: None or (angle, width, face bits) of an absorbing layer."""
     import torch
     lib = load_library()
     p = Params()
@@ -149,6 +151,8 @@ def make_params(dim: int, level_max: int, level_min: int = 1, theta: float = 0.0
     p.restrict_form = RESTRICT_FORMS[restrict_form]
     p.sweep = SWEEPS[sweep]
     p.inner_rtol = inner_rtol
+    if layer is not None:
+        p.layer_theta, p.layer_width, p.layer_faces = float(layer[0]), float(layer[1]), int(layer[2])
     return p, keep
 
 
@@ -158,11 +162,12 @@ class Solver:
     def __init__(self, dim: int, level_max: int, level_min: int = 1, theta: float = 0.0,
                  phi: complex = 0.0, phi_field=None, variant: str = "bpx", omega_scheme: str = "const",
                  omega: complex = 0.6, omega_L: int = 1, precision: str = "fp64", conjugate: bool = False,
-                 restrict_form: str = "auto", sweep: str = "auto", stream=None, inner_rtol: float = 0.0):
+                 restrict_form: str = "auto", sweep: str = "auto", stream=None, inner_rtol: float = 0.0,
+                 layer=None):
         import torch
         lib = load_library()
         p, keep = make_params(dim, level_max, level_min, theta, phi, phi_field, variant, omega_scheme, omega,
-                              omega_L, precision, conjugate, restrict_form, sweep, inner_rtol)
+                              omega_L, precision, conjugate, restrict_form, sweep, inner_rtol, layer)
         self._phi_keep = keep
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         ctx = ctypes.c_void_p()
