@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the complex additive multilevel cycle on one MI355X.
 
-Workload (default): d = 3, levels 1..5 (243^3 finest cells, 244^3 complex128
-vertices), -Lap u - k^2 u with k = 20 on the complex grid h exp(i pi/6), load =
-four Gaussians plus 1e-3 complex noise, BPX, omega 0.6 on every level.  One
-step = one pipelined additive cycle over the whole hierarchy (coarse descent,
-fused finest sweep, coarse backtracking, residual norm).  Inputs are resident
-in HBM before timing starts.
+Headline workload: d = 3, levels 1..6 (729^3 finest cells, 730^3 = 389 M
+complex128 vertices), -Lap u - phi u with phi = k^2 (1 + 0.5i), k = 40,
+theta = 0, one Gaussian load, BPX, omega 0.6 on every level.  One step = one
+pipelined additive cycle over the whole hierarchy (coarse descent, fused
+finest sweep, coarse backtracking, residual norm).  Inputs are resident in
+HBM before timing starts.
 
 Printed JSON line (last line of stdout): vertex-updates/s per cycle (interior
 vertices of all levels per cycle time), the finest sweep's achieved HBM
-bandwidth against the 8 TB/s peak, the FP64 CPU oracle's rate on a bounded
-sample, the hierarchical-basis variant's rate, and time to relative residual
-1e-10 with the BiCGStab driver.
+bandwidth against the 8 TB/s peak, time to relative residual 1e-10 with the
+BiCGStab driver in FP64 and with complex64 corrections inside FP64 residual
+refinement (and the mixed solution's deviation from the FP64 one), the FP64
+CPU oracle's rate on a bounded sample, and extras: the 3D level-5 k = 20
+complex-grid workload (BPX and hb cycles, time to 1e-10 from zero and from a
+nested start) and the 96-problem batched workload.
 """
 
 from __future__ import annotations
@@ -70,12 +73,12 @@ def fused_source_digest():
     return h.hexdigest()
 
 
-def traffic_from_profiles(tile):
+def traffic_from_profiles(tile, level):
     """HBM traffic of the finest sweep from the committed rocprofv3 counter
-    summary, scaled by the copy-kernel calibration; None when absent, when the
-    kernel sources changed since the counters were taken or when the counters
-    were taken for another tile."""
-    path = os.path.join(ROOT, "profiles", "fused3_traffic.json")
+    summary of that level, scaled by the copy-kernel calibration; None when
+    absent, when the kernel sources changed since the counters were taken or
+    when the counters were taken for another tile."""
+    path = os.path.join(ROOT, "profiles", f"fused3_l{level}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -109,28 +112,81 @@ def time_cycles(s, steps, warmup, torch, ramp_s=0.3):
     return ms / steps, sweep_ms / max(cnt, 1), cnt
 
 
-def cpu_baseline(prob, variant, cycles):
-    """The FP64 oracle as it stands on the host (numpy, one BLAS thread)."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
+def _oracle_pipeline(level):
+    """The FP64 oracle's pipelined cycle state for the 3D k = 40 problem at
+    `level` (setup: input, load, helpers)."""
     import oracle as O
     from oracle.cycle import Params
-    L, dim = prob.level_max, prob.dim
-    p = Params(dim=dim, level_max=L, theta=prob.theta, phi=prob.phi, variant=variant, omega=0.6)
-    b = O.lumped_rhs(prob.chi, L, prob.theta)
+    from paper_1508_03954_amd.inputs import config_3d_large
+    prob = config_3d_large(level_max=level)
+    p = Params(dim=3, level_max=level, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
+    b = O.lumped_rhs(prob.chi, level, prob.theta)
+    return O.Pipelined(p, b)
+
+
+def _timed_cycle(pipe):
+    """Wall time of one oracle cycle with numpy on one BLAS thread."""
+    from threadpoolctl import threadpool_limits
     with threadpool_limits(1):
-        pipe = O.Pipelined(p, b)
         t0 = time.perf_counter()
-        for _ in range(cycles):
-            pipe.cycle()
-        dt = (time.perf_counter() - t0) / cycles
+        pipe.cycle()
+        return time.perf_counter() - t0
+
+
+def _oracle_worker(level, barrier, q):
+    pipe = _oracle_pipeline(level)
+    barrier.wait()
+    q.put(_timed_cycle(pipe))
+
+
+def host_cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(procs=0, level=5):
+    """The FP64 oracle as it stands, on the host: one pipelined cycle of the
+    3D k = 40 problem (the headline's problem family) at level 5, 244^3, the
+    largest size whose oracle cycle fits a bounded sample (its cost is linear
+    in the vertex count; level 6 would need ~30x the memory).  Timed in one
+    process, then in `procs` processes that start their cycles together after
+    their setup (the oracle's numpy arithmetic is single-threaded, so the
+    cores are used by processes): rate = all their vertex updates over the
+    slowest process's cycle time."""
+    import multiprocessing as mp
+    import psutil
+    ups = updates_per_cycle(3, level)
+    t1 = _timed_cycle(_oracle_pipeline(level))
+    ncpu = os.cpu_count() or 1
+    if procs <= 0:
+        # each process peaks near 12 GB at level 5; use at most 40 % of the
+        # free memory, at most 8 processes and the cores there are
+        per_proc = 12e9
+        procs = max(1, min(8, ncpu, int(0.4 * psutil.virtual_memory().available / per_proc)))
+    ctx = mp.get_context("fork")
+    barrier, q = ctx.Barrier(procs), ctx.Queue()
+    ps = [ctx.Process(target=_oracle_worker, args=(level, barrier, q)) for _ in range(procs)]
+    for p in ps:
+        p.start()
+    times = [q.get() for _ in ps]
+    for p in ps:
+        p.join()
     return {
-        "value": updates_per_cycle(dim, L) / dt,
+        "value": procs * ups / max(times),
         "unit": "vertex-updates/s",
-        "cores": 1,
+        "cores": procs,
         "kind": "oracle",
-        "sample": f"{cycles} pipelined FP64 oracle cycle(s) of the same {dim}D L={L} {variant} workload "
-                  f"(full size; setup excluded), numpy with one BLAS thread; {dt:.2f} s per cycle",
+        "sample": f"one pipelined FP64 oracle cycle (numpy, one BLAS thread per process) of the 3D k=40, "
+                  f"phi=k^2(1+0.5i), BPX problem at level {level} ({3 ** level + 1}^3 vertices, {ups} vertex "
+                  f"updates) in each of {procs} processes started together after their setup; rate = their "
+                  f"updates over the slowest process's cycle time ({max(times):.2f} s)",
+        "single_thread": {"value": ups / t1, "cores": 1, "seconds_per_cycle": t1},
+        "host": {"nproc": ncpu, "cpu_model": host_cpu_model()},
     }
 
 
@@ -223,28 +279,184 @@ def refine_extra(torch, level):
     return res
 
 
+def cycle_record(s, L, variant, steps, warmup, ramp_s, torch, tune_reps=3, tile=None, autotune=True):
+    """Autotuned (or fixed-tile) timing of one hierarchy's pipelined cycle:
+    vertex-updates/s, the finest sweep's live duration and its roofline."""
+    dim = 3
+    tune = None
+    if tile is not None:
+        s.set_tile(tile)
+        tune = {"tile": tile, "fixed": True}
+    elif autotune:
+        best, best_us, times = s.autotune(reps=tune_reps)
+        tune = {"tile": best, "us_per_tile": [round(t, 1) for t in times]}
+        log(f"[bench] autotune L={L}: tile {best} ({best_us:.1f} us); all: {', '.join(f'{t:.1f}' for t in times)}")
+    ms_step, sweep_ms, nsw = time_cycles(s, steps, warmup, torch, ramp_s)
+    ups = updates_per_cycle(dim, L)
+    fb = fused_bytes(dim, L, variant)
+    achieved = fb / (sweep_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(s.tiles()[0], L)
+    log(f"[bench] L={L} {variant}: cycle {ms_step * 1e3:.1f} us, finest sweep {sweep_ms * 1e3:.1f} us ({nsw} timed), "
+        f"{achieved:.0f} GB/s algorithmic")
+    roof = {
+        "kernel": "k_fused3 (finest-level fused sweep)",
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS,
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": fb,
+        "avg_launch_us": sweep_ms * 1e3,
+        "launches_timed": nsw,
+        # the whole cycle priced at the method's single-touch byte count
+        "cycle_effective_GBs": single_touch_bytes(dim, L) / (ms_step * 1e-3) / 1e9,
+    }
+    return ms_step, ups, roof, tune
+
+
+def time_solve(s, b, torch, driver="bicgstab", maxit=3000):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, its, rel, rc = s.solve(b, rtol=1e-10, maxit=maxit, driver=driver)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return u, {"seconds": dt, "iterations": its, "relres": rel, "status": rc}
+
+
+def headline(args, torch):
+    """The 3D level-6 problem: k = 40, phi = k^2 (1 + 0.5i), theta = 0, BPX,
+    omega 0.6 on every level.  Plain complex128 cycle rate and sweep roofline;
+    BiCGStab to 1e-10 in FP64 and with complex64 corrections inside FP64
+    residual refinement, and the deviation of the mixed solution from the
+    FP64 one."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_3d_large
+    L = args.level
+    prob = config_3d_large(level_max=L)
+    chi = torch.from_numpy(prob.chi).cuda()
+    theta, phi = prob.theta, prob.phi
+    name = prob.name
+    del prob
+    log(f"[bench] {name}: 3D L={L} ({3 ** L + 1}^3 vertices), steps={args.steps} warmup={args.warmup}")
+    s = mg.Solver(3, L, theta=theta, phi=phi, variant="bpx", omega=0.6, sweep=args.sweep)
+    b = s.rhs_from_nodal(chi)
+    s.set_rhs(b)
+    s.set_solution(torch.zeros_like(b))
+    ms_step, ups, roof, tune = cycle_record(s, L, "bpx", args.steps, args.warmup, args.ramp_s, torch,
+                                           tune_reps=2, tile=args.tile,
+                                           autotune=args.sweep != "generic" and not args.no_autotune)
+    s.set_rhs(b)
+    s.set_solution(torch.zeros_like(b))
+    rh, _ = s.cycle(3)
+    log(f"[bench] residual h-norms of the first cycles: {', '.join(f'{v:.3e}' for v in rh)}")
+    rec = {"ms_per_step": ms_step, "value": ups / (ms_step * 1e-3), "ups": ups, "roofline": roof, "tune": tune,
+           "workload": f"{name}: d=3, levels 1..{L} ({3 ** L + 1}^3 complex128 vertices), k=40, "
+                       f"phi=k^2(1+0.5i), theta=0, one Gaussian load (sigma 0.05), bpx, omega=0.6 on every level"}
+    if args.no_solve:
+        return rec
+    b0 = torch.zeros_like(b)
+    bnorm = s.residual_norm(b0, b)
+    u64, r64 = time_solve(s, b, torch)
+    r64["true_relres"] = s.residual_norm(u64, b) / bnorm
+    log(f"[bench] FP64 BiCGStab to 1e-10: {r64['seconds']:.2f} s, {r64['iterations']} iterations, "
+        f"relres {r64['true_relres']:.2e}")
+    del s
+    torch.cuda.empty_cache()
+    m = mg.Solver(3, L, theta=theta, phi=phi, variant="bpx", omega=0.6, precision="fp32_refine")
+    um, rm = time_solve(m, b, torch)
+    del m
+    torch.cuda.empty_cache()
+    # the mixed solution's true residual with an FP64 operator
+    chk = mg.Solver(3, L, level_min=L, theta=theta, phi=phi, variant="bpx", omega=0.6, sweep="generic")
+    rm["true_relres"] = chk.residual_norm(um, b) / bnorm
+    del chk
+    err = (torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64)).item()
+    log(f"[bench] complex64-in-FP64 refinement to 1e-10: {rm['seconds']:.2f} s, {rm['iterations']} inner "
+        f"iterations, relres {rm['true_relres']:.2e}, |u_mixed - u_fp64| / |u_fp64| = {err:.2e}")
+    rec["time_to_1e-10"] = {
+        "driver": "bicgstab (preconditioner: one zero-start additive cycle)",
+        "seconds": r64["seconds"],
+        "fp64": r64,
+        "fp32_refine": dict(rm, form="complex64 level corrections, FP64 residual and update"),
+        "mixed_vs_fp64_rel_error": err,
+        "speedup_mixed_over_fp64": r64["seconds"] / rm["seconds"],
+    }
+    del u64, um, b, chi
+    torch.cuda.empty_cache()
+    return rec
+
+
+def csg_extra(args, torch):
+    """The 3D level-5 problem: k = 20 on the complex grid h exp(i pi/6), four
+    Gaussians plus 1e-3 noise; BPX and hb cycles, BiCGStab to 1e-10 from zero
+    and from a nested start."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_3d_csg
+    L = 5
+    prob = config_3d_csg(level_max=L, variant="bpx")
+    chi = torch.from_numpy(prob.chi).cuda()
+    out = {"workload": f"{prob.name}: d=3, levels 1..{L} ({3 ** L + 1}^3 complex128 vertices), k=20, "
+                       f"theta=pi/6, 4 Gaussians + 1e-3 noise, omega=0.6 on every level"}
+    for variant in ("bpx", "hb"):
+        s = mg.Solver(3, L, theta=prob.theta, phi=prob.phi, variant=variant, omega=0.6)
+        b = s.rhs_from_nodal(chi)
+        s.set_rhs(b)
+        s.set_solution(torch.zeros_like(b))
+        ms, ups, roof, tune = cycle_record(s, L, variant, 200, 10, args.ramp_s, torch, tune_reps=5,
+                                           autotune=not args.no_autotune)
+        out[variant] = {"value": ups / (ms * 1e-3), "ms_per_step": ms, "vertex_updates_per_cycle": ups,
+                        "roofline": roof, "autotune": tune}
+        if variant == "bpx":
+            b0 = torch.zeros_like(b)
+            bnorm = s.residual_norm(b0, b)
+            u, rec = time_solve(s, b, torch, maxit=2000)
+            rec["true_relres"] = s.residual_norm(u, b) / bnorm
+            out["time_to_1e-10"] = dict(rec, driver="bicgstab (preconditioner: one zero-start additive cycle)")
+            log(f"[bench] L=5 BiCGStab to 1e-10: {rec['seconds']:.3f} s, {rec['iterations']} iterations")
+            # nested start: levels 3 and 4 solved to 1e-2 with the sampled load,
+            # each from the prolonged level below (one untimed call makes the
+            # coarser levels' contexts)
+            s.solve_nested(chi, level_start=L - 2, coarse_rtol=1e-2, rtol=1e-10, maxit=2000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, its, rel, rc = s.solve_nested(chi, level_start=L - 2, coarse_rtol=1e-2, rtol=1e-10, maxit=2000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out["time_to_1e-10_nested"] = {
+                "driver": "bicgstab from the prolonged solutions of levels L-2 and L-1 (each solved to 1e-2)",
+                "seconds": t1 - t0, "finest_iterations": its, "relres": rel,
+                "true_relres": s.residual_norm(u, b) / bnorm, "status": rc}
+            log(f"[bench] L=5 nested BiCGStab to 1e-10: {t1 - t0:.3f} s, {its} finest iterations")
+        del s, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--level", type=int, default=5)
-    ap.add_argument("--variant", default="bpx", choices=["add", "hb", "bpx"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--level", type=int, default=6, help="finest level of the 3D k=40 workload (default 6: 730^3)")
     ap.add_argument("--sweep", default="auto", choices=["auto", "generic", "fused"])
-    ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes of the all-core CPU baseline (0: as many as cores and memory allow, "
+                         "at most 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the hb-variant and time-to-residual runs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 244^3 and batched workloads")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-10 solves of the headline")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--ramp-s", type=float, default=0.3,
                     help="seconds of untimed cycles before the warmup cycles (device clock ramp)")
     ap.add_argument("--tile", type=int, default=None, help="fixed tile variant of the fused sweep (no autotune)")
-    ap.add_argument("--refine-level", type=int, default=0,
-                    help="also solve the 3D k=40 problem at this level with complex64 refinement vs FP64 (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy three times (calibrates hardware byte counters)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the 96-problem batched measurement (and the copy probe if asked) and print "
                          "its record; for counter runs of the batched kernel")
+    ap.add_argument("--csg-only", action="store_true",
+                    help="run only the 3D level-5 k=20 workload and print its record; for counter runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -253,143 +465,62 @@ def main():
                                    "kernel; run with --gpus 1"}))
         sys.exit(2)
 
-    import numpy as np
+    # the CPU baseline runs first, before the device is touched: its worker
+    # processes are forked from a process without GPU state
+    cpu = None
+    if not (args.no_cpu_baseline or args.batched_only or args.csg_only):
+        log("[bench] CPU baseline: FP64 oracle on the host ...")
+        cpu = cpu_baseline(args.cpu_procs)
+        log(f"[bench] oracle {cpu['value']:.3e} vertex-updates/s on {cpu['cores']} processes, "
+            f"{cpu['single_thread']['value']:.3e} on one")
+
     import torch
     from paper_1508_03954_amd import mg
-    from paper_1508_03954_amd.inputs import config_3d_csg
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     mg.load_library()
-    if args.batched_only:
-        out = {"batched": batched_extra(torch)}
+    if args.batched_only or args.csg_only:
+        out = {"batched": batched_extra(torch)} if args.batched_only else {"csg_l5": csg_extra(args, torch)}
         if args.copy_probe:
             copy_probe(torch, out)
         print(json.dumps(out))
         return
-    L, dim = args.level, 3
-    prob = config_3d_csg(level_max=L, variant=args.variant)
-    chi = torch.from_numpy(prob.chi).cuda()
 
-    def make(variant):
-        s = mg.Solver(dim, L, theta=prob.theta, phi=prob.phi, variant=variant, omega=0.6, sweep=args.sweep)
-        b = s.rhs_from_nodal(chi)
-        s.set_rhs(b)
-        s.set_solution(torch.zeros_like(b))
-        return s, b
-
-    s, b = make(args.variant)
-    log(f"[bench] {prob.name}: {dim}D L={L} ({3 ** L + 1}^3 vertices), steps={args.steps} warmup={args.warmup}")
-    tune = None
-    if args.tile is not None:
-        s.set_tile(args.tile)
-        tune = {"tile": args.tile, "fixed": True}
-    elif args.sweep != "generic" and not args.no_autotune:
-        best, best_us, times = s.autotune(reps=5)
-        tune = {"tile": best, "us_per_tile": [round(t, 1) for t in times]}
-        log(f"[bench] autotune: tile {best} ({best_us:.1f} us); all: {', '.join(f'{t:.1f}' for t in times)}")
-    ms_step, sweep_ms, nsw = time_cycles(s, args.steps, args.warmup, torch, args.ramp_s)
-    ups = updates_per_cycle(dim, L)
-    value = ups / (ms_step * 1e-3)
-    fb = fused_bytes(dim, L, args.variant)
-    achieved = fb / (sweep_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(s.tiles()[0])
-    log(f"[bench] cycle {ms_step * 1e3:.1f} us, finest sweep {sweep_ms * 1e3:.1f} us ({nsw} timed), "
-        f"{achieved:.0f} GB/s algorithmic")
-    # residual history sanity (the stationary cycle on this indefinite problem may grow)
-    s.set_rhs(b)
-    s.set_solution(torch.zeros_like(b))
-    rh, _ = s.cycle(3)
-    log(f"[bench] residual h-norms of the first cycles: {', '.join(f'{v:.3e}' for v in rh)}")
-
+    h = headline(args, torch)
+    L = args.level
     out = {
         "metric": "vertex-updates/s per additive cycle",
-        "value": value,
+        "value": h["value"],
         "unit": "vertex-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "warmup_ramp_s": args.ramp_s,
-        "ms_per_step": ms_step,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{prob.name}: d=3, levels 1..{L} ({3 ** L + 1}^3 complex128 vertices), k=20, "
-                        f"theta=pi/6, 4 Gaussians + 1e-3 noise, {args.variant}, omega=0.6 on every level",
-            "vertex_updates_per_cycle": ups,
+            "workload": h["workload"],
+            "vertex_updates_per_cycle": h["ups"],
             "parallelism": "single GPU",
             "sweep": "fused" if args.sweep != "generic" else "generic",
-            "autotune": tune,
+            "autotune": h["tune"],
         },
-        "roofline": {
-            "kernel": "k_fused3 (finest-level fused sweep)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": fb,
-            "avg_launch_us": sweep_ms * 1e3,
-            "launches_timed": nsw,
-            # the whole cycle priced at the method's single-touch byte count
-            "cycle_effective_GBs": single_touch_bytes(dim, L) / (ms_step * 1e-3) / 1e9,
-        },
+        "roofline": h["roofline"],
     }
-
+    if "time_to_1e-10" in h:
+        out["time_to_1e-10"] = h["time_to_1e-10"]
     if not args.no_extras:
-        other = "hb" if args.variant != "hb" else "bpx"
-        s2, b2 = make(other)
-        if args.sweep != "generic" and not args.no_autotune and args.tile is None:
-            s2.autotune(reps=5)
-        ms2, sw2, _ = time_cycles(s2, args.steps, args.warmup, torch, args.ramp_s)
-        out["extra_variant"] = {"variant": other, "value": ups / (ms2 * 1e-3), "ms_per_step": ms2,
-                                "sweep_us": sw2 * 1e3,
-                                "sweep_GBs": fused_bytes(dim, L, other) / (sw2 * 1e-3) / 1e9}
-        del s2
-        # time to relative residual 1e-10: BiCGStab preconditioned by one zero-start cycle
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u, its, rel, rc = s.solve(b, rtol=1e-10, maxit=2000, driver="bicgstab")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        true_rel = s.residual_norm(u, b) / s.residual_norm(torch.zeros_like(b), b)
-        out["time_to_1e-10"] = {"driver": "bicgstab (preconditioner: one zero-start additive cycle)",
-                                "seconds": t1 - t0, "iterations": its, "relres": rel,
-                                "true_relres": true_rel, "status": rc}
-        log(f"[bench] BiCGStab to 1e-10: {t1 - t0:.3f} s, {its} iterations, relres {true_rel:.2e}")
-        # the same from a nested start: levels 3 and 4 solved to 1e-2 with the
-        # sampled load, each from the prolonged level below (one untimed call
-        # makes the coarser levels' contexts)
-        s.solve_nested(chi, level_start=L - 2, coarse_rtol=1e-2, rtol=1e-10, maxit=2000)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        u, its, rel, rc = s.solve_nested(chi, level_start=L - 2, coarse_rtol=1e-2, rtol=1e-10, maxit=2000)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        true_rel = s.residual_norm(u, b) / s.residual_norm(torch.zeros_like(b), b)
-        out["time_to_1e-10_nested"] = {"driver": "bicgstab from the prolonged solutions of levels L-2 and L-1 "
-                                                  "(each solved to 1e-2)", "seconds": t1 - t0,
-                                       "finest_iterations": its, "relres": rel, "true_relres": true_rel,
-                                       "status": rc}
-        log(f"[bench] nested BiCGStab to 1e-10: {t1 - t0:.3f} s, {its} finest iterations, relres {true_rel:.2e}")
-
-    if not args.no_extras:
+        out["extra_3d_k20_l5"] = csg_extra(args, torch)
         out["batched"] = batched_extra(torch)
-    if args.refine_level:
-        out["fp32_refinement"] = refine_extra(torch, args.refine_level)
-
-    if not args.no_cpu_baseline:
-        log("[bench] CPU baseline: FP64 oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(prob, args.variant, args.cpu_cycles)
-        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} vertex-updates/s")
-
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     if args.copy_probe:
         copy_probe(torch, out)
-
     print(json.dumps(out))
 
 

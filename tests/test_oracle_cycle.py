@@ -273,3 +273,33 @@ def test_fas_coarse_residual_rounding_floor():
     r1 = np.linalg.norm(ref[1]["b"])
     assert np.linalg.norm(pipe.b[1]) > 300 * r1
     assert np.linalg.norm(O.zero_boundary(pipe.b[1] - p.H(pipe.u[1], 1)) - ref[1]["b"]) > 1e-13 * r1
+
+
+def test_chain_factor_bounds_entrywise_perturbation(rng):
+    """The coarse-field bound of the GPU tests: an entrywise relative
+    perturbation eps of the finest residual moves R^(L-l) r_L by at most
+    eps c_l relative to its own norm (R has nonnegative weights), and c_l
+    grows as the iteration converges."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from coarse_bound import chain_factors
+    from paper_1508_03954_amd.inputs import config_2d_bpx
+    prob = config_2d_bpx(level_max=4)
+    p = Params(dim=2, level_max=4, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
+    pipe = O.Pipelined(p, O.lumped_rhs(prob.chi, 4, prob.theta))
+    first = None
+    for k in range(25):
+        pipe.cycle()
+        if k == 0:
+            first = chain_factors(pipe)
+    cf = chain_factors(pipe)
+    assert cf[1] > 10 * first[1] and all(cf[l] >= 1 for l in cf)
+    eps = 1e-6
+    rL = O.zero_boundary(pipe.residual)
+    pert = rL * (1 + eps * rng.uniform(-1, 1, rL.shape))
+    a, b = rL, pert
+    for lev in range(3, 0, -1):
+        a, b = O.restrict(a), O.restrict(b)
+        dev = np.linalg.norm(b - a) / np.linalg.norm(a)
+        assert dev <= eps * cf[lev] * (1 + 1e-9), (lev, dev, cf[lev])
