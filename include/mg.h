@@ -211,6 +211,19 @@ int mg_solve(mg_ctx* ctx, const mg_c128* b, mg_c128* u, double rtol, int maxit,
 /* res_h = |b - H u|_h (FP64). */
 int mg_residual_norm(mg_ctx* ctx, const mg_c128* u, const mg_c128* b, double* res_h);
 
+/* For callers that cannot allocate device memory in the call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same norms as mg_residual_norm, res_h = |b - H u|_h and res_max = max |r_j|
+ * over interior vertices (FP64; either output may be NULL, not both), without
+ * any allocation.  The residual is not stored; the per-block partials and
+ * the two results live in a fixed library array of 2 * 1024 + 2 doubles per
+ * device (resolved at mg_setup, held until the process ends), so every level
+ * with at most 1024 * 64 vertices per axis is accepted (MG_EINVAL beyond).
+ * All calls on one device share that array: calls that overlap on a device
+ * (other host threads or streams) race.  Synchronises the context stream. */
+int mg_residual_norm_noalloc(mg_ctx* ctx, const mg_c128* u, const mg_c128* b, double* res_h,
+                             double* res_max);
+
 /* uf = P uc: d-linear prolongation (factor 3) from level - 1 to level, the
  * paper's P of Section 4.  uc: device buffer of (3^(level-1)+1)^dim entries,
  * uf: (3^level+1)^dim entries (C order, x fastest), not aliased; uf is zero

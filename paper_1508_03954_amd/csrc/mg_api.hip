@@ -1,5 +1,39 @@
 // Context, cycle and solve drivers, and the extern "C" entry points of mg.h.
+#include <mutex>
+
 #include "mg_engine.h"
+
+// Scratch of mg_residual_norm_noalloc: the per-block partials of one residual
+// pass (a (sum, max) pair for each of at most kRedBlocks blocks) followed by
+// the two results of the second reduction stage.  Each device holds its own
+// copy until the process ends; every call on a device shares it, so calls
+// that overlap on one device race.  Host code never passes `scratch` itself
+// (in host code the name is a stand-in, not a device address): mg_setup
+// resolves each device's address once with hipGetSymbolAddress and the entry
+// point passes that.
+constexpr int kNoAllocDoubles = 2 * kRedBlocks + 2;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_ptr;   // per device, nullptr until resolved
+
+// Resolves the scratch address of the current device (once per device) and
+// returns that device's index.
+static int resolve_scratch(int* device) {
+  MG_HIP(hipGetDevice(device));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= *device) g_scratch_ptr.resize(*device + 1, nullptr);
+  if (!g_scratch_ptr[*device]) {
+    void* p = nullptr;
+    MG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[*device] = (double*)p;
+  }
+  return MG_OK;
+}
+
+static double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
 
 static int check_params(const mg_params* p) {
   if (!p) return fail(MG_EINVAL, "params is NULL");
@@ -54,10 +88,13 @@ int mg_setup(const mg_params* p, void* hip_stream, mg_ctx** out) {
   if (!out) return fail(MG_EINVAL, "out is NULL");
   *out = nullptr;
   MG_TRY(check_params(p));
+  int device = 0;
+  MG_TRY(resolve_scratch(&device));
   mg_ctx* c = new mg_ctx();
   c->p = *p;
   c->p.phi_field = nullptr;
   c->s = (hipStream_t)hip_stream;
+  c->device = device;
   const cpx<double>* phi = (const cpx<double>*)p->phi_field;
   int rc;
   if (p->precision == MG_FP64) {
@@ -221,6 +258,28 @@ int mg_precondition_apply(mg_ctx* c, const mg_c128* v, mg_c128* z, mg_c128* y) {
 int mg_residual_norm(mg_ctx* c, const mg_c128* u, const mg_c128* b, double* res_h) {
   if (!c || !u || !b || !res_h) return fail(MG_EINVAL, "NULL argument");
   return c->e64->resid_norm((const cpx<double>*)u, (const cpx<double>*)b, res_h, nullptr);
+}
+
+int mg_residual_norm_noalloc(mg_ctx* c, const mg_c128* u, const mg_c128* b, double* res_h, double* res_max) {
+  if (!c || !u || !b || (!res_h && !res_max)) return fail(MG_EINVAL, "NULL argument");
+  const int n = (int)ipow(3, c->p.level_max) + 1;
+  const int blocks = resid_norm_blocks(c->p.dim, n);
+  if (blocks < 1 || 2 * blocks + 2 > kNoAllocDoubles)
+    return fail(MG_EINVAL, "level too wide for the fixed scratch of mg_residual_norm_noalloc (" +
+                               std::to_string(kNoAllocDoubles) + " doubles)");
+  double* sp = scratch_of(c->device);
+  if (!sp) return fail(MG_EDEVICE, "scratch address of the context's device was not resolved");
+  int np = 0;
+  MG_HIP(launch_resid<double>(c->p.dim, c->op64, (const cpx<double>*)b, (const cpx<double>*)u, nullptr, sp, &np,
+                              c->s));
+  if (np != blocks) return fail(MG_EDEVICE, "residual pass used an unexpected block count");
+  MG_HIP(launch_finish_sum_max(sp, np, sp + 2 * kRedBlocks, c->s));
+  double h[2];
+  MG_HIP(hipMemcpyAsync(h, sp + 2 * kRedBlocks, sizeof(h), hipMemcpyDeviceToHost, c->s));
+  MG_HIP(hipStreamSynchronize(c->s));
+  if (res_h) *res_h = std::sqrt(std::pow(3.0, -c->p.dim * c->p.level_max) * h[0]);
+  if (res_max) *res_max = h[1];
+  return MG_OK;
 }
 
 // FP64 residual refinement with complex64 inner corrections:

@@ -937,6 +937,7 @@ using namespace mg;
 struct mg_ctx {
   mg_params p;
   hipStream_t s = nullptr;
+  int device = 0;                 // the device current at setup (the stream's)
   Engine<double>* e64 = nullptr;  // FP64 engine (precision FP64) or FP64 finest operator holder
   Engine<float>* e32 = nullptr;   // complex64 corrections (precision FP32_REFINE)
   cpx<double>* phi64 = nullptr;   // copy of the nodal phi field (FP64 operator with FP32 engine)

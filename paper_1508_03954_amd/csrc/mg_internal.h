@@ -71,10 +71,12 @@ template <class T>
 hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>* uhat, hipStream_t s);
 
 // r = b - H x; when partials != nullptr also writes per-block (sum |r|^2, max |r|)
-// and stores the number of blocks (<= kRedBlocks) in *nparts.
+// and stores the number of blocks (<= kRedBlocks) in *nparts.  r == nullptr:
+// partials only, the residual is not stored (resid_norm_blocks(dim, n) blocks).
 template <class T>
 hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
                         double* partials, int* nparts, hipStream_t s);
+int resid_norm_blocks(int dim, int n);   // -1 if a level is too wide for kRedBlocks partials
 
 // Coarse post-phase of level l in the Galerkin form (op of level l): restriction
 // rho_c = R rho into the coarser b slot plus the pointwise update of level l.

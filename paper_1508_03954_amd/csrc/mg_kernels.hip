@@ -166,7 +166,7 @@ __global__ void k_resid(OpData<T> op, const cpx<T>* __restrict__ b, const cpx<T>
       s2 += a2;
       mx = fmax(mx, a2);
     }
-    r[i] = v;
+    if (r) r[i] = v;
   }
   if (partials) block_sum_max(s2, sqrt(mx), partials);
 }
@@ -819,7 +819,7 @@ hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>
 template <class T>
 hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx<T>* x, cpx<T>* r,
                         double* partials, int* nparts, hipStream_t s) {
-  const int sb = dim == 3 && !op.cmass ? stencil3_blocks(op.n) : -1;
+  const int sb = dim == 3 && !op.cmass && r ? stencil3_blocks(op.n) : -1;
   if (sb > 0 && (!partials || sb <= kRedBlocks))
     return launch_stencil3<T>(0, op.n, op.coef, b, x, r, partials, nparts, s);
   dim3 g = row_grid(op.n, dim);
@@ -830,6 +830,13 @@ hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx
   }
   MG_DISPATCH(dim, k_resid, g, op, b, x, r, partials);
   return hipGetLastError();
+}
+
+int resid_norm_blocks(int dim, int n) {
+  const dim3 g = row_grid(n, dim);
+  const int gx = (int)g.x;
+  if (gx > kRedBlocks) return -1;
+  return gx * std::max(1, std::min((int)g.y, kRedBlocks / gx));
 }
 
 template <class T>

@@ -32,6 +32,7 @@ EXPORTED = [
     "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
     "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
     "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested", "mg_batch_set_spin_limit",
+    "mg_residual_norm_noalloc",
 ]
 
 
@@ -88,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_precondition_apply.argtypes = [P, P, P, P]
     lib.mg_solve.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.mg_residual_norm.argtypes = [P, P, P, ctypes.POINTER(D)]
+    lib.mg_residual_norm_noalloc.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.mg_grad_potential.argtypes = [P, P, P, P]
     lib.mg_prolong.argtypes = [P, I, P, P]
     lib.mg_solve_nested.argtypes = [P, P, P, I, D, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D)]
@@ -318,6 +320,19 @@ class Solver:
         out = ctypes.c_double(0.0)
         _check(self._lib.mg_residual_norm(self._ctx, _ptr(u), _ptr(b), ctypes.byref(out)))
         return out.value
+
+    def residual_norm_noalloc(self, u, b):
+        """(|b - H u|_h, max |r|) without any device allocation: u and b must
+        already be contiguous complex128 device tensors of the finest shape
+        (nothing is converted or copied here)."""
+        t = self._torch
+        for x in (u, b):
+            if (not isinstance(x, t.Tensor) or not x.is_cuda or x.dtype != t.complex128
+                    or not x.is_contiguous() or tuple(x.shape) != self.shape):
+                raise ValueError("residual_norm_noalloc needs contiguous complex128 device tensors of the finest shape")
+        rh, rm = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        _check(self._lib.mg_residual_norm_noalloc(self._ctx, _ptr(u), _ptr(b), ctypes.byref(rh), ctypes.byref(rm)))
+        return rh.value, rm.value
 
     def tiles(self):
         """(current tile, number of tile variants) of the fused sweep; (-1, 0) without one."""
