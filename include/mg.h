@@ -354,10 +354,31 @@ int mg_batch_set_spin_limit(mg_batch* batch, long long polls);
 int mg_batch_trace(mg_batch* batch, int enable);
 int mg_batch_get_trace(mg_batch* batch, long long* out, int cap, int* count);
 
-/* Solves every problem i: H_i u_i = b_i (device complex128 buffers bs[i],
- * us[i] of each problem's finest size; us[i] holds the initial guess) with
- * mg_solve semantics per problem.  iters / relres: arrays of count entries or
- * NULL.  Returns MG_OK, or the first MG_ENOTCONV / MG_EDIVERGED. */
+/* z_i = B_i v_i and y_i = H_i z_i for every problem of the batch in one
+ * persistent launch, B_i the problem's additive cycle from a zero start (the
+ * preconditioner of the Krylov driver: restrictions down to level_min, then
+ * omega_l D_l^-1 on every level with the variant's level operator and P going
+ * up; Section 5's cycle applied to u = 0).  vs, zs, ys: arrays of count
+ * device pointers to complex128 vectors of each problem's finest size (v
+ * boundary entries ignored; z, y zero on the boundary; none may alias).
+ * Complex64 batches compute in complex64 and convert.  Synchronises. */
+int mg_batch_precondition_apply(mg_batch* batch, const mg_c128* const* vs, mg_c128* const* zs,
+                                mg_c128* const* ys);
+
+/* Solves H_i u_i = b_i for every problem of the batch (bs[i], us[i]: device
+ * complex128 vectors of each problem's finest size; us[i] holds the initial
+ * guess and receives the solution) to |b - H u| <= rtol |b| per problem.
+ * MG_BICGSTAB: BiCGStab for all problems in lockstep, each iteration's two
+ * preconditioner applications with the operator and the dot products in one
+ * persistent launch each (mg_batch_precondition_apply) and every vector update
+ * of all problems in one launch, inside FP64 residual refinement: r = b - H u
+ * and |r| in FP64, the batched solve of H e = r / |r| in the batch's
+ * precision (complex64 to each problem's inner_rtol, 1e-4 if 0; an FP64
+ * batch to rtol directly), u += |r| e in FP64.  maxit bounds each problem's
+ * inner iterations.  MG_STATIONARY solves problem by problem with mg_solve.
+ * iters / relres: arrays of count entries or NULL (inner iterations; the
+ * final FP64 relative residual).  Returns MG_OK, MG_ENOTCONV or MG_EDIVERGED
+ * (the worst over the problems; outputs valid).  Synchronises. */
 int mg_batch_solve(mg_batch* batch, const mg_c128* const* bs, mg_c128* const* us, double rtol,
                    int maxit, int driver, int* iters, double* relres);
 

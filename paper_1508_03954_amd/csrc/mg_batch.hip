@@ -386,6 +386,347 @@ __global__ __launch_bounds__(kBThreads, kBatchWavesHint<T>) void k_batch_cycle(B
 }
 
 // ---------------------------------------------------------------------------
+// Batched Krylov solve.  BiCGStab advances every problem of the batch in
+// lockstep.  Per iteration each of the two preconditioner applications,
+// with the operator on its result and the dot products of the step, runs for
+// every problem in one persistent launch (k_batch_prec), and each vector
+// update of every problem in one plain launch (k_batch_vec).  The
+// preconditioner is one additive cycle from a zero start, the operator of
+// Engine::precondition: the restriction chain down to level l_min, then
+// z_l = Lop(omega_l D_l^-1 rho_l) + P g going up (BPX: g = z_(l-1) - I s_l),
+// and on the finest level z and y = H z.  Items and waits work as in the
+// cycle kernel: a problem's phase depends on all items of its previous phase.
+
+enum PrecKind { PK_R3 = 0, PK_SEAM = 1, PK_R = 2, PK_UP = 3, PK_G = 4, PK_PA3 = 5, PK_APPLY = 6, PK_DOT = 7 };
+constexpr int kPMaxPhases = 24;
+
+template <class T>
+struct PProb {
+  int dim, L, lmin, variant, nphase, zc3, fgx, fgy, ftiles, nslots;
+  int phase_items[kPMaxPhases];
+  int phase_kind[kPMaxPhases];
+  int phase_level[kPMaxPhases];
+  OpData<T> op[kBMaxLevels];
+  cpx<T> omega[kBMaxLevels];   // omega_l of a zero-start cycle (the scheme at n = 1)
+  cpx<T>* pr[kBMaxLevels];     // coarse rho, then g (BPX)
+  cpx<T>* pz[kBMaxLevels];     // coarse z
+  cpx<T>* spill;               // seam rows of the 3D finest restriction
+  cpx<T> wsL;                  // omega_L / D_L
+  double* part;                // 3 dot partials per slot (finest tile in 3D, apply item in 2D)
+};
+
+// Per problem and call: input v, outputs z = B v and y = H z, the partner v2
+// of the dots and where their sums go; inactive problems' items do nothing.
+template <class T>
+struct PIO {
+  const cpx<T>* v;
+  cpx<T>* z;
+  cpx<T>* y;
+  const cpx<T>* v2;
+  double* out;
+  int active;
+};
+
+template <class T>
+struct PrecArgs {
+  const BItem* items;
+  int nitems;
+  const PProb<T>* probs;
+  const PIO<T>* io;
+  int* done;          // [nprob][kPMaxPhases]
+  int* queue;
+  int* err;
+  int dot;            // 1: conj(v2) y (2 values); 2: conj(y) v2 and |y|^2 (3 values)
+  unsigned spin_limit;
+};
+
+// Fixed-order block sums of three values (waves in order after a wave
+// shuffle); thread 0 returns them.
+__device__ inline void block_sum3(double (&v)[3], double* out) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+  __shared__ double s3[3][kBWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) s3[k][wv] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) {
+      double a = 0;
+      for (int w = 0; w < kBWaves; ++w) a += s3[k][w];
+      out[k] = a;
+    }
+  __syncthreads();
+}
+
+// The dots of the finest level from y and v2 at one vertex (DOT 1: conj(v2) y;
+// DOT 2: conj(y) v2 and |y|^2).
+template <class T>
+__device__ inline void dot_terms(int dot, cpx<T> y, cpx<T> v2, double (&acc)[3]) {
+  const double yr = y.re, yi = y.im, vr = v2.re, vi = v2.im;
+  if (dot == 1) {
+    acc[0] += vr * yr + vi * yi;
+    acc[1] += vr * yi - vi * yr;
+  } else {
+    acc[0] += yr * vr + yi * vi;
+    acc[1] += yr * vi - yi * vr;
+    acc[2] += yr * yr + yi * yi;
+  }
+}
+
+template <class T, int DOT, int VAR>
+__device__ inline void prec_pa3(const FusedArgs<T>& f, int zc3, int bx, int by, int bz, double* part,
+                                F3Lds<T, 2, 2, false>& sm0) {
+  if (zc3 == 0) fused3_tile<T, 2, 2, 9, VAR, kPrecApply, 1, DOT>(f, bx, by, bz, part, sm0);
+  else fused3_tile<T, 2, 2, 27, VAR, kPrecApply, 1, DOT>(f, bx, by, bz, part, sm0);
+}
+
+template <class T, int D>
+__device__ __attribute__((always_inline)) inline void prec_item(const PrecArgs<T>& A, const PProb<T>& P,
+                                                                const PIO<T>& io, int phase, int tile,
+                                                                F3Lds<T, 2, 2, true>* f3lds) {
+  const int kind = P.phase_kind[phase], lev = P.phase_level[phase];
+  const int L = P.L, lmin = P.lmin;
+  const bool bpx = P.variant == MG_BPX, hb = P.variant == MG_HB;
+  auto& sm0 = reinterpret_cast<F3Lds<T, 2, 2, false>&>(*f3lds);
+  if (kind == PK_R) {
+    // rho_(lev-1) = R (v on the finest level, rho_lev below it)
+    const int nc = P.op[lev - 1].n, nf = P.op[lev].n;
+    const cpx<T>* src = lev == L ? io.v : P.pr[lev];
+    cpx<T>* dst = P.pr[lev - 1];
+    for_rows<T, D>(nc, tile, [&](const int m[3], long long ic) {
+      cpx<T> p[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) p[k] = restrict_part<T, D>(src, nf, m, k - 2);
+      dst[ic] = csel(is_interior<D>(m, nc), post_galerkin_combine(p), czero<T>());
+    });
+  } else if (kind == PK_UP) {
+    const cpx<T>* rho = lev == L ? io.v : P.pr[lev];
+    const cpx<T>* gc = lev > lmin ? (bpx ? P.pr[lev - 1] : P.pz[lev - 1]) : nullptr;
+    cpx<T>* z = lev == L ? io.z : P.pz[lev];
+    for_rows<T, D>(P.op[lev].n, tile, [&](const int j[3], long long i) {
+      prec_up_vertex<T, D>(P.op[lev], j, i, rho, P.omega[lev], hb ? 1 : 0, lev == lmin ? 1 : 0, gc, z);
+    });
+  } else if (kind == PK_G) {
+    const cpx<T>* rho = lev == L ? io.v : P.pr[lev];
+    for_rows<T, D>(P.op[lev - 1].n, tile, [&](const int m[3], long long ic) {
+      prec_g_vertex<T, D>(P.op[lev], m, ic, rho, P.omega[lev], P.pz[lev - 1], P.pr[lev - 1]);
+    });
+  } else if (kind == PK_APPLY) {
+    // y = H z on the finest level (2D) with the dot partials of this item
+    const int n = P.op[L].n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for_rows<T, D>(n, tile, [&](const int j[3], long long i) {
+      cpx<T> yv = czero<T>();
+      if (is_interior<D>(j, n)) yv = apply_row<T, D>(io.z, n, j, P.op[L]);
+      io.y[i] = yv;
+      dot_terms(A.dot, yv, io.v2[i], acc);
+    });
+    block_sum3(acc, P.part + 3 * tile);
+  } else if (kind == PK_DOT) {
+    // fixed-order second stage over the problem's slots
+    __shared__ double s0[3][kBThreads];
+    const int t = threadIdx.x;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = t; i < P.nslots; i += kBThreads)
+      for (int k = 0; k < 3; ++k) a[k] += P.part[3 * i + k];
+    for (int k = 0; k < 3; ++k) s0[k][t] = a[k];
+    __syncthreads();
+    if (t == 0) {
+      for (int k = 0; k < 3; ++k) {
+        double q = 0.0;
+        for (int w = 0; w < kBThreads; ++w) q += s0[k][w];
+        io.out[k] = q;
+      }
+    }
+    __syncthreads();
+  } else if (kind == PK_SEAM) {
+    // rho_(L-1) += the seam rows of the 3D finest restriction (tiles of 2 coarse rows)
+    const int nc = P.op[L - 1].n, nseam = P.fgy - 1;
+    cpx<T>* dst = P.pr[L - 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < kBRows / kBWaves; ++k) {
+      const int row = tile * kBRows + wv + kBWaves * k;
+      if (row >= nc * nseam) break;
+      const int mz = row / nseam, sidx = row - mz * nseam, my = 2 * (sidx + 1);
+      if (mz < 1 || mz > nc - 2 || my > nc - 2) continue;
+      for (int mx = lane; mx < nc; mx += 64) {
+        if (mx < 1 || mx > nc - 2) continue;
+        cpx<T>& d = dst[((long long)mz * nc + my) * nc + mx];
+        const cpx<T> e = P.spill[((long long)mz * nc + my) * nc + mx];
+        d = mk(d.re + e.re, d.im + e.im);
+      }
+    }
+  } else if (D == 3) {
+    const int bx = tile % P.fgx, by = (tile / P.fgx) % P.fgy, bz = tile / (P.fgx * P.fgy);
+    FusedArgs<T> f = {};
+    f.n = P.op[L].n;
+    f.nc = P.op[L - 1].n;
+    if (kind == PK_R3) {
+      f.b = io.v;
+      f.rhoc = P.pr[L - 1];
+      f.spill = P.spill;
+      f.variant = 1;
+      if (P.zc3 == 0) fused3_tile<T, 2, 2, 9, 1, kRestrict>(f, bx, by, bz, nullptr, sm0);
+      else fused3_tile<T, 2, 2, 27, 1, kRestrict>(f, bx, by, bz, nullptr, sm0);
+    } else {   // PK_PA3: z = s + P g, y = H z and the dot partials of the tile
+      f.w = io.v;
+      f.scc = bpx ? P.pr[L - 1] : P.pz[L - 1];
+      f.zout = io.z;
+      f.wout = io.y;
+      f.b = io.v2;
+      for (int q = 0; q < 4; ++q) f.coef[q] = P.op[L].coef[q];
+      f.ws = P.wsL;
+      f.variant = hb ? 1 : 0;
+      double* part = P.part + 3 * tile;
+      if (A.dot == 1) {
+        if (hb) prec_pa3<T, 1, 1>(f, P.zc3, bx, by, bz, part, sm0);
+        else prec_pa3<T, 1, 0>(f, P.zc3, bx, by, bz, part, sm0);
+      } else {
+        if (hb) prec_pa3<T, 2, 1>(f, P.zc3, bx, by, bz, part, sm0);
+        else prec_pa3<T, 2, 0>(f, P.zc3, bx, by, bz, part, sm0);
+      }
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBThreads, 2) void k_batch_prec(PrecArgs<T> A) {
+  __shared__ int s_item, s_ok, s_acq;
+  int acq_prob = -1, acq_phase = -1;
+  __shared__ F3Lds<T, 2, 2, true> f3lds;
+  // the claim / wait / publish protocol of k_batch_cycle (see there)
+  if (threadIdx.x == 0) s_item = atomicAdd(A.queue, 1);
+  __syncthreads();
+  for (;;) {
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= A.nitems) break;
+    BItem w = A.items[it];
+    w.prob = __builtin_amdgcn_readfirstlane(w.prob);
+    w.phase = __builtin_amdgcn_readfirstlane(w.phase);
+    w.tile = __builtin_amdgcn_readfirstlane(w.tile);
+    const PProb<T>& P = A.probs[w.prob];
+    const PIO<T>& io = A.io[w.prob];
+    if (threadIdx.x == 0) {
+      int ok = 1, acq = 0;
+      if (w.phase > 0 && (w.prob != acq_prob || w.phase != acq_phase)) {
+        acq = 1;
+        const int need = P.phase_items[w.phase - 1];
+        int* cnt = A.done + w.prob * kPMaxPhases + w.phase - 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (++spins > A.spin_limit) {
+            ok = 0;
+            atomicOr(A.err, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (ok) {
+          acq_prob = w.prob;
+          acq_phase = w.phase;
+        }
+      }
+      s_ok = ok && io.active;
+      s_acq = acq;
+    }
+    __syncthreads();
+    if (s_acq) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (s_ok) {
+      if (P.dim == 3) prec_item<T, 3>(A, P, io, w.phase, w.tile, &f3lds);
+      else prec_item<T, 2>(A, P, io, w.phase, w.tile, &f3lds);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_fetch_add(A.done + w.prob * kPMaxPhases + w.phase, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = atomicAdd(A.queue, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// Vector updates of BiCGStab for every active problem in one launch: block b
+// works on chunk b - first[p] of problem p (VB elements per block) and
+// writes three partial sums to part[3 b]; k_batch_vec_finish adds each
+// problem's partials in block order.
+constexpr int kVecChunk = 8 * kBThreads;
+enum VecOp { VO_INIT = 0, VO_P = 1, VO_S = 2, VO_XR = 3 };
+
+template <class T>
+struct VSet {
+  cpx<T>*r, *rh, *p, *v, *s, *t, *y, *z, *x;
+  const cpx<T>* b;
+  long long N;
+  cpx<double> alpha, beta, omega;
+  int active;
+};
+
+template <class T>
+__global__ __launch_bounds__(kBThreads) void k_batch_vec(const VSet<T>* __restrict__ vs,
+                                                         const int* __restrict__ blk_prob,
+                                                         const int* __restrict__ blk_first, int op, double* part) {
+  const int b = blockIdx.x;
+  const int pi = blk_prob[b];
+  const VSet<T>& V = vs[pi];
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (V.active) {
+    const long long base = (long long)(b - blk_first[pi]) * kVecChunk;
+    const long long end = min(base + (long long)kVecChunk, V.N);
+    for (long long i = base + threadIdx.x; i < end; i += kBThreads) {
+      if (op == VO_INIT) {
+        // x = 0; r = rh = b; p = v = 0; |r|^2
+        const cpx<T> bv = V.b[i];
+        V.x[i] = czero<T>();
+        V.r[i] = bv;
+        V.rh[i] = bv;
+        V.p[i] = czero<T>();
+        V.v[i] = czero<T>();
+        acc[0] += (double)bv.re * bv.re + (double)bv.im * bv.im;
+      } else if (op == VO_P) {
+        // p = r + beta (p - omega v), in double precision
+        const cpx<T> rv = V.r[i], pv = V.p[i], vv = V.v[i];
+        const double qr = pv.re - (V.omega.re * vv.re - V.omega.im * vv.im);
+        const double qi = pv.im - (V.omega.re * vv.im + V.omega.im * vv.re);
+        V.p[i] = mk(T(rv.re + V.beta.re * qr - V.beta.im * qi), T(rv.im + V.beta.re * qi + V.beta.im * qr));
+      } else if (op == VO_S) {
+        // s = r - alpha v and |s|^2
+        const cpx<T> rv = V.r[i], vv = V.v[i];
+        const cpx<T> sv = mk(T(rv.re - (V.alpha.re * vv.re - V.alpha.im * vv.im)),
+                             T(rv.im - (V.alpha.re * vv.im + V.alpha.im * vv.re)));
+        V.s[i] = sv;
+        acc[0] += (double)sv.re * sv.re + (double)sv.im * sv.im;
+      } else {
+        // x += alpha y + omega z; r = s - omega t; |r|^2 and conj(rh) r
+        const cpx<T> yv = V.y[i], zv = V.z[i], xv = V.x[i], sv = V.s[i], tv = V.t[i], hv = V.rh[i];
+        const double xr = xv.re + V.alpha.re * yv.re - V.alpha.im * yv.im + V.omega.re * zv.re - V.omega.im * zv.im;
+        const double xi = xv.im + V.alpha.re * yv.im + V.alpha.im * yv.re + V.omega.re * zv.im + V.omega.im * zv.re;
+        V.x[i] = mk(T(xr), T(xi));
+        const cpx<T> rv = mk(T(sv.re - (V.omega.re * tv.re - V.omega.im * tv.im)),
+                             T(sv.im - (V.omega.re * tv.im + V.omega.im * tv.re)));
+        V.r[i] = rv;
+        acc[0] += (double)rv.re * rv.re + (double)rv.im * rv.im;
+        acc[1] += (double)hv.re * rv.re + (double)hv.im * rv.im;
+        acc[2] += (double)hv.re * rv.im - (double)hv.im * rv.re;
+      }
+    }
+  }
+  block_sum3(acc, part + 3 * b);
+}
+
+template <class T>
+__global__ __launch_bounds__(64) void k_batch_vec_finish(const VSet<T>* __restrict__ vs, const int* __restrict__ blk_first,
+                                                         const double* __restrict__ part, double* out) {
+  const int pi = blockIdx.x;
+  if (threadIdx.x != 0 || !vs[pi].active) return;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int b = blk_first[pi]; b < blk_first[pi + 1]; ++b)
+    for (int k = 0; k < 3; ++k) a[k] += part[3 * b + k];
+  for (int k = 0; k < 3; ++k) out[3 * pi + k] = a[k];
+}
+
+// ---------------------------------------------------------------------------
 // Host driver.
 
 template <class T>
@@ -407,6 +748,9 @@ struct BatchBase {
   virtual int autotune(int reps, int* best, double* best_us, double* times) = 0;
   virtual int set_trace(bool on) = 0;
   virtual int get_trace(long long* out, int cap, int* count) = 0;
+  virtual int solve(const cpx<double>* const* bs, cpx<double>* const* us, double rtol, int maxit, int* iters,
+                    double* relres) = 0;
+  virtual int precondition_apply(const cpx<double>* const* vs, cpx<double>* const* zs, cpx<double>* const* ys) = 0;
   std::vector<mg_ctx*> ctx;
   hipStream_t s = nullptr;
 };
@@ -697,6 +1041,423 @@ struct Batch : BatchBase {
     return build_items();
   }
 
+  // ---- batched Krylov solve --------------------------------------------
+  std::vector<PProb<T>> hpp;
+  PProb<T>* dpp = nullptr;
+  std::vector<PIO<T>> hio;
+  PIO<T>* dio = nullptr;
+  int* dpdone = nullptr;               // [np][kPMaxPhases], queue, error word
+  BItem* dpitems = nullptr;
+  int npitems = 0, pgrid = 0;
+  std::vector<VSet<T>> hvs;
+  VSet<T>* dvs = nullptr;
+  int* dblk_prob = nullptr;
+  int* dblk_first = nullptr;
+  int nvblocks = 0;
+  double* dvpart = nullptr;            // 3 per vector block
+  double* dvout = nullptr;             // 3 per problem
+  double* dpout = nullptr;             // 3 per problem
+  std::vector<cpx<T>*> xbuf, bbuf;     // inner solution and right-hand side per problem
+  bool kready = false;
+
+  int rows_items(int dim, int n) const {
+    const int rows = dim == 3 ? n * n : n;
+    return (rows + kBRows - 1) / kBRows;
+  }
+
+  // Phases of one preconditioner application with the operator (see PK_*).
+  int describe_prec(int i, PProb<T>& P) {
+    Engine<T>& E = *engine_of<T>(ctx[i]);
+    std::memset(&P, 0, sizeof(P));
+    P.dim = E.dim;
+    P.L = E.L;
+    P.lmin = E.lmin;
+    P.variant = E.variant;
+    P.zc3 = zc3;
+    const int L = E.L, lmin = E.lmin, d = E.dim;
+    const bool bpx = E.variant == MG_BPX;
+    for (int l = lmin; l <= L; ++l) {
+      P.op[l] = E.lv[l].op;
+      P.omega[l] = to_c<T>(omega_level(E.scheme, E.omega, E.omega_L, L - l, 1));
+      if (l < L) {
+        P.pr[l] = E.lv[l].pr;
+        P.pz[l] = E.lv[l].pz;
+      }
+    }
+    P.spill = E.spill;
+    const complex<double> wL = omega_level(E.scheme, E.omega, E.omega_L, 0, 1);
+    P.wsL = to_c<T>(wL * complex<double>(E.lv[L].op.invD.re, E.lv[L].op.invD.im));
+    const int nc = E.lv[L - 1].n;
+    int k = 0;
+    auto add = [&](int kind, int lev, int items) {
+      P.phase_kind[k] = kind;
+      P.phase_level[k] = lev;
+      P.phase_items[k++] = items;
+    };
+    if (d == 3) {
+      if (!E.spill) return fail(MG_EINVAL, "batched solve: a 3D problem without the fused sweep's seam array");
+      P.fgx = f3_xtiles(nc);
+      P.fgy = f3_ytiles(nc, 2);
+      P.ftiles = P.fgx * P.fgy * ((nc + kBZc3[zc3] - 1) / kBZc3[zc3]);
+      add(PK_R3, L, P.ftiles);
+      if (P.fgy > 1) add(PK_SEAM, L - 1, (nc * (P.fgy - 1) + kBRows - 1) / kBRows);
+    } else {
+      add(PK_R, L, rows_items(d, nc));
+    }
+    for (int l = L - 1; l > lmin; --l) add(PK_R, l, rows_items(d, E.lv[l - 1].n));
+    add(PK_UP, lmin, rows_items(d, E.lv[lmin].n));
+    for (int l = lmin + 1; l < L; ++l) {
+      if (bpx) add(PK_G, l, rows_items(d, E.lv[l - 1].n));
+      add(PK_UP, l, rows_items(d, E.lv[l].n));
+    }
+    if (bpx) add(PK_G, L, rows_items(d, nc));
+    if (d == 3) {
+      add(PK_PA3, L, P.ftiles);
+      P.nslots = P.ftiles;
+    } else {
+      add(PK_UP, L, rows_items(d, E.lv[L].n));
+      add(PK_APPLY, L, rows_items(d, E.lv[L].n));
+      P.nslots = rows_items(d, E.lv[L].n);
+    }
+    add(PK_DOT, L, 1);
+    P.nphase = k;
+    if (k > kPMaxPhases) return fail(MG_EINVAL, "too many phases for a batched preconditioner");
+    MG_TRY(dalloc(&P.part, 3 * (size_t)P.nslots));
+    MG_HIP(launch_fill(P.part, 3 * (size_t)P.nslots * sizeof(double), s));
+    return MG_OK;
+  }
+
+  int krylov_setup() {
+    if (kready) return MG_OK;
+    hpp.resize(np);
+    hio.resize(np);
+    hvs.resize(np);
+    xbuf.resize(np);
+    bbuf.resize(np);
+    std::vector<std::array<long long, 4>> keys;
+    std::vector<int> blk_prob, blk_first(np + 1, 0);
+    for (int i = 0; i < np; ++i) {
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      MG_TRY(E.ensure_krylov());
+      MG_TRY(describe_prec(i, hpp[i]));
+      MG_TRY(dalloc(&xbuf[i], E.NL()));
+      MG_TRY(dalloc(&bbuf[i], E.NL()));
+      const PProb<T>& P = hpp[i];
+      const long long size = (long long)E.NL();
+      for (int ph = 0; ph < P.nphase; ++ph)
+        for (int t = 0; t < P.phase_items[ph]; ++t) keys.push_back({((long long)ph << 40) - size, i, ph, t});
+      VSet<T>& V = hvs[i];
+      std::memset(&V, 0, sizeof(V));
+      V.r = E.kv[0];
+      V.rh = E.kv[1];
+      V.p = E.kv[2];
+      V.v = E.kv[3];
+      V.s = E.kv[4];
+      V.t = E.kv[5];
+      V.y = E.kv[6];
+      V.z = E.kv[7];
+      V.x = xbuf[i];
+      V.b = bbuf[i];
+      V.N = (long long)E.NL();
+      const int nb = (int)((V.N + kVecChunk - 1) / kVecChunk);
+      blk_first[i] = (int)blk_prob.size();
+      for (int q = 0; q < nb; ++q) blk_prob.push_back(i);
+    }
+    blk_first[np] = (int)blk_prob.size();
+    nvblocks = (int)blk_prob.size();
+    std::stable_sort(keys.begin(), keys.end(),
+                     [](const std::array<long long, 4>& a, const std::array<long long, 4>& b) { return a[0] < b[0]; });
+    std::vector<BItem> items(keys.size());
+    for (size_t k = 0; k < keys.size(); ++k) items[k] = BItem{(int)keys[k][1], (int)keys[k][2], (int)keys[k][3]};
+    npitems = (int)items.size();
+    MG_TRY(dalloc(&dpitems, items.size()));
+    MG_HIP(hipMemcpy(dpitems, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice));
+    MG_TRY(dalloc(&dpp, np));
+    MG_HIP(hipMemcpy(dpp, hpp.data(), np * sizeof(PProb<T>), hipMemcpyHostToDevice));
+    MG_TRY(dalloc(&dio, np));
+    MG_TRY(dalloc(&dpdone, (size_t)np * kPMaxPhases + 2));
+    MG_TRY(dalloc(&dvs, np));
+    MG_TRY(dalloc(&dblk_prob, nvblocks));
+    MG_TRY(dalloc(&dblk_first, np + 1));
+    MG_HIP(hipMemcpy(dblk_prob, blk_prob.data(), nvblocks * sizeof(int), hipMemcpyHostToDevice));
+    MG_HIP(hipMemcpy(dblk_first, blk_first.data(), (np + 1) * sizeof(int), hipMemcpyHostToDevice));
+    MG_TRY(dalloc(&dvpart, 3 * (size_t)nvblocks));
+    MG_TRY(dalloc(&dvout, 3 * (size_t)np));
+    MG_TRY(dalloc(&dpout, 3 * (size_t)np));
+    int dev = 0, ncu = 0, per = 0;
+    MG_HIP(hipGetDevice(&dev));
+    MG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    MG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_prec<T>, kBThreads, 0));
+    if (per < 1) return fail(MG_EDEVICE, "the batched preconditioner kernel cannot be resident");
+    pgrid = per * ncu;
+    kready = true;
+    return MG_OK;
+  }
+
+  // One preconditioner application with the operator for every active
+  // problem: io[i] set by the caller (dot 1 or 2), sums in dpout.
+  int prec_apply(int dot) {
+    MG_HIP(hipMemcpyAsync(dio, hio.data(), np * sizeof(PIO<T>), hipMemcpyHostToDevice, s));
+    MG_HIP(launch_fill(dpdone, ((size_t)np * kPMaxPhases + 2) * sizeof(int), s));
+    PrecArgs<T> A;
+    A.items = dpitems;
+    A.nitems = npitems;
+    A.probs = dpp;
+    A.io = dio;
+    A.done = dpdone;
+    A.queue = dpdone + (size_t)np * kPMaxPhases;
+    A.err = A.queue + 1;
+    A.dot = dot;
+    A.spin_limit = spin_limit;
+    hipLaunchKernelGGL(k_batch_prec<T>, dim3(pgrid), dim3(kBThreads), 0, s, A);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+  }
+
+  int vec(int op) {
+    MG_HIP(hipMemcpyAsync(dvs, hvs.data(), np * sizeof(VSet<T>), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_batch_vec<T>, dim3(nvblocks), dim3(kBThreads), 0, s, dvs, dblk_prob, dblk_first, op, dvpart);
+    MG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_batch_vec_finish<T>, dim3(np), dim3(64), 0, s, dvs, dblk_first, dvpart, dvout);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+  }
+
+  int fetch(double* hv, double* hp) {
+    if (hv) MG_HIP(hipMemcpyAsync(hv, dvout, 3 * (size_t)np * sizeof(double), hipMemcpyDeviceToHost, s));
+    int err = 0;
+    if (hp) {
+      MG_HIP(hipMemcpyAsync(hp, dpout, 3 * (size_t)np * sizeof(double), hipMemcpyDeviceToHost, s));
+      MG_HIP(hipMemcpyAsync(&err, dpdone + (size_t)np * kPMaxPhases + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    MG_HIP(hipStreamSynchronize(s));
+    if (err) return fail(MG_EDEVICE, "batched preconditioner: a dependency wait exceeded its bound");
+    return MG_OK;
+  }
+
+  // BiCGStab in the engines' precision for the problems with act[i], right-hand
+  // side bbuf[i], solution xbuf[i] (from zero), each to |r| <= tol[i] |b|, all
+  // in lockstep (the same steps as Engine::bicgstab).  its[i]: iterations,
+  // st[i]: MG_OK / MG_ENOTCONV / MG_EDIVERGED.
+  int krylov_inner(std::vector<int> act, const std::vector<double>& tol, int maxit, std::vector<int>& its,
+                   std::vector<int>& st) {
+    std::vector<double> hv(3 * (size_t)np), hpo(3 * (size_t)np), bn(np, 0.0), r0(np, 1.0);
+    std::vector<complex<double>> rho(np, 1.0), rho_new(np, 1.0), alpha(np, 1.0), om(np, 1.0);
+    std::vector<int> at_s(np, 0);
+    its.assign(np, 0);
+    st.assign(np, MG_OK);
+    for (int i = 0; i < np; ++i) hvs[i].active = act[i];
+    MG_TRY(vec(VO_INIT));
+    MG_TRY(fetch(hv.data(), nullptr));
+    int nact = 0;
+    for (int i = 0; i < np; ++i) {
+      if (!act[i]) continue;
+      bn[i] = std::sqrt(hv[3 * i]);
+      rho_new[i] = hv[3 * i];   // (rh, r) with rh = r
+      if (bn[i] == 0.0 || 1.0 <= tol[i]) {
+        act[i] = 0;
+        continue;
+      }
+      ++nact;
+    }
+    for (int it = 1; it <= maxit && nact > 0; ++it) {
+      for (int i = 0; i < np; ++i) {
+        hvs[i].active = act[i];
+        hio[i].active = act[i];
+        if (!act[i]) continue;
+        const complex<double> beta = (rho_new[i] / rho[i]) * (alpha[i] / om[i]);
+        hvs[i].beta = to_c<double>(beta);
+        hvs[i].omega = to_c<double>(om[i]);
+      }
+      MG_TRY(vec(VO_P));
+      // y = B p, v = H y and (rh, v)
+      for (int i = 0; i < np; ++i) {
+        const VSet<T>& V = hvs[i];
+        hio[i] = PIO<T>{V.p, V.y, V.v, V.rh, dpout + 3 * i, act[i]};
+      }
+      MG_TRY(prec_apply(1));
+      MG_TRY(fetch(nullptr, hpo.data()));
+      for (int i = 0; i < np; ++i) {
+        if (!act[i]) continue;
+        alpha[i] = rho_new[i] / complex<double>(hpo[3 * i], hpo[3 * i + 1]);
+        hvs[i].alpha = to_c<double>(alpha[i]);
+      }
+      // s = r - alpha v, |s|^2; z = B s, t = H z, (t, s) and |t|^2
+      MG_TRY(vec(VO_S));
+      for (int i = 0; i < np; ++i) {
+        const VSet<T>& V = hvs[i];
+        hio[i] = PIO<T>{V.s, V.z, V.t, V.s, dpout + 3 * i, act[i]};
+      }
+      MG_TRY(prec_apply(2));
+      MG_TRY(fetch(hv.data(), hpo.data()));
+      for (int i = 0; i < np; ++i) {
+        if (!act[i]) continue;
+        const double sn = std::sqrt(hv[3 * i]);
+        if (sn / bn[i] <= tol[i]) {
+          at_s[i] = 1;
+          om[i] = 0.0;   // x += alpha y, r = s
+        } else {
+          om[i] = complex<double>(hpo[3 * i], hpo[3 * i + 1]) / hpo[3 * i + 2];
+        }
+        hvs[i].omega = to_c<double>(om[i]);
+      }
+      MG_TRY(vec(VO_XR));
+      MG_TRY(fetch(hv.data(), nullptr));
+      for (int i = 0; i < np; ++i) {
+        if (!act[i]) continue;
+        rho[i] = rho_new[i];
+        rho_new[i] = complex<double>(hv[3 * i + 1], hv[3 * i + 2]);
+        const double rel = std::sqrt(hv[3 * i]) / bn[i];
+        if (it == 1) r0[i] = rel;
+        if (at_s[i] || rel <= tol[i]) {
+          its[i] = it;
+          act[i] = 0;
+          --nact;
+        } else if (!std::isfinite(rel) || rel > 1e8 * std::max(r0[i], 1e-300)) {
+          its[i] = it;
+          st[i] = MG_EDIVERGED;
+          act[i] = 0;
+          --nact;
+        }
+      }
+    }
+    for (int i = 0; i < np; ++i)
+      if (act[i]) {
+        its[i] = maxit;
+        st[i] = MG_ENOTCONV;
+      }
+    return MG_OK;
+  }
+
+  // z_i = B_i v_i and y_i = H_i z_i for every problem in one persistent
+  // launch (inputs and outputs complex128; complex64 batches convert).
+  int precondition_apply(const cpx<double>* const* vs, cpx<double>* const* zs, cpx<double>* const* ys) override {
+    MG_TRY(krylov_setup());
+    for (int i = 0; i < np; ++i) {
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      const int n = E.lv[E.L].n;
+      MG_HIP((launch_convert<double, T>(E.NL(), vs[i], E.kv[4], 1.0, s)));
+      MG_HIP(launch_zero_boundary_copy<T>(E.dim, n, E.kv[4], bbuf[i], mk(T(1), T(0)), s));
+      hio[i] = PIO<T>{bbuf[i], xbuf[i], E.kv[6], bbuf[i], dpout + 3 * i, 1};
+    }
+    MG_TRY(prec_apply(1));
+    for (int i = 0; i < np; ++i) {
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      MG_HIP((launch_convert<T, double>(E.NL(), xbuf[i], zs[i], 1.0, s)));
+      MG_HIP((launch_convert<T, double>(E.NL(), E.kv[6], ys[i], 1.0, s)));
+    }
+    std::vector<double> sums(3 * (size_t)np);
+    return fetch(nullptr, sums.data());
+  }
+
+  // Residual refinement in FP64 around the batched inner solve: for every
+  // problem r = b - H u and rho = |r| in FP64, the inner solve of H e = r / rho
+  // in the engines' precision (complex64 corrections to their inner
+  // tolerance; an FP64 batch solves to the final tolerance directly), then
+  // u += rho e in FP64, until |r| <= rtol |b| or maxit inner iterations.
+  int solve(const cpx<double>* const* bs, cpx<double>* const* us, double rtol, int maxit, int* iters,
+            double* relres) override {
+    MG_TRY(krylov_setup());
+    std::vector<double> bn(np, 0.0), rn(np, 0.0), rel(np, 1.0), rel0(np, -1.0);
+    std::vector<int> act(np, 1), total(np, 0), status(np, MG_ENOTCONV);
+    std::vector<double> hr(4 * (size_t)np);
+    auto norms = [&](std::vector<double>& out, bool residual) -> int {
+      for (int i = 0; i < np; ++i) {
+        if (!act[i]) continue;
+        mg_ctx* c = ctx[i];
+        Engine<double>& E = *c->e64;
+        const cpx<double>* v = E.tRh;
+        if (residual) {
+          MG_HIP(launch_resid<double>(c->p.dim, c->op64, E.tRh, us[i], E.tR, nullptr, nullptr, s));
+          v = E.tR;
+        }
+        MG_HIP(launch_norm2<double>(E.NL(), v, E.partials, s));
+        MG_HIP(launch_finish_sum_max(E.partials, kRedBlocks, E.red, s));
+        MG_HIP(hipMemcpyAsync(&hr[4 * i], E.red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      }
+      MG_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < np; ++i)
+        if (act[i]) out[i] = std::sqrt(hr[4 * i]);
+      return MG_OK;
+    };
+    for (int i = 0; i < np; ++i) {
+      mg_ctx* c = ctx[i];
+      Engine<double>& E = *c->e64;
+      MG_TRY(E.ensure_scratch());
+      const int n = E.lv[E.L].n;
+      MG_HIP(launch_zero_boundary_copy<double>(E.dim, n, us[i], us[i], mk(1.0, 0.0), s));
+      MG_HIP(launch_zero_boundary_copy<double>(E.dim, n, bs[i], E.tRh, mk(1.0, 0.0), s));
+    }
+    MG_TRY(norms(bn, false));
+    for (int i = 0; i < np; ++i)
+      if (bn[i] == 0.0) {
+        MG_HIP(launch_fill(us[i], ctx[i]->e64->NL() * sizeof(cpx<double>), s));
+        act[i] = 0;
+        rel[i] = 0.0;
+        status[i] = MG_OK;
+      }
+    for (int outer = 0; outer < 100; ++outer) {
+      MG_TRY(norms(rn, true));
+      std::vector<int> inner(np, 0);
+      std::vector<double> tol(np, 1.0);
+      int any = 0;
+      for (int i = 0; i < np; ++i) {
+        if (!act[i]) continue;
+        rel[i] = rn[i] / bn[i];
+        if (rel0[i] < 0) rel0[i] = rel[i];
+        if (!std::isfinite(rel[i]) || rel[i] > 1e8 * std::max(rel0[i], 1e-300)) {
+          status[i] = MG_EDIVERGED;
+          act[i] = 0;
+        } else if (rel[i] <= rtol) {
+          status[i] = MG_OK;
+          act[i] = 0;
+        } else if (total[i] >= maxit) {
+          status[i] = MG_ENOTCONV;
+          act[i] = 0;
+        } else {
+          inner[i] = 1;
+          any = 1;
+          const double it_tol = ctx[i]->p.inner_rtol > 0 ? ctx[i]->p.inner_rtol : 1e-4;
+          tol[i] = std::is_same<T, float>::value ? it_tol : std::max(0.5 * rtol / rel[i], 1e-15);
+          const mg_ctx* c = ctx[i];
+          MG_HIP((launch_convert<double, T>(c->e64->NL(), c->e64->tR, bbuf[i], 1.0 / rn[i], s)));
+        }
+      }
+      if (!any) break;
+      int budget = 1;
+      for (int i = 0; i < np; ++i)
+        if (inner[i]) budget = std::max(budget, maxit - total[i]);
+      std::vector<int> its, st;
+      MG_TRY(krylov_inner(inner, tol, budget, its, st));
+      for (int i = 0; i < np; ++i) {
+        if (!inner[i]) continue;
+        total[i] += std::max(its[i], 1);
+        if (st[i] == MG_EDIVERGED) {
+          status[i] = MG_EDIVERGED;
+          act[i] = 0;
+          continue;
+        }
+        mg_ctx* c = ctx[i];
+        const size_t N = c->e64->NL();
+        if (std::is_same<T, float>::value)
+          MG_HIP(launch_accum32(N, reinterpret_cast<const cpx<float>*>(xbuf[i]), rn[i], us[i], s));
+        else
+          MG_HIP(launch_axpby<double>(N, mk(rn[i], 0.0), reinterpret_cast<const cpx<double>*>(xbuf[i]),
+                                      mk(1.0, 0.0), us[i], s));
+      }
+    }
+    int worst = MG_OK;
+    for (int i = 0; i < np; ++i) {
+      if (act[i]) status[i] = MG_ENOTCONV;
+      if (iters) iters[i] = total[i];
+      if (relres) relres[i] = rel[i];
+      if (status[i] == MG_EDIVERGED) worst = MG_EDIVERGED;
+      else if (status[i] == MG_ENOTCONV && worst == MG_OK) worst = MG_ENOTCONV;
+    }
+    MG_HIP(hipStreamSynchronize(s));
+    return worst;
+  }
+
   int autotune(int reps, int* best, double* best_us, double* times) override {
     hipEvent_t e0, e1;
     MG_HIP(hipEventCreate(&e0));
@@ -806,9 +1567,29 @@ int mg_batch_get_trace(mg_batch* b, long long* out, int cap, int* count) {
   return b->impl->get_trace(out, cap, count);
 }
 
+int mg_batch_precondition_apply(mg_batch* b, const mg_c128* const* vs, mg_c128* const* zs, mg_c128* const* ys) {
+  if (!b || !vs || !zs || !ys) return fail(MG_EINVAL, "NULL argument");
+  for (size_t i = 0; i < b->impl->ctx.size(); ++i) {
+    if (!vs[i] || !zs[i] || !ys[i]) return fail(MG_EINVAL, "NULL problem vector");
+    if ((const void*)vs[i] == (const void*)zs[i] || (const void*)vs[i] == (const void*)ys[i] ||
+        (const void*)zs[i] == (const void*)ys[i])
+      return fail(MG_EINVAL, "v, z and y of a problem must not alias");
+  }
+  return b->impl->precondition_apply(reinterpret_cast<const cpx<double>* const*>(vs),
+                                     reinterpret_cast<cpx<double>* const*>(zs), reinterpret_cast<cpx<double>* const*>(ys));
+}
+
 int mg_batch_solve(mg_batch* b, const mg_c128* const* bs, mg_c128* const* us, double rtol, int maxit, int driver,
                    int* iters, double* relres) {
   if (!b || !bs || !us) return fail(MG_EINVAL, "NULL argument");
+  if (!(rtol > 0) || maxit < 1) return fail(MG_EINVAL, "need rtol > 0 and maxit >= 1");
+  if (driver != MG_STATIONARY && driver != MG_BICGSTAB) return fail(MG_EINVAL, "bad driver");
+  for (size_t i = 0; i < b->impl->ctx.size(); ++i)
+    if (!bs[i] || !us[i]) return fail(MG_EINVAL, "NULL problem vector");
+  if (driver == MG_BICGSTAB)
+    return b->impl->solve(reinterpret_cast<const cpx<double>* const*>(bs), reinterpret_cast<cpx<double>* const*>(us),
+                          rtol, maxit, iters, relres);
+  // the stationary driver solves problem by problem
   int worst = MG_OK;
   for (size_t i = 0; i < b->impl->ctx.size(); ++i) {
     int it = 0;

@@ -13,7 +13,15 @@ namespace mg {
 // block i is given the (i div 8)-th tile of the i mod 8-th contiguous chunk of
 // tiles numbered y fastest: the tiles an XCD runs at one time are y and x
 // neighbours, and the halo rows they share are fetched into that XCD's L2 once.
-// The mapping is a bijection for any tile count; a different dispatch order
+// Order 2: the XCDs take y bands.  Tiles are numbered band by band (a band
+// is ceil(gy / 8) y tiles high, the last one may be lower), inside a band z
+// major and x fastest, and block i takes the (i div 8)-th tile of the (i mod
+// 8)-th contiguous chunk of that numbering.  The tiles an XCD runs at one time
+// are then the x and y neighbours of one z range: the halo rows and columns
+// they share stay in its L2, and whole rows of the grid are read together
+// (order 1 groups y neighbours only, and reads each row in tile-wide pieces
+// far apart in time, which costs more than it saves on large grids).
+// Every mapping is a bijection for any tile count; a different dispatch order
 // changes only the speed.
 __device__ inline void fused3_block_tile(int order, int gx, int gy, int gz, int& bx, int& by, int& bz) {
   const int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
@@ -26,9 +34,21 @@ __device__ inline void fused3_block_tile(int order, int gx, int gy, int gz, int&
   const int N = gx * gy * gz, q = N >> 3, rem = N & 7;
   const int k = lin & 7, local = lin >> 3;
   const int t = k * q + min(k, rem) + local;
-  by = t % gy;
-  bx = (t / gy) % gx;
-  bz = t / (gx * gy);
+  if (order == 1) {
+    by = t % gy;
+    bx = (t / gy) % gx;
+    bz = t / (gx * gy);
+    return;
+  }
+  const int h = (gy + 7) >> 3;
+  const int band_tiles = gx * h * gz;
+  const int b = t / band_tiles;
+  const int y0 = b * h;
+  const int hb = min(h, gy - y0);
+  const int r = t - b * band_tiles;
+  bx = r % gx;
+  by = y0 + (r / gx) % hb;
+  bz = (r / gx) / hb;
 }
 
 // PF > 1 tiles keep PF planes of loads in flight and take more registers:
@@ -60,7 +80,8 @@ constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0, 1},  {2, 2, 14, 0, 1}, {2, 2, 21,
                                   {2, 2, 28, 0, 1}, {4, 2, 14, 0, 1}, {4, 2, 21, 0, 1}, {4, 2, 28, 0, 1},
                                   {2, 1, 14, 0, 1}, {2, 1, 21, 0, 1}, {2, 2, 9, 1, 1},  {2, 2, 21, 1, 1},
                                   {4, 2, 28, 0, 2}, {4, 2, 28, 0, 3}, {2, 2, 28, 0, 2}, {2, 2, 28, 0, 3},
-                                  {4, 2, 28, 1, 3}, {2, 2, 28, 1, 3}};
+                                  {4, 2, 28, 1, 3}, {2, 2, 28, 1, 3}, {2, 2, 9, 2, 1},  {4, 2, 14, 2, 1},
+                                  {4, 2, 28, 2, 3}, {2, 2, 28, 2, 3}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
@@ -140,6 +161,10 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s, hipEvent_
       case 14: launch3<T, 2, 2, 28, 2>(a, g, s, t0, t1); break;
       case 15: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
       case 16: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 17: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 18: launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
+      case 19: launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
+      case 20: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
       default: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
     }
   } else {
@@ -188,14 +213,14 @@ size_t fused_spill_count(int dim, int n) {
 }
 
 // rho_c = R x (3D) with the sweep's march and restriction (no operator): the
-// 4 x 2 x 28 tile with prefetch depth 3 in the XCD-chunked block order; the
-// seam rows go through the seam array and k_seam3.
-constexpr int kRTyc = 4, kRRpt = 2, kRZc = 28;
+// 4 x 2 x 28 tile with prefetch depth 3 in the y-band block order (order 2);
+// the seam rows go through the seam array and k_seam3.
+constexpr int kRTyc = 4, kRRpt = 2, kRZc = 28, kKrylovOrder = 2;
 template <class T, int DOT>
 __global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_restrict3(FusedArgs<T> a) {
   __shared__ F3Lds<T, kRTyc, kRRpt, false, true> sm;
   int bx, by, bz;
-  fused3_block_tile(1, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
+  fused3_block_tile(kKrylovOrder, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
   // |s|^2 partials are indexed by tile (summation order independent of the block order)
   double* part = DOT ? a.partials + (bx + gridDim.x * (by + gridDim.y * bz)) : nullptr;
   fused3_tile<T, kRTyc, kRRpt, kRZc, 1, kRestrict, 3, DOT>(a, bx, by, bz, part, sm);
@@ -215,7 +240,7 @@ hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill
   a.rhoc = rhoc;
   a.spill = spill;
   a.variant = 1;
-  a.order = 1;
+  a.order = kKrylovOrder;
   const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
   constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
   hipLaunchKernelGGL((k_restrict3<T, 0>), g, NT, 0, s, a);
@@ -243,7 +268,7 @@ hipError_t launch_restrict3_s(int nc, const cpx<T>* r, const cpx<T>* v, cpx<doub
   a.spill = spill;
   a.partials = partials;
   a.variant = 1;
-  a.order = 1;
+  a.order = kKrylovOrder;
   const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
   constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
   hipLaunchKernelGGL((k_restrict3<T, 3>), g, NT, 0, s, a);
@@ -263,7 +288,7 @@ template <class T, int VAR, int DOT>
 __global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_prec_apply3(FusedArgs<T> a) {
   __shared__ F3Lds<T, kRTyc, kRRpt, false, true> sm;
   int bx, by, bz;
-  fused3_block_tile(1, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
+  fused3_block_tile(kKrylovOrder, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
   // dot partials are indexed by tile, so their summation order does not depend on the block order
   constexpr int ND = DOT == 1 ? 2 : 3;
   double* part = DOT ? a.partials + ND * (bx + gridDim.x * (by + gridDim.y * bz)) : nullptr;
@@ -303,7 +328,7 @@ hipError_t launch_prec_apply3(int n, const cpx<T>* coef, cpx<T> ws, int mask_c, 
   for (int q = 0; q < 4; ++q) a.coef[q] = coef[q];
   a.ws = ws;
   a.variant = mask_c ? 1 : 0;
-  a.order = 1;
+  a.order = kKrylovOrder;
   const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
   if (mask_c) launch_pa3<T, 1>(dot, g, a, s);
   else launch_pa3<T, 0>(dot, g, a, s);

@@ -214,31 +214,6 @@ __global__ __launch_bounds__(256) void k_post_galerkin(OpData<T> op, const cpx<T
   if (valid && part == 0) rhoc[vv] = csel(is_interior<D>(m, nc), mk(re, im), czero<T>());
 }
 
-// R v = P^T v: per axis weights 1 - |o|/3 for fine offsets o in [-2, 2] around 3m;
-// zero on the coarse boundary.
-// Part of (R v)(m) over the offsets whose outermost component (z in 3D, y in
-// 2D) is oo; all loads independent (indices clamped, boundary m gives 0 later).
-template <class T, int D>
-__device__ inline cpx<T> restrict_part(const cpx<T>* __restrict__ vf, int nf, const int m[3], int oo) {
-  constexpr T w[5] = {T(1.0 / 3.0), T(2.0 / 3.0), T(1), T(2.0 / 3.0), T(1.0 / 3.0)};
-  constexpr int IL = D == 3 ? -2 : 0, IH = D == 3 ? 2 : 0;
-  cpx<T> acc = czero<T>();
-#pragma unroll
-  for (int oi = IL; oi <= IH; ++oi) {
-    cpx<T> accx = czero<T>();
-#pragma unroll
-    for (int ox = -2; ox <= 2; ++ox) {
-      const int o[3] = {ox, D == 3 ? oi : oo, oo};
-      int j[3] = {0, 0, 0};
-#pragma unroll
-      for (int q = 0; q < D; ++q) j[q] = min(max(3 * m[q] + o[q], 0), nf - 1);
-      accx = accx + w[ox + 2] * vf[(unsigned)ravel<D>(j, nf)];
-    }
-    acc = acc + (D == 3 ? w[oi + 2] * w[oo + 2] : w[oo + 2]) * accx;
-  }
-  return acc;
-}
-
 // R v = P^T v (weights 1 - |o|/3 per axis around 3m; zero on the coarse
 // boundary): eight lanes per coarse vertex, lanes 0..4 take the parts
 // oo = -2..2, summed by a xor shuffle.
@@ -302,56 +277,26 @@ __global__ void k_prolong(int n, const cpx<T>* __restrict__ uc, cpx<T>* __restri
   }
 }
 
-// Zero-start cycle, upward part on one level:
-//   s = omega rho / D;  z = Lop(s) + P z_c, Lop = id (add), c-point mask (hb),
-//   s - P I s (BPX); on the coarsest level z = s.
-// Zero-start cycle, one level going up: z = Lop(omega D^-1 rho) + P g with
-// g the coarse correction (BPX: already minus I s, see k_prec_g); hb masks s
-// on c-points (mask_c); the coarsest level has no g.
 template <class T, int D>
 __global__ void k_prec_up(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, int mask_c, int is_lmin,
                           const cpx<T>* __restrict__ gc, cpx<T>* __restrict__ z) {
-  const int n = op.n;
-  const int nc = (n - 1) / 3 + 1;
-  MG_ROWS(D, n) {
+  MG_ROWS(D, op.n) {
     int j[3];
     long long i;
-    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    cpx<T> out = czero<T>();
-    if (is_interior<D>(j, n)) {
-      cpx<T> id = op.invD;
-      if (op.invDv) id = op.invDv[i];
-      cpx<T> s = cmul(omega, cmul(id, rho[i]));
-      if (!is_lmin) {
-        s = csel(mask_c && is_cpoint<D>(j), czero<T>(), s);
-        s = s + prolong_at<T, D>(gc, nc, j);
-      }
-      out = s;
-    }
-    z[i] = out;
+    if (!row_vertex<D>(row_, x_, op.n, j, i)) continue;
+    prec_up_vertex<T, D>(op, j, i, rho, omega, mask_c, is_lmin, gc, z);
   }
 }
 
-// BPX coarse correction of the zero-start cycle at level l (op): on coarse
-// vertex m, g = z_c(m) - (I s)(m) with s = omega D^-1 rho at 3m, so that
-// z = s + P g = s - P I s + P z_c.
 template <class T, int D>
 __global__ void k_prec_g(OpData<T> op, const cpx<T>* __restrict__ rho, cpx<T> omega, const cpx<T>* __restrict__ zc,
                          cpx<T>* __restrict__ g) {
-  const int n = op.n, nc = (n - 1) / 3 + 1;
+  const int nc = (op.n - 1) / 3 + 1;
   MG_ROWS(D, nc) {
     int m[3];
     long long ic;
     if (!row_vertex<D>(row_, x_, nc, m, ic)) continue;
-    const int j[3] = {3 * m[0], 3 * m[1], D == 3 ? 3 * m[2] : 0};
-    cpx<T> q = czero<T>();
-    if (is_interior<D>(j, n)) {
-      const long long i = ravel<D>(j, n);
-      cpx<T> id = op.invD;
-      if (op.invDv) id = op.invDv[i];
-      q = cmul(omega, cmul(id, rho[i]));
-    }
-    g[ic] = zc[ic] - q;
+    prec_g_vertex<T, D>(op, m, ic, rho, omega, zc, g);
   }
 }
 

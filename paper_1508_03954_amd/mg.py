@@ -32,7 +32,7 @@ EXPORTED = [
     "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
     "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
     "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested", "mg_batch_set_spin_limit",
-    "mg_residual_norm_noalloc",
+    "mg_residual_norm_noalloc", "mg_batch_precondition_apply",
 ]
 
 
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_batch_get_trace.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]
     lib.mg_batch_solve.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, I, ctypes.POINTER(I),
                                    ctypes.POINTER(D)]
+    lib.mg_batch_precondition_apply.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)]
     for name in EXPORTED:
         if name not in ("mg_params_default", "mg_destroy", "mg_last_error", "mg_batch_destroy"):
             getattr(lib, name).restype = I
@@ -449,6 +450,20 @@ class Batch:
         buf = (ctypes.c_longlong * (8 * cnt.value))()
         _check(self._lib.mg_batch_get_trace(self._b, buf, cnt.value, ctypes.byref(cnt)))
         return np.array(buf[:], dtype=np.int64).reshape(cnt.value, 8)
+
+    def precondition_apply(self, vs):
+        """(zs, ys) with z_i = B_i v_i (one zero-start cycle) and y_i = H_i z_i,
+        every problem in one persistent launch."""
+        t = self._torch
+        vs = [s._as_dev(v) for s, v in zip(self.solvers, vs)]
+        zs = [t.zeros_like(v) for v in vs]
+        ys = [t.zeros_like(v) for v in vs]
+        n = self.count
+        pv = (ctypes.c_void_p * n)(*[_ptr(v) for v in vs])
+        pz = (ctypes.c_void_p * n)(*[_ptr(z) for z in zs])
+        py = (ctypes.c_void_p * n)(*[_ptr(y) for y in ys])
+        _check(self._lib.mg_batch_precondition_apply(self._b, pv, pz, py))
+        return zs, ys
 
     def solve(self, bs, us, rtol: float = 1e-10, maxit: int = 500, driver: str = "bicgstab"):
         """Solves every problem (device complex128 tensors; us[i] initial guess,

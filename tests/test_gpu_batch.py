@@ -6,8 +6,12 @@ wavenumbers and variants) advanced by one persistent launch per cycle.
   tiling (FP64 and complex64), for the default and for every autotuned batch
   configuration.
 * FP64 batched cycles against the pipelined FP64 oracle (1e-12).
-* The batched solve (complex64 corrections inside FP64 refinement) reaches the
-  requested residual on members of the many-problem workload.
+* The batched preconditioner with the operator (one persistent launch for all
+  problems) against the oracle's zero-start cycle and operator (1e-12).
+* The batched Krylov solve (lockstep BiCGStab, FP64 or complex64 corrections
+  inside FP64 refinement) against dense LU on tiny grids, its residual against
+  the oracle's operator, and on members of the many-problem workload against
+  the FP64 solve of the same problem.
 """
 
 import numpy as np
@@ -119,10 +123,93 @@ def test_batched_cycles_match_oracle():
     batch.close()
 
 
+def test_batched_precondition_apply_matches_oracle():
+    """z_i = B_i v_i and y_i = H_i z_i for nine problems (2D and 3D, every
+    variant, two rotations) in one persistent launch, against the oracle's
+    zero-start cycle (the semantic cycle from u = 0) and operator."""
+    from paper_1508_03954_amd import mg
+    probs, kws = small_batch("fp64")
+    batch = mg.Batch(kws)
+    vs = []
+    for i, p in enumerate(probs):
+        rng = np.random.default_rng(100 + i)
+        vs.append(rng.standard_normal((p.n,) * p.dim) + 1j * rng.standard_normal((p.n,) * p.dim))
+    print(f"\n[case] batched preconditioner, {len(probs)} problems", flush=True)
+    zs, ys = batch.precondition_apply(vs)
+    for p, kw, v, z, y in zip(probs, kws, vs, zs, ys):
+        op = Params(dim=p.dim, level_max=p.level_max, theta=kw["theta"], phi=p.phi, variant=kw["variant"], omega=0.6)
+        zr = O.zero_start_cycle(op, O.zero_boundary(v))
+        yr = op.H(zr, p.level_max)
+        ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
+        ey = np.linalg.norm(y.cpu().numpy() - yr) / np.linalg.norm(yr)
+        assert ez <= 1e-12 and ey <= 1e-12, (p.name, kw["variant"], ez, ey)
+    batch.close()
+
+
+TINY = [(2, 2, 30.0, "bpx"), (2, 3, 12.0, "hb"), (2, 3, 45.0, "add"), (3, 2, 20.0, "bpx"), (3, 2, 9.0, "hb")]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batched_solve_matches_dense_lu(precision):
+    """Five tiny problems (every variant, 2D and 3D, k = 9..45, CSL shift
+    0.5i k^2, rotation 0.2) solved together to 1e-10 by the batched Krylov
+    driver, against the oracle's dense LU solutions: relative error 1e-8 (a
+    relative residual of 1e-10 bounds it by cond(H) 1e-10, cond below 1e2
+    here), and the residual of the returned solution, formed with the oracle's
+    operator, within 1e-10 of |b|."""
+    from paper_1508_03954_amd import mg
+    kws, refs, bs = [], [], []
+    for i, (dim, L, k, variant) in enumerate(TINY):
+        kws.append(dict(dim=dim, level_max=L, theta=0.2, phi=k * k * (1 + 0.5j), variant=variant, omega=0.6,
+                        precision=precision))
+        rng = np.random.default_rng(200 + i)
+        n = 3 ** L + 1
+        b = O.zero_boundary(rng.standard_normal((n,) * dim) + 1j * rng.standard_normal((n,) * dim))
+        op = Params(dim=dim, level_max=L, theta=0.2, phi=k * k * (1 + 0.5j), variant=variant, omega=0.6)
+        refs.append((op, O.dense_solve(op, b)))
+        bs.append(b)
+    batch = mg.Batch(kws)
+    bt = [torch.from_numpy(b).cuda() for b in bs]
+    us = [torch.zeros_like(b) for b in bt]
+    print(f"\n[case] batched Krylov solve of {len(TINY)} tiny problems ({precision})", flush=True)
+    its, rel, rc = batch.solve(bt, us, rtol=1e-10, maxit=500)
+    print(f"iterations {its.tolist()}, relres {[f'{r:.1e}' for r in rel]}", flush=True)
+    assert rc == 0 and np.all(rel <= 1e-10)
+    for (op, uref), b, u in zip(refs, bs, us):
+        un = u.cpu().numpy()
+        err = np.linalg.norm(un - uref) / np.linalg.norm(uref)
+        res = np.linalg.norm(O.zero_boundary(b - op.H(un, op.level_max))) / np.linalg.norm(b)
+        assert err <= 1e-8 and res <= 1e-10, (op.dim, op.level_max, op.variant, err, res)
+    batch.close()
+
+
+def test_batched_solve_residual_against_oracle():
+    """The nine-problem batch (2D levels 3..5, 3D levels 3..4, every variant)
+    with complex64 corrections in FP64 refinement to 1e-10: every returned
+    solution's residual, formed with the oracle's operator, is within
+    1.01e-10 of |b| (the driver's own FP64 residual decides convergence)."""
+    from paper_1508_03954_amd import mg
+    probs, kws = small_batch("fp32_refine")
+    batch = mg.Batch(kws)
+    bs = [s.rhs_from_nodal(torch.from_numpy(p.chi).cuda()) for s, p in zip(batch.solvers, probs)]
+    us = [torch.zeros_like(b) for b in bs]
+    print(f"\n[case] batched Krylov solve, nine problems, complex64 corrections", flush=True)
+    its, rel, rc = batch.solve(bs, us, rtol=1e-10, maxit=2000)
+    print(f"iterations {its.tolist()}", flush=True)
+    assert rc == 0
+    for p, kw, b, u in zip(probs, kws, bs, us):
+        op = Params(dim=p.dim, level_max=p.level_max, theta=kw["theta"], phi=p.phi, variant=kw["variant"], omega=0.6)
+        bn, un = b.cpu().numpy(), u.cpu().numpy()
+        res = np.linalg.norm(O.zero_boundary(bn - op.H(un, p.level_max))) / np.linalg.norm(bn)
+        assert res <= 1.01e-10, (p.name, kw["variant"], res)
+    batch.close()
+
+
 def test_batched_solve_fp32_refinement():
     """Members of the many-problem workload (both dimensions, the deepest
-    levels) solved to 1e-10 with complex64 corrections in FP64 refinement; the
-    result against the FP64 solve of the same problem."""
+    levels) solved together to 1e-10 by the batched Krylov driver with
+    complex64 corrections in FP64 refinement; the result against the FP64
+    solve of the same problem."""
     from paper_1508_03954_amd import mg
     from paper_1508_03954_amd.inputs import config_batched
     probs = config_batched()
@@ -134,7 +221,7 @@ def test_batched_solve_fp32_refinement():
     batch = mg.Batch(kws)
     bs = [s.rhs_from_nodal(torch.from_numpy(p.chi).cuda()) for s, p in zip(batch.solvers, sub)]
     us = [torch.zeros_like(b) for b in bs]
-    its, rel, rc = batch.solve(bs, us, rtol=1e-10, maxit=400)
+    its, rel, rc = batch.solve(bs, us, rtol=1e-10, maxit=4000)
     print(f"\n[case] batched solve of problems {pick}: iterations {its.tolist()}, relres {rel.tolist()}", flush=True)
     assert rc == 0 and np.all(rel <= 1e-10)
     for p, b, u in zip(sub, bs, us):
