@@ -15,7 +15,9 @@ BiCGStab driver in FP64 and with complex64 corrections inside FP64 residual
 refinement (and the mixed solution's deviation from the FP64 one), the FP64
 CPU oracle's rate on a bounded sample, and extras: the 3D level-5 k = 20
 complex-grid workload (BPX and hb cycles, time to 1e-10 from zero and from a
-nested start) and the 96-problem batched workload.
+nested start), the 2D level-5 k = 10 workload's 30-cycle latency, the
+potential workload's varying-phi cycle and adjoint gradient, the same-grid
+multichannel cycle, and the 96-problem batched workload.
 """
 
 from __future__ import annotations
@@ -190,10 +192,11 @@ def cpu_baseline(procs=0, level=5):
     }
 
 
-def batched_extra(torch):
+def batched_extra(torch, solve=True):
     """96 independent problems (64 2D with finest level 3..6, 32 3D with 3..5,
     k in [5, 60], phi = k^2 (1 + 0.5i), complex64 corrections): one batched
     persistent cycle vs the same cycles launched problem by problem."""
+    import numpy as np
     from paper_1508_03954_amd import mg
     from paper_1508_03954_amd.inputs import config_batched
     probs = config_batched()
@@ -232,6 +235,44 @@ def batched_extra(torch):
     t_seq = e0.elapsed_time(e1) / reps
     U = sum(updates_per_cycle(p.dim, p.level_max) for p in probs)
     NL = sum((3 ** p.level_max + 1) ** p.dim for p in probs)
+    # time to 1e-10 for all 96 problems: the batched Krylov driver (lockstep
+    # BiCGStab, complex64 corrections in FP64 refinement) against the same
+    # solves run problem by problem
+    if not solve:
+        b.close()
+        return {"workload": "96 problems: 64 2D (finest level 3..6) + 32 3D (3..5), k~U[5,60], phi=k^2(1+0.5i), "
+                            "BPX, complex64 corrections, seeds [4, i]",
+                "finest_vertices": NL, "vertex_updates_per_cycle": U, "batched_ms_per_cycle": t_batch,
+                "sequential_ms_per_cycle": t_seq, "speedup": t_seq / t_batch,
+                "autotune": {"config": best, "us_per_config": [round(t, 1) for t in times]}}
+    us = [torch.zeros_like(r) for r in rhs]
+    b.solve(rhs, us, rtol=1e-2, maxit=50)       # first call sets up the batched Krylov buffers
+    us = [torch.zeros_like(r) for r in rhs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, rel, rc = b.solve(rhs, us, rtol=1e-10, maxit=20000)
+    torch.cuda.synchronize()
+    t_bsolve = time.perf_counter() - t0
+    log(f"[bench] batched solve to 1e-10: {t_bsolve:.2f} s (status {rc}, worst relres {max(rel):.2e}, "
+        f"inner iterations up to {max(its)})")
+    useq = [torch.zeros_like(r) for r in rhs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_its, seq_rc = [], 0
+    for s, r, u in zip(b.solvers, rhs, useq):
+        _, it, rr, rc1 = s.solve(r, u0=u, rtol=1e-10, maxit=20000)
+        seq_its.append(it)
+        seq_rc = seq_rc or rc1
+    torch.cuda.synchronize()
+    t_ssolve = time.perf_counter() - t0
+    log(f"[bench] the same solves problem by problem: {t_ssolve:.2f} s")
+    solve = {"driver": "batched BiCGStab in lockstep (one persistent launch per preconditioner application), "
+                       "complex64 corrections in FP64 refinement", "seconds": t_bsolve, "status": int(rc),
+             "max_relres": float(max(rel)), "max_inner_iterations": int(max(its)),
+             "hardest_problem": int(np.argmax(its)),
+             "sequential_seconds": t_ssolve, "sequential_status": int(seq_rc),
+             "sequential_max_inner_iterations": int(max(seq_its)),
+             "speedup": t_ssolve / t_bsolve}
     b.close()
     log(f"[bench] batched: {t_batch * 1e3:.0f} us per cycle of all 96 problems vs {t_seq * 1e3:.0f} us "
         f"problem by problem (configuration {best})")
@@ -241,7 +282,8 @@ def batched_extra(torch):
             "batched_ms_per_cycle": t_batch, "sequential_ms_per_cycle": t_seq,
             "batched_vertex_updates_per_s": U / (t_batch * 1e-3),
             "sequential_vertex_updates_per_s": U / (t_seq * 1e-3),
-            "speedup": t_seq / t_batch, "autotune": {"config": best, "us_per_config": [round(t, 1) for t in times]}}
+            "speedup": t_seq / t_batch, "autotune": {"config": best, "us_per_config": [round(t, 1) for t in times]},
+            "time_to_1e-10": solve}
 
 
 def refine_extra(torch, level):
@@ -433,6 +475,144 @@ def csg_extra(args, torch):
     return out
 
 
+def latency_extra(torch):
+    """The 2D problem: levels 1..5 (244^2), k = 10, phi = k^2 (1 + 0.5i), one
+    Gaussian load, BPX, omega 0.6: its 30 cycles from u = 0 as one call (the
+    grid is cache-resident, so this measures per-cycle latency)."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_2d_bpx
+    prob = config_2d_bpx(level_max=5)
+    s = mg.Solver(2, 5, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
+    b = s.rhs_from_nodal(torch.from_numpy(prob.chi).cuda())
+    tile, _, _ = s.autotune(reps=5)
+    reps, ms = 20, []
+    for _ in range(reps + 2):
+        s.set_rhs(b)
+        s.set_solution(torch.zeros_like(b))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        s.cycle(prob.cycles, norms=False)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ms = sorted(ms[2:])
+    med = ms[len(ms) // 2]
+    s.set_rhs(b)
+    s.set_solution(torch.zeros_like(b))
+    rh, _ = s.cycle(prob.cycles)
+    ups = updates_per_cycle(2, 5)
+    log(f"[bench] 2D k=10: {prob.cycles} cycles in {med * 1e3:.0f} us ({med / prob.cycles * 1e3:.1f} us per cycle)")
+    return {"workload": f"{prob.name}: d=2, levels 1..5 (244^2 complex128 vertices), k=10, phi=k^2(1+0.5i), "
+                        f"one Gaussian load, bpx, omega=0.6, {prob.cycles} cycles from u=0",
+            "ms_for_30_cycles": med, "us_per_cycle": med / prob.cycles * 1e3,
+            "vertex_updates_per_s": ups * prob.cycles / (med * 1e-3), "tile": tile,
+            "residual_reduction_30_cycles": rh[-1] / rh[0], "samples": reps}
+
+
+def adjoint_extra(torch):
+    """The potential problem: 3D levels 1..5, k = 15, V = 8 Gaussians, phi =
+    k^2 (1 + 0.3i) - V (nodal phi: the per-cell path with the FAS form).  The
+    varying-phi cycle's rate, then J = sum over the shell of |u|^2 and dJ/dV
+    through torch.autograd: forward solve, adjoint solve and gradient kernel,
+    BiCGStab to 1e-10 each."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.adjoint import ShellFunctional
+    from paper_1508_03954_amd.inputs import config_potential, shell_mask
+    prob = config_potential(level_max=5)
+    L = prob.level_max
+    phi = torch.from_numpy(prob.phi_field()).cuda()
+    s = mg.Solver(3, L, theta=prob.theta, phi=0.0, phi_field=phi, variant="bpx", omega=0.6)
+    b = s.rhs_from_nodal(torch.from_numpy(prob.chi).cuda())
+    s.set_rhs(b)
+    s.set_solution(torch.zeros_like(b))
+    s.cycle(5, norms=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.cycle(20, norms=False)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms_cycle = e0.elapsed_time(e1) / 20
+    del s
+    cfg = {"dim": 3, "level_max": L, "theta": prob.theta, "phi0": prob.phi, "variant": "bpx", "rtol": 1e-10,
+           "maxit": 3000}
+    shell = torch.from_numpy(shell_mask(L, 3, 0.9, 0.95)).cuda()
+    V = torch.from_numpy(prob.potential).cuda().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = ShellFunctional.apply(V, b, shell, cfg)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ups = updates_per_cycle(3, L)
+    log(f"[bench] potential workload: varying-phi cycle {ms_cycle * 1e3:.0f} us; forward solve {t1 - t0:.3f} s, "
+        f"adjoint solve + gradient {t2 - t1:.3f} s")
+    return {"workload": f"{prob.name}: d=3, levels 1..5 (244^3 complex128 vertices), k=15, phi=k^2(1+0.3i)-V(x), "
+                        "V = 8 Gaussians, shell 0.9<|x|<0.95, bpx, omega=0.6",
+            "varying_phi_cycle_ms": ms_cycle, "varying_phi_vertex_updates_per_s": ups / (ms_cycle * 1e-3),
+            "forward_solve_s": t1 - t0, "adjoint_and_gradient_s": t2 - t1, "J": J.item(),
+            "rtol": 1e-10}
+
+
+def multichannel_extra(torch, level=5):
+    """Same-grid multichannel form on the 3D level-5 grid (244^3): nchan
+    channels with k spread over [5, 40] (phi = k^2 (1 + 0.5i)), BPX, omega
+    0.6, one AoS cycle for all channels, against the same channels cycled one
+    by one by single-channel contexts (fused sweep, and the generic passes the
+    multichannel cycle is built from).  Reported per channel and vertex."""
+    from paper_1508_03954_amd import mg
+    n = 3 ** level + 1
+    ups = updates_per_cycle(3, level)
+    out = {"workload": f"3D levels 1..{level} ({n}^3 vertices), k in [5, 40], phi=k^2(1+0.5i), bpx, omega=0.6",
+           "channels": {}}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for nchan in (1, 2, 4, 8, 16):
+        ks = [5.0 + 35.0 * c / max(nchan - 1, 1) for c in range(nchan)]
+        phis = [k * k * (1 + 0.5j) for k in ks]
+        m = mg.MultiChannel(3, level, phis, variant="bpx", omega=0.6)
+        g = torch.Generator(device="cuda").manual_seed(nchan)
+        b = torch.randn((n, n, n, nchan), dtype=torch.complex128, device="cuda", generator=g)
+        m.set_rhs(b)
+        m.set_solution(torch.zeros_like(b))
+        ms = timed(lambda: m.cycle(1, norms=False), 5)
+        m.close()
+        del b
+        torch.cuda.empty_cache()
+        rec = {"ms_per_cycle": ms, "ns_per_vertex_update_per_channel": ms * 1e6 / (ups * nchan)}
+        if nchan in (1, 16):
+            # the same channels one by one, single-channel contexts
+            for sweep in ("fused", "generic"):
+                tot = 0.0
+                for ph in phis[: min(nchan, 4)]:
+                    s = mg.Solver(3, level, phi=ph, variant="bpx", omega=0.6, sweep=sweep)
+                    bb = torch.randn((n, n, n), dtype=torch.complex128, device="cuda")
+                    s.set_rhs(bb)
+                    s.set_solution(torch.zeros_like(bb))
+                    tot += timed(lambda: s.cycle(1, norms=False), 5)
+                    del s, bb
+                    torch.cuda.empty_cache()
+                per = tot / min(nchan, 4)
+                rec[f"single_channel_{sweep}_ms_per_channel"] = per
+        out["channels"][str(nchan)] = rec
+        log(f"[bench] multichannel {nchan}: {ms:.2f} ms per cycle, "
+            f"{rec['ns_per_vertex_update_per_channel']:.3f} ns per vertex update and channel")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -457,6 +637,10 @@ def main():
                          "its record; for counter runs of the batched kernel")
     ap.add_argument("--csg-only", action="store_true",
                     help="run only the 3D level-5 k=20 workload and print its record; for counter runs")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the potential (varying phi, adjoint) workload and print its record")
+    ap.add_argument("--multichannel-only", action="store_true",
+                    help="run only the same-grid multichannel measurement and print its record")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -468,7 +652,7 @@ def main():
     # the CPU baseline runs first, before the device is touched: its worker
     # processes are forked from a process without GPU state
     cpu = None
-    if not (args.no_cpu_baseline or args.batched_only or args.csg_only):
+    if not (args.no_cpu_baseline or args.batched_only or args.csg_only or args.adjoint_only or args.multichannel_only):
         log("[bench] CPU baseline: FP64 oracle on the host ...")
         cpu = cpu_baseline(args.cpu_procs)
         log(f"[bench] oracle {cpu['value']:.3e} vertex-updates/s on {cpu['cores']} processes, "
@@ -480,8 +664,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     mg.load_library()
-    if args.batched_only or args.csg_only:
-        out = {"batched": batched_extra(torch)} if args.batched_only else {"csg_l5": csg_extra(args, torch)}
+    if args.batched_only or args.csg_only or args.adjoint_only or args.multichannel_only:
+        if args.batched_only:
+            out = {"batched": batched_extra(torch, solve=not args.no_solve)}
+        elif args.csg_only:
+            out = {"csg_l5": csg_extra(args, torch)}
+        elif args.adjoint_only:
+            out = {"potential_adjoint": adjoint_extra(torch)}
+        else:
+            out = {"multichannel": multichannel_extra(torch)}
         if args.copy_probe:
             copy_probe(torch, out)
         print(json.dumps(out))
@@ -516,7 +707,10 @@ def main():
         out["time_to_1e-10"] = h["time_to_1e-10"]
     if not args.no_extras:
         out["extra_3d_k20_l5"] = csg_extra(args, torch)
-        out["batched"] = batched_extra(torch)
+        out["extra_2d_k10_latency"] = latency_extra(torch)
+        out["extra_potential_adjoint"] = adjoint_extra(torch)
+        out["extra_multichannel"] = multichannel_extra(torch)
+        out["batched"] = batched_extra(torch, solve=not args.no_solve)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     if args.copy_probe:
