@@ -333,6 +333,12 @@ int mg_batch_autotune(mg_batch* batch, int reps, int* config, double* us_per_cyc
 /* Number of batch configurations the autotuner tries. */
 int mg_batch_configs(void);
 
+/* Selects batch configuration `config` (0 <= config < mg_batch_configs()),
+ * as the autotuner would: the 3D and 2D sweep tiles and the queue order of
+ * the cycle, and the tiles of the batched preconditioner.  The problems'
+ * state is kept.  MG_EINVAL out of range. */
+int mg_batch_set_config(mg_batch* batch, int config);
+
 /* Bound of every dependency wait inside the batched kernel, in polls (default
  * 2^20, about a second; 0 <= polls <= 2^26, MG_EINVAL otherwise).  A wait
  * that reaches it gives up: the item is skipped, the launch still drains, and
@@ -381,6 +387,38 @@ int mg_batch_precondition_apply(mg_batch* batch, const mg_c128* const* vs, mg_c1
  * (the worst over the problems; outputs valid).  Synchronises. */
 int mg_batch_solve(mg_batch* batch, const mg_c128* const* bs, mg_c128* const* us, double rtol,
                    int maxit, int driver, int* iters, double* relres);
+
+/* ---------------------------------------------------------------------------
+ * Same-grid multichannel form (Section 7.5): nchan channels -- independent
+ * problems  -Lap u_c - phi_c u_c = chi_c  that share the grid, the rotation,
+ * the variant and the relaxation -- fused into one problem on one grid.  Every
+ * vector is array-of-structures: nchan complex128 values per vertex, channel
+ * c of vertex i (C order, x fastest, boundary included) at i * nchan + c.  One
+ * cycle advances every channel by the pipelined additive cycle (Galerkin form
+ * of the coarse right-hand side, Lemma 2); index, stencil and transfer work is
+ * shared by the channels of a vertex.
+ */
+typedef struct mg_mc mg_mc;
+
+/* p: dim, levels (level_min < level_max), theta, variant, omega scheme and
+ * omega, conjugate; p->phi is ignored, phi_field must be NULL, no absorbing
+ * layer, FP64.  nchan in {1, 2, 4, 8, 16}; phis: host array of the nchan
+ * constant phi_c.  Allocates 16 nchan bytes per vertex per field.  MG_EINVAL
+ * for anything else. */
+int mg_mc_setup(const mg_params* p, int nchan, const mg_c128* phis, void* hip_stream, mg_mc** out);
+void mg_mc_destroy(mg_mc* ctx);
+/* y_c = H_c x_c for every channel (interior; y = 0 on the boundary). */
+int mg_mc_apply(mg_mc* ctx, const mg_c128* x, mg_c128* y);
+/* Finest right-hand sides of all channels; helpers and cycle counter reset. */
+int mg_mc_set_rhs(mg_mc* ctx, const mg_c128* b);
+/* Finest iterates of all channels; helpers and cycle counter reset. */
+int mg_mc_set_solution(mg_mc* ctx, const mg_c128* u);
+/* ncycles cycles; res_h (host, ncycles * nchan, or NULL) receives
+ * |b_c - H_c u_c|_h of the iterate each cycle started from, cycle-major. */
+int mg_mc_cycle(mg_mc* ctx, int ncycles, double* res_h);
+/* Applies the pending update and copies every channel's finest iterate to u
+ * (device, AoS; may be NULL). */
+int mg_mc_flush(mg_mc* ctx, mg_c128* u);
 
 #ifdef __cplusplus
 }

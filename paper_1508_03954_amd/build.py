@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip", "mg_batch.hip"]
+SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip", "mg_batch.hip", "mg_multichannel.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

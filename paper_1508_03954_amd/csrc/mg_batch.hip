@@ -402,7 +402,7 @@ constexpr int kPMaxPhases = 24;
 
 template <class T>
 struct PProb {
-  int dim, L, lmin, variant, nphase, zc3, fgx, fgy, ftiles, nslots;
+  int dim, L, lmin, variant, nphase, zc3, fgx, fgy, ftiles, nslots, nslots_cap;
   int phase_items[kPMaxPhases];
   int phase_kind[kPMaxPhases];
   int phase_level[kPMaxPhases];
@@ -751,6 +751,7 @@ struct BatchBase {
   virtual int solve(const cpx<double>* const* bs, cpx<double>* const* us, double rtol, int maxit, int* iters,
                     double* relres) = 0;
   virtual int precondition_apply(const cpx<double>* const* vs, cpx<double>* const* zs, cpx<double>* const* ys) = 0;
+  virtual int set_config(int cfg) = 0;
   std::vector<mg_ctx*> ctx;
   hipStream_t s = nullptr;
 };
@@ -1038,7 +1039,14 @@ struct Batch : BatchBase {
     zc2 = z2;
     schedule = sch;
     for (int i = 0; i < np; ++i) MG_TRY(describe(i, hp[i]));
+    kready = false;   // the Krylov marches take the batch's z extent
     return build_items();
+  }
+
+  int set_config(int cfg) override {
+    const int n3 = (int)(sizeof(kBZc3) / sizeof(kBZc3[0])), n2 = (int)(sizeof(kBZc2) / sizeof(kBZc2[0]));
+    if (cfg < 0 || cfg >= n3 * n2 * 2) return fail(MG_EINVAL, "configuration out of range");
+    return configure(cfg % n3, (cfg / n3) % n2, cfg / (n3 * n2));
   }
 
   // ---- batched Krylov solve --------------------------------------------
@@ -1049,6 +1057,9 @@ struct Batch : BatchBase {
   int* dpdone = nullptr;               // [np][kPMaxPhases], queue, error word
   BItem* dpitems = nullptr;
   int npitems = 0, pgrid = 0;
+  std::vector<BItem> hpitems_all;      // every problem's items in queue order
+  int pitem_cap = 0;
+  std::vector<int> pitems_active;      // the active set the device list was built for
   std::vector<VSet<T>> hvs;
   VSet<T>* dvs = nullptr;
   int* dblk_prob = nullptr;
@@ -1066,7 +1077,7 @@ struct Batch : BatchBase {
   }
 
   // Phases of one preconditioner application with the operator (see PK_*).
-  int describe_prec(int i, PProb<T>& P) {
+  int describe_prec(int i, PProb<T>& P, double* part = nullptr, int part_cap = 0) {
     Engine<T>& E = *engine_of<T>(ctx[i]);
     std::memset(&P, 0, sizeof(P));
     P.dim = E.dim;
@@ -1122,13 +1133,44 @@ struct Batch : BatchBase {
     add(PK_DOT, L, 1);
     P.nphase = k;
     if (k > kPMaxPhases) return fail(MG_EINVAL, "too many phases for a batched preconditioner");
-    MG_TRY(dalloc(&P.part, 3 * (size_t)P.nslots));
+    if (part && P.nslots <= part_cap) {
+      P.part = part;
+      P.nslots_cap = part_cap;
+    } else {
+      MG_TRY(dalloc(&P.part, 3 * (size_t)P.nslots));
+      P.nslots_cap = P.nslots;
+    }
     MG_HIP(launch_fill(P.part, 3 * (size_t)P.nslots * sizeof(double), s));
     return MG_OK;
   }
 
   int krylov_setup() {
     if (kready) return MG_OK;
+    if (dpp) {
+      // rebuilt after a configuration change: descriptors and items only
+      std::vector<std::array<long long, 4>> keys;
+      for (int i = 0; i < np; ++i) {
+        double* part = hpp[i].part;
+        const int cap = hpp[i].nslots_cap;
+        MG_TRY(describe_prec(i, hpp[i], part, cap));
+        const long long size = (long long)engine_of<T>(ctx[i])->NL();
+        for (int ph = 0; ph < hpp[i].nphase; ++ph)
+          for (int t = 0; t < hpp[i].phase_items[ph]; ++t) keys.push_back({((long long)ph << 40) - size, i, ph, t});
+      }
+      std::stable_sort(keys.begin(), keys.end(),
+                       [](const std::array<long long, 4>& a, const std::array<long long, 4>& b) { return a[0] < b[0]; });
+      hpitems_all.resize(keys.size());
+      for (size_t k = 0; k < keys.size(); ++k)
+        hpitems_all[k] = BItem{(int)keys[k][1], (int)keys[k][2], (int)keys[k][3]};
+      if ((int)hpitems_all.size() > pitem_cap) {
+        MG_TRY(dalloc(&dpitems, hpitems_all.size()));
+        pitem_cap = (int)hpitems_all.size();
+      }
+      MG_HIP(hipMemcpy(dpp, hpp.data(), np * sizeof(PProb<T>), hipMemcpyHostToDevice));
+      pitems_active.clear();
+      kready = true;
+      return MG_OK;
+    }
     hpp.resize(np);
     hio.resize(np);
     hvs.resize(np);
@@ -1167,11 +1209,12 @@ struct Batch : BatchBase {
     nvblocks = (int)blk_prob.size();
     std::stable_sort(keys.begin(), keys.end(),
                      [](const std::array<long long, 4>& a, const std::array<long long, 4>& b) { return a[0] < b[0]; });
-    std::vector<BItem> items(keys.size());
-    for (size_t k = 0; k < keys.size(); ++k) items[k] = BItem{(int)keys[k][1], (int)keys[k][2], (int)keys[k][3]};
-    npitems = (int)items.size();
-    MG_TRY(dalloc(&dpitems, items.size()));
-    MG_HIP(hipMemcpy(dpitems, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice));
+    hpitems_all.resize(keys.size());
+    for (size_t k = 0; k < keys.size(); ++k)
+      hpitems_all[k] = BItem{(int)keys[k][1], (int)keys[k][2], (int)keys[k][3]};
+    MG_TRY(dalloc(&dpitems, hpitems_all.size()));
+    pitem_cap = (int)hpitems_all.size();
+    pitems_active.clear();
     MG_TRY(dalloc(&dpp, np));
     MG_HIP(hipMemcpy(dpp, hpp.data(), np * sizeof(PProb<T>), hipMemcpyHostToDevice));
     MG_TRY(dalloc(&dio, np));
@@ -1194,9 +1237,33 @@ struct Batch : BatchBase {
     return MG_OK;
   }
 
+  // The device queue holds the items of the active problems only (in the
+  // global queue order, which keeps every item after its dependencies):
+  // rebuilt when the active set changes, so that the late iterations of a
+  // lockstep solve, with few problems left, walk only their items.
+  int select_items() {
+    std::vector<int> act(np);
+    for (int i = 0; i < np; ++i) act[i] = hio[i].active;
+    if (act == pitems_active) return MG_OK;
+    std::vector<BItem> items;
+    items.reserve(hpitems_all.size());
+    for (const BItem& w : hpitems_all)
+      if (act[w.prob]) items.push_back(w);
+    npitems = (int)items.size();
+    if (npitems) {
+      MG_HIP(hipStreamSynchronize(s));
+      MG_HIP(hipMemcpyAsync(dpitems, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, s));
+      MG_HIP(hipStreamSynchronize(s));
+    }
+    pitems_active = act;
+    return MG_OK;
+  }
+
   // One preconditioner application with the operator for every active
   // problem: io[i] set by the caller (dot 1 or 2), sums in dpout.
   int prec_apply(int dot) {
+    MG_TRY(select_items());
+    if (npitems == 0) return MG_OK;
     MG_HIP(hipMemcpyAsync(dio, hio.data(), np * sizeof(PIO<T>), hipMemcpyHostToDevice, s));
     MG_HIP(launch_fill(dpdone, ((size_t)np * kPMaxPhases + 2) * sizeof(int), s));
     PrecArgs<T> A;
@@ -1550,6 +1617,11 @@ int mg_batch_autotune(mg_batch* b, int reps, int* config, double* us_per_cycle, 
 }
 
 int mg_batch_configs(void) { return kBatchConfigs; }
+
+int mg_batch_set_config(mg_batch* b, int config) {
+  if (!b) return fail(MG_EINVAL, "NULL batch");
+  return b->impl->set_config(config);
+}
 
 int mg_batch_set_spin_limit(mg_batch* b, long long polls) {
   if (!b || polls < 0 || polls > kMaxSpinLimit) return fail(MG_EINVAL, "spin limit out of range");

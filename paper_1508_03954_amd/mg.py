@@ -32,7 +32,8 @@ EXPORTED = [
     "mg_sweep_time", "mg_tiles", "mg_set_tile", "mg_autotune", "mg_batch_setup", "mg_batch_destroy",
     "mg_batch_problem", "mg_batch_cycle", "mg_batch_autotune", "mg_batch_configs", "mg_batch_solve",
     "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested", "mg_batch_set_spin_limit",
-    "mg_residual_norm_noalloc", "mg_batch_precondition_apply",
+    "mg_residual_norm_noalloc", "mg_batch_precondition_apply", "mg_mc_setup", "mg_mc_destroy", "mg_mc_apply",
+    "mg_mc_set_rhs", "mg_mc_set_solution", "mg_mc_cycle", "mg_mc_flush", "mg_batch_set_config",
 ]
 
 
@@ -105,14 +106,23 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_batch_cycle.argtypes = [P, I, ctypes.POINTER(D)]
     lib.mg_batch_autotune.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.mg_batch_configs.argtypes = []
+    lib.mg_batch_set_config.argtypes = [P, I]
     lib.mg_batch_set_spin_limit.argtypes = [P, ctypes.c_longlong]
     lib.mg_batch_trace.argtypes = [P, I]
     lib.mg_batch_get_trace.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), I, ctypes.POINTER(I)]
     lib.mg_batch_solve.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, I, ctypes.POINTER(I),
                                    ctypes.POINTER(D)]
     lib.mg_batch_precondition_apply.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)]
+    lib.mg_mc_setup.argtypes = [ctypes.POINTER(Params), I, ctypes.POINTER(c128), P, ctypes.POINTER(P)]
+    lib.mg_mc_destroy.argtypes = [P]
+    lib.mg_mc_destroy.restype = None
+    lib.mg_mc_apply.argtypes = [P, P, P]
+    lib.mg_mc_set_rhs.argtypes = [P, P]
+    lib.mg_mc_set_solution.argtypes = [P, P]
+    lib.mg_mc_cycle.argtypes = [P, I, ctypes.POINTER(D)]
+    lib.mg_mc_flush.argtypes = [P, P]
     for name in EXPORTED:
-        if name not in ("mg_params_default", "mg_destroy", "mg_last_error", "mg_batch_destroy"):
+        if name not in ("mg_params_default", "mg_destroy", "mg_last_error", "mg_batch_destroy", "mg_mc_destroy"):
             getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -430,6 +440,10 @@ class Batch:
         _check(self._lib.mg_batch_autotune(self._b, reps, ctypes.byref(cfg), ctypes.byref(us), times))
         return cfg.value, us.value, list(times)
 
+    def set_config(self, config: int):
+        """Selects one of the autotuner's configurations (state kept)."""
+        _check(self._lib.mg_batch_set_config(self._b, config))
+
     def trace(self, enable: bool = True):
         _check(self._lib.mg_batch_trace(self._b, 1 if enable else 0))
 
@@ -476,3 +490,73 @@ class Batch:
         rc = self._lib.mg_batch_solve(self._b, pb, pu, rtol, maxit, DRIVERS[driver], its, rel)
         _check(rc, allow=(MG_ENOTCONV, MG_EDIVERGED))
         return np.array(its[:]), np.array(rel[:]), rc
+
+
+class MultiChannel:
+    """Same-grid multichannel problem: nchan channels (one constant phi each)
+    on one grid, every vector shaped (n,)*dim + (nchan,) complex128 (the
+    channels of a vertex contiguous)."""
+
+    def __init__(self, dim: int, level_max: int, phis, stream=None, **kw):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self._lib = lib
+        p, _ = make_params(dim, level_max, **kw)
+        self.nchan = len(phis)
+        arr = (c128 * self.nchan)(*[c128(complex(f).real, complex(f).imag) for f in phis])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        m = ctypes.c_void_p()
+        _check(lib.mg_mc_setup(ctypes.byref(p), self.nchan, arr, self.stream.cuda_stream, ctypes.byref(m)))
+        self._m = m
+        self.dim, self.level_max = dim, level_max
+        self.n = 3 ** level_max + 1
+        self.shape = (self.n,) * dim + (self.nchan,)
+
+    def close(self):
+        if getattr(self, "_m", None) is not None and self._m.value:
+            self._lib.mg_mc_destroy(self._m)
+            self._m = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _as_dev(self, x):
+        t = self._torch
+        if not isinstance(x, t.Tensor):
+            x = t.from_numpy(np.ascontiguousarray(x))
+        x = x.to(device="cuda", dtype=t.complex128).contiguous()
+        if tuple(x.shape) != self.shape:
+            raise ValueError(f"expected shape {self.shape}, got {tuple(x.shape)}")
+        return x
+
+    def apply(self, x):
+        x = self._as_dev(x)
+        y = self._torch.zeros_like(x)
+        _check(self._lib.mg_mc_apply(self._m, _ptr(x), _ptr(y)))
+        return y
+
+    def set_rhs(self, b):
+        b = self._as_dev(b)
+        _check(self._lib.mg_mc_set_rhs(self._m, _ptr(b)))
+
+    def set_solution(self, u):
+        u = self._as_dev(u)
+        _check(self._lib.mg_mc_set_solution(self._m, _ptr(u)))
+
+    def cycle(self, ncycles: int = 1, norms: bool = True):
+        """ncycles cycles; an (ncycles, nchan) array of |r|_h per channel (or None)."""
+        if not norms:
+            _check(self._lib.mg_mc_cycle(self._m, ncycles, None))
+            return None
+        res = (ctypes.c_double * (ncycles * self.nchan))()
+        _check(self._lib.mg_mc_cycle(self._m, ncycles, res))
+        return np.array(res[:]).reshape(ncycles, self.nchan)
+
+    def flush(self):
+        u = self._torch.zeros(self.shape, dtype=self._torch.complex128, device="cuda")
+        _check(self._lib.mg_mc_flush(self._m, _ptr(u)))
+        return u
