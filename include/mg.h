@@ -96,7 +96,7 @@ typedef struct {
   int restrict_form;         /* MG_RESTRICT_*                                      */
   int sweep;                 /* MG_SWEEP_*                                         */
   double inner_rtol;         /* MG_FP32_REFINE: relative residual each complex64   */
-                             /* inner solve aims for (0: 1e-4); an outer step      */
+                             /* inner solve aims for (0: 0.3); an outer step       */
                              /* then reduces the FP64 residual by about this much  */
   /* Absorbing layer (Section 7.4): on every level, a cell whose centre lies   */
   /* closer than layer_width to one of the faces in layer_faces is rotated by  */
@@ -360,8 +360,10 @@ int mg_batch_set_spin_limit(mg_batch* batch, long long polls);
 int mg_batch_trace(mg_batch* batch, int enable);
 int mg_batch_get_trace(mg_batch* batch, long long* out, int cap, int* count);
 
-/* z_i = B_i v_i and y_i = H_i z_i for every problem of the batch in one
- * persistent launch, B_i the problem's additive cycle from a zero start (the
+/* z_i = B_i v_i and y_i = H_i z_i for every problem of the batch, the
+ * problems with fewer than 2^22 finest vertices in one persistent launch and
+ * each larger one with its own launches (mg_precondition_apply's; such a level
+ * fills the device by itself), B_i the problem's additive cycle from a zero start (the
  * preconditioner of the Krylov driver: restrictions down to level_min, then
  * omega_l D_l^-1 on every level with the variant's level operator and P going
  * up; Section 5's cycle applied to u = 0).  vs, zs, ys: arrays of count
@@ -375,11 +377,12 @@ int mg_batch_precondition_apply(mg_batch* batch, const mg_c128* const* vs, mg_c1
  * complex128 vectors of each problem's finest size; us[i] holds the initial
  * guess and receives the solution) to |b - H u| <= rtol |b| per problem.
  * MG_BICGSTAB: BiCGStab for all problems in lockstep, each iteration's two
- * preconditioner applications with the operator and the dot products in one
- * persistent launch each (mg_batch_precondition_apply) and every vector update
+ * preconditioner applications with the operator and the dot products as in
+ * mg_batch_precondition_apply (one persistent launch for the problems below
+ * 2^22 finest vertices, own launches for the larger ones) and every vector update
  * of all problems in one launch, inside FP64 residual refinement: r = b - H u
  * and |r| in FP64, the batched solve of H e = r / |r| in the batch's
- * precision (complex64 to each problem's inner_rtol, 1e-4 if 0; an FP64
+ * precision (complex64 to each problem's inner_rtol, 0.3 if 0; an FP64
  * batch to rtol directly), u += |r| e in FP64.  maxit bounds each problem's
  * inner iterations.  MG_STATIONARY solves problem by problem with mg_solve.
  * iters / relres: arrays of count entries or NULL (inner iterations; the

@@ -310,7 +310,7 @@ static int refine_solve(mg_ctx* c, const cpx<double>* b, cpx<double>* u, double 
     if (relres_out) *relres_out = 0.0;
     return MG_OK;
   }
-  const double inner_tol = c->p.inner_rtol > 0 ? c->p.inner_rtol : 1e-4;
+  const double inner_tol = c->p.inner_rtol > 0 ? c->p.inner_rtol : kInnerRtolDefault;
   int total_inner = 0, status = MG_ENOTCONV;
   double rel = 1.0, rel0 = -1.0;
   for (int outer = 0; outer < 100; ++outer) {

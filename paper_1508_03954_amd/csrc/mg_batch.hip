@@ -715,15 +715,21 @@ __global__ __launch_bounds__(kBThreads) void k_batch_vec(const VSet<T>* __restri
   block_sum3(acc, part + 3 * b);
 }
 
+// One wavefront per problem: lane t adds the partials of blocks t, t + 64, ...
+// in order, then a shuffle tree adds the lanes (a fixed order, so the sums do
+// not change from run to run).
 template <class T>
 __global__ __launch_bounds__(64) void k_batch_vec_finish(const VSet<T>* __restrict__ vs, const int* __restrict__ blk_first,
                                                          const double* __restrict__ part, double* out) {
   const int pi = blockIdx.x;
-  if (threadIdx.x != 0 || !vs[pi].active) return;
+  if (!vs[pi].active) return;
   double a[3] = {0.0, 0.0, 0.0};
-  for (int b = blk_first[pi]; b < blk_first[pi + 1]; ++b)
+  for (int b = blk_first[pi] + (int)threadIdx.x; b < blk_first[pi + 1]; b += 64)
     for (int k = 0; k < 3; ++k) a[k] += part[3 * b + k];
-  for (int k = 0; k < 3; ++k) out[3 * pi + k] = a[k];
+  for (int k = 0; k < 3; ++k)
+    for (int off = 32; off > 0; off >>= 1) a[k] += __shfl_down(a[k], off, 64);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) out[3 * pi + k] = a[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -735,6 +741,14 @@ template <>
 Engine<double>* engine_of<double>(mg_ctx* c) { return c->e64; }
 template <>
 Engine<float>* engine_of<float>(mg_ctx* c) { return c->e32; }
+
+// Finest-level size (vertices) from which a problem of a batched Krylov solve
+// applies its preconditioner with the engine's own launches: such a level
+// fills the device by itself, and the engine's marches (deeper tiles, more
+// waves per SIMD) then run its finest passes about three times faster than
+// the persistent kernel's items; smaller problems stay in the persistent
+// launch, where launch latency is what they would otherwise pay.
+constexpr long long kBOwnVertices = 1ll << 22;
 
 // Polls of one dependency wait before it gives up: the default bounds a wait
 // to about a second; the settable maximum to about a minute.
@@ -1069,6 +1083,7 @@ struct Batch : BatchBase {
   double* dvout = nullptr;             // 3 per problem
   double* dpout = nullptr;             // 3 per problem
   std::vector<cpx<T>*> xbuf, bbuf;     // inner solution and right-hand side per problem
+  std::vector<int> own;                // problems that apply their preconditioner with their own launches
   bool kready = false;
 
   int rows_items(int dim, int n) const {
@@ -1153,6 +1168,7 @@ struct Batch : BatchBase {
         double* part = hpp[i].part;
         const int cap = hpp[i].nslots_cap;
         MG_TRY(describe_prec(i, hpp[i], part, cap));
+        if (own[i]) continue;
         const long long size = (long long)engine_of<T>(ctx[i])->NL();
         for (int ph = 0; ph < hpp[i].nphase; ++ph)
           for (int t = 0; t < hpp[i].phase_items[ph]; ++t) keys.push_back({((long long)ph << 40) - size, i, ph, t});
@@ -1178,15 +1194,18 @@ struct Batch : BatchBase {
     bbuf.resize(np);
     std::vector<std::array<long long, 4>> keys;
     std::vector<int> blk_prob, blk_first(np + 1, 0);
+    own.assign(np, 0);
     for (int i = 0; i < np; ++i) {
       Engine<T>& E = *engine_of<T>(ctx[i]);
       MG_TRY(E.ensure_krylov());
+      MG_TRY(E.ensure_scratch());
       MG_TRY(describe_prec(i, hpp[i]));
       MG_TRY(dalloc(&xbuf[i], E.NL()));
       MG_TRY(dalloc(&bbuf[i], E.NL()));
       const PProb<T>& P = hpp[i];
       const long long size = (long long)E.NL();
-      for (int ph = 0; ph < P.nphase; ++ph)
+      own[i] = size >= kBOwnVertices;
+      for (int ph = 0; ph < P.nphase && !own[i]; ++ph)
         for (int t = 0; t < P.phase_items[ph]; ++t) keys.push_back({((long long)ph << 40) - size, i, ph, t});
       VSet<T>& V = hvs[i];
       std::memset(&V, 0, sizeof(V));
@@ -1219,6 +1238,7 @@ struct Batch : BatchBase {
     MG_HIP(hipMemcpy(dpp, hpp.data(), np * sizeof(PProb<T>), hipMemcpyHostToDevice));
     MG_TRY(dalloc(&dio, np));
     MG_TRY(dalloc(&dpdone, (size_t)np * kPMaxPhases + 2));
+    MG_HIP(launch_fill(dpdone, ((size_t)np * kPMaxPhases + 2) * sizeof(int), s));
     MG_TRY(dalloc(&dvs, np));
     MG_TRY(dalloc(&dblk_prob, nvblocks));
     MG_TRY(dalloc(&dblk_first, np + 1));
@@ -1262,6 +1282,14 @@ struct Batch : BatchBase {
   // One preconditioner application with the operator for every active
   // problem: io[i] set by the caller (dot 1 or 2), sums in dpout.
   int prec_apply(int dot) {
+    // problems with a finest level of kBOwnVertices or more: the engine's own
+    // launches (each fills the device), dots copied into the batch's slots
+    for (int i = 0; i < np; ++i) {
+      if (!own[i] || !hio[i].active) continue;
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      MG_TRY(E.precondition_apply_enqueue(hio[i].v, hio[i].z, hio[i].y, dot, hio[i].v2));
+      if (dot) MG_HIP(hipMemcpyAsync(dpout + 3 * i, E.red, 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     MG_TRY(select_items());
     if (npitems == 0) return MG_OK;
     MG_HIP(hipMemcpyAsync(dio, hio.data(), np * sizeof(PIO<T>), hipMemcpyHostToDevice, s));
@@ -1484,7 +1512,7 @@ struct Batch : BatchBase {
         } else {
           inner[i] = 1;
           any = 1;
-          const double it_tol = ctx[i]->p.inner_rtol > 0 ? ctx[i]->p.inner_rtol : 1e-4;
+          const double it_tol = ctx[i]->p.inner_rtol > 0 ? ctx[i]->p.inner_rtol : kInnerRtolDefault;
           tol[i] = std::is_same<T, float>::value ? it_tol : std::max(0.5 * rtol / rel[i], 1e-15);
           const mg_ctx* c = ctx[i];
           MG_HIP((launch_convert<double, T>(c->e64->NL(), c->e64->tR, bbuf[i], 1.0 / rn[i], s)));

@@ -146,6 +146,50 @@ def test_batched_precondition_apply_matches_oracle():
     batch.close()
 
 
+def test_batched_precondition_apply_large_member():
+    """A batch with a 3D level-5 member (244^3 = 14.5 M finest vertices, above
+    the 2^22 from which a member applies its preconditioner with its own
+    launches) and two small members, every autotuner configuration: the large
+    member's z and y match mg_precondition_apply of the same problem set up
+    alone to 1e-13 in the max norm (the same passes; the batch runs the march
+    instantiation that also sums the Krylov dots, whose code generation may
+    contract multiply-adds differently), and the small members, which stay in
+    the persistent launch, match the oracle (1e-12)."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_batched
+    probs = config_batched()
+    pick = [next(i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 5),
+            next(i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 3),
+            next(i for i, p in enumerate(probs) if p.dim == 2 and p.level_max == 4)]
+    sub = [probs[i] for i in pick]
+    kws = [dict(dim=p.dim, level_max=p.level_max, phi=p.phi, variant=v, omega=0.6)
+           for p, v in zip(sub, ["bpx", "hb", "bpx"])]
+    batch = mg.Batch(kws)
+    g = torch.Generator().manual_seed(77)
+    vs = [torch.randn((p.n,) * p.dim, dtype=torch.complex128, generator=g) for p in sub]
+    alone = mg.Solver(**kws[0], sweep="fused")   # a batch's members run the fused sweep
+    z_ref, y_ref = alone.precondition_apply(vs[0])
+    refs = []
+    for p, kw, v in zip(sub[1:], kws[1:], vs[1:]):
+        op = Params(dim=p.dim, level_max=p.level_max, theta=0.0, phi=p.phi, variant=kw["variant"], omega=0.6)
+        zr = O.zero_start_cycle(op, O.zero_boundary(v.numpy()))
+        refs.append((zr, op.H(zr, p.level_max)))
+    for cfg in range(mg.load_library().mg_batch_configs()):
+        batch.set_config(cfg)
+        print(f"\n[case] batched preconditioner with a 244^3 member, configuration {cfg}", flush=True)
+        zs, ys = batch.precondition_apply(vs)
+        dz = ((zs[0] - z_ref).abs().max() / z_ref.abs().max()).item()
+        dy = ((ys[0] - y_ref).abs().max() / y_ref.abs().max()).item()
+        print(f"large member against mg_precondition_apply: z {dz:.2e}, y {dy:.2e}", flush=True)
+        assert dz <= 1e-13 and dy <= 1e-13, (cfg, dz, dy)
+        for (zr, yr), z, y in zip(refs, zs[1:], ys[1:]):
+            ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
+            ey = np.linalg.norm(y.cpu().numpy() - yr) / np.linalg.norm(yr)
+            assert ez <= 1e-12 and ey <= 1e-12, (cfg, ez, ey)
+    alone.close()
+    batch.close()
+
+
 TINY = [(2, 2, 30.0, "bpx"), (2, 3, 12.0, "hb"), (2, 3, 45.0, "add"), (3, 2, 20.0, "bpx"), (3, 2, 9.0, "hb")]
 
 
