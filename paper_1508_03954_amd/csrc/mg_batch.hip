@@ -519,7 +519,7 @@ __device__ __attribute__((always_inline)) inline void prec_item(const PrecArgs<T
     double acc[3] = {0.0, 0.0, 0.0};
     for_rows<T, D>(n, tile, [&](const int j[3], long long i) {
       cpx<T> yv = czero<T>();
-      if (is_interior<D>(j, n)) yv = apply_row<T, D>(io.z, n, j, P.op[L]);
+      if (is_interior<D>(j, n)) yv = stencil_const<T, D>(io.z, n, j, P.op[L]);   // batches have constant phi
       io.y[i] = yv;
       dot_terms(A.dot, yv, io.v2[i], acc);
     });

@@ -214,39 +214,49 @@ __device__ inline T elem_stiff(int a, int b) {
 // assembled S_K stencil is replaced by the cell loop).
 template <class T, int D>
 __device__ cpx<T> stencil_var(const cpx<T>* __restrict__ x, int n, const int j[3], const OpData<T>& op) {
+  // the 3^d neighbourhood of j, loaded once (zero outside the interior);
+  // neighbour (ox, oy, oz) at index (ox + 1) + 3 (oy + 1) + 9 (oz + 1)
+  constexpr int NB = D == 3 ? 27 : 9;
+  cpx<T> xv[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int k[3] = {j[0] + q % 3 - 1, j[1] + (q / 3) % 3 - 1, D == 3 ? j[2] + q / 9 - 1 : 0};
+    xv[q] = czero<T>();
+    if (is_interior<D>(k, n)) xv[q] = x[ravel<D>(k, n)];
+  }
   cpx<T> st = czero<T>();
   if (!op.cstiff) {
-    const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-    for (int oz = zlo; oz <= zhi; ++oz)
-      for (int oy = -1; oy <= 1; ++oy)
-        for (int ox = -1; ox <= 1; ++ox) {
-          int k[3] = {j[0] + ox, j[1] + oy, j[2] + oz};
-          if (!is_interior<D>(k, n)) continue;
-          const int cls = (ox != 0) + (oy != 0) + (oz != 0);
-          st = st + stiff_weight<T, D>(cls) * x[ravel<D>(k, n)];
-        }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int cls = (q % 3 != 1) + ((q / 3) % 3 != 1) + (D == 3 ? (q / 9 != 1) : 0);
+      st = st + stiff_weight<T, D>(cls) * xv[q];
+    }
     st = cmul(op.alpha, st);
   }
   cpx<T> ms = czero<T>();
   const int nc = n - 1;
+#pragma unroll
   for (int c = 0; c < (1 << D); ++c) {
-    int loc = 0, cell[3] = {0, 0, 0};
+    // cell j - bits(c); j is its local vertex c
+    int cell[3] = {0, 0, 0};
     bool ok = true;
     for (int a = 0; a < D; ++a) {
-      const int bit = (c >> a) & 1;   // position of j inside the cell along a
-      loc |= bit << a;
-      cell[a] = j[a] - bit;
+      cell[a] = j[a] - ((c >> a) & 1);
       if (cell[a] < 0 || cell[a] >= nc) ok = false;
     }
     if (!ok) continue;
     cpx<T> am = czero<T>(), ak = czero<T>();
+#pragma unroll
     for (int kk = 0; kk < (1 << D); ++kk) {
-      int v[3] = {0, 0, 0};
-      for (int a = 0; a < D; ++a) v[a] = cell[a] + ((kk >> a) & 1);
-      if (!is_interior<D>(v, n)) continue;
-      const cpx<T> xv = x[ravel<D>(v, n)];
-      am = am + elem_mass<T, D>(loc, kk) * xv;
-      if (op.cstiff) ak = ak + elem_stiff<T, D>(loc, kk) * xv;
+      // local vertex kk of the cell sits at offset bits(kk) - bits(c) from j
+      int q = 0, stride = 1;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        q += (((kk >> a) & 1) - ((c >> a) & 1) + 1) * stride;
+        stride *= 3;
+      }
+      am = am + elem_mass<T, D>(c, kk) * xv[q];
+      if (op.cstiff) ak = ak + elem_stiff<T, D>(c, kk) * xv[q];
     }
     const long long ci = ravel<D>(cell, nc);
     ms = ms + cmul(op.cmass[ci], am);

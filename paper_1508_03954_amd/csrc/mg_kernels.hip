@@ -77,8 +77,10 @@ __device__ inline void block_sumN(double (&v)[N], double* partials) {
 }
 
 // ---------------------------------------------------------------------------
+// (256-thread blocks, as every row kernel is launched: the bound lets the
+// per-cell path keep its 3^d neighbourhood in registers.)
 template <class T, int D>
-__global__ void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
+__global__ __launch_bounds__(256) void k_apply(OpData<T> op, const cpx<T>* __restrict__ x, cpx<T>* __restrict__ y) {
   MG_ROWS(D, op.n) {
     int j[3];
     long long i;
@@ -152,8 +154,8 @@ __global__ void k_uhat(int n, const cpx<T>* __restrict__ u, const cpx<T>* __rest
 
 // r = b - H x (interior), optional norm partials.
 template <class T, int D>
-__global__ void k_resid(OpData<T> op, const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ x,
-                        cpx<T>* __restrict__ r, double* partials) {
+__global__ __launch_bounds__(256) void k_resid(OpData<T> op, const cpx<T>* __restrict__ b, const cpx<T>* __restrict__ x,
+                                               cpx<T>* __restrict__ r, double* partials) {
   double s2 = 0, mx = 0;
   MG_ROWS(D, op.n) {
     int j[3];
