@@ -288,7 +288,8 @@ int mg_time_sweeps(mg_ctx* ctx, int enable);
 int mg_sweep_time(mg_ctx* ctx, double* total_ms, int* count);
 
 /* ---------------------------------------------------------------------------
- * Batched cycles (many independent problems, one persistent launch per cycle).
+ * Batched cycles (many independent problems; one persistent launch per cycle
+ * for the problems below 2^22 finest vertices).
  *
  * The multilevel cycle of the method (Section 5, the pipelined additive
  * schemes tdAdd and tdBPX) applied to a set of independent problems --
@@ -301,8 +302,11 @@ int mg_sweep_time(mg_ctx* ctx, double* total_ms, int* count);
  * phi, level_max > level_min, level_max <= 7, an iteration-independent omega
  * scheme (not MG_OMEGA_TRANSITION or MG_OMEGA_TWO_PHASE); all problems share
  * one precision.
- * Problems are advanced concurrently: a call overlaps the coarse levels of
- * small problems with the finest sweeps of large ones. */
+ * Problems below 2^22 finest vertices are advanced concurrently in one
+ * persistent launch per cycle, which overlaps their coarse levels with the
+ * finest sweeps of others; a problem of 2^22 finest vertices or more fills the
+ * device by itself and runs mg_cycle's own launches (its fused tile chosen by
+ * its own autotuner, 3D default: 4 coarse rows, 28 planes, y-band order). */
 typedef struct mg_batch mg_batch;
 
 /* Creates `count` contexts from params[0..count-1] (sweep forced to FUSED) on
@@ -311,8 +315,9 @@ int mg_batch_setup(const mg_params* params, int count, void* hip_stream, mg_batc
 void mg_batch_destroy(mg_batch* batch);
 
 /* The context of problem i (owned by the batch; do not mg_destroy it).  Its
- * fused tile (mg_tiles) is kept equal to the batch's tiling of that problem,
- * so mg_cycle on it reproduces a batched cycle exactly. */
+ * fused tile (mg_tiles) is kept equal to the batch's tiling of that problem
+ * (for a large problem: the tile it runs with), so mg_cycle on it reproduces
+ * a batched cycle exactly. */
 int mg_batch_problem(mg_batch* batch, int i, mg_ctx** ctx);
 
 /* ncycles batched cycles.  res_h, when not NULL, receives ncycles * count
@@ -322,8 +327,10 @@ int mg_batch_problem(mg_batch* batch, int i, mg_ctx** ctx);
  * is then undefined). */
 int mg_batch_cycle(mg_batch* batch, int ncycles, double* res_h);
 
-/* Times every batch configuration (fused z extent per dimension, queue order)
- * with `reps` batched cycles each and keeps the fastest.  The cycles run on
+/* Autotunes the fused tile of each problem of 2^22 finest vertices or more
+ * (mg_autotune, state untouched), then times every batch configuration (fused
+ * z extent per dimension, queue order) with `reps` batched cycles each and
+ * keeps the fastest.  The cycles run on
  * the contexts' current data and advance them: reset the state afterwards.
  * config / us_per_cycle may be NULL; times_us, when not NULL, receives the
  * average microseconds per batched cycle of each of the mg_batch_configs()

@@ -749,6 +749,10 @@ Engine<float>* engine_of<float>(mg_ctx* c) { return c->e32; }
 // the persistent kernel's items; smaller problems stay in the persistent
 // launch, where launch latency is what they would otherwise pay.
 constexpr long long kBOwnVertices = 1ll << 22;
+// Their 3D fused-sweep tile: 4 coarse rows of 2 rows per thread, 28 coarse
+// planes, y-band block order, prefetch depth 3 (the autotuner's choice for
+// the 244^3 and 730^3 grids); mg_batch_autotune retunes it per problem.
+constexpr int kBOwnTile3 = 20;
 
 // Polls of one dependency wait before it gives up: the default bounds a wait
 // to about a second; the settable maximum to about a minute.
@@ -839,7 +843,7 @@ struct Batch : BatchBase {
     // cycle on it partitions the finest sweep (and its norm) identically
     const int same = E.dim == 3 ? fused_tile_index(3, 2, 2, kBZc3[zc3]) : fused_tile_index(2, 0, 0, kBZc2[zc2]);
     if (same < 0) return fail(MG_EINVAL, "batch tiling has no standalone counterpart");
-    E.set_tile(same);
+    if (!own[i]) E.set_tile(same);
     const int nL = E.lv[E.L].n, nc = E.lv[E.L - 1].n;
     int k = 0;
     auto rows_items = [&](int n) { const int rows = E.dim == 3 ? n * n : n; return (rows + kBRows - 1) / kBRows; };
@@ -892,6 +896,7 @@ struct Batch : BatchBase {
     int maxf = 0;
     for (int i = 0; i < np; ++i) maxf = std::max(maxf, hp[i].L - hp[i].lmin);
     for (int i = 0; i < np; ++i) {
+      if (own[i]) continue;   // cycled with the engine's own launches
       const BProb<T>& P = hp[i];
       const long long size = (long long)P.lv[P.L].n * P.lv[P.L].n * (P.dim == 3 ? P.lv[P.L].n : 1);
       for (int ph = 0; ph < P.nphase; ++ph) {
@@ -966,6 +971,12 @@ struct Batch : BatchBase {
       MG_TRY(mg_setup(&q, stream, &c));
       ctx.push_back(c);
     }
+    own.assign(np, 0);
+    for (int i = 0; i < np; ++i) {
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      own[i] = (long long)E.NL() >= kBOwnVertices;
+      if (own[i] && E.dim == 3) E.set_tile(kBOwnTile3);
+    }
     hp.resize(np);
     for (int i = 0; i < np; ++i) MG_TRY(describe(i, hp[i]));
     MG_TRY(dalloc(&dp, np));
@@ -1003,7 +1014,11 @@ struct Batch : BatchBase {
       hp[i].w[1] = E.w[1];
     }
     MG_HIP(hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(BProb<T>), hipMemcpyHostToDevice, s));
-    for (int k = 0; k < ncycles; ++k) {
+    // the large problems: the engine's own cycles (fused sweep with its tile,
+    // coarse chain), norms in the engine's history
+    for (int i = 0; i < np; ++i)
+      if (own[i]) MG_TRY(engine_of<T>(ctx[i])->cycles(ncycles, nullptr, nullptr));
+    for (int k = 0; k < ncycles && nitems > 0; ++k) {
       // completion counters and the queue head (not the error word after them)
       MG_HIP(launch_fill(ddone, ((size_t)np * kBMaxPhases + 1) * sizeof(int), s));
       BatchArgs<T> A;
@@ -1022,14 +1037,21 @@ struct Batch : BatchBase {
     }
     int err = 0;
     MG_HIP(hipMemcpyAsync(&err, dq + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    std::vector<double> h;
+    std::vector<double> h, ho;
     if (res) {
       h.resize((size_t)2 * np * ncycles);
-      MG_HIP(hipMemcpyAsync(h.data(), dhist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      ho.resize((size_t)2 * np * ncycles);
+      if (nitems > 0) MG_HIP(hipMemcpyAsync(h.data(), dhist, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      for (int i = 0; i < np; ++i)
+        if (own[i])
+          MG_HIP(hipMemcpyAsync(ho.data() + (size_t)2 * ncycles * i, engine_of<T>(ctx[i])->hist,
+                                (size_t)2 * ncycles * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     MG_HIP(hipStreamSynchronize(s));
-    // the engines advance with the device state
+    // the engines advance with the device state (the own problems' engines
+    // have advanced themselves)
     for (int i = 0; i < np; ++i) {
+      if (own[i]) continue;
       Engine<T>& E = *engine_of<T>(ctx[i]);
       if (ncycles & 1) {
         E.cur = 1 - E.cur;
@@ -1042,7 +1064,8 @@ struct Batch : BatchBase {
       for (int k = 0; k < ncycles; ++k)
         for (int i = 0; i < np; ++i) {
           Engine<T>& E = *engine_of<T>(ctx[i]);
-          res[(size_t)k * np + i] = std::sqrt(E.hnorm_scale() * h[(size_t)2 * (np * k + i)]);
+          const double h2 = own[i] ? ho[(size_t)2 * ncycles * i + 2 * k] : h[(size_t)2 * (np * k + i)];
+          res[(size_t)k * np + i] = std::sqrt(E.hnorm_scale() * h2);
         }
     }
     return MG_OK;
@@ -1083,7 +1106,7 @@ struct Batch : BatchBase {
   double* dvout = nullptr;             // 3 per problem
   double* dpout = nullptr;             // 3 per problem
   std::vector<cpx<T>*> xbuf, bbuf;     // inner solution and right-hand side per problem
-  std::vector<int> own;                // problems that apply their preconditioner with their own launches
+  std::vector<int> own;                // problems of kBOwnVertices or more: the engine's own launches
   bool kready = false;
 
   int rows_items(int dim, int n) const {
@@ -1194,7 +1217,6 @@ struct Batch : BatchBase {
     bbuf.resize(np);
     std::vector<std::array<long long, 4>> keys;
     std::vector<int> blk_prob, blk_first(np + 1, 0);
-    own.assign(np, 0);
     for (int i = 0; i < np; ++i) {
       Engine<T>& E = *engine_of<T>(ctx[i]);
       MG_TRY(E.ensure_krylov());
@@ -1204,7 +1226,6 @@ struct Batch : BatchBase {
       MG_TRY(dalloc(&bbuf[i], E.NL()));
       const PProb<T>& P = hpp[i];
       const long long size = (long long)E.NL();
-      own[i] = size >= kBOwnVertices;
       for (int ph = 0; ph < P.nphase && !own[i]; ++ph)
         for (int t = 0; t < P.phase_items[ph]; ++t) keys.push_back({((long long)ph << 40) - size, i, ph, t});
       VSet<T>& V = hvs[i];
@@ -1559,6 +1580,9 @@ struct Batch : BatchBase {
     MG_HIP(hipEventCreate(&e1));
     int bcfg = 0;
     double bt = 1e300;
+    // the large problems keep the fused-sweep tile their own autotuner picks
+    for (int i = 0; i < np; ++i)
+      if (own[i]) MG_TRY(engine_of<T>(ctx[i])->autotune(reps, nullptr, nullptr, nullptr));
     const int n3 = (int)(sizeof(kBZc3) / sizeof(kBZc3[0])), n2 = (int)(sizeof(kBZc2) / sizeof(kBZc2[0]));
     for (int cfg = 0; cfg < n3 * n2 * 2; ++cfg) {
       MG_TRY(configure(cfg % n3, (cfg / n3) % n2, cfg / (n3 * n2)));
