@@ -753,6 +753,9 @@ constexpr long long kBOwnVertices = 1ll << 22;
 // planes, y-band block order, prefetch depth 3 (the autotuner's choice for
 // the 244^3 and 730^3 grids); mg_batch_autotune retunes it per problem.
 constexpr int kBOwnTile3 = 20;
+// Side streams the large problems' cycles are spread over (with the batch
+// stream, four hardware queues).
+constexpr int kBSideStreams = 3;
 
 // Polls of one dependency wait before it gives up: the default bounds a wait
 // to about a second; the settable maximum to about a minute.
@@ -792,6 +795,62 @@ struct Batch : BatchBase {
   ~Batch() override {
     for (void* p : owned) (void)hipFree(p);
     for (mg_ctx* c : ctx) mg_destroy(c);
+    for (hipEvent_t e : side_ev) (void)hipEventDestroy(e);
+    for (hipStream_t q : side) (void)hipStreamDestroy(q);
+  }
+
+  // Side streams of the large problems' own cycles (default priority): a
+  // call forks them from the batch stream with an event and joins them back,
+  // so one problem's latency-bound coarse launches overlap another's sweep
+  // and the persistent launch of the small problems.
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> side_ev;   // [0]: fork; [1 + q]: join of side stream q
+
+  int ensure_side(int nown) {
+    const int want = std::min(nown, kBSideStreams);
+    while ((int)side.size() < want) {
+      hipStream_t q;
+      MG_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      side.push_back(q);
+    }
+    while ((int)side_ev.size() < 1 + (int)side.size()) {
+      hipEvent_t e;
+      MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      side_ev.push_back(e);
+    }
+    return MG_OK;
+  }
+
+  // ncycles of every large problem on the side streams (round robin), forked
+  // from and joined back into the batch stream by the caller's two calls.
+  int own_cycles_fork(int ncycles, int* nused) {
+    int nown = 0;
+    for (int i = 0; i < np; ++i) nown += own[i];
+    *nused = 0;
+    if (!nown) return MG_OK;
+    MG_TRY(ensure_side(nown));
+    const int nq = (int)side.size();
+    MG_HIP(hipEventRecord(side_ev[0], s));
+    for (int q = 0; q < nq; ++q) MG_HIP(hipStreamWaitEvent(side[q], side_ev[0], 0));
+    int k = 0;
+    for (int i = 0; i < np; ++i) {
+      if (!own[i]) continue;
+      Engine<T>& E = *engine_of<T>(ctx[i]);
+      E.s = side[k++ % nq];
+      const int rc = E.cycles(ncycles, nullptr, nullptr);
+      E.s = s;
+      MG_TRY(rc);
+    }
+    *nused = std::min(nown, nq);
+    return MG_OK;
+  }
+
+  int own_cycles_join(int nused) {
+    for (int q = 0; q < nused; ++q) {
+      MG_HIP(hipEventRecord(side_ev[1 + q], side[q]));
+      MG_HIP(hipStreamWaitEvent(s, side_ev[1 + q], 0));
+    }
+    return MG_OK;
   }
 
   template <class P>
@@ -1015,9 +1074,9 @@ struct Batch : BatchBase {
     }
     MG_HIP(hipMemcpyAsync(dp, hp.data(), hp.size() * sizeof(BProb<T>), hipMemcpyHostToDevice, s));
     // the large problems: the engine's own cycles (fused sweep with its tile,
-    // coarse chain), norms in the engine's history
-    for (int i = 0; i < np; ++i)
-      if (own[i]) MG_TRY(engine_of<T>(ctx[i])->cycles(ncycles, nullptr, nullptr));
+    // coarse chain) on the side streams, norms in the engine's history
+    int nside = 0;
+    MG_TRY(own_cycles_fork(ncycles, &nside));
     for (int k = 0; k < ncycles && nitems > 0; ++k) {
       // completion counters and the queue head (not the error word after them)
       MG_HIP(launch_fill(ddone, ((size_t)np * kBMaxPhases + 1) * sizeof(int), s));
@@ -1035,6 +1094,7 @@ struct Batch : BatchBase {
       hipLaunchKernelGGL(k_batch_cycle<T>, dim3(grid), dim3(kBThreads), 0, s, A);
       MG_HIP(hipGetLastError());
     }
+    MG_TRY(own_cycles_join(nside));
     int err = 0;
     MG_HIP(hipMemcpyAsync(&err, dq + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     std::vector<double> h, ho;
@@ -1304,13 +1364,34 @@ struct Batch : BatchBase {
   // problem: io[i] set by the caller (dot 1 or 2), sums in dpout.
   int prec_apply(int dot) {
     // problems with a finest level of kBOwnVertices or more: the engine's own
-    // launches (each fills the device), dots copied into the batch's slots
-    for (int i = 0; i < np; ++i) {
-      if (!own[i] || !hio[i].active) continue;
-      Engine<T>& E = *engine_of<T>(ctx[i]);
-      MG_TRY(E.precondition_apply_enqueue(hio[i].v, hio[i].z, hio[i].y, dot, hio[i].v2));
-      if (dot) MG_HIP(hipMemcpyAsync(dpout + 3 * i, E.red, 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // launches on the side streams (forked from and joined back into the
+    // batch stream), dots copied into the batch's slots
+    int nown = 0, nused = 0;
+    for (int i = 0; i < np; ++i) nown += own[i] && hio[i].active;
+    if (nown) {
+      MG_TRY(ensure_side(nown));
+      nused = std::min(nown, (int)side.size());
+      MG_HIP(hipEventRecord(side_ev[0], s));
+      for (int q = 0; q < nused; ++q) MG_HIP(hipStreamWaitEvent(side[q], side_ev[0], 0));
+      int k = 0;
+      for (int i = 0; i < np; ++i) {
+        if (!own[i] || !hio[i].active) continue;
+        Engine<T>& E = *engine_of<T>(ctx[i]);
+        hipStream_t q = side[k++ % nused];
+        E.s = q;
+        const int rc = E.precondition_apply_enqueue(hio[i].v, hio[i].z, hio[i].y, dot, hio[i].v2);
+        E.s = s;
+        MG_TRY(rc);
+        if (dot) MG_HIP(hipMemcpyAsync(dpout + 3 * i, E.red, 3 * sizeof(double), hipMemcpyDeviceToDevice, q));
+      }
     }
+    const int rc = prec_apply_small(dot);
+    MG_TRY(own_cycles_join(nused));
+    return rc;
+  }
+
+  // The persistent launch of the problems below kBOwnVertices.
+  int prec_apply_small(int dot) {
     MG_TRY(select_items());
     if (npitems == 0) return MG_OK;
     MG_HIP(hipMemcpyAsync(dio, hio.data(), np * sizeof(PIO<T>), hipMemcpyHostToDevice, s));
