@@ -84,6 +84,7 @@ constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0, 1},  {2, 2, 14, 0, 1}, {2, 2, 21,
                                   {4, 2, 28, 2, 3}, {2, 2, 28, 2, 3}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
+static_assert(kNumTiles3 == 22, "launch_fused has one case per entry of kTiles3");
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 
 int fused_tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
@@ -119,14 +120,19 @@ int fused_partials_blocks(int dim, int n, int tile) {
 
 // The sweep is launched through hipExtLaunchKernel: the optional events t0 / t1
 // take the kernel's own start and end times (nullptr: no timing).
+// (The case of launch_fused must instantiate the shape its tile entry names:
+// the grid comes from the entry, the block's coverage from the template.)
 template <class T, int TYC, int RPT, int ZC, int PF = 1>
-static void launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+static hipError_t launch3(const FusedArgs<T>& a0, dim3 g, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  const TileShape3 e = kTiles3[a0.tile];
+  if (e.tyc != TYC || e.rpt != RPT || e.zc != ZC || e.pf != PF) return hipErrorInvalidValue;
   const dim3 b(F3<T, TYC, RPT, ZC, false>::NT);
   FusedArgs<T> a = a0;
   a.order = kTiles3[a0.tile].order;
   if (a.variant == 2) hipExtLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 2, PF>), g, b, 0, s, t0, t1, 0, a);
   else if (a.variant == 1) hipExtLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 1, PF>), g, b, 0, s, t0, t1, 0, a);
   else hipExtLaunchKernelGGL((k_fused3<T, TYC, RPT, ZC, 0, PF>), g, b, 0, s, t0, t1, 0, a);
+  return hipSuccess;
 }
 
 template <class T, int ZC>
@@ -143,30 +149,33 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s, hipEvent_
   if (dim == 3 && a.spill == nullptr) return hipErrorInvalidValue;
   const dim3 g = fused_grid(dim, a.n, a.tile);
   if (dim == 3) {
+    hipError_t e;
     switch (a.tile) {
-      case 0: launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
-      case 1: launch3<T, 2, 2, 14>(a, g, s, t0, t1); break;
-      case 2: launch3<T, 2, 2, 21>(a, g, s, t0, t1); break;
-      case 3: launch3<T, 2, 2, 27>(a, g, s, t0, t1); break;
-      case 4: launch3<T, 2, 2, 28>(a, g, s, t0, t1); break;
-      case 5: launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
-      case 6: launch3<T, 4, 2, 21>(a, g, s, t0, t1); break;
-      case 7: launch3<T, 4, 2, 28>(a, g, s, t0, t1); break;
-      case 8: launch3<T, 2, 1, 14>(a, g, s, t0, t1); break;
-      case 9: launch3<T, 2, 1, 21>(a, g, s, t0, t1); break;
-      case 10: launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
-      case 11: launch3<T, 2, 2, 21>(a, g, s, t0, t1); break;
-      case 12: launch3<T, 4, 2, 28, 2>(a, g, s, t0, t1); break;
-      case 13: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
-      case 14: launch3<T, 2, 2, 28, 2>(a, g, s, t0, t1); break;
-      case 15: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
-      case 16: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
-      case 17: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
-      case 18: launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
-      case 19: launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
-      case 20: launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
-      default: launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 0: e = launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
+      case 1: e = launch3<T, 2, 2, 14>(a, g, s, t0, t1); break;
+      case 2: e = launch3<T, 2, 2, 21>(a, g, s, t0, t1); break;
+      case 3: e = launch3<T, 2, 2, 27>(a, g, s, t0, t1); break;
+      case 4: e = launch3<T, 2, 2, 28>(a, g, s, t0, t1); break;
+      case 5: e = launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
+      case 6: e = launch3<T, 4, 2, 21>(a, g, s, t0, t1); break;
+      case 7: e = launch3<T, 4, 2, 28>(a, g, s, t0, t1); break;
+      case 8: e = launch3<T, 2, 1, 14>(a, g, s, t0, t1); break;
+      case 9: e = launch3<T, 2, 1, 21>(a, g, s, t0, t1); break;
+      case 10: e = launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
+      case 11: e = launch3<T, 2, 2, 21>(a, g, s, t0, t1); break;
+      case 12: e = launch3<T, 4, 2, 28, 2>(a, g, s, t0, t1); break;
+      case 13: e = launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 14: e = launch3<T, 2, 2, 28, 2>(a, g, s, t0, t1); break;
+      case 15: e = launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 16: e = launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 17: e = launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 18: e = launch3<T, 2, 2, 9>(a, g, s, t0, t1); break;
+      case 19: e = launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
+      case 20: e = launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 21: e = launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      default: return hipErrorInvalidValue;   // every entry of kTiles3 has its case above
     }
+    if (e != hipSuccess) return e;
   } else {
     switch (a.tile) {
       case 0: launch2<T, 2>(a, g, s, t0, t1); break;
