@@ -68,7 +68,8 @@ enum { MG_STATIONARY = 0, MG_BICGSTAB = 1 };
  * GALERKIN: b_(l-1) = R r_l + H_(l-1) u_(l-1) (the paper's Lemma 2), valid
  *           when R H_l P = H_(l-1): constant phi and uniform rotation.  The
  *           coarse b slot then holds R r_l and the coarse residual is read
- *           from it directly;
+ *           from it directly, so the coarse iterates u_l (l < level_max) are
+ *           read by no step and are not formed;
  * AUTO:     GALERKIN for constant phi, FAS otherwise. */
 enum { MG_RESTRICT_AUTO = 0, MG_RESTRICT_FAS = 1, MG_RESTRICT_GALERKIN = 2 };
 
@@ -174,7 +175,8 @@ int mg_flush(mg_ctx* ctx, mg_c128* u_out);
  * Finest level: MG_FIELD_U returns the folded iterate u + sc (the finest
  * smoothing update is applied eagerly, only the coarse correction is
  * pending); MG_FIELD_SC/SF/SI return zeros.  Coarse levels with the GALERKIN
- * form: MG_FIELD_B returns the restricted residual R r_(l+1) (= b_l - H_l u_l). */
+ * form: MG_FIELD_B returns the restricted residual R r_(l+1) (= b_l - H_l u_l)
+ * and MG_FIELD_U returns zeros (the coarse iterates are not formed). */
 int mg_get_level(mg_ctx* ctx, int level, int field, mg_c128* out);
 
 /* z = B v: one additive cycle from a zero start with right-hand side v

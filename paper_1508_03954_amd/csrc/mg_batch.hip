@@ -878,7 +878,7 @@ struct Batch : BatchBase {
     for (int l = E.lmin; l <= E.L; ++l) {
       BLevel<T>& v = P.lv[l];
       v.n = E.lv[l].n;
-      v.u = E.lv[l].u;
+      v.u = l < E.L ? E.coarse_u(l) : E.lv[l].u;
       v.b = E.lv[l].b;
       v.sc = E.lv[l].sc;
       v.sf = E.lv[l].sf;

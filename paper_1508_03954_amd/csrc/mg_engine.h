@@ -373,9 +373,14 @@ struct Engine {
     return zero_helpers();
   }
 
+  // Coarse iterate of level l < L, or nullptr in the Galerkin form: there the
+  // coarse b slot holds the restricted residual itself, so no step reads the
+  // coarse iterates and they are not formed.
+  cpx<T>* coarse_u(int l) const { return galerkin ? nullptr : lv[l].u; }
+
   int set_solution(const cpx<T>* u) {
     MG_HIP(launch_zero_boundary_copy<T>(dim, lv[L].n, u, w[cur], mk(T(1), T(0)), s));
-    for (int l = L; l > lmin; --l) {
+    for (int l = L; l > lmin && !galerkin; --l) {
       const cpx<T>* src = l == L ? w[cur] : lv[l].u;
       MG_HIP(launch_inject<T>(dim, lv[l - 1].n, src, lv[l - 1].u, s));
     }
@@ -403,7 +408,7 @@ struct Engine {
     for (int k = 0; k < nl; ++k) {
       const Level<T>& v = lv[lmin + k];
       a.lv[k].n = v.n;
-      a.lv[k].u = v.u;
+      a.lv[k].u = coarse_u(lmin + k);
       a.lv[k].b = v.b;
       a.lv[k].sc = v.sc;
       a.lv[k].sf = v.sf;
@@ -426,8 +431,8 @@ struct Engine {
     for (int l = l0; l < L; ++l) {
       Level<T>& v = lv[l];
       const bool hc = l > lmin;
-      MG_HIP(launch_pre<T>(dim, v.n, v.u, v.sc, v.sf, hc ? lv[l - 1].sc : nullptr, hc ? lv[l - 1].si : nullptr,
-                           hc ? 1 : 0, variant == MG_BPX ? 1 : 0, s));
+      MG_HIP(launch_pre<T>(dim, v.n, coarse_u(l), v.sc, v.sf, hc ? lv[l - 1].sc : nullptr,
+                           hc ? lv[l - 1].si : nullptr, hc ? 1 : 0, variant == MG_BPX ? 1 : 0, s));
     }
     return MG_OK;
   }
@@ -625,7 +630,7 @@ struct Engine {
       return nullptr;
     }
     switch (f) {
-      case MG_FIELD_U: return v.u;
+      case MG_FIELD_U: return coarse_u(level);
       case MG_FIELD_B: return v.b;
       case MG_FIELD_SC: return v.sc;
       case MG_FIELD_SF: return v.sf;

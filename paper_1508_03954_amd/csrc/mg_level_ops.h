@@ -7,6 +7,8 @@ namespace mg {
 
 // Coarse-level pre-phase (descent of tdAdd / tdBPX) at vertex j:
 //   sc += P sc_c ;  BPX: sc -= P si_c off c-points ;  u += sc + sf.
+// u == nullptr: the coarse iterate is not formed (the Galerkin form of the
+// coarse right-hand side never reads it), and sf is not read either.
 template <class T, int D>
 __device__ inline void pre_vertex(int n, const int j[3], long long i, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc,
                                   const cpx<T>* __restrict__ sf, const cpx<T>* __restrict__ scc,
@@ -19,7 +21,7 @@ __device__ inline void pre_vertex(int n, const int j[3], long long i, cpx<T>* __
     if (bpx && !is_cpoint<D>(j)) s = s - prolong_at<T, D>(sic, nc, j);
     sc[i] = s;
   }
-  u[i] = u[i] + s + sf[i];
+  if (u) u[i] = u[i] + s + sf[i];
 }
 
 // Post-phase pointwise part at vertex j: s = omega r / D, sc = s (0 at c-points

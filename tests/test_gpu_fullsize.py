@@ -45,10 +45,12 @@ def compare_state(s, pipe, p, k, tol=1e-12):
     for lev in range(p.level_min, L + 1):
         for field in ("u", "b", "sc", "sf", "si"):
             got = to_np(s.get_level(lev, field))
+            if lev < L and field == "u":
+                # the Galerkin form does not form coarse iterates (mg_get_level gives zeros)
+                assert not np.any(got), (k, lev)
+                continue
             if lev == L:
                 ref = {"u": pipe.u[L] + pipe.sc[L], "b": pipe.b[L]}.get(field, np.zeros_like(got))
-            elif field == "u":
-                ref = pipe.u[lev]
             else:
                 ref = chain[lev][field]
             if not np.any(ref):
