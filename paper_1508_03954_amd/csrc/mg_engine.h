@@ -25,6 +25,12 @@ namespace mg {
 // because the inner solves stall well above their target.
 constexpr double kInnerRtolDefault = 0.3;
 
+// Coarse levels of at least this many vertices per axis (3D) take the
+// backtracking as a streaming update pass plus the restriction march instead
+// of k_post_galerkin, whose gathered restriction support runs at about 40 % of
+// the streaming rate on such a level (244^3: 221 µs).
+constexpr int kPostSplitMinN = 244;
+
 inline thread_local std::string g_err;
 
 inline int fail(int code, const std::string& msg) {
@@ -495,6 +501,15 @@ struct Engine {
       const complex<double> wl = omega_level(scheme, omega, omega_L, L - l, iter);
       const cpx<T>* r;
       if (galerkin && hcc) {
+        if (dim == 3 && spill && v.n >= kPostSplitMinN) {
+          // a large level: the pointwise update as one streaming pass, then
+          // R of its b slot by the restriction march (the seam array is free
+          // once the finest sweep's seam pass has run)
+          MG_HIP(launch_update<T>(dim, v.op, v.b, to_c<T>(wl), variant != MG_ADD ? 1 : 0, nullptr, v.sc, v.sf,
+                                  variant == MG_ADD ? cc->sf : nullptr, variant == MG_BPX ? cc->si : nullptr, s));
+          MG_HIP(launch_restrict3<T>(cc->n, v.b, cc->b, spill, s));
+          continue;
+        }
         MG_HIP(launch_post_galerkin<T>(dim, v.op, v.b, to_c<T>(wl), variant != MG_ADD ? 1 : 0, v.sc, v.sf, cc->b,
                                        variant == MG_ADD ? cc->sf : nullptr, variant == MG_BPX ? cc->si : nullptr, s));
         continue;

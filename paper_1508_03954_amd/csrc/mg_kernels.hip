@@ -117,6 +117,76 @@ __global__ __launch_bounds__(256) void k_pre_flat3(int n, cpx<T>* __restrict__ u
   }
 }
 
+// The same descent on a large 3D level as a march along z: a wavefront takes
+// 64 vertices of one row and a chunk of kPreTz planes.  P is separable, so a
+// lane interpolates its coarse corners in x and y once per coarse plane (four
+// loads per coarse array) and keeps the two coarse planes that bracket its z
+// in registers: a fine vertex then costs its own sc (and u, sf) and no
+// gathered load.  Same values as pre_vertex up to the order of the additions.
+constexpr int kPreTz = 8;
+constexpr int kPreMarchMinN = 244;   // levels of 244^3 vertices and more (rows of >= 4 wavefronts)
+
+template <class T>
+__device__ inline cpx<T> pre_xy_interp(const cpx<T>* __restrict__ v, int nc, int mz, const long long cidx[4],
+                                       const T cw[4]) {
+  const long long base = (long long)mz * nc * nc;
+  cpx<T> acc = czero<T>();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc = acc + cw[k] * v[base + cidx[k]];
+  return acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pre_march3(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc,
+                                                    const cpx<T>* __restrict__ sf, const cpx<T>* __restrict__ scc,
+                                                    const cpx<T>* __restrict__ sic, int bpx) {
+  const int nc = (n - 1) / 3 + 1;
+  const int x = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  const int nzc = (n + kPreTz - 1) / kPreTz;
+  for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
+       t += gridDim.y * 4) {
+    const int y = t % n, zs = (t / n) * kPreTz, ze = min(zs + kPreTz, n);
+    // the descent leaves non-interior vertices alone
+    if (x < 1 || x > n - 2 || y < 1 || y > n - 2) continue;
+    const int z0 = max(zs, 1), z1 = min(ze, n - 1);
+    if (z0 >= z1) continue;
+    // x and y corners (the second with weight 0 on a coarse line; its index
+    // stays inside the coarse grid for an interior vertex)
+    const int mx = x / 3, qx = x % 3, my = y / 3, qy = y % 3;
+    const T wx1 = T(qx) / T(3), wx0 = qx == 0 ? T(1) : T(1) - wx1;
+    const T wy1 = T(qy) / T(3), wy0 = qy == 0 ? T(1) : T(1) - wy1;
+    const long long cidx[4] = {(long long)my * nc + mx, (long long)my * nc + mx + 1, (long long)(my + 1) * nc + mx,
+                               (long long)(my + 1) * nc + mx + 1};
+    const T cwt[4] = {wy0 * wx0, wy0 * wx1, wy1 * wx0, wy1 * wx1};
+    const bool cxy = qx == 0 && qy == 0;
+    int mz = z0 / 3;
+    cpx<T> s0 = pre_xy_interp(scc, nc, mz, cidx, cwt), s1 = pre_xy_interp(scc, nc, mz + 1, cidx, cwt);
+    cpx<T> i0 = czero<T>(), i1 = czero<T>();
+    if (bpx) {
+      i0 = pre_xy_interp(sic, nc, mz, cidx, cwt);
+      i1 = pre_xy_interp(sic, nc, mz + 1, cidx, cwt);
+    }
+    for (int z = z0; z < z1; ++z) {
+      if (z / 3 != mz) {   // the next coarse interval: shift the bracket by one plane
+        mz = z / 3;
+        s0 = s1;
+        s1 = pre_xy_interp(scc, nc, mz + 1, cidx, cwt);
+        if (bpx) {
+          i0 = i1;
+          i1 = pre_xy_interp(sic, nc, mz + 1, cidx, cwt);
+        }
+      }
+      const int qz = z % 3;
+      const T wz1 = T(qz) / T(3), wz0 = qz == 0 ? T(1) : T(1) - wz1;
+      const long long e = ((long long)z * n + y) * n + x;
+      cpx<T> v = sc[e] + (wz0 * s0 + wz1 * s1);
+      if (bpx && !(cxy && qz == 0)) v = v - (wz0 * i0 + wz1 * i1);
+      sc[e] = v;
+      if (u) u[e] = u[e] + v + sf[e];
+    }
+  }
+}
+
 // Finest-level pre-phase on the folded iterate w = u + sc:
 //   u = w + P sc_c (- P si_c off c-points for BPX), written to a second buffer.
 template <class T, int D>
@@ -740,6 +810,12 @@ hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y
 template <class T>
 hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
                       const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s) {
+  if (dim == 3 && has_coarse && n >= kPreMarchMinN) {
+    const long long items = (long long)n * ((n + kPreTz - 1) / kPreTz);
+    const dim3 g((unsigned)((n + 63) / 64), (unsigned)std::min<long long>((items + 3) / 4, 65535));
+    hipLaunchKernelGGL(k_pre_march3<T>, g, 256, 0, s, n, u, sc, sf, scc, sic, bpx);
+    return hipGetLastError();
+  }
   if (dim == 3 && n <= kFastDivMaxN && n % 64 != 0) {
     const long long N = (long long)n * n * n;
     hipLaunchKernelGGL(k_pre_flat3<T>, dim3((unsigned)((N + 255) / 256)), 256, 0, s, n, u, sc, sf, scc, sic, has_coarse,

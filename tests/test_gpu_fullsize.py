@@ -172,7 +172,11 @@ def test_3d_level6_fused_sweep_sampled():
         finest pre-phase u = w + P sc_5 - P si_5 (off c-points).
     Per sampled coarse vertex m (13^3 fine window around 3m): r = b - H u,
     s = omega r / D, w' = u + s (0 on c-points) on the 5^3 fine vertices
-    around 3m, rho_5(m) = (R r)(m) and si_5(m) = s(3m).  Sample set 2-norm
+    around 3m, rho_5(m) = (R r)(m) and si_5(m) = s(3m).  Then the backtracking
+    of level 5 (on a 244^3 level: the update pass and the restriction march)
+    from the GPU's rho_5 after the cycle: sc_5 = omega rho_5 / D_5 off the
+    c-points at sampled level-5 vertices, si_4(m) = omega rho_5(3m) / D_5 and
+    rho_4(m) = (R rho_5)(m) at sampled level-4 vertices.  Sample set 2-norm
     relative error <= 1e-12 per field."""
     from paper_1508_03954_amd import mg
     from paper_1508_03954_amd.inputs import config_3d_large, random_complex, sample_vertices
@@ -180,6 +184,8 @@ def test_3d_level6_fused_sweep_sampled():
     L, dim, n = 6, 3, 730
     p5 = Params(dim=3, level_max=L - 1, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
     D = O.diag_H(4, 3, L, prob.theta, prob.phi)[1, 1, 1]
+    D5 = O.diag_H(4, 3, L - 1, prob.theta, prob.phi)[1, 1, 1]
+    ms4 = sample_vertices(L - 2, 3, 250, seed=67)
     s = mg.Solver(dim, L, theta=prob.theta, phi=prob.phi, variant="bpx", omega=0.6)
     tile, us, _ = s.autotune(reps=2)
     print(f"\n[case] level 6 fused sweep, tile {tile} ({us:.0f} us)", flush=True)
@@ -230,10 +236,25 @@ def test_3d_level6_fused_sweep_sampled():
             ref["si"].append(sm[6, 6, 6])
             got["rho"].append(RHO[tuple(int(c) for c in m)].item())
             got["si"].append(SI[tuple(int(c) for c in m)].item())
-        for f in ("w", "rho", "si"):
+        # the backtracking of level 5, from the GPU's rho_5
+        SC5, SI4, RHO4 = s.get_level(L - 1, "sc"), s.get_level(L - 2, "si"), s.get_level(L - 2, "b")
+        for f in ("sc5", "si4", "rho4"):
+            got[f], ref[f] = [], []
+        for m in ms:
+            j = tuple(int(c) for c in m)
+            cpv = all(c % 3 == 0 for c in j)
+            ref["sc5"].append(0.0 if cpv else 0.6 * RHO[j].item() / D5)
+            got["sc5"].append(SC5[j].item())
+        for m in ms4:
+            lo = [3 * int(c) - 6 for c in m]
+            ref["rho4"].append(O.restrict(_win(RHO, lo, 13))[2, 2, 2])
+            got["rho4"].append(RHO4[tuple(int(c) for c in m)].item())
+            ref["si4"].append(0.6 * RHO[tuple(3 * int(c) for c in m)].item() / D5)
+            got["si4"].append(SI4[tuple(int(c) for c in m)].item())
+        for f in ("w", "rho", "si", "sc5", "si4", "rho4"):
             g, rf = np.hstack(got[f]), np.hstack(ref[f])
             err = np.linalg.norm(g - rf) / np.linalg.norm(rf)
             print(f"[level 6] cycle {cyc} {f}: {g.size} samples, relative error {err:.2e}", flush=True)
             assert err <= 1e-12, (cyc, f, err)
-        del W, RHO, SI
+        del W, RHO, SI, SC5, SI4, RHO4
         torch.cuda.empty_cache()
