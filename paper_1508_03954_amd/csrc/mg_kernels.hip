@@ -243,6 +243,116 @@ __global__ __launch_bounds__(256) void k_resid(OpData<T> op, const cpx<T>* __res
   if (partials) block_sum_max(s2, sqrt(mx), partials);
 }
 
+// r = b - H x with per-cell coefficients (varying phi, absorbing layer) in 3D
+// as a march along z: a wavefront takes 64 vertices of one row and a chunk of
+// kVarTz planes, keeps the 3 x 3 neighbourhoods of the planes z - 1, z, z + 1
+// in registers and the coefficients of the two layers of cells around z, so a
+// step loads one plane's nine values and one layer's four cells (eight with a
+// per-cell stiffness) instead of stencil_var's 27 + 8 cell loads plus its
+// 64 vertex loads.  The arithmetic is stencil_var's, in its order.
+constexpr int kVarTz = 8;
+
+template <class T>
+__device__ inline void var_plane(const cpx<T>* __restrict__ x, int n, int xx, int y, int z, cpx<T> v[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int j[3] = {xx + k % 3 - 1, y + k / 3 - 1, z};
+    v[k] = czero<T>();
+    if (is_interior<3>(j, n)) v[k] = x[ravel<3>(j, n)];
+  }
+}
+
+// The four cells of layer cz around (xx, y): cell (xx - bx, y - by, cz) at 2 by + bx.
+template <class T, bool STIFF>
+__device__ inline void var_cells(const OpData<T>& op, int n, int xx, int y, int cz, cpx<T> cm[4], cpx<T> ck[4]) {
+  const int nc = n - 1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c[3] = {xx - (k & 1), y - (k >> 1), cz};
+    const long long ci = ravel<3>(c, nc);
+    cm[k] = op.cmass[ci];
+    if (STIFF) ck[k] = op.cstiff[ci];
+  }
+}
+
+// STIFF: per-cell stiffness coefficients (op.cstiff, the absorbing layer);
+// otherwise the uniform stiffness op.alpha with the assembled 27-point weights.
+// b == nullptr: r = H x (the operator alone, as k_apply).
+template <class T, bool STIFF>
+__global__ __launch_bounds__(256) void k_resid_var3(OpData<T> op, const cpx<T>* __restrict__ b,
+                                                    const cpx<T>* __restrict__ x, cpx<T>* __restrict__ r,
+                                                    double* partials) {
+  const int n = op.n;
+  const int xx = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  const int nzc = (n + kVarTz - 1) / kVarTz;
+  double s2 = 0, mx = 0;
+  for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
+       t += gridDim.y * 4) {
+    const int y = t % n, zs = (t / n) * kVarTz, ze = min(zs + kVarTz, n);
+    if (xx >= n) continue;
+    const bool in_xy = xx >= 1 && xx <= n - 2 && y >= 1 && y <= n - 2;
+    const int z0 = max(zs, 1), z1 = min(ze, n - 1);
+    if (r)
+      for (int z = zs; z < ze; ++z)
+        if (!in_xy || z < z0 || z >= z1) r[((long long)z * n + y) * n + xx] = czero<T>();
+    if (!in_xy || z0 >= z1) continue;
+    constexpr int NK = STIFF ? 4 : 1;
+    cpx<T> pa[9], pb[9], pc[9], cmL[4], ckL[NK], cmU[4], ckU[NK];
+    var_plane(x, n, xx, y, z0 - 1, pa);
+    var_plane(x, n, xx, y, z0, pb);
+    var_cells<T, STIFF>(op, n, xx, y, z0 - 1, cmL, ckL);
+    for (int z = z0; z < z1; ++z) {
+      var_plane(x, n, xx, y, z + 1, pc);
+      var_cells<T, STIFF>(op, n, xx, y, z, cmU, ckU);
+      // xv[q], q = (ox + 1) + 3 (oy + 1) + 9 (oz + 1): pa, pb, pc
+      cpx<T> st = czero<T>();
+      if (!STIFF) {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+          const cpx<T> v = q < 9 ? pa[q] : (q < 18 ? pb[q - 9] : pc[q - 18]);
+          const int cls = (q % 3 != 1) + ((q / 3) % 3 != 1) + (q / 9 != 1);
+          st = st + stiff_weight<T, 3>(cls) * v;
+        }
+        st = cmul(op.alpha, st);
+      }
+      cpx<T> ms = czero<T>();
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        // cell j - bits(c): layer z - 1 for bit 2 set (cmL), z otherwise (cmU)
+        cpx<T> am = czero<T>(), ak = czero<T>();
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const int q = (((kk >> 0) & 1) - ((c >> 0) & 1) + 1) + 3 * (((kk >> 1) & 1) - ((c >> 1) & 1) + 1) +
+                        9 * (((kk >> 2) & 1) - ((c >> 2) & 1) + 1);
+          const cpx<T> v = q < 9 ? pa[q] : (q < 18 ? pb[q - 9] : pc[q - 18]);
+          am = am + elem_mass<T, 3>(c, kk) * v;
+          if (STIFF) ak = ak + elem_stiff<T, 3>(c, kk) * v;
+        }
+        const int k4 = c & 3;
+        const cpx<T> cmv = (c & 4) ? cmL[k4] : cmU[k4];
+        ms = ms + cmul(cmv, am);
+        if (STIFF) st = st + cmul((c & 4) ? ckL[k4 % NK] : ckU[k4 % NK], ak);
+      }
+      const long long e = ((long long)z * n + y) * n + xx;
+      const cpx<T> v = b ? b[e] - (st - ms) : st - ms;
+      if (r) r[e] = v;
+      const double a2 = (double)v.re * v.re + (double)v.im * v.im;
+      s2 += a2;
+      mx = fmax(mx, a2);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        pa[k] = pb[k];
+        pb[k] = pc[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cmL[k] = cmU[k];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) ckL[k] = ckU[k];
+    }
+  }
+  if (partials) block_sum_max(s2, sqrt(mx), partials);
+}
+
 // Post-phase pointwise part, see update_vertex.
 template <class T, int D>
 __global__ void k_update(OpData<T> op, const cpx<T>* __restrict__ r, cpx<T> omega, int mask_c,
@@ -803,6 +913,7 @@ template <class T>
 hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y, hipStream_t s) {
   if (dim == 3 && !op.cmass && stencil3_blocks(op.n) > 0)
     return launch_stencil3<T>(1, op.n, op.coef, nullptr, x, y, nullptr, nullptr, s);
+  if (dim == 3 && op.cmass) return launch_resid<T>(dim, op, nullptr, x, y, nullptr, nullptr, s);
   MG_DISPATCH(dim, k_apply, row_grid(op.n, dim), op, x, y);
   return hipGetLastError();
 }
@@ -845,6 +956,20 @@ hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx
   const int sb = dim == 3 && !op.cmass && r ? stencil3_blocks(op.n) : -1;
   if (sb > 0 && (!partials || sb <= kRedBlocks))
     return launch_stencil3<T>(0, op.n, op.coef, b, x, r, partials, nparts, s);
+  if (dim == 3 && op.cmass) {
+    const int gx = (op.n + 63) / 64;
+    const long long items = (long long)op.n * ((op.n + kVarTz - 1) / kVarTz);
+    int gy = (int)std::min<long long>((items + 3) / 4, 65535);
+    if (partials) {
+      // the row kernel's block count (resid_norm_blocks); blocks past the
+      // items only write zero partials
+      gy = std::max(1, std::min((int)row_grid(op.n, dim).y, kRedBlocks / gx));
+      if (nparts) *nparts = gx * gy;
+    }
+    if (op.cstiff) hipLaunchKernelGGL((k_resid_var3<T, true>), dim3(gx, gy), 256, 0, s, op, b, x, r, partials);
+    else hipLaunchKernelGGL((k_resid_var3<T, false>), dim3(gx, gy), 256, 0, s, op, b, x, r, partials);
+    return hipGetLastError();
+  }
   dim3 g = row_grid(op.n, dim);
   if (partials) {
     const int gx = (int)g.x;
@@ -856,6 +981,7 @@ hipError_t launch_resid(int dim, const OpData<T>& op, const cpx<T>* b, const cpx
 }
 
 int resid_norm_blocks(int dim, int n) {
+  // (the per-cell 3D march is launched with the same count when it writes partials)
   const dim3 g = row_grid(n, dim);
   const int gx = (int)g.x;
   if (gx > kRedBlocks) return -1;
