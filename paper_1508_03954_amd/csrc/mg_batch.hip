@@ -38,7 +38,7 @@ constexpr int kBThreads = 64 * kBWaves;
 constexpr int kBRows = 8 * kBWaves;
 // 3D tiles of a 3-wave workgroup: coarse rows 2, rows per thread 2; z extent
 // selectable.  2D: one tile per wavefront, three per item.
-constexpr int kBZc3[] = {9, 27};
+constexpr int kBZc3[] = {9, 3};
 constexpr int kBZc2[] = {1, 2, 4, 8};
 // configurations: z extent (3D) x z extent (2D) x queue order
 constexpr int kBatchConfigs = 2 * 4 * 2;
@@ -175,9 +175,9 @@ __device__ inline void batch_fused3(const BProb<T>* Pp, int cyc, int tile, F3Lds
     else if (add) fused3_tile<T, 2, 2, 9, 0>(f, bx, by, bz, part, sm0);
     else fused3_tile<T, 2, 2, 9, 1>(f, bx, by, bz, part, sm0);
   } else {
-    if (bpx) fused3_tile<T, 2, 2, 27, 2>(f, bx, by, bz, part, sm);
-    else if (add) fused3_tile<T, 2, 2, 27, 0>(f, bx, by, bz, part, sm0);
-    else fused3_tile<T, 2, 2, 27, 1>(f, bx, by, bz, part, sm0);
+    if (bpx) fused3_tile<T, 2, 2, 3, 2>(f, bx, by, bz, part, sm);
+    else if (add) fused3_tile<T, 2, 2, 3, 0>(f, bx, by, bz, part, sm0);
+    else fused3_tile<T, 2, 2, 3, 1>(f, bx, by, bz, part, sm0);
   }
 }
 
@@ -479,7 +479,7 @@ template <class T, int DOT, int VAR>
 __device__ inline void prec_pa3(const FusedArgs<T>& f, int zc3, int bx, int by, int bz, double* part,
                                 F3Lds<T, 2, 2, false>& sm0) {
   if (zc3 == 0) fused3_tile<T, 2, 2, 9, VAR, kPrecApply, 1, DOT>(f, bx, by, bz, part, sm0);
-  else fused3_tile<T, 2, 2, 27, VAR, kPrecApply, 1, DOT>(f, bx, by, bz, part, sm0);
+  else fused3_tile<T, 2, 2, 3, VAR, kPrecApply, 1, DOT>(f, bx, by, bz, part, sm0);
 }
 
 template <class T, int D>
@@ -569,7 +569,7 @@ __device__ __attribute__((always_inline)) inline void prec_item(const PrecArgs<T
       f.spill = P.spill;
       f.variant = 1;
       if (P.zc3 == 0) fused3_tile<T, 2, 2, 9, 1, kRestrict>(f, bx, by, bz, nullptr, sm0);
-      else fused3_tile<T, 2, 2, 27, 1, kRestrict>(f, bx, by, bz, nullptr, sm0);
+      else fused3_tile<T, 2, 2, 3, 1, kRestrict>(f, bx, by, bz, nullptr, sm0);
     } else {   // PK_PA3: z = s + P g, y = H z and the dot partials of the tile
       f.w = io.v;
       f.scc = bpx ? P.pr[L - 1] : P.pz[L - 1];

@@ -324,11 +324,12 @@ struct Engine {
 
   int tile = 0;
 
-  // Default tile: short z chunks while the grid is small (more blocks),
-  // otherwise 2 coarse rows by 21 coarse planes.
+  // Default tile: short z chunks while the grid is small (more blocks and
+  // shorter marches: on 28^3 and 82^3 the march of 3 coarse planes takes about
+  // half the time of one of 9), otherwise 2 coarse rows by 21 coarse planes.
   int default_tile() const {
     if (dim == 2) return lv[L].n <= 250 ? 1 : 0;
-    return fused_tile_index(3, 2, 2, lv[L].n <= 82 ? 9 : 21);
+    return fused_tile_index(3, 2, 2, lv[L].n <= 82 ? 3 : 21);
   }
   void set_tile(int t) {
     tile = t;

@@ -81,10 +81,10 @@ constexpr TileShape3 kTiles3[] = {{2, 2, 9, 0, 1},  {2, 2, 14, 0, 1}, {2, 2, 21,
                                   {2, 1, 14, 0, 1}, {2, 1, 21, 0, 1}, {2, 2, 9, 1, 1},  {2, 2, 21, 1, 1},
                                   {4, 2, 28, 0, 2}, {4, 2, 28, 0, 3}, {2, 2, 28, 0, 2}, {2, 2, 28, 0, 3},
                                   {4, 2, 28, 1, 3}, {2, 2, 28, 1, 3}, {2, 2, 9, 2, 1},  {4, 2, 14, 2, 1},
-                                  {4, 2, 28, 2, 3}, {2, 2, 28, 2, 3}};
+                                  {4, 2, 28, 2, 3}, {2, 2, 28, 2, 3}, {2, 2, 3, 0, 1},  {2, 2, 3, 2, 1}};
 constexpr int kTiles2[] = {2, 1, 4, 8};
 constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
-static_assert(kNumTiles3 == 22, "launch_fused has one case per entry of kTiles3");
+static_assert(kNumTiles3 == 24, "launch_fused has one case per entry of kTiles3");
 constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 
 int fused_tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
@@ -173,6 +173,8 @@ hipError_t launch_fused(int dim, const FusedArgs<T>& a, hipStream_t s, hipEvent_
       case 19: e = launch3<T, 4, 2, 14>(a, g, s, t0, t1); break;
       case 20: e = launch3<T, 4, 2, 28, 3>(a, g, s, t0, t1); break;
       case 21: e = launch3<T, 2, 2, 28, 3>(a, g, s, t0, t1); break;
+      case 22: e = launch3<T, 2, 2, 3>(a, g, s, t0, t1); break;
+      case 23: e = launch3<T, 2, 2, 3>(a, g, s, t0, t1); break;
       default: return hipErrorInvalidValue;   // every entry of kTiles3 has its case above
     }
     if (e != hipSuccess) return e;
