@@ -257,8 +257,10 @@ def test_batched_solve_fp32_refinement():
     from paper_1508_03954_amd import mg
     from paper_1508_03954_amd.inputs import config_batched
     probs = config_batched()
-    pick = [i for i, p in enumerate(probs) if (p.dim == 2 and p.level_max == 6) or
-            (p.dim == 3 and p.level_max == 5)][:2]
+    # the first 2D level-6 and 3D level-5 members (the latter on its own
+    # launches: 2^22 finest vertices or more) and two level-3 members
+    pick = [next(i for i, p in enumerate(probs) if p.dim == 2 and p.level_max == 6),
+            next(i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 5)]
     pick += [i for i, p in enumerate(probs) if p.level_max == 3][:2]
     sub = [probs[i] for i in pick]
     kws = [dict(dim=p.dim, level_max=p.level_max, phi=p.phi, variant="bpx", precision="fp32_refine") for p in sub]
@@ -275,6 +277,38 @@ def test_batched_solve_fp32_refinement():
         err = (torch.linalg.vector_norm(u - u64) / torch.linalg.vector_norm(u64)).item()
         # relative residual 1e-10 bounds the error by cond(H) * 1e-10
         assert err <= 1e-6, (p.name, err)
+    batch.close()
+
+
+def test_batched_cycles_with_large_members_on_side_streams():
+    """Four 3D level-5 members (244^3, each on its own launches; the three side
+    streams take them round robin, so one stream runs two) and two small
+    members: two batched cycles leave every member's finest iterate, level-4
+    fields and residual history equal, bit for bit, to those of the same
+    problem cycled alone with the same tile."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_batched
+    probs = config_batched()
+    big = [i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 5][:4]
+    small = [next(i for i, p in enumerate(probs) if p.dim == 2 and p.level_max == 4),
+             next(i for i, p in enumerate(probs) if p.dim == 3 and p.level_max == 3)]
+    sub = [probs[i] for i in big + small]
+    kws = [dict(dim=p.dim, level_max=p.level_max, phi=p.phi, variant="bpx", omega=0.6) for p in sub]
+    batch = mg.Batch(kws)
+    print(f"\n[case] batch with large members {big} and small members {small}", flush=True)
+    for s, p in zip(batch.solvers, sub):
+        start(s, p.chi)
+    res = batch.cycle(2)
+    for i, (s, p, kw) in enumerate(zip(batch.solvers, sub, kws)):
+        alone = mg.Solver(**kw, sweep="fused")
+        alone.set_tile(s.tiles()[0])
+        start(alone, p.chi)
+        rh, _ = alone.cycle(2)
+        assert np.array_equal(np.asarray(rh), res[:, i]), (i, rh, res[:, i])
+        L = p.level_max
+        for lev, f in ((L, "u"), (L - 1, "b"), (L - 1, "sc"), (L - 1, "si")):
+            assert torch.equal(s.get_level(lev, f), alone.get_level(lev, f)), (i, lev, f)
+        alone.close()
     batch.close()
 
 
