@@ -503,11 +503,17 @@ struct Engine {
       const cpx<T>* r;
       if (galerkin && hcc) {
         if (dim == 3 && spill && v.n >= kPostSplitMinN) {
-          // a large level: the pointwise update as one streaming pass, then
-          // R of its b slot by the restriction march (the seam array is free
-          // once the finest sweep's seam pass has run)
-          MG_HIP(launch_update<T>(dim, v.op, v.b, to_c<T>(wl), variant != MG_ADD ? 1 : 0, nullptr, v.sc, v.sf,
-                                  variant == MG_ADD ? cc->sf : nullptr, variant == MG_BPX ? cc->si : nullptr, s));
+          // a large level: the restriction march of its b slot (the seam array
+          // is free once the finest sweep's seam pass has run), which forms the
+          // pointwise update on the way for hb and BPX; the additive variant,
+          // whose injection also reads sf, takes the update as a pass of its own
+          if (variant != MG_ADD) {
+            const cpx<T> wsl = to_c<T>(wl * complex<double>(v.op.invD.re, v.op.invD.im));
+            MG_HIP(launch_post3<T>(cc->n, variant, v.b, wsl, v.sc, variant == MG_BPX ? cc->si : nullptr, cc->b,
+                                   spill, s));
+            continue;
+          }
+          MG_HIP(launch_update<T>(dim, v.op, v.b, to_c<T>(wl), 0, nullptr, v.sc, v.sf, cc->sf, nullptr, s));
           MG_HIP(launch_restrict3<T>(cc->n, v.b, cc->b, spill, s));
           continue;
         }

@@ -239,6 +239,51 @@ __global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_restrict3(Fused
 
 int restrict3_blocks(int nc) { return f3_xtiles(nc) * f3_ytiles(nc, kRTyc) * ((nc + kRZc - 1) / kRZc); }
 
+// Backtracking of a coarse level in the Galerkin form as the restriction
+// march (DOT 4): rho_c = R rho with the level's update sc = ws rho (masked)
+// and, for BPX (VAR 2), the injection si_c = ws rho, in one pass.
+template <class T, int VAR>
+__global__ __launch_bounds__(64 * (3 * kRTyc / kRRpt), 2) void k_post3(FusedArgs<T> a) {
+  __shared__ F3Lds<T, kRTyc, kRRpt, VAR == 2, true> sm;
+  int bx, by, bz;
+  fused3_block_tile(kKrylovOrder, gridDim.x, gridDim.y, gridDim.z, bx, by, bz);
+  fused3_tile<T, kRTyc, kRRpt, kRZc, VAR, kRestrict, 3, 4>(a, bx, by, bz, nullptr, sm);
+}
+
+template <class T>
+hipError_t launch_post3(int nc, int variant, const cpx<T>* rho, cpx<T> ws, cpx<T>* sc, cpx<T>* sic, cpx<T>* rhoc,
+                        cpx<T>* spill, hipStream_t s) {
+  const int n = 3 * (nc - 1) + 1;
+  // variant: 1 hierarchical basis, 2 BPX (the fused kernels' numbering)
+  if (n < 10 || spill == nullptr || (variant != 1 && variant != 2)) return hipErrorInvalidValue;
+  if (variant == 2 && sic == nullptr) return hipErrorInvalidValue;
+  FusedArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nc = nc;
+  a.b = rho;
+  a.rhoc = rhoc;
+  a.spill = spill;
+  a.zout = sc;
+  a.sic_out = sic;
+  a.ws = ws;
+  a.variant = variant;
+  a.order = kKrylovOrder;
+  const dim3 g(f3_xtiles(nc), f3_ytiles(nc, kRTyc), (nc + kRZc - 1) / kRZc);
+  constexpr int NT = F3<T, kRTyc, kRRpt, kRZc, false>::NT;
+  if (variant == 2) hipLaunchKernelGGL((k_post3<T, 2>), g, NT, 0, s, a);
+  else hipLaunchKernelGGL((k_post3<T, 1>), g, NT, 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nseam = f3_ytiles(nc, kRTyc) - 1;
+  if (nseam >= 1) hipLaunchKernelGGL(k_seam3<T>, dim3(nseam, nc), dim3(128), 0, s, rhoc, spill, nc, kRTyc);
+  return hipGetLastError();
+}
+template hipError_t launch_post3<double>(int, int, const cpx<double>*, cpx<double>, cpx<double>*, cpx<double>*,
+                                         cpx<double>*, cpx<double>*, hipStream_t);
+template hipError_t launch_post3<float>(int, int, const cpx<float>*, cpx<float>, cpx<float>*, cpx<float>*,
+                                        cpx<float>*, cpx<float>*, hipStream_t);
+
 template <class T>
 hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s) {
   const int n = 3 * (nc - 1) + 1;

@@ -300,6 +300,10 @@ __host__ __device__ inline int f3_ytiles(int nc, int tyc) { return (nc + tyc - 1
 // BiCGStab update of its second half-step, formed in double precision, which
 // keeps the cancellation in s exact for complex64 vectors) instead of b,
 // stores s to zout and sums |s|^2 over the owned vertices into part.
+// kRestrict with DOT 4 is the backtracking of a coarse level in the Galerkin
+// form: rho_c = R rho of the level's b slot (in b), and on the way the
+// pointwise update sc = ws rho (zero on c-points for VAR 1 and 2) stored to
+// zout, with s = ws rho injected into sic_out at c-points for VAR 2.
 constexpr int kSweep = 0, kResid = 1, kApply = 2, kRestrict = 3, kPrecApply = 4;
 constexpr bool f3_full_lds(int mode) { return mode == kSweep || mode == kRestrict || mode == kPrecApply; }
 
@@ -409,9 +413,9 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
   double nsum = 0.0, nmax = 0.0;
   // dots of the preconditioner-apply march: v2 of plane P is loaded at step P
   // (register set = parity of P relative to p0) and used one step later
-  static_assert(DOT == 0 || (MODE == kPrecApply && DOT <= 2) || (MODE == kRestrict && DOT == 3),
-                "dots of the preconditioner-apply march, or the s update of the restriction march");
-  constexpr int ND = DOT == 0 || DOT == 3 ? 1 : (DOT == 1 ? 2 : 3);
+  static_assert(DOT == 0 || (MODE == kPrecApply && DOT <= 2) || (MODE == kRestrict && (DOT == 3 || DOT == 4)),
+                "dots of the preconditioner-apply march, the s update or the backtracking of the restriction march");
+  constexpr int ND = DOT == 0 || DOT >= 3 ? 1 : (DOT == 1 ? 2 : 3);
   double dacc[ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) dacc[k] = 0.0;
@@ -605,6 +609,21 @@ __device__ inline void fused3_tile(const FusedArgs<T>& a, int bx, int by, int bz
           if (q_own && vst[j] != kOOB) dacc[0] += (double)r[j].re * r[j].re + (double)r[j].im * r[j].im;
         }
         load_v2(p + PF - 1, pofs + (PF - 1) * pstride, Vr[DOT == 3 ? E : 0]);
+      }
+      if (DOT == 4) {
+        // the level's pointwise update on the way (owned vertices of plane q)
+        const bool q_own = q >= zown_lo && q <= zown_hi;
+        constexpr bool q_c = K % 3 == 1;
+        const auto so = frs(a.zout, pofs - pstride, q_own);
+        const auto co = crs(a.sic_out, kofs + (K / 3) * cstride, q_own && q_c && VAR == 2);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int y = ybase + j;
+          const cpx<T> sv = f_mul(ws, r[j]);
+          const bool cp = q_c && q >= 0 && ccol && x >= 0 && (y % 3) == 0;
+          bstore<kStream>(f_sel(VAR != 0 && cp, f_zero<T>(), sv), so, vst[j]);
+          if (VAR == 2) bstore(sv, co, vcp[j]);
+        }
       }
       load_b(p + PF - 1, pofs + (PF - 1) * pstride, Br[E]);
       restrict_r(K_, r, kb, kofs);

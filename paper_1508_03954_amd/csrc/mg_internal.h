@@ -260,6 +260,13 @@ int fused_partials_blocks(int dim, int n, int tile);  // -1 if unsupported
 // with the sweep's march; spill: fused_spill_count(3, n) entries of scratch.
 template <class T>
 hipError_t launch_restrict3(int nc, const cpx<T>* x, cpx<T>* rhoc, cpx<T>* spill, hipStream_t s);
+// Backtracking of a coarse level (level size 3 (nc - 1) + 1, 3D, hb or BPX) in
+// the Galerkin form as the restriction march: rhoc = R rho, sc = ws rho (zero
+// on c-points), for BPX sic = ws rho at c-points; the seam rows go through
+// spill (coarse-level sized) and k_seam3.
+template <class T>
+hipError_t launch_post3(int nc, int variant, const cpx<T>* rho, cpx<T> ws, cpx<T>* sc, cpx<T>* sic, cpx<T>* rhoc,
+                        cpx<T>* spill, hipStream_t s);
 // The same for s = r - alpha v, computed in the march: s is stored to sv and
 // partials[one per block, restrict3_blocks(nc)] receive |s|^2 over the block.
 int restrict3_blocks(int nc);

@@ -258,3 +258,55 @@ def test_3d_level6_fused_sweep_sampled():
             assert err <= 1e-12, (cyc, f, err)
         del W, RHO, SI, SC5, SI4, RHO4
         torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("variant", ["bpx", "hb", "add"])
+def test_3d_level6_backtracking_of_level5(variant):
+    """One 730^3 cycle per variant (levels 1..6, k = 40); the backtracking of
+    level 5 (244^3: for hb and BPX the restriction march that forms the
+    update on the way, for add the update pass and the march) checked at
+    sampled vertices from the GPU's own rho_5 (the level's b slot, which the
+    backtracking reads and leaves): sc_5 = omega rho_5 / D_5, zero on c-points
+    for hb and BPX; rho_4(m) = (R rho_5)(m); BPX: si_4(m) = omega rho_5(3m) / D_5;
+    add: sf_4(m) = sf_5(3m) + sc_5(3m).  Sample set 2-norm relative error <= 1e-12."""
+    from paper_1508_03954_amd import mg
+    from paper_1508_03954_amd.inputs import config_3d_large, random_complex, sample_vertices
+    prob = config_3d_large(level_max=6)
+    L, n = 6, 730
+    D5 = O.diag_H(4, 3, L - 1, prob.theta, prob.phi)[1, 1, 1]
+    s = mg.Solver(3, L, theta=prob.theta, phi=prob.phi, variant=variant, omega=0.6)
+    print(f"\n[case] level-5 backtracking at 730^3, {variant}", flush=True)
+    s.set_rhs(s.rhs_from_nodal(torch.from_numpy(prob.chi).cuda()))
+    s.set_solution(torch.from_numpy(random_complex((n,) * 3, seed=607)).cuda())
+    s.cycle(1)
+    RHO5, SC5, SF5 = s.get_level(L - 1, "b"), s.get_level(L - 1, "sc"), s.get_level(L - 1, "sf")
+    RHO4, SI4, SF4 = s.get_level(L - 2, "b"), s.get_level(L - 2, "si"), s.get_level(L - 2, "sf")
+    got, ref = {"sc5": [], "rho4": [], "inj4": []}, {"sc5": [], "rho4": [], "inj4": []}
+    for m in sample_vertices(L - 1, 3, 250, seed=68):
+        j = tuple(int(c) for c in m)
+        cpv = all(c % 3 == 0 for c in j)
+        ref["sc5"].append(0.0 if (cpv and variant != "add") else 0.6 * RHO5[j].item() / D5)
+        got["sc5"].append(SC5[j].item())
+    for m in sample_vertices(L - 2, 3, 250, seed=69):
+        mc = tuple(int(c) for c in m)
+        jf = tuple(3 * c for c in mc)
+        lo = [3 * c - 6 for c in mc]
+        ref["rho4"].append(O.restrict(_win(RHO5, lo, 13))[2, 2, 2])
+        got["rho4"].append(RHO4[mc].item())
+        if variant == "bpx":
+            ref["inj4"].append(0.6 * RHO5[jf].item() / D5)
+            got["inj4"].append(SI4[mc].item())
+        elif variant == "add":
+            ref["inj4"].append(SF5[jf].item() + SC5[jf].item())
+            got["inj4"].append(SF4[mc].item())
+    for f in ("sc5", "rho4", "inj4"):
+        if not ref[f]:
+            continue
+        g, rf = np.array(got[f]), np.array(ref[f])
+        err = np.linalg.norm(g - rf) / np.linalg.norm(rf)
+        print(f"[level 6 {variant}] {f}: {g.size} samples, relative error {err:.2e}", flush=True)
+        assert err <= 1e-12, (variant, f, err)
+    if variant == "hb":
+        # no injection below level 5 for hb: the coarse si and sf stay zero
+        assert not torch.any(SI4.abs() > 0) and not torch.any(SF4.abs() > 0)
