@@ -136,20 +136,33 @@ __device__ inline cpx<T> pre_xy_interp(const cpx<T>* __restrict__ v, int nc, int
   return acc;
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_pre_march3(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc,
-                                                    const cpx<T>* __restrict__ sf, const cpx<T>* __restrict__ scc,
-                                                    const cpx<T>* __restrict__ sic, int bpx) {
+// Modes of the prolongation march: the coarse descent sc += P scc (- P sic
+// off c-points for BPX; u += sc + sf when the coarse iterate is formed), the
+// finest descent out = w + P scc (- P sic off c-points), and the hierarchical
+// surplus out = w - P scc.  The last two write zero off the interior.
+enum { kPmPre = 0, kPmFine = 1, kPmSurplus = 2 };
+constexpr int kProlongMarchMinN = 82;   // finest descent and surplus: 3D levels of 82^3 and more
+
+template <class T, int KIND>
+__global__ __launch_bounds__(256) void k_prolong_march3(int n, cpx<T>* __restrict__ u, cpx<T>* __restrict__ sc,
+                                                        const cpx<T>* __restrict__ sf,
+                                                        const cpx<T>* __restrict__ scc,
+                                                        const cpx<T>* __restrict__ sic, int bpx) {
   const int nc = (n - 1) / 3 + 1;
   const int x = blockIdx.x * 64 + (int)(threadIdx.x & 63);
   const int nzc = (n + kPreTz - 1) / kPreTz;
+  // kPmFine / kPmSurplus: sc is the input w, u the output
   for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
        t += gridDim.y * 4) {
     const int y = t % n, zs = (t / n) * kPreTz, ze = min(zs + kPreTz, n);
-    // the descent leaves non-interior vertices alone
-    if (x < 1 || x > n - 2 || y < 1 || y > n - 2) continue;
+    if (x >= n) continue;
+    const bool in_xy = x >= 1 && x <= n - 2 && y >= 1 && y <= n - 2;
     const int z0 = max(zs, 1), z1 = min(ze, n - 1);
-    if (z0 >= z1) continue;
+    if (KIND != kPmPre)
+      for (int z = zs; z < ze; ++z)
+        if (!in_xy || z < z0 || z >= z1) u[((long long)z * n + y) * n + x] = czero<T>();
+    // the coarse descent leaves non-interior vertices alone
+    if (!in_xy || z0 >= z1) continue;
     // x and y corners (the second with weight 0 on a coarse line; its index
     // stays inside the coarse grid for an interior vertex)
     const int mx = x / 3, qx = x % 3, my = y / 3, qy = y % 3;
@@ -159,10 +172,11 @@ __global__ __launch_bounds__(256) void k_pre_march3(int n, cpx<T>* __restrict__ 
                                (long long)(my + 1) * nc + mx + 1};
     const T cwt[4] = {wy0 * wx0, wy0 * wx1, wy1 * wx0, wy1 * wx1};
     const bool cxy = qx == 0 && qy == 0;
+    const bool use_i = KIND != kPmSurplus && bpx;
     int mz = z0 / 3;
     cpx<T> s0 = pre_xy_interp(scc, nc, mz, cidx, cwt), s1 = pre_xy_interp(scc, nc, mz + 1, cidx, cwt);
     cpx<T> i0 = czero<T>(), i1 = czero<T>();
-    if (bpx) {
+    if (use_i) {
       i0 = pre_xy_interp(sic, nc, mz, cidx, cwt);
       i1 = pre_xy_interp(sic, nc, mz + 1, cidx, cwt);
     }
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(256) void k_pre_march3(int n, cpx<T>* __restrict__ 
         mz = z / 3;
         s0 = s1;
         s1 = pre_xy_interp(scc, nc, mz + 1, cidx, cwt);
-        if (bpx) {
+        if (use_i) {
           i0 = i1;
           i1 = pre_xy_interp(sic, nc, mz + 1, cidx, cwt);
         }
@@ -179,12 +193,30 @@ __global__ __launch_bounds__(256) void k_pre_march3(int n, cpx<T>* __restrict__ 
       const int qz = z % 3;
       const T wz1 = T(qz) / T(3), wz0 = qz == 0 ? T(1) : T(1) - wz1;
       const long long e = ((long long)z * n + y) * n + x;
-      cpx<T> v = sc[e] + (wz0 * s0 + wz1 * s1);
-      if (bpx && !(cxy && qz == 0)) v = v - (wz0 * i0 + wz1 * i1);
+      const cpx<T> ps = wz0 * s0 + wz1 * s1;
+      if (KIND == kPmSurplus) {
+        u[e] = sc[e] - ps;
+        continue;
+      }
+      cpx<T> v = sc[e] + ps;
+      if (use_i && !(cxy && qz == 0)) v = v - (wz0 * i0 + wz1 * i1);
+      if (KIND == kPmFine) {
+        u[e] = v;
+        continue;
+      }
       sc[e] = v;
       if (u) u[e] = u[e] + v + sf[e];
     }
   }
+}
+
+template <class T, int KIND>
+static hipError_t launch_prolong_march3(int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
+                                        const cpx<T>* sic, int bpx, hipStream_t s) {
+  const long long items = (long long)n * ((n + kPreTz - 1) / kPreTz);
+  const dim3 g((unsigned)((n + 63) / 64), (unsigned)std::min<long long>((items + 3) / 4, 65535));
+  hipLaunchKernelGGL((k_prolong_march3<T, KIND>), g, 256, 0, s, n, u, sc, sf, scc, sic, bpx);
+  return hipGetLastError();
 }
 
 // Finest-level pre-phase on the folded iterate w = u + sc:
@@ -921,12 +953,8 @@ hipError_t launch_apply(int dim, const OpData<T>& op, const cpx<T>* x, cpx<T>* y
 template <class T>
 hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, const cpx<T>* scc,
                       const cpx<T>* sic, int has_coarse, int bpx, hipStream_t s) {
-  if (dim == 3 && has_coarse && n >= kPreMarchMinN) {
-    const long long items = (long long)n * ((n + kPreTz - 1) / kPreTz);
-    const dim3 g((unsigned)((n + 63) / 64), (unsigned)std::min<long long>((items + 3) / 4, 65535));
-    hipLaunchKernelGGL(k_pre_march3<T>, g, 256, 0, s, n, u, sc, sf, scc, sic, bpx);
-    return hipGetLastError();
-  }
+  if (dim == 3 && has_coarse && n >= kPreMarchMinN)
+    return launch_prolong_march3<T, kPmPre>(n, u, sc, sf, scc, sic, bpx, s);
   if (dim == 3 && n <= kFastDivMaxN && n % 64 != 0) {
     const long long N = (long long)n * n * n;
     hipLaunchKernelGGL(k_pre_flat3<T>, dim3((unsigned)((N + 255) / 256)), 256, 0, s, n, u, sc, sf, scc, sic, has_coarse,
@@ -940,12 +968,16 @@ hipError_t launch_pre(int dim, int n, cpx<T>* u, cpx<T>* sc, const cpx<T>* sf, c
 template <class T>
 hipError_t launch_fine_pre(int dim, int n, const cpx<T>* w, cpx<T>* u, const cpx<T>* scc, const cpx<T>* sic,
                            int has_coarse, int bpx, hipStream_t s) {
+  if (dim == 3 && has_coarse && n >= kProlongMarchMinN)
+    return launch_prolong_march3<T, kPmFine>(n, u, const_cast<cpx<T>*>(w), nullptr, scc, sic, bpx, s);
   MG_DISPATCH(dim, k_fine_pre, row_grid(n, dim), n, w, u, scc, sic, has_coarse, bpx);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_uhat(int dim, int n, const cpx<T>* u, const cpx<T>* uc, cpx<T>* uh, hipStream_t s) {
+  if (dim == 3 && n >= kProlongMarchMinN)
+    return launch_prolong_march3<T, kPmSurplus>(n, uh, const_cast<cpx<T>*>(u), nullptr, uc, nullptr, 0, s);
   MG_DISPATCH(dim, k_uhat, row_grid(n, dim), n, u, uc, uh);
   return hipGetLastError();
 }

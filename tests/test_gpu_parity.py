@@ -118,6 +118,9 @@ CYCLE_CASES = [
     (3, 3, 1, "bpx", "galerkin", "generic", "const", "const"),
     (3, 3, 1, "bpx", "fas", "generic", "varying", "const"),
     (3, 3, 3, "bpx", "galerkin", "generic", "const", "const"),
+    # 82^3: the finest descent and the surplus as z marches
+    (3, 4, 1, "bpx", "fas", "generic", "varying", "const"),
+    (3, 4, 2, "hb", "galerkin", "generic", "const", "exp"),
     # fused finest sweep: grids of several tiles with ragged tails in every axis
     (2, 4, 1, "add", "galerkin", "fused", "const", "const"),
     (2, 5, 1, "hb", "galerkin", "fused", "const", "exp"),
