@@ -613,6 +613,79 @@ def multichannel_extra(torch, level=5):
     return out
 
 
+def adapt_extra(torch, reps=10):
+    """Feature-based adaptivity on the headline envelope (3D levels 1..6,
+    730^3 finest): base grid 244^3; level 5 is marked (10 % refine, 2 % erase,
+    20 bins, residual veto 1e-2) and adapted, then the partial level 6 is
+    marked and its hanging and new vertices interpolated.  Field: four complex
+    Gaussian bumps on noise, drawn on the device; residual: uniform noise of
+    size 1e-4.  Marking reads u and r of every persistent vertex and the class
+    byte of every vertex and writes one mark byte per vertex: 2 B per vertex
+    of the envelope + 32 B per candidate is the algorithmic traffic."""
+    import numpy as np
+    from paper_1508_03954_amd import mg
+    dim, lmin, lkeep, lmax = 3, 1, 5, 6
+    a = mg.Adapt(dim, lmin, lkeep, lmax)
+
+    def field(level, seed, scale=None):
+        n = 3 ** level + 1
+        g = torch.Generator(device="cuda").manual_seed(seed)
+        if scale is not None:
+            return torch.complex(scale * (2 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64) - 1),
+                                 scale * (2 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64) - 1))
+        u = torch.complex(1e-3 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64),
+                          1e-3 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64))
+        rng = np.random.default_rng(seed)
+        x = torch.arange(n, device="cuda", dtype=torch.float64) / 3 ** level
+        for _ in range(4):
+            c, sig = rng.uniform(0.2, 0.8, 3), rng.uniform(0.03, 0.08)
+            amp = complex(rng.uniform(-1, 1), rng.uniform(-1, 1))
+            gz, gy, gx = (torch.exp(-(x - c[i]) ** 2 / (2 * sig * sig)) for i in range(3))
+            u += amp * (gz[:, None, None] * gy[None, :, None] * gx[None, None, :])
+        return u
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"workload": "3D envelope levels 1..6 (730^3 finest), base grid 244^3, 20 bins, 10 % refine, 2 % erase, "
+                       "veto 1e-2; u = 4 complex Gaussian bumps on noise, r = noise 1e-4"}
+    u5, r5 = field(5, 81), field(5, 82, 1e-4)
+    ms5 = timed(lambda: a.mark(5, u5, r5, 1.0, stats=False))
+    st5 = a.mark(5, u5, r5, 1.0)
+    counts = a.adapt()
+    n5, n6 = (3 ** 5 + 1) ** 3, (3 ** 6 + 1) ** 3
+    out["level5"] = {"mark_ms": ms5, "candidates": st5["n"], "refined": st5["refined"], "erased": st5["erased"],
+                     "k": st5["k"], "e": st5["e"],
+                     "mark_GBs": (2 * n5 + 32 * st5["n"]) / (ms5 * 1e-3) / 1e9}
+    out["level6_classes"] = dict(zip(("absent", "persistent", "hanging", "boundary"), counts[6]))
+    del u5, r5
+    u6, r6 = field(6, 83), field(6, 84, 1e-4)
+    ms6 = timed(lambda: a.mark(6, u6, r6, 1.0, stats=False))
+    st6 = a.mark(6, u6, r6, 1.0)
+    out["level6"] = {"mark_ms": ms6, "candidates": st6["n"], "erased": st6["erased"],
+                     "mark_GBs": (2 * n6 + 32 * st6["n"]) / (ms6 * 1e-3) / 1e9}
+    del r6
+    # one adaptation step of every level (cells, then classes; no new marks)
+    out["adapt_ms"] = timed(lambda: a.adapt(counts=False))
+    uc = field(5, 85, 1.0)
+    out["interpolate_level6_ms"] = timed(lambda: a.interpolate(6, uc, u6))
+    a.close()
+    del u6, uc
+    torch.cuda.empty_cache()
+    log(f"[bench] adaptivity: mark 244^3 {ms5:.3f} ms ({out['level5']['mark_GBs']:.0f} GB/s), "
+        f"mark 730^3 envelope ({st6['n']} candidates) {ms6:.3f} ms ({out['level6']['mark_GBs']:.0f} GB/s), "
+        f"adapt {out['adapt_ms']:.3f} ms, interpolate 730^3 {out['interpolate_level6_ms']:.3f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -639,6 +712,8 @@ def main():
                     help="run only the 3D level-5 k=20 workload and print its record; for counter runs")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the potential (varying phi, adjoint) workload and print its record")
+    ap.add_argument("--adapt-only", action="store_true",
+                    help="run only the feature-based adaptivity measurement and print its record")
     ap.add_argument("--multichannel-only", action="store_true",
                     help="run only the same-grid multichannel measurement and print its record")
     args = ap.parse_args()
@@ -652,7 +727,7 @@ def main():
     # the CPU baseline runs first, before the device is touched: its worker
     # processes are forked from a process without GPU state
     cpu = None
-    if not (args.no_cpu_baseline or args.batched_only or args.csg_only or args.adjoint_only or args.multichannel_only):
+    if not (args.no_cpu_baseline or args.batched_only or args.csg_only or args.adjoint_only or args.multichannel_only or args.adapt_only):
         log("[bench] CPU baseline: FP64 oracle on the host ...")
         cpu = cpu_baseline(args.cpu_procs)
         log(f"[bench] oracle {cpu['value']:.3e} vertex-updates/s on {cpu['cores']} processes, "
@@ -664,13 +739,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     mg.load_library()
-    if args.batched_only or args.csg_only or args.adjoint_only or args.multichannel_only:
+    if args.batched_only or args.csg_only or args.adjoint_only or args.multichannel_only or args.adapt_only:
         if args.batched_only:
             out = {"batched": batched_extra(torch, solve=not args.no_solve)}
         elif args.csg_only:
             out = {"csg_l5": csg_extra(args, torch)}
         elif args.adjoint_only:
             out = {"potential_adjoint": adjoint_extra(torch)}
+        elif args.adapt_only:
+            out = {"adapt": adapt_extra(torch)}
         else:
             out = {"multichannel": multichannel_extra(torch)}
         if args.copy_probe:
@@ -710,6 +787,7 @@ def main():
         out["extra_2d_k10_latency"] = latency_extra(torch)
         out["extra_potential_adjoint"] = adjoint_extra(torch)
         out["extra_multichannel"] = multichannel_extra(torch)
+        out["extra_adapt"] = adapt_extra(torch)
         out["batched"] = batched_extra(torch, solve=not args.no_solve)
     if cpu is not None:
         out["cpu_baseline"] = cpu

@@ -432,6 +432,75 @@ int mg_mc_cycle(mg_mc* ctx, int ncycles, double* res_h);
  * (device, AoS; may be NULL). */
 int mg_mc_flush(mg_mc* ctx, mg_c128* u);
 
+/* ---------------------------------------------------------------------------
+ * Feature-based dynamic adaptivity (Section 5.3) with hanging vertices
+ * (Section 4), on a dense envelope of levels level_min..level_max: every level
+ * is held as its full regular grid (3^l + 1 vertices per axis, C order, x
+ * fastest), with one byte per cell ("refined into the 3^d cells of level
+ * l+1", levels below level_max) and one class byte per vertex.  A cell is
+ * present on level_min, and below it where its parent cell is refined.
+ *
+ * Vertex classes: MG_AMR_ABSENT (no adjacent cell present), PERSISTENT
+ * (interior, all 2^d adjacent cells present: an unknown of the level),
+ * HANGING (interior, some adjacent cells present: its value comes from the
+ * coarser level through P), BOUNDARY (on the domain boundary, present).
+ * Marks: MG_AMR_KEEP, REFINE (refine the vertex's 2^d cells), ERASE (return
+ * them to leaves).  The device arrays are owned by the object; all calls run
+ * on its stream; calls with host outputs synchronise it.
+ */
+typedef struct mg_amr mg_amr;
+enum { MG_AMR_ABSENT = 0, MG_AMR_PERSISTENT = 1, MG_AMR_HANGING = 2, MG_AMR_BOUNDARY = 3 };
+enum { MG_AMR_KEEP = 0, MG_AMR_REFINE = 1, MG_AMR_ERASE = 2 };
+
+/* dim 2 or 3, 1 <= level_min <= level_keep <= level_max (3D: <= 6, 2D: <= 9).
+ * level_keep is the coarsest admissible mesh (h_max = 3^-level_keep): cells of
+ * coarser levels stay refined; level_max the finest (h_min).  Starts as the
+ * regular grid of level_keep.  Allocates 3 bytes per vertex and 1 per cell of
+ * every level.  MG_EINVAL / MG_ENOMEM / MG_EDEVICE; *out NULL on failure. */
+int mg_amr_setup(int dim, int level_min, int level_keep, int level_max, void* hip_stream, mg_amr** out);
+void mg_amr_destroy(mg_amr* amr);
+
+/* Marks one level (Section 5.3).  u: DEVICE level field (complex128, n^d);
+ * r: DEVICE residual of the level or NULL (no veto); diag: the level's
+ * (constant) diagonal.  Candidates are the persistent vertices; their
+ * criterion s = max over axes a of |u(j+e_a) - 2u(j) + u(j-e_a)| is binned
+ * into nbins (1..64; the paper: 20) equal subranges of [min s, max s]; the k
+ * top bins whose count is closest to refine_pct % of the candidates are
+ * marked REFINE (none on level_max), the e bottom bins closest to erase_pct %
+ * (e <= nbins - k) ERASE (none below level_keep); ties take fewer bins.  A
+ * vertex with |r|^2 > veto^2 |diag|^2 (the paper: veto 1e-2) keeps.  The
+ * marks are kept for mg_amr_adapt (and readable with mg_amr_get).
+ * counts (HOST, nbins + 5, or NULL): the bin counts, k, e, candidates, REFINE
+ * marks, ERASE marks; s_range (HOST, 2, or NULL): min s, max s. */
+int mg_amr_mark(mg_amr* amr, int level, const mg_c128* u, const mg_c128* r, mg_c128 diag, int nbins,
+                int refine_pct, int erase_pct, double veto, long long* counts, double* s_range);
+
+/* One adaptation step from the marks of the levels marked since the last
+ * step: refined-cell flags from level_max - 1 up to level_min (REFINE refines
+ * the vertex's cells; ERASE returns a cell to a leaf unless a REFINE mark also
+ * touches it or one of its children is refined after the step), then the
+ * vertex classes of every level (the previous ones are kept for
+ * mg_amr_interpolate).  class_counts (HOST, 4 per level from level_min, or
+ * NULL): absent, persistent, hanging, boundary vertices. */
+int mg_amr_adapt(mg_amr* amr, long long* class_counts);
+
+/* Values of level `level` (level_min < level <= level_max) after a step
+ * (Sections 4 and 5.3): vertices now hanging, and vertices now persistent that
+ * were not, take (P u_coarse); absent and boundary vertices are set to 0; the
+ * others keep theirs.  u_coarse: DEVICE level - 1 field; u: DEVICE, in/out. */
+int mg_amr_interpolate(mg_amr* amr, int level, const mg_c128* u_coarse, mg_c128* u);
+
+/* Copies state to DEVICE memory: what 0 = vertex classes, 1 = classes before
+ * the last step (n^d bytes each), 2 = refined-cell flags ((n-1)^d bytes, not
+ * on level_max), 3 = the level's last marks (n^d bytes). */
+int mg_amr_get(mg_amr* amr, int level, int what, unsigned char* out);
+
+/* Replaces the refined-cell flags of one level (level_min <= level <
+ * level_max) from DEVICE bytes and recomputes every level's classes (previous
+ * classes = new ones).  A refined cell whose parent is not refined is the
+ * caller's error and is not checked. */
+int mg_amr_set_cells(mg_amr* amr, int level, const unsigned char* cells);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmg.so")
-SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip", "mg_batch.hip", "mg_multichannel.hip"]
+SOURCES = ["mg_kernels.hip", "mg_fused.hip", "mg_api.hip", "mg_batch.hip", "mg_multichannel.hip", "mg_adapt.hip"]
+# per-source flags: the adaptivity marks are integer decisions taken from FP64
+# values, so that file rounds every operation on its own (no contraction)
+EXTRA = {"mg_adapt.hip": ["-ffp-contract=off"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -29,7 +32,7 @@ FLAGS = [
 
 def _compile(src: str, build_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -34,6 +34,8 @@ EXPORTED = [
     "mg_batch_trace", "mg_batch_get_trace", "mg_prolong", "mg_solve_nested", "mg_batch_set_spin_limit",
     "mg_residual_norm_noalloc", "mg_batch_precondition_apply", "mg_mc_setup", "mg_mc_destroy", "mg_mc_apply",
     "mg_mc_set_rhs", "mg_mc_set_solution", "mg_mc_cycle", "mg_mc_flush", "mg_batch_set_config",
+    "mg_amr_setup", "mg_amr_destroy", "mg_amr_mark", "mg_amr_adapt", "mg_amr_interpolate", "mg_amr_get",
+    "mg_amr_set_cells",
 ]
 
 
@@ -121,8 +123,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_mc_set_solution.argtypes = [P, P]
     lib.mg_mc_cycle.argtypes = [P, I, ctypes.POINTER(D)]
     lib.mg_mc_flush.argtypes = [P, P]
+    L = ctypes.c_longlong
+    lib.mg_amr_setup.argtypes = [I, I, I, I, P, ctypes.POINTER(P)]
+    lib.mg_amr_destroy.argtypes = [P]
+    lib.mg_amr_destroy.restype = None
+    lib.mg_amr_mark.argtypes = [P, I, P, P, c128, I, I, I, D, ctypes.POINTER(L), ctypes.POINTER(D)]
+    lib.mg_amr_adapt.argtypes = [P, ctypes.POINTER(L)]
+    lib.mg_amr_interpolate.argtypes = [P, I, P, P]
+    lib.mg_amr_get.argtypes = [P, I, I, P]
+    lib.mg_amr_set_cells.argtypes = [P, I, P]
     for name in EXPORTED:
-        if name not in ("mg_params_default", "mg_destroy", "mg_last_error", "mg_batch_destroy", "mg_mc_destroy"):
+        if name not in ("mg_params_default", "mg_destroy", "mg_last_error", "mg_batch_destroy", "mg_mc_destroy",
+                        "mg_amr_destroy"):
             getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -560,3 +572,107 @@ class MultiChannel:
         u = self._torch.zeros(self.shape, dtype=self._torch.complex128, device="cuda")
         _check(self._lib.mg_mc_flush(self._m, _ptr(u)))
         return u
+
+
+AMR_CLASSES = {"absent": 0, "persistent": 1, "hanging": 2, "boundary": 3}
+AMR_MARKS = {"keep": 0, "refine": 1, "erase": 2}
+
+
+class Adapt:
+    """Feature-based adaptivity state of a dense envelope of levels
+    level_min..level_max (one refined flag per cell, one class per vertex)."""
+
+    def __init__(self, dim: int, level_min: int, level_keep: int, level_max: int, stream=None):
+        import torch
+        self._torch = torch
+        lib = load_library()
+        self._lib = lib
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        a = ctypes.c_void_p()
+        _check(lib.mg_amr_setup(dim, level_min, level_keep, level_max, self.stream.cuda_stream, ctypes.byref(a)))
+        self._a = a
+        self.dim, self.level_min, self.level_keep, self.level_max = dim, level_min, level_keep, level_max
+
+    def close(self):
+        if getattr(self, "_a", None) is not None and self._a.value:
+            self._lib.mg_amr_destroy(self._a)
+            self._a = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n(self, level: int) -> int:
+        return 3 ** level + 1
+
+    def _field(self, x, level):
+        t = self._torch
+        if not isinstance(x, t.Tensor):
+            x = t.from_numpy(np.ascontiguousarray(x))
+        x = x.to(device="cuda", dtype=t.complex128).contiguous()
+        if tuple(x.shape) != (self.n(level),) * self.dim:
+            raise ValueError(f"expected shape {(self.n(level),) * self.dim}, got {tuple(x.shape)}")
+        return x
+
+    def mark(self, level: int, u, r=None, diag: complex = 1.0, nbins: int = 20, refine_pct: int = 10,
+             erase_pct: int = 2, veto: float = 1e-2, stats: bool = True):
+        """Marks a level; returns a dict of the statistics (or None)."""
+        u = self._field(u, level)
+        rp = None
+        if r is not None:
+            r = self._field(r, level)
+            rp = _ptr(r)
+        d = complex(diag)
+        if not stats:
+            _check(self._lib.mg_amr_mark(self._a, level, _ptr(u), rp, c128(d.real, d.imag), nbins, refine_pct,
+                                         erase_pct, veto, None, None))
+            return None
+        cnt = (ctypes.c_longlong * (nbins + 5))()
+        rng = (ctypes.c_double * 2)()
+        _check(self._lib.mg_amr_mark(self._a, level, _ptr(u), rp, c128(d.real, d.imag), nbins, refine_pct,
+                                     erase_pct, veto, cnt, rng))
+        c = list(cnt)
+        return dict(counts=np.array(c[:nbins], dtype=np.int64), k=c[nbins], e=c[nbins + 1], n=c[nbins + 2],
+                    refined=c[nbins + 3], erased=c[nbins + 4], s_min=rng[0], s_max=rng[1])
+
+    def adapt(self, counts: bool = True):
+        """One adaptation step; per level (absent, persistent, hanging, boundary) counts or None."""
+        if not counts:
+            _check(self._lib.mg_amr_adapt(self._a, None))
+            return None
+        nl = self.level_max - self.level_min + 1
+        out = (ctypes.c_longlong * (4 * nl))()
+        _check(self._lib.mg_amr_adapt(self._a, out))
+        return {l: tuple(out[4 * (l - self.level_min):4 * (l - self.level_min) + 4])
+                for l in range(self.level_min, self.level_max + 1)}
+
+    def interpolate(self, level: int, u_coarse, u):
+        """In place on the device tensor u (level `level`); returns u."""
+        uc = self._field(u_coarse, level - 1)
+        if not (isinstance(u, self._torch.Tensor) and u.is_cuda and u.dtype == self._torch.complex128
+                and u.is_contiguous() and tuple(u.shape) == (self.n(level),) * self.dim):
+            raise ValueError("u must be a contiguous complex128 device tensor of the level's shape")
+        _check(self._lib.mg_amr_interpolate(self._a, level, _ptr(uc), _ptr(u)))
+        return u
+
+    def get(self, level: int, what: str):
+        """'classes', 'classes_old', 'cells' or 'marks' of a level (uint8 device tensor)."""
+        t = self._torch
+        code = {"classes": 0, "classes_old": 1, "cells": 2, "marks": 3}[what]
+        shape = (3 ** level,) * self.dim if code == 2 else (self.n(level),) * self.dim
+        out = t.empty(shape, dtype=t.uint8, device="cuda")
+        _check(self._lib.mg_amr_get(self._a, level, code, _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def set_cells(self, level: int, cells):
+        t = self._torch
+        if not isinstance(cells, t.Tensor):
+            cells = t.from_numpy(np.ascontiguousarray(cells, dtype=np.uint8))
+        cells = cells.to(device="cuda", dtype=t.uint8).contiguous()
+        if tuple(cells.shape) != (3 ** level,) * self.dim:
+            raise ValueError("cells must have (3^level,)*dim entries")
+        _check(self._lib.mg_amr_set_cells(self._a, level, _ptr(cells)))
+        self.stream.synchronize()
