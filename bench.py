@@ -618,8 +618,9 @@ def adapt_extra(torch, reps=10):
     730^3 finest): base grid 244^3; level 5 is marked (10 % refine, 2 % erase,
     20 bins, residual veto 1e-2) and adapted, then the partial level 6 is
     marked and its hanging and new vertices interpolated.  Field: four complex
-    Gaussian bumps on noise, drawn on the device; residual: uniform noise of
-    size 1e-4.  Marking reads u and r of every persistent vertex and the class
+    Gaussian bumps on uniform noise of size 1e-5 (small against the bumps'
+    curvature, so that refinement follows the bumps), drawn on the device;
+    residual: uniform noise of size 1e-4.  Marking reads u and r of every persistent vertex and the class
     byte of every vertex and writes one mark byte per vertex: 2 B per vertex
     of the envelope + 32 B per candidate is the algorithmic traffic."""
     import numpy as np
@@ -633,8 +634,8 @@ def adapt_extra(torch, reps=10):
         if scale is not None:
             return torch.complex(scale * (2 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64) - 1),
                                  scale * (2 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64) - 1))
-        u = torch.complex(1e-3 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64),
-                          1e-3 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64))
+        u = torch.complex(1e-5 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64),
+                          1e-5 * torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64))
         rng = np.random.default_rng(seed)
         x = torch.arange(n, device="cuda", dtype=torch.float64) / 3 ** level
         for _ in range(4):
@@ -656,7 +657,7 @@ def adapt_extra(torch, reps=10):
         return e0.elapsed_time(e1) / reps
 
     out = {"workload": "3D envelope levels 1..6 (730^3 finest), base grid 244^3, 20 bins, 10 % refine, 2 % erase, "
-                       "veto 1e-2; u = 4 complex Gaussian bumps on noise, r = noise 1e-4"}
+                       "veto 1e-2; u = 4 complex Gaussian bumps on noise 1e-5, r = noise 1e-4"}
     u5, r5 = field(5, 81), field(5, 82, 1e-4)
     ms5 = timed(lambda: a.mark(5, u5, r5, 1.0, stats=False))
     st5 = a.mark(5, u5, r5, 1.0)

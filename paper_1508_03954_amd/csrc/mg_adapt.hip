@@ -118,6 +118,194 @@ __global__ __launch_bounds__(256) void k_amr_range(int n, const cpx<double>* __r
   }
 }
 
+// The two criterion passes on a 3D level as a march along z: a wavefront
+// takes 64 x of one row and a chunk of kAmrTz planes.  A chunk without a
+// candidate is skipped on one bit of the level's activity map (kept by the
+// classification).  The class bytes of an active chunk are read first (one
+// round trip); a plane in which no lane of the
+// wavefront holds a candidate costs nothing more.  On the others the
+// wavefront reads its row of u and keeps the rows z-1, z, z+1 in registers,
+// takes x-1 and x+1 from the neighbouring lanes (the two end lanes read
+// theirs), and reads the rows y-1 and y+1 and the residual for its
+// candidates; when the next plane has candidates too, its reads are issued
+// before this plane is evaluated, so that they are in flight meanwhile.  The
+// differences are formed in the same order as amr_s2.  MODE 0: range
+// partials (as k_amr_range); MODE 1: bins, veto bits and bin counts (as
+// k_amr_bin).
+constexpr int kAmrTz = 8;
+constexpr int kLaneLeft = 0x138;    // wave shift: lane l receives lane l-1 (0 at lane 0)
+constexpr int kLaneRight = 0x130;   // lane l receives lane l+1 (0 at lane 63)
+
+template <int CTRL>
+__device__ inline double lane_move(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo));
+}
+
+__device__ inline double axis_m2(cpx<double> p, cpx<double> m, double cr, double ci) {
+  const double dr = (p.re + m.re) - cr, di = (p.im + m.im) - ci;
+  return dr * dr + di * di;
+}
+
+dim3 amr_march_grid(int n) {
+  const int gx = (n + 63) / 64;
+  const long long items = (long long)n * ((n + kAmrTz - 1) / kAmrTz);
+  const long long gy = std::max<long long>(1, std::min<long long>((items + 3) / 4, kAmrMaxParts / gx));
+  return dim3((unsigned)gx, (unsigned)gy);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __restrict__ u,
+                                                   const cpx<double>* __restrict__ r,
+                                                   const uint8_t* __restrict__ cls,
+                                                   const uint32_t* __restrict__ act_map, double* __restrict__ part,
+                                                   const double* __restrict__ stats, int nb,
+                                                   uint8_t* __restrict__ marks,
+                                                   unsigned long long* __restrict__ hist) {
+  const int lane = threadIdx.x & 63;
+  const int x = blockIdx.x * 64 + lane;
+  const bool xin = x < n;
+  const int xc = xin ? x : n - 1;   // lanes past the row read a valid vertex and hold no candidate
+  // the end lanes' extra read: x-1 for lane 0, x+1 for lane 63 (0 where it would leave the row)
+  const int hoff = (lane == 0 && xc > 0) ? -1 : ((lane == 63 && xc < n - 1) ? 1 : 0);
+  const int nzc = (n + kAmrTz - 1) / kAmrTz;
+  const long long plane = (long long)n * n;
+  const long long safe = plane + n + 1;   // vertex (1, 1, 1): reads of lanes without a candidate go there
+  __shared__ unsigned sh[kAmrMaxBins];
+  __shared__ double shr[3][4];
+  double smin = 0, smax = 0, thr = 0, range = 1, dnb = (double)nb;
+  bool spread = false;
+  if (MODE == 1) {
+    for (int t = threadIdx.x; t < kAmrMaxBins; t += 256) sh[t] = 0;
+    __syncthreads();
+    smin = stats[0];
+    smax = stats[1];
+    thr = stats[3];
+    spread = smax > smin;
+    range = smax - smin;
+  }
+  double lo = HUGE_VAL, hi = -HUGE_VAL, cnt = 0;
+  unsigned mine = 0;
+  for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
+       t += gridDim.y * 4) {
+    const long long it = (long long)t * gridDim.x + blockIdx.x;
+    if (!((act_map[it >> 5] >> (it & 31)) & 1u)) continue;   // no candidate in the chunk
+    const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
+    const long long row = (long long)y * n + xc;
+    bool cand[kAmrTz];
+    unsigned act = 0;   // bit q: plane zs + q has a candidate in the wavefront
+#pragma unroll
+    for (int q = 0; q < kAmrTz; ++q) {
+      const int z = min(zs + q, ze - 1);
+      cand[q] = xin && cls[(long long)z * plane + row] == kPersistent;
+      if (zs + q < ze && __ballot(cand[q]) != 0) act |= 1u << q;
+    }
+    bool ready = false;
+    cpx<double> cm = czero<double>(), c0 = czero<double>(), cp = czero<double>();
+    cpx<double> ym = czero<double>(), yp = czero<double>(), h = czero<double>(), rv = czero<double>();
+#pragma unroll
+    for (int q = 0; q < kAmrTz; ++q) {
+      const int z = zs + q;
+      if (z >= ze) break;
+      const long long i = (long long)z * plane + row;
+      if (!(act & (1u << q))) {
+        ready = false;
+        if (MODE == 1 && xin) marks[i] = kNotCand;
+        continue;
+      }
+      const bool p = cand[q];
+      if (!ready) {
+        const long long k = p ? i : safe;
+        cm = u[i - (z > 0 ? plane : 0)];
+        c0 = u[i];
+        cp = u[i + (z < n - 1 ? plane : 0)];
+        ym = u[k - n];
+        yp = u[k + n];
+        h = u[i + hoff];
+        if (MODE == 1 && r) rv = r[k];
+      }
+      // the next plane's reads, issued before this plane is evaluated
+      const bool nxt = q + 1 < kAmrTz && (act & (2u << q));
+      cpx<double> cp1 = czero<double>(), ym1 = czero<double>(), yp1 = czero<double>(), h1 = czero<double>(),
+                  rv1 = czero<double>();
+      if (nxt) {
+        const long long i1 = i + plane;
+        const long long k1 = cand[q + 1] ? i1 : safe;
+        cp1 = u[i1 + (z + 2 <= n - 1 ? plane : 0)];
+        ym1 = u[k1 - n];
+        yp1 = u[k1 + n];
+        h1 = u[i1 + hoff];
+        if (MODE == 1 && r) rv1 = r[k1];
+      }
+      cpx<double> xm = mk(lane_move<kLaneLeft>(c0.re), lane_move<kLaneLeft>(c0.im));
+      cpx<double> xp = mk(lane_move<kLaneRight>(c0.re), lane_move<kLaneRight>(c0.im));
+      if (lane == 0) xm = h;
+      if (lane == 63) xp = h;
+      const double cr = c0.re + c0.re, ci = c0.im + c0.im;
+      double s2 = axis_m2(xp, xm, cr, ci);
+      const double my = axis_m2(yp, ym, cr, ci), mz = axis_m2(cp, cm, cr, ci);
+      s2 = my > s2 ? my : s2;
+      s2 = mz > s2 ? mz : s2;
+      if (MODE == 0) {
+        if (p) {
+          lo = fmin(lo, s2);
+          hi = fmax(hi, s2);
+          cnt += 1;
+        }
+      } else {
+        const double sv = sqrt(s2);
+        int b = 0;
+        if (spread) {
+          const double qq = floor(((sv - smin) / range) * dnb);
+          b = qq >= dnb - 1 ? nb - 1 : (int)qq;
+        }
+        const bool v = r && (rv.re * rv.re + rv.im * rv.im > thr);
+        if (xin) marks[i] = p ? (uint8_t)(b | (v ? kVetoBit : 0)) : kNotCand;
+        const int bp = p ? b : -1;
+        for (int k = 0; k < nb; ++k) {
+          const unsigned long long bm = __ballot(bp == k);
+          if (lane == k) mine += (unsigned)__popcll(bm);
+        }
+      }
+      ready = nxt;
+      if (nxt) {
+        cm = c0;
+        c0 = cp;
+        cp = cp1;
+        ym = ym1;
+        yp = yp1;
+        h = h1;
+        rv = rv1;
+      }
+    }
+  }
+  if (MODE == 0) {
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    cnt = wave_sum(cnt);
+    const int w = threadIdx.x >> 6;
+    if (lane == 0) {
+      shr[0][w] = lo;
+      shr[1][w] = hi;
+      shr[2][w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const long long b = blockIdx.y * (long long)gridDim.x + blockIdx.x;
+      part[3 * b + 0] = fmin(fmin(shr[0][0], shr[0][1]), fmin(shr[0][2], shr[0][3]));
+      part[3 * b + 1] = fmax(fmax(shr[1][0], shr[1][1]), fmax(shr[1][2], shr[1][3]));
+      part[3 * b + 2] = (shr[2][0] + shr[2][1]) + (shr[2][2] + shr[2][3]);
+    }
+  } else {
+    if (lane < nb && mine) atomicAdd(&sh[lane], mine);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb; q += 256)
+      if (sh[q]) atomicAdd(&hist[q], (unsigned long long)sh[q]);
+  }
+}
+
 // One block: s_min, s_max, count and the veto threshold veto^2 |diag|^2 into
 // stats; clears the bin counts and the mark counters.
 __global__ __launch_bounds__(256) void k_amr_range_finish(const double* __restrict__ part, int nparts,
@@ -235,35 +423,38 @@ __device__ inline void amr_choose(const unsigned long long* hist, int nb, long l
   }
 }
 
-// Bins to marks, four bytes per lane; counts the refine and erase marks.
+// One thread: the numbers of top and bottom bins into stats[4], stats[5].
+__global__ void k_amr_choose(const unsigned long long* __restrict__ hist, double* __restrict__ stats, int nb,
+                             int rpct, int epct) {
+  if (threadIdx.x != 0) return;
+  unsigned long long h[kAmrMaxBins];
+  for (int t = 0; t < nb; ++t) h[t] = hist[t];
+  int k, e;
+  amr_choose(h, nb, (long long)stats[2], rpct, epct, k, e);
+  stats[4] = k;
+  stats[5] = e;
+}
+
+// Bins to marks, four bytes per lane (with the four class bytes); counts the
+// refine and erase marks.
 __global__ __launch_bounds__(256) void k_amr_decide(long long nwords, uint32_t* __restrict__ marks,
+                                                    const uint32_t* __restrict__ cls,
                                                     const unsigned long long* __restrict__ hist,
                                                     double* __restrict__ stats, int nb, int rpct, int epct,
                                                     int can_refine, int can_erase,
                                                     unsigned long long* __restrict__ counters) {
-  __shared__ int sk, se;
   __shared__ double sr[4], se_[4];
-  if (threadIdx.x == 0) {
-    int k, e;
-    amr_choose(hist, nb, (long long)stats[2], rpct, epct, k, e);
-    sk = k;
-    se = e;
-    if (blockIdx.x == 0) {
-      stats[4] = k;
-      stats[5] = e;
-    }
-  }
-  __syncthreads();
-  const uint32_t top = (uint32_t)(nb - sk), bot = (uint32_t)se;
+  const uint32_t top = (uint32_t)(nb - (int)stats[4]), bot = (uint32_t)(int)stats[5];
   double nr = 0, ne = 0;
   for (long long w = blockIdx.x * 256ll + threadIdx.x; w < nwords; w += (long long)gridDim.x * 256) {
-    const uint32_t v = marks[w];
+    const uint32_t v = marks[w], cw = cls[w];
     uint32_t o = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t m = (v >> (8 * q)) & 0xFFu;
       uint32_t d = kKeep;
-      if (!(m & (kNotCand | kVetoBit))) {
+      // only candidates carry a bin (other bytes may be left from earlier calls)
+      if (((cw >> (8 * q)) & 0xFFu) == kPersistent && !(m & (kNotCand | kVetoBit))) {
         const uint32_t b = m & kBinMask;
         if (can_refine && b >= top) d = kRefine;
         else if (can_erase && b < bot) d = kErase;
@@ -340,31 +531,45 @@ __global__ __launch_bounds__(256) void k_amr_cells(int ncell, uint8_t* __restric
 // cell is present).
 template <int D>
 __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict__ cls,
-                                                      const uint8_t* __restrict__ parent) {
+                                                      const uint8_t* __restrict__ parent,
+                                                      uint32_t* __restrict__ act_map) {
+  const long long pc = (n - 1) / 3;
   MG_ROWS(D, n) {
     int j[3];
     long long i;
-    if (!row_vertex<D>(row_, x_, n, j, i)) continue;
-    bool inner = true;
-    for (int a = 0; a < D; ++a) inner = inner && j[a] >= 1 && j[a] <= n - 2;
-    int cnt = 0;
-    const long long pc = (n - 1) / 3;
-    for (int k = 0; k < (1 << D); ++k) {
-      int c[3] = {j[0] - (k & 1), j[1] - ((k >> 1) & 1), D == 3 ? j[2] - ((k >> 2) & 1) : 0};
-      bool ok = true;
-      for (int a = 0; a < D; ++a) ok = ok && c[a] >= 0 && c[a] <= n - 2;
-      if (!ok) continue;
-      if (parent) {
-        long long pi = c[0] / 3 + pc * (c[1] / 3);
-        if (D == 3) pi += pc * pc * (c[2] / 3);
-        if (!parent[pi]) continue;
+    const bool in_row = row_vertex<D>(row_, x_, n, j, i);
+    uint8_t v = kAbsent;
+    if (in_row) {
+      bool inner = true;
+      for (int a = 0; a < D; ++a) inner = inner && j[a] >= 1 && j[a] <= n - 2;
+      // the 2^d cells around the vertex: loads with clamped indices and no
+      // branch, validity applied afterwards, so that they issue together
+      int cnt = 0;
+#pragma unroll
+      for (int k = 0; k < (1 << D); ++k) {
+        bool ok = true;
+        long long pi = 0, mul = 1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const int c = j[a] - ((k >> a) & 1);
+          ok = ok && c >= 0 && c <= n - 2;
+          pi += mul * (min(max(c, 0), n - 2) / 3);
+          mul *= pc;
+        }
+        const int pv = parent ? (int)parent[pi] : 1;
+        cnt += (ok && pv != 0) ? 1 : 0;
       }
-      ++cnt;
+      if (inner) v = cnt == (1 << D) ? kPersistent : (cnt > 0 ? kHanging : kAbsent);
+      else v = cnt > 0 ? kBoundary : kAbsent;
+      cls[i] = v;
     }
-    uint8_t v;
-    if (inner) v = cnt == (1 << D) ? kPersistent : (cnt > 0 ? kHanging : kAbsent);
-    else v = cnt > 0 ? kBoundary : kAbsent;
-    cls[i] = v;
+    // activity map of the 3D criterion march: one bit per (64 x, row, chunk
+    // of kAmrTz planes) that holds a candidate
+    if (D == 3 && act_map && __ballot(v == kPersistent) != 0 && lane_ == 0) {
+      const int z = row_ / n, y = row_ - z * n;
+      const long long it = ((long long)(z / kAmrTz) * n + y) * gridDim.x + blockIdx.x;
+      atomicOr(&act_map[it >> 5], 1u << (it & 31));
+    }
   }
 }
 
@@ -382,6 +587,59 @@ __global__ __launch_bounds__(256) void k_amr_interp(int n, const uint8_t* __rest
     const uint8_t a = cls_new[i];
     if (a == kHanging || (a == kPersistent && cls_old[i] != kPersistent)) u[i] = prolong_at<double, D>(uc, nc, j);
     else if (a == kAbsent || a == kBoundary) u[i] = czero<double>();
+  }
+}
+
+// The same on a 3D level as a march along z: P is separable, so a lane
+// interpolates its coarse corners in x and y once per coarse plane and keeps
+// the two coarse planes that bracket its z in registers; a fine vertex then
+// costs its two class bytes and its store.  Corners are clamped so that every
+// lane (boundary ones included) computes a bracket inside the coarse grid.
+__device__ inline cpx<double> amr_xy(const cpx<double>* __restrict__ v, long long base, const long long ci[4],
+                                     const double cw[4]) {
+  cpx<double> acc = czero<double>();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc = acc + cw[k] * v[base + ci[k]];
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_amr_interp3(int n, const uint8_t* __restrict__ cls_old,
+                                                     const uint8_t* __restrict__ cls_new,
+                                                     const cpx<double>* __restrict__ uc,
+                                                     cpx<double>* __restrict__ u) {
+  const int nc = (n - 1) / 3 + 1;
+  const int lane = threadIdx.x & 63;
+  const int x = blockIdx.x * 64 + lane;
+  const bool xin = x < n;
+  const int nzc = (n + kAmrTz - 1) / kAmrTz;
+  const long long pl = (long long)nc * nc;
+  const int xs = xin ? x : n - 1;
+  const int mx = min(xs / 3, nc - 2);
+  const double wx1 = (double)(xs - 3 * mx) / 3.0, wx0 = 1.0 - wx1;
+  for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
+       t += gridDim.y * 4) {
+    const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
+    const int my = min(y / 3, nc - 2);
+    const double wy1 = (double)(y - 3 * my) / 3.0, wy0 = 1.0 - wy1;
+    const long long ci[4] = {(long long)my * nc + mx, (long long)my * nc + mx + 1, (long long)(my + 1) * nc + mx,
+                             (long long)(my + 1) * nc + mx + 1};
+    const double cw[4] = {wy0 * wx0, wy0 * wx1, wy1 * wx0, wy1 * wx1};
+    int mz = min(zs / 3, nc - 2);
+    cpx<double> s0 = amr_xy(uc, mz * pl, ci, cw), s1 = amr_xy(uc, (mz + 1) * pl, ci, cw);
+    for (int z = zs; z < ze; ++z) {
+      const int m = min(z / 3, nc - 2);
+      if (m != mz) {   // the next coarse interval: shift the bracket by one plane
+        mz = m;
+        s0 = s1;
+        s1 = amr_xy(uc, (mz + 1) * pl, ci, cw);
+      }
+      if (!xin) continue;
+      const long long e = ((long long)z * n + y) * n + x;
+      const uint8_t a = cls_new[e], o = cls_old[e];
+      const double wz1 = (double)(z - 3 * mz) / 3.0, wz0 = 1.0 - wz1;
+      if (a == kHanging || (a == kPersistent && o != kPersistent)) u[e] = wz0 * s0 + wz1 * s1;
+      else if (a == kAbsent || a == kBoundary) u[e] = czero<double>();
+    }
   }
 }
 
@@ -410,6 +668,10 @@ __global__ void k_amr_zero(unsigned long long* __restrict__ p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
+__global__ void k_amr_zero32(uint32_t* __restrict__ p, long long n) {
+  for (long long k = blockIdx.x * 256ll + threadIdx.x; k < n; k += (long long)gridDim.x * 256) p[k] = 0;
+}
+
 template <class F2, class F3, class... A>
 hipError_t amr_launch(int dim, F2 k2, F3 k3, dim3 g, hipStream_t s, A... a) {
   if (dim == 3) hipLaunchKernelGGL(k3, g, dim3(256), 0, s, a...);
@@ -425,6 +687,8 @@ struct AmrLevel {
   uint8_t* marks = nullptr;
   uint8_t* cells = nullptr;   // levels below the finest only
   long long ncells = 0;
+  uint32_t* act = nullptr;    // 3D: activity map of the criterion march
+  long long nact = 0;         // its words
   bool marked = false;
 };
 
@@ -462,8 +726,13 @@ struct mg_amr {
     for (int l = lmin; l <= lmax; ++l) {
       AmrLevel& v = at(l);
       std::swap(v.cls, v.cls_old);
+      if (v.act) {
+        hipLaunchKernelGGL(k_amr_zero32, dim3((unsigned)std::min<long long>((v.nact + 255) / 256, 1024)), dim3(256),
+                           0, s, v.act, v.nact);
+        MG_HIP(hipGetLastError());
+      }
       MG_HIP(amr_launch(dim, k_amr_classify<2>, k_amr_classify<3>, amr_grid(v.n, dim), s, v.n, v.cls,
-                        (const uint8_t*)(l > lmin ? at(l - 1).cells : nullptr)));
+                        (const uint8_t*)(l > lmin ? at(l - 1).cells : nullptr), v.act));
     }
     return MG_OK;
   }
@@ -500,6 +769,13 @@ int mg_amr_setup(int dim, int level_min, int level_keep, int level_max, void* hi
     if (rc == MG_OK) rc = a->alloc((void**)&v.cls_old, v.N);
     if (rc == MG_OK) rc = a->alloc((void**)&v.marks, v.N);
     if (rc == MG_OK && v.ncells) rc = a->alloc((void**)&v.cells, v.ncells);
+    if (rc == MG_OK && dim == 3) {
+      // bits per (x block of 64, row, chunk of planes), as the classification and the march enumerate them
+      const dim3 gc = amr_grid(v.n, dim);
+      const long long bits = (long long)gc.x * v.n * ((v.n + kAmrTz - 1) / kAmrTz);
+      v.nact = (bits + 31) / 32;
+      rc = a->alloc((void**)&v.act, v.nact * sizeof(uint32_t));
+    }
     if (rc == MG_OK && v.ncells) {
       const hipError_t e = hipMemsetAsync(v.cells, l < level_keep ? 1 : 0, v.ncells, a->s);
       if (e != hipSuccess) rc = fail(MG_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
@@ -541,16 +817,32 @@ int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c12
   const dim3 g = amr_grid(v.n, a->dim);
   const int nparts = (int)(g.x * g.y);
   unsigned long long* counters = a->hist + kAmrMaxBins;
-  MG_HIP(amr_launch(a->dim, k_amr_range<2>, k_amr_range<3>, g, a->s, v.n, (const cpx<double>*)u,
-                    (const uint8_t*)v.cls, a->part));
-  hipLaunchKernelGGL(k_amr_range_finish, dim3(1), dim3(256), 0, a->s, (const double*)a->part, nparts, diag.re,
+  const dim3 gm = amr_march_grid(v.n);
+  const bool march = a->dim == 3;
+  const int nparts_used = march ? (int)(gm.x * gm.y) : nparts;
+  if (march) hipLaunchKernelGGL(k_amr_crit3<0>, gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
+                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint32_t*)v.act, a->part,
+                                (const double*)a->stats,
+                                nbins, v.marks, a->hist);
+  else hipLaunchKernelGGL(k_amr_range<2>, g, dim3(256), 0, a->s, v.n, (const cpx<double>*)u, (const uint8_t*)v.cls,
+                          a->part);
+  MG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_amr_range_finish, dim3(1), dim3(256), 0, a->s, (const double*)a->part, nparts_used, diag.re,
                      diag.im, veto, a->stats, a->hist, counters);
   MG_HIP(hipGetLastError());
-  MG_HIP(amr_launch(a->dim, k_amr_bin<2>, k_amr_bin<3>, g, a->s, v.n, (const cpx<double>*)u, (const cpx<double>*)r,
-                    (const uint8_t*)v.cls, (const double*)a->stats, nbins, v.marks, a->hist));
+  if (march) hipLaunchKernelGGL(k_amr_crit3<1>, gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
+                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint32_t*)v.act, a->part,
+                                (const double*)a->stats,
+                                nbins, v.marks, a->hist);
+  else hipLaunchKernelGGL(k_amr_bin<2>, g, dim3(256), 0, a->s, v.n, (const cpx<double>*)u, (const cpx<double>*)r,
+                          (const uint8_t*)v.cls, (const double*)a->stats, nbins, v.marks, a->hist);
+  MG_HIP(hipGetLastError());
   const long long nwords = v.N / 4;
   const unsigned gd = (unsigned)std::min<long long>((nwords + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_amr_decide, dim3(gd), dim3(256), 0, a->s, nwords, (uint32_t*)v.marks,
+  hipLaunchKernelGGL(k_amr_choose, dim3(1), dim3(64), 0, a->s, (const unsigned long long*)a->hist, a->stats, nbins,
+                     refine_pct, erase_pct);
+  MG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_amr_decide, dim3(gd), dim3(256), 0, a->s, nwords, (uint32_t*)v.marks, (const uint32_t*)v.cls,
                      (const unsigned long long*)a->hist, a->stats, nbins, refine_pct, erase_pct,
                      level < a->lmax ? 1 : 0, level >= a->lkeep ? 1 : 0, counters);
   MG_HIP(hipGetLastError());
@@ -611,9 +903,15 @@ int mg_amr_interpolate(mg_amr* a, int level, const mg_c128* u_coarse, mg_c128* u
   if (!a || !u_coarse || !u) return fail(MG_EINVAL, "NULL argument");
   if (level <= a->lmin || level > a->lmax) return fail(MG_EINVAL, "level must lie in (level_min, level_max]");
   AmrLevel& v = a->at(level);
-  MG_HIP(amr_launch(a->dim, k_amr_interp<2>, k_amr_interp<3>, amr_grid(v.n, a->dim), a->s, v.n,
-                    (const uint8_t*)v.cls_old, (const uint8_t*)v.cls, (const cpx<double>*)u_coarse,
-                    (cpx<double>*)u));
+  if (a->dim == 3) {
+    hipLaunchKernelGGL(k_amr_interp3, amr_march_grid(v.n), dim3(256), 0, a->s, v.n, (const uint8_t*)v.cls_old,
+                       (const uint8_t*)v.cls, (const cpx<double>*)u_coarse, (cpx<double>*)u);
+    MG_HIP(hipGetLastError());
+  } else {
+    MG_HIP(amr_launch(a->dim, k_amr_interp<2>, k_amr_interp<3>, amr_grid(v.n, a->dim), a->s, v.n,
+                      (const uint8_t*)v.cls_old, (const uint8_t*)v.cls, (const cpx<double>*)u_coarse,
+                      (cpx<double>*)u));
+  }
   return MG_OK;
 }
 
