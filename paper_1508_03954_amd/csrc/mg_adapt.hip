@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_amr_range(int n, const cpx<double>* __r
 
 // The two criterion passes on a 3D level as a march along z: a wavefront
 // takes 64 x of one row and a chunk of kAmrTz planes.  A chunk without a
-// candidate is skipped on one bit of the level's activity map (kept by the
+// candidate is skipped on one byte of the level's activity map (kept by the
 // classification).  The class bytes of an active chunk are read first (one
 // round trip); a plane in which no lane of the
 // wavefront holds a candidate costs nothing more.  On the others the
@@ -160,7 +160,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __restrict__ u,
                                                    const cpx<double>* __restrict__ r,
                                                    const uint8_t* __restrict__ cls,
-                                                   const uint32_t* __restrict__ act_map, double* __restrict__ part,
+                                                   const uint8_t* __restrict__ act_map, double* __restrict__ part,
                                                    const double* __restrict__ stats, int nb,
                                                    uint8_t* __restrict__ marks,
                                                    unsigned long long* __restrict__ hist) {
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __r
   for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
        t += gridDim.y * 4) {
     const long long it = (long long)t * gridDim.x + blockIdx.x;
-    if (!((act_map[it >> 5] >> (it & 31)) & 1u)) continue;   // no candidate in the chunk
+    if (!act_map[it]) continue;   // no candidate in the chunk
     const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
     const long long row = (long long)y * n + xc;
     bool cand[kAmrTz];
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(256) void k_amr_cells(int ncell, uint8_t* __restric
 template <int D>
 __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict__ cls,
                                                       const uint8_t* __restrict__ parent,
-                                                      uint32_t* __restrict__ act_map) {
+                                                      uint8_t* __restrict__ act_map) {
   const long long pc = (n - 1) / 3;
   MG_ROWS(D, n) {
     int j[3];
@@ -563,12 +563,12 @@ __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict
       else v = cnt > 0 ? kBoundary : kAbsent;
       cls[i] = v;
     }
-    // activity map of the 3D criterion march: one bit per (64 x, row, chunk
-    // of kAmrTz planes) that holds a candidate
+    // activity map of the 3D criterion march: one byte per (64 x, row, chunk
+    // of kAmrTz planes), set to 1 by every wavefront that finds a candidate
+    // there (all writers store the same value, so no atomic is needed)
     if (D == 3 && act_map && __ballot(v == kPersistent) != 0 && lane_ == 0) {
       const int z = row_ / n, y = row_ - z * n;
-      const long long it = ((long long)(z / kAmrTz) * n + y) * gridDim.x + blockIdx.x;
-      atomicOr(&act_map[it >> 5], 1u << (it & 31));
+      act_map[((long long)(z / kAmrTz) * n + y) * gridDim.x + blockIdx.x] = 1;
     }
   }
 }
@@ -687,8 +687,8 @@ struct AmrLevel {
   uint8_t* marks = nullptr;
   uint8_t* cells = nullptr;   // levels below the finest only
   long long ncells = 0;
-  uint32_t* act = nullptr;    // 3D: activity map of the criterion march
-  long long nact = 0;         // its words
+  uint8_t* act = nullptr;     // 3D: activity map of the criterion march
+  long long nact = 0;         // its size in 4-byte words
   bool marked = false;
 };
 
@@ -728,7 +728,7 @@ struct mg_amr {
       std::swap(v.cls, v.cls_old);
       if (v.act) {
         hipLaunchKernelGGL(k_amr_zero32, dim3((unsigned)std::min<long long>((v.nact + 255) / 256, 1024)), dim3(256),
-                           0, s, v.act, v.nact);
+                           0, s, (uint32_t*)v.act, v.nact);
         MG_HIP(hipGetLastError());
       }
       MG_HIP(amr_launch(dim, k_amr_classify<2>, k_amr_classify<3>, amr_grid(v.n, dim), s, v.n, v.cls,
@@ -770,10 +770,10 @@ int mg_amr_setup(int dim, int level_min, int level_keep, int level_max, void* hi
     if (rc == MG_OK) rc = a->alloc((void**)&v.marks, v.N);
     if (rc == MG_OK && v.ncells) rc = a->alloc((void**)&v.cells, v.ncells);
     if (rc == MG_OK && dim == 3) {
-      // bits per (x block of 64, row, chunk of planes), as the classification and the march enumerate them
+      // one byte per (x block of 64, row, chunk of planes), as the classification and the march enumerate them
       const dim3 gc = amr_grid(v.n, dim);
-      const long long bits = (long long)gc.x * v.n * ((v.n + kAmrTz - 1) / kAmrTz);
-      v.nact = (bits + 31) / 32;
+      const long long items = (long long)gc.x * v.n * ((v.n + kAmrTz - 1) / kAmrTz);
+      v.nact = (items + 3) / 4;
       rc = a->alloc((void**)&v.act, v.nact * sizeof(uint32_t));
     }
     if (rc == MG_OK && v.ncells) {
@@ -821,7 +821,7 @@ int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c12
   const bool march = a->dim == 3;
   const int nparts_used = march ? (int)(gm.x * gm.y) : nparts;
   if (march) hipLaunchKernelGGL(k_amr_crit3<0>, gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
-                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint32_t*)v.act, a->part,
+                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint8_t*)v.act, a->part,
                                 (const double*)a->stats,
                                 nbins, v.marks, a->hist);
   else hipLaunchKernelGGL(k_amr_range<2>, g, dim3(256), 0, a->s, v.n, (const cpx<double>*)u, (const uint8_t*)v.cls,
@@ -831,7 +831,7 @@ int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c12
                      diag.im, veto, a->stats, a->hist, counters);
   MG_HIP(hipGetLastError());
   if (march) hipLaunchKernelGGL(k_amr_crit3<1>, gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
-                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint32_t*)v.act, a->part,
+                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint8_t*)v.act, a->part,
                                 (const double*)a->stats,
                                 nbins, v.marks, a->hist);
   else hipLaunchKernelGGL(k_amr_bin<2>, g, dim3(256), 0, a->s, v.n, (const cpx<double>*)u, (const cpx<double>*)r,
