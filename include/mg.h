@@ -486,8 +486,10 @@ int mg_amr_adapt(mg_amr* amr, long long* class_counts);
 
 /* Values of level `level` (level_min < level <= level_max) after a step
  * (Sections 4 and 5.3): vertices now hanging, and vertices now persistent that
- * were not, take (P u_coarse); absent and boundary vertices are set to 0; the
- * others keep theirs.  u_coarse: DEVICE level - 1 field; u: DEVICE, in/out. */
+ * were not, take (P u_coarse); vertices that became absent or boundary are set
+ * to 0; every other vertex keeps its value (a caller that starts a level from
+ * zeros keeps zeros on its absent and boundary vertices).  u_coarse: DEVICE
+ * level - 1 field; u: DEVICE, in/out. */
 int mg_amr_interpolate(mg_amr* amr, int level, const mg_c128* u_coarse, mg_c128* u);
 
 /* Copies state to DEVICE memory: what 0 = vertex classes, 1 = classes before

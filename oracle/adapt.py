@@ -40,8 +40,10 @@ Readings (where the paper leaves a choice open; the HIP path takes the same):
   * Vertex classes after a step: absent (no adjacent cell present), persistent
     (interior, all 2^d adjacent cells present), hanging (interior, some but not
     all present), boundary (on the domain boundary, some adjacent cell present).
-    A vertex that becomes persistent or hanging takes P u_(l-1); absent and
-    boundary vertices hold zero (homogeneous Dirichlet data).
+    A hanging vertex, and one that becomes persistent, takes P u_(l-1); one
+    that becomes absent or boundary is set to zero (homogeneous Dirichlet
+    data); every other vertex keeps its value (Section 5.3 gives values only
+    to the vertices a step creates).
 
 Pinned by: the closed form of s for quadratic and d-linear fields, hand-counted
 bins and bin choices, hand-built refinement patterns in 2D and the closed-form
@@ -209,10 +211,12 @@ def classify(cells: dict, dim: int, level_min: int, level: int) -> np.ndarray:
 
 def interpolate(cls_old: np.ndarray, cls_new: np.ndarray, u_coarse: np.ndarray, u_fine: np.ndarray) -> np.ndarray:
     """Level values after a step: hanging and newly persistent vertices take
-    P u_coarse, absent and boundary vertices zero, the rest keep theirs."""
+    P u_coarse, vertices that became absent or boundary are set to zero, the
+    rest keep theirs."""
     out = np.array(u_fine, dtype=np.complex128, copy=True)
     pu = prolong(u_coarse)
     take = (cls_new == HANGING) | ((cls_new == PERSISTENT) & (cls_old != PERSISTENT))
     out[take] = pu[take]
-    out[(cls_new == ABSENT) | (cls_new == BOUNDARY)] = 0
+    gone = ((cls_new == ABSENT) | (cls_new == BOUNDARY)) & (cls_new != cls_old)
+    out[gone] = 0
     return out

@@ -26,7 +26,8 @@
 // or one of its children stays refined), then the vertex classes of every
 // level are derived from the presence of the adjacent cells (a cell is present
 // on the coarsest level, and below it where its parent is refined).  Finally
-// a vertex that became persistent or hanging takes P u of the coarser level.
+// a vertex that is hanging or became persistent takes P u of the coarser
+// level, one that became absent or boundary is set to zero.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -573,8 +574,72 @@ __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict
   }
 }
 
-// Vertices that became persistent, and hanging vertices, take P u_c; absent
-// and boundary vertices hold zero; the others keep their values.
+// The same on a 3D level as a march along z (the grid of the criterion
+// march): the parent flags a lane needs for a chunk of kAmrTz planes -- the
+// cells x-1 and x, y-1 and y, and z-1 and z for every plane of the chunk lie
+// under at most 2 x 2 x 4 parent cells -- are read once per chunk into a bit
+// mask, and the activity byte of the chunk is written once (0 or 1), so the
+// map needs no clearing.
+__global__ __launch_bounds__(256) void k_amr_classify3(int n, uint8_t* __restrict__ cls,
+                                                       const uint8_t* __restrict__ parent,
+                                                       uint8_t* __restrict__ act_map) {
+  const int lane = threadIdx.x & 63;
+  const int x = blockIdx.x * 64 + lane;
+  const bool xin = x < n;
+  const int xc = xin ? x : n - 1;
+  const int nzc = (n + kAmrTz - 1) / kAmrTz;
+  const long long plane = (long long)n * n;
+  const long long pc = (n - 1) / 3;   // parent cells per axis
+  // x: cell xc-1 (present only if xc >= 1) and cell xc (only if xc <= n-2)
+  const bool vx[2] = {xc >= 1, xc <= n - 2};
+  const long long px[2] = {(long long)(max(xc - 1, 0) / 3), (long long)(min(xc, n - 2) / 3)};
+  for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
+       t += gridDim.y * 4) {
+    const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
+    const bool vy[2] = {y >= 1, y <= n - 2};
+    const long long py[2] = {(long long)(max(y - 1, 0) / 3), (long long)(min(y, n - 2) / 3)};
+    // parent planes under the cells zs-1 .. ze-1 (clamped to the grid of cells)
+    const int pz0 = max(zs - 1, 0) / 3, pz1 = min(ze - 1, n - 2) / 3;
+    unsigned ex = 0xFFFFu;   // bit 4 (pz - pz0) + 2 b + a: parent (px[a], py[b], pz) refined
+    if (parent) {
+      ex = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pz = min(pz0 + q, pz1);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            if (parent[((long long)pz * pc + py[b]) * pc + px[a]]) ex |= 1u << (4 * q + 2 * b + a);
+      }
+    }
+    bool any = false;
+    for (int z = zs; z < ze; ++z) {
+      const bool vz[2] = {z >= 1, z <= n - 2};
+      const int qz[2] = {max(z - 1, 0) / 3 - pz0, min(z, n - 2) / 3 - pz0};
+      int cnt = 0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            cnt += (vz[c] && vy[b] && vx[a] && ((ex >> (4 * qz[c] + 2 * b + a)) & 1u)) ? 1 : 0;
+      const bool inner = xc >= 1 && xc <= n - 2 && y >= 1 && y <= n - 2 && z >= 1 && z <= n - 2;
+      uint8_t v;
+      if (inner) v = cnt == 8 ? kPersistent : (cnt > 0 ? kHanging : kAbsent);
+      else v = cnt > 0 ? kBoundary : kAbsent;
+      if (xin) cls[(long long)z * plane + (long long)y * n + x] = v;
+      any = any || (xin && v == kPersistent);
+    }
+    const bool act = __ballot(any) != 0;
+    if (act_map && lane == 0) act_map[(long long)t * gridDim.x + blockIdx.x] = act ? 1 : 0;
+  }
+}
+
+// Vertices that became persistent, and hanging vertices, take P u_c;
+// vertices that became absent or boundary are set to zero; the others keep
+// their values.
 template <int D>
 __global__ __launch_bounds__(256) void k_amr_interp(int n, const uint8_t* __restrict__ cls_old,
                                                     const uint8_t* __restrict__ cls_new,
@@ -585,16 +650,19 @@ __global__ __launch_bounds__(256) void k_amr_interp(int n, const uint8_t* __rest
     long long i;
     if (!row_vertex<D>(row_, x_, n, j, i)) continue;
     const uint8_t a = cls_new[i];
-    if (a == kHanging || (a == kPersistent && cls_old[i] != kPersistent)) u[i] = prolong_at<double, D>(uc, nc, j);
-    else if (a == kAbsent || a == kBoundary) u[i] = czero<double>();
+    const uint8_t o = cls_old[i];
+    if (a == kHanging || (a == kPersistent && o != kPersistent)) u[i] = prolong_at<double, D>(uc, nc, j);
+    else if ((a == kAbsent || a == kBoundary) && a != o) u[i] = czero<double>();
   }
 }
 
-// The same on a 3D level as a march along z: P is separable, so a lane
-// interpolates its coarse corners in x and y once per coarse plane and keeps
-// the two coarse planes that bracket its z in registers; a fine vertex then
-// costs its two class bytes and its store.  Corners are clamped so that every
-// lane (boundary ones included) computes a bracket inside the coarse grid.
+// The same on a 3D level as a march along z.  The class bytes of a chunk of
+// kAmrTz planes are read first; a chunk in which no lane has a vertex to
+// write costs nothing more.  Where some lane takes P u_c: P is separable, so a
+// lane interpolates its coarse corners in x and y once per coarse plane and
+// keeps the two coarse planes that bracket its z in registers.  Corners are
+// clamped so that every lane (boundary ones included) computes a bracket
+// inside the coarse grid.
 __device__ inline cpx<double> amr_xy(const cpx<double>* __restrict__ v, long long base, const long long ci[4],
                                      const double cw[4]) {
   cpx<double> acc = czero<double>();
@@ -613,32 +681,57 @@ __global__ __launch_bounds__(256) void k_amr_interp3(int n, const uint8_t* __res
   const bool xin = x < n;
   const int nzc = (n + kAmrTz - 1) / kAmrTz;
   const long long pl = (long long)nc * nc;
+  const long long plane = (long long)n * n;
   const int xs = xin ? x : n - 1;
   const int mx = min(xs / 3, nc - 2);
   const double wx1 = (double)(xs - 3 * mx) / 3.0, wx0 = 1.0 - wx1;
   for (int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * 4 + (threadIdx.x >> 6))); t < n * nzc;
        t += gridDim.y * 4) {
     const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
-    const int my = min(y / 3, nc - 2);
-    const double wy1 = (double)(y - 3 * my) / 3.0, wy0 = 1.0 - wy1;
-    const long long ci[4] = {(long long)my * nc + mx, (long long)my * nc + mx + 1, (long long)(my + 1) * nc + mx,
-                             (long long)(my + 1) * nc + mx + 1};
-    const double cw[4] = {wy0 * wx0, wy0 * wx1, wy1 * wx0, wy1 * wx1};
+    const long long row = (long long)y * n + xs;
+    // what each plane of the chunk asks of this lane: 1 take P u_c, 2 set to zero
+    unsigned acts = 0;
+#pragma unroll
+    for (int q = 0; q < kAmrTz; ++q) {
+      const long long e = (long long)min(zs + q, ze - 1) * plane + row;
+      const uint8_t a = xin ? cls_new[e] : (uint8_t)kAbsent, o = xin ? cls_old[e] : (uint8_t)kAbsent;
+      const unsigned act = (a == kHanging || (a == kPersistent && o != kPersistent))
+                               ? 1u
+                               : (((a == kAbsent || a == kBoundary) && a != o) ? 2u : 0u);
+      if (zs + q < ze) acts |= act << (2 * q);
+    }
+    if (__ballot(acts != 0) == 0) continue;
+    const bool take = __ballot((acts & 0x5555u) != 0) != 0;
+    long long ci[4] = {0, 0, 0, 0};
+    double cw[4] = {0, 0, 0, 0};
     int mz = min(zs / 3, nc - 2);
-    cpx<double> s0 = amr_xy(uc, mz * pl, ci, cw), s1 = amr_xy(uc, (mz + 1) * pl, ci, cw);
+    cpx<double> s0 = czero<double>(), s1 = czero<double>();
+    if (take) {
+      const int my = min(y / 3, nc - 2);
+      const double wy1 = (double)(y - 3 * my) / 3.0, wy0 = 1.0 - wy1;
+      ci[0] = (long long)my * nc + mx;
+      ci[1] = ci[0] + 1;
+      ci[2] = ci[0] + nc;
+      ci[3] = ci[2] + 1;
+      cw[0] = wy0 * wx0;
+      cw[1] = wy0 * wx1;
+      cw[2] = wy1 * wx0;
+      cw[3] = wy1 * wx1;
+      s0 = amr_xy(uc, mz * pl, ci, cw);
+      s1 = amr_xy(uc, (mz + 1) * pl, ci, cw);
+    }
     for (int z = zs; z < ze; ++z) {
       const int m = min(z / 3, nc - 2);
-      if (m != mz) {   // the next coarse interval: shift the bracket by one plane
+      if (take && m != mz) {   // the next coarse interval: shift the bracket by one plane
         mz = m;
         s0 = s1;
         s1 = amr_xy(uc, (mz + 1) * pl, ci, cw);
       }
-      if (!xin) continue;
-      const long long e = ((long long)z * n + y) * n + x;
-      const uint8_t a = cls_new[e], o = cls_old[e];
-      const double wz1 = (double)(z - 3 * mz) / 3.0, wz0 = 1.0 - wz1;
-      if (a == kHanging || (a == kPersistent && o != kPersistent)) u[e] = wz0 * s0 + wz1 * s1;
-      else if (a == kAbsent || a == kBoundary) u[e] = czero<double>();
+      const unsigned act = (acts >> (2 * (z - zs))) & 3u;
+      if (!xin || act == 0) continue;
+      const long long e = (long long)z * plane + row;
+      const double wz1 = (double)(z - 3 * m) / 3.0, wz0 = 1.0 - wz1;
+      u[e] = csel(act == 1, wz0 * s0 + wz1 * s1, czero<double>());
     }
   }
 }
@@ -726,13 +819,14 @@ struct mg_amr {
     for (int l = lmin; l <= lmax; ++l) {
       AmrLevel& v = at(l);
       std::swap(v.cls, v.cls_old);
-      if (v.act) {
-        hipLaunchKernelGGL(k_amr_zero32, dim3((unsigned)std::min<long long>((v.nact + 255) / 256, 1024)), dim3(256),
-                           0, s, (uint32_t*)v.act, v.nact);
+      const uint8_t* par = l > lmin ? at(l - 1).cells : nullptr;
+      if (dim == 3) {
+        hipLaunchKernelGGL(k_amr_classify3, amr_march_grid(v.n), dim3(256), 0, s, v.n, v.cls, par, v.act);
         MG_HIP(hipGetLastError());
+      } else {
+        MG_HIP(amr_launch(dim, k_amr_classify<2>, k_amr_classify<3>, amr_grid(v.n, dim), s, v.n, v.cls, par,
+                          (uint8_t*)nullptr));
       }
-      MG_HIP(amr_launch(dim, k_amr_classify<2>, k_amr_classify<3>, amr_grid(v.n, dim), s, v.n, v.cls,
-                        (const uint8_t*)(l > lmin ? at(l - 1).cells : nullptr), v.act));
     }
     return MG_OK;
   }

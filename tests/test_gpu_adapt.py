@@ -233,6 +233,8 @@ def test_full_size_mark_and_adapt_level6():
         fine = A.prolong(uc[m[0]:m[0] + 2, m[1]:m[1] + 2, m[2]:m[2] + 2])
         q = p - 3 * m
         np.testing.assert_allclose(v, fine[tuple(q)], rtol=0, atol=1e-14)
-    assert bool((uf[cls6_dev == A.ABSENT] == 0).all().item())
-    assert bool((uf[cls6_dev == A.BOUNDARY] == 0).all().item())
+    # level 6 was absent before the step: vertices that stay absent keep their
+    # values; none became absent or boundary (the step only refined)
+    assert bool((uf[cls6_dev == A.ABSENT] == 7.0 + 7.0j).all().item())
+    assert bool((uf[cls6_dev == A.PERSISTENT] != 7.0 + 7.0j).all().item())
     a.close()

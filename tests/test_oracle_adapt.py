@@ -173,7 +173,12 @@ def test_interpolation_is_exact_on_linear_fields():
     out = A.interpolate(cls_old, cls_new, f(Xc), u_fine)
     take = (cls_new == A.HANGING) | (cls_new == A.PERSISTENT)
     np.testing.assert_allclose(out[take], f(Xf)[take], rtol=0, atol=1e-15)
-    assert np.all(out[~take] == 0)
+    # level 2 was absent before: the new boundary vertices are set to zero,
+    # the vertices that stay absent keep what they held
+    became = (cls_new == A.BOUNDARY) & (cls_old == A.ABSENT)
+    assert became.any() and np.all(out[became] == 0)
+    stay = (cls_new == A.ABSENT) & (cls_old == A.ABSENT)
+    assert np.all(out[stay] == 9.0 + 9.0j)
     # a second call with nothing new keeps the persistent values
     out2 = A.interpolate(cls_new, cls_new, 0 * f(Xc), out)
     np.testing.assert_array_equal(out2[cls_new == A.PERSISTENT], out[cls_new == A.PERSISTENT])
