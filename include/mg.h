@@ -462,18 +462,22 @@ void mg_amr_destroy(mg_amr* amr);
 
 /* Marks one level (Section 5.3).  u: DEVICE level field (complex128, n^d);
  * r: DEVICE residual of the level or NULL (no veto); diag: the level's
- * (constant) diagonal.  Candidates are the persistent vertices; their
+ * constant diagonal, or diag_field: DEVICE per-vertex diagonal (n^d; varying
+ * phi or a layer), which replaces diag when not NULL.  Candidates are the
+ * persistent vertices; their
  * criterion s = max over axes a of |u(j+e_a) - 2u(j) + u(j-e_a)| is binned
  * into nbins (1..64; the paper: 20) equal subranges of [min s, max s]; the k
  * top bins whose count is closest to refine_pct % of the candidates are
  * marked REFINE (none on level_max), the e bottom bins closest to erase_pct %
  * (e <= nbins - k) ERASE (none below level_keep); ties take fewer bins.  A
- * vertex with |r|^2 > veto^2 |diag|^2 (the paper: veto 1e-2) keeps.  The
+ * vertex with |r|^2 > veto^2 |diag|^2 (the paper: veto 1e-2; |diag_i| with a
+ * diagonal field) keeps.  The
  * marks are kept for mg_amr_adapt (and readable with mg_amr_get).
  * counts (HOST, nbins + 5, or NULL): the bin counts, k, e, candidates, REFINE
  * marks, ERASE marks; s_range (HOST, 2, or NULL): min s, max s. */
-int mg_amr_mark(mg_amr* amr, int level, const mg_c128* u, const mg_c128* r, mg_c128 diag, int nbins,
-                int refine_pct, int erase_pct, double veto, long long* counts, double* s_range);
+int mg_amr_mark(mg_amr* amr, int level, const mg_c128* u, const mg_c128* r, mg_c128 diag,
+                const mg_c128* diag_field, int nbins, int refine_pct, int erase_pct, double veto,
+                long long* counts, double* s_range);
 
 /* One adaptation step from the marks of the levels marked since the last
  * step: refined-cell flags from level_max - 1 up to level_min (REFINE refines

@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void k_amr_range(int n, const cpx<double>* __r
 // before this plane is evaluated, so that they are in flight meanwhile.  The
 // differences are formed in the same order as amr_s2.  MODE 0: range
 // partials (as k_amr_range); MODE 1: bins, veto bits and bin counts (as
-// k_amr_bin).
+// k_amr_bin).  DG: the veto compares with a per-vertex diagonal (an instance
+// of its own, so that the constant-diagonal pass carries no extra registers).
 constexpr int kAmrTz = 8;
 constexpr int kLaneLeft = 0x138;    // wave shift: lane l receives lane l-1 (0 at lane 0)
 constexpr int kLaneRight = 0x130;   // lane l receives lane l+1 (0 at lane 63)
@@ -157,9 +158,10 @@ dim3 amr_march_grid(int n) {
   return dim3((unsigned)gx, (unsigned)gy);
 }
 
-template <int MODE>
+template <int MODE, bool DG>
 __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __restrict__ u,
                                                    const cpx<double>* __restrict__ r,
+                                                   const cpx<double>* __restrict__ dg, double veto2,
                                                    const uint8_t* __restrict__ cls,
                                                    const uint8_t* __restrict__ act_map, double* __restrict__ part,
                                                    const double* __restrict__ stats, int nb,
@@ -206,6 +208,7 @@ __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __r
     bool ready = false;
     cpx<double> cm = czero<double>(), c0 = czero<double>(), cp = czero<double>();
     cpx<double> ym = czero<double>(), yp = czero<double>(), h = czero<double>(), rv = czero<double>();
+    cpx<double> dv = czero<double>();
 #pragma unroll
     for (int q = 0; q < kAmrTz; ++q) {
       const int z = zs + q;
@@ -226,11 +229,12 @@ __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __r
         yp = u[k + n];
         h = u[i + hoff];
         if (MODE == 1 && r) rv = r[k];
+        if (DG && r) dv = dg[k];
       }
       // the next plane's reads, issued before this plane is evaluated
       const bool nxt = q + 1 < kAmrTz && (act & (2u << q));
       cpx<double> cp1 = czero<double>(), ym1 = czero<double>(), yp1 = czero<double>(), h1 = czero<double>(),
-                  rv1 = czero<double>();
+                  rv1 = czero<double>(), dv1 = czero<double>();
       if (nxt) {
         const long long i1 = i + plane;
         const long long k1 = cand[q + 1] ? i1 : safe;
@@ -239,6 +243,7 @@ __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __r
         yp1 = u[k1 + n];
         h1 = u[i1 + hoff];
         if (MODE == 1 && r) rv1 = r[k1];
+        if (DG && r) dv1 = dg[k1];
       }
       cpx<double> xm = mk(lane_move<kLaneLeft>(c0.re), lane_move<kLaneLeft>(c0.im));
       cpx<double> xp = mk(lane_move<kLaneRight>(c0.re), lane_move<kLaneRight>(c0.im));
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __r
           const double qq = floor(((sv - smin) / range) * dnb);
           b = qq >= dnb - 1 ? nb - 1 : (int)qq;
         }
-        const bool v = r && (rv.re * rv.re + rv.im * rv.im > thr);
+        const bool v = r && (rv.re * rv.re + rv.im * rv.im > (DG ? veto2 * (dv.re * dv.re + dv.im * dv.im) : thr));
         if (xin) marks[i] = p ? (uint8_t)(b | (v ? kVetoBit : 0)) : kNotCand;
         const int bp = p ? b : -1;
         for (int k = 0; k < nb; ++k) {
@@ -279,6 +284,7 @@ __global__ __launch_bounds__(256) void k_amr_crit3(int n, const cpx<double>* __r
         yp = yp1;
         h = h1;
         rv = rv1;
+        dv = dv1;
       }
     }
   }
@@ -352,6 +358,7 @@ __global__ __launch_bounds__(256) void k_amr_range_finish(const double* __restri
 template <int D>
 __global__ __launch_bounds__(256) void k_amr_bin(int n, const cpx<double>* __restrict__ u,
                                                  const cpx<double>* __restrict__ r,
+                                                 const cpx<double>* __restrict__ dg, double veto2,
                                                  const uint8_t* __restrict__ cls, const double* __restrict__ stats,
                                                  int nb, uint8_t* __restrict__ marks,
                                                  unsigned long long* __restrict__ hist) {
@@ -380,7 +387,12 @@ __global__ __launch_bounds__(256) void k_amr_bin(int n, const cpx<double>* __res
         bool v = false;
         if (r) {
           const cpx<double> rv = r[i];
-          v = rv.re * rv.re + rv.im * rv.im > thr;
+          double t2 = thr;
+          if (dg) {
+            const cpx<double> d = dg[i];
+            t2 = veto2 * (d.re * d.re + d.im * d.im);
+          }
+          v = rv.re * rv.re + rv.im * rv.im > t2;
         }
         m = (uint8_t)(b | (v ? kVetoBit : 0));
       }
@@ -899,7 +911,8 @@ void mg_amr_destroy(mg_amr* a) {
   delete a;
 }
 
-int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c128 diag, int nbins, int refine_pct,
+int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c128 diag, const mg_c128* diag_field,
+                int nbins, int refine_pct,
                 int erase_pct, double veto, long long* counts, double* s_range) {
   if (!a || !u) return fail(MG_EINVAL, "NULL argument");
   if (level < a->lmin || level > a->lmax) return fail(MG_EINVAL, "level outside the envelope");
@@ -908,14 +921,16 @@ int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c12
     return fail(MG_EINVAL, "percentages in 0..100 and veto >= 0");
   AmrLevel& v = a->at(level);
   if (v.N % 4) return fail(MG_EINVAL, "level size not a multiple of 4 bytes");
+  const double veto2 = veto * veto;   // the per-vertex threshold veto^2 |diag_i|^2
   const dim3 g = amr_grid(v.n, a->dim);
   const int nparts = (int)(g.x * g.y);
   unsigned long long* counters = a->hist + kAmrMaxBins;
   const dim3 gm = amr_march_grid(v.n);
   const bool march = a->dim == 3;
   const int nparts_used = march ? (int)(gm.x * gm.y) : nparts;
-  if (march) hipLaunchKernelGGL(k_amr_crit3<0>, gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
-                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint8_t*)v.act, a->part,
+  if (march) hipLaunchKernelGGL((k_amr_crit3<0, false>), gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
+                                (const cpx<double>*)r, (const cpx<double>*)diag_field, veto2, (const uint8_t*)v.cls,
+                                (const uint8_t*)v.act, a->part,
                                 (const double*)a->stats,
                                 nbins, v.marks, a->hist);
   else hipLaunchKernelGGL(k_amr_range<2>, g, dim3(256), 0, a->s, v.n, (const cpx<double>*)u, (const uint8_t*)v.cls,
@@ -924,11 +939,16 @@ int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c12
   hipLaunchKernelGGL(k_amr_range_finish, dim3(1), dim3(256), 0, a->s, (const double*)a->part, nparts_used, diag.re,
                      diag.im, veto, a->stats, a->hist, counters);
   MG_HIP(hipGetLastError());
-  if (march) hipLaunchKernelGGL(k_amr_crit3<1>, gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
-                                (const cpx<double>*)r, (const uint8_t*)v.cls, (const uint8_t*)v.act, a->part,
-                                (const double*)a->stats,
-                                nbins, v.marks, a->hist);
+  if (march && diag_field && r)
+    hipLaunchKernelGGL((k_amr_crit3<1, true>), gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
+                       (const cpx<double>*)r, (const cpx<double>*)diag_field, veto2, (const uint8_t*)v.cls,
+                       (const uint8_t*)v.act, a->part, (const double*)a->stats, nbins, v.marks, a->hist);
+  else if (march)
+    hipLaunchKernelGGL((k_amr_crit3<1, false>), gm, dim3(256), 0, a->s, v.n, (const cpx<double>*)u,
+                       (const cpx<double>*)r, (const cpx<double>*)nullptr, veto2, (const uint8_t*)v.cls,
+                       (const uint8_t*)v.act, a->part, (const double*)a->stats, nbins, v.marks, a->hist);
   else hipLaunchKernelGGL(k_amr_bin<2>, g, dim3(256), 0, a->s, v.n, (const cpx<double>*)u, (const cpx<double>*)r,
+                          (const cpx<double>*)diag_field, veto2,
                           (const uint8_t*)v.cls, (const double*)a->stats, nbins, v.marks, a->hist);
   MG_HIP(hipGetLastError());
   const long long nwords = v.N / 4;

@@ -127,7 +127,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_amr_setup.argtypes = [I, I, I, I, P, ctypes.POINTER(P)]
     lib.mg_amr_destroy.argtypes = [P]
     lib.mg_amr_destroy.restype = None
-    lib.mg_amr_mark.argtypes = [P, I, P, P, c128, I, I, I, D, ctypes.POINTER(L), ctypes.POINTER(D)]
+    lib.mg_amr_mark.argtypes = [P, I, P, P, c128, P, I, I, I, D, ctypes.POINTER(L), ctypes.POINTER(D)]
     lib.mg_amr_adapt.argtypes = [P, ctypes.POINTER(L)]
     lib.mg_amr_interpolate.argtypes = [P, I, P, P]
     lib.mg_amr_get.argtypes = [P, I, I, P]
@@ -616,22 +616,32 @@ class Adapt:
             raise ValueError(f"expected shape {(self.n(level),) * self.dim}, got {tuple(x.shape)}")
         return x
 
-    def mark(self, level: int, u, r=None, diag: complex = 1.0, nbins: int = 20, refine_pct: int = 10,
+    def mark(self, level: int, u, r=None, diag=1.0, nbins: int = 20, refine_pct: int = 10,
              erase_pct: int = 2, veto: float = 1e-2, stats: bool = True):
-        """Marks a level; returns a dict of the statistics (or None)."""
+        """Marks a level; diag is a constant or a per-vertex field of the
+        level's diagonal; returns a dict of the statistics (or None)."""
         u = self._field(u, level)
         rp = None
         if r is not None:
             r = self._field(r, level)
             rp = _ptr(r)
-        d = complex(diag)
+        dp, d = None, 1.0 + 0j
+        if isinstance(diag, self._torch.Tensor):
+            scalar = diag.dim() == 0
+        else:
+            scalar = np.ndim(diag) == 0
+        if scalar:
+            d = complex(diag)
+        else:
+            diag = self._field(diag, level)
+            dp = _ptr(diag)
         if not stats:
-            _check(self._lib.mg_amr_mark(self._a, level, _ptr(u), rp, c128(d.real, d.imag), nbins, refine_pct,
+            _check(self._lib.mg_amr_mark(self._a, level, _ptr(u), rp, c128(d.real, d.imag), dp, nbins, refine_pct,
                                          erase_pct, veto, None, None))
             return None
         cnt = (ctypes.c_longlong * (nbins + 5))()
         rng = (ctypes.c_double * 2)()
-        _check(self._lib.mg_amr_mark(self._a, level, _ptr(u), rp, c128(d.real, d.imag), nbins, refine_pct,
+        _check(self._lib.mg_amr_mark(self._a, level, _ptr(u), rp, c128(d.real, d.imag), dp, nbins, refine_pct,
                                      erase_pct, veto, cnt, rng))
         c = list(cnt)
         return dict(counts=np.array(c[:nbins], dtype=np.int64), k=c[nbins], e=c[nbins + 1], n=c[nbins + 2],

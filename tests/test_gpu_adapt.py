@@ -32,7 +32,7 @@ def _check_mark(a, level, u, r, diag, cls, lkeep, lmax, **kw):
     mg = _mg()
     st = a.mark(level, u, r, diag, **kw)
     got = a.get(level, "marks").cpu().numpy()
-    want, ost = A.mark_level(u, r, np.complex128(diag), cls, level, lkeep, lmax,
+    want, ost = A.mark_level(u, r, np.asarray(diag, dtype=np.complex128), cls, level, lkeep, lmax,
                              **{k: v for k, v in kw.items()})
     assert st["n"] == ost["n"]
     if ost["n"]:
@@ -63,6 +63,12 @@ def test_mark_of_a_regular_level_matches_oracle(dim, level, seed):
     # odd bin counts and percentages
     _check_mark(a, level, u, r, diag, cls, level, level + 1, nbins=7, refine_pct=33, erase_pct=5)
     _check_mark(a, level, u, r, diag, cls, level, level + 1, nbins=1, refine_pct=100, erase_pct=0)
+    # a per-vertex diagonal (varying phi): the veto threshold moves with it
+    dfield = diag * (1.0 + 0.5 * random_complex(u.shape, seed + 200))
+    r2 = 1e-2 * abs(diag) * random_complex(u.shape, seed + 300)
+    marks_f, _ = _check_mark(a, level, u, r2, dfield, cls, level, level + 1)
+    marks_c, _ = _check_mark(a, level, u, r2, diag, cls, level, level + 1)
+    assert not np.array_equal(marks_f, marks_c)
     a.close()
 
 
