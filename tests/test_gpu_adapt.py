@@ -244,3 +244,39 @@ def test_full_size_mark_and_adapt_level6():
     assert bool((uf[cls6_dev == A.ABSENT] == 7.0 + 7.0j).all().item())
     assert bool((uf[cls6_dev == A.PERSISTENT] != 7.0 + 7.0j).all().item())
     a.close()
+
+
+@pytest.mark.parametrize("dim,lmin,lmax", [(2, 1, 5), (3, 1, 4)])
+def test_set_cells_matches_oracle(dim, lmin, lmax):
+    """Refined-cell flags set directly (random, each refined cell under a
+    refined parent): every level's classes bit for bit, then one marked step
+    from that state."""
+    mg = _mg()
+    rng = np.random.default_rng(90 + dim)
+    a = mg.Adapt(dim, lmin, lmin, lmax)
+    cells = A.regular_cells(dim, lmin, lmin, lmax)
+    for l in range(lmin, lmax):
+        flags = (rng.random((3 ** l,) * dim) < 0.35).astype(np.uint8)
+        if l > lmin:
+            flags &= A.cell_exists(cells, l, lmin, dim).astype(np.uint8)
+        cells[l] = flags
+        a.set_cells(l, flags)
+    for l in range(lmin, lmax):
+        np.testing.assert_array_equal(a.get(l, "cells").cpu().numpy(), cells[l])
+    cls = {}
+    for l in range(lmin, lmax + 1):
+        cls[l] = A.classify(cells, dim, lmin, l)
+        np.testing.assert_array_equal(a.get(l, "classes").cpu().numpy(), cls[l], err_msg=f"level {l}")
+        np.testing.assert_array_equal(a.get(l, "classes_old").cpu().numpy(), cls[l])
+    # one step from the set state: marks on two levels, cells and classes
+    marks = {}
+    for level in (lmin + 1, lmin + 2):
+        u = feature_field(dim, level, 95 + level)
+        marks[level], _ = _check_mark(a, level, u, None, 1.0, cls[level], lmin, lmax, erase_pct=20)
+    a.adapt()
+    cells = A.adapt(cells, marks, dim, lmin, lmax)
+    for l in range(lmin, lmax):
+        np.testing.assert_array_equal(a.get(l, "cells").cpu().numpy(), cells[l], err_msg=f"level {l}")
+    for l in range(lmin, lmax + 1):
+        np.testing.assert_array_equal(a.get(l, "classes").cpu().numpy(), A.classify(cells, dim, lmin, l))
+    a.close()
