@@ -4,10 +4,13 @@
 // The spacetree is held as one byte per cell and level ("refined into the 3^d
 // cells of the next level") over the full regular grid of every level, plus
 // one class byte per vertex (absent / persistent / hanging / boundary).  Every
-// pass is then a coalesced row sweep over a regular array: no pointer chasing,
-// no per-vertex index tables; the cost of a level pass scales with the level's
-// envelope, not with the vertices present (the envelope of a 3D level-6
-// hierarchy, 389 M vertices, takes 1.2 GB of class and mark bytes).
+// pass is then a coalesced sweep over a regular array: no pointer chasing, no
+// per-vertex index tables (the envelope of a 3D level-6 hierarchy, 389 M
+// vertices, takes 1.2 GB of class and mark bytes).  The classification and
+// the decision pass cost the level's envelope; on a 3D level the criterion
+// passes and the interpolation march over chunks of planes and skip, on one
+// byte of a per-level activity map or on the chunk's class bytes, the chunks
+// that hold nothing to do, so that they cost what is present.
 //
 // Marking one level: the criterion s = max_a |u(j+e_a) - 2u(j) + u(j-e_a)| of
 // every persistent vertex is formed twice -- a first pass reduces its range,
@@ -544,8 +547,7 @@ __global__ __launch_bounds__(256) void k_amr_cells(int ncell, uint8_t* __restric
 // cell is present).
 template <int D>
 __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict__ cls,
-                                                      const uint8_t* __restrict__ parent,
-                                                      uint8_t* __restrict__ act_map) {
+                                                      const uint8_t* __restrict__ parent) {
   const long long pc = (n - 1) / 3;
   MG_ROWS(D, n) {
     int j[3];
@@ -575,13 +577,6 @@ __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict
       if (inner) v = cnt == (1 << D) ? kPersistent : (cnt > 0 ? kHanging : kAbsent);
       else v = cnt > 0 ? kBoundary : kAbsent;
       cls[i] = v;
-    }
-    // activity map of the 3D criterion march: one byte per (64 x, row, chunk
-    // of kAmrTz planes), set to 1 by every wavefront that finds a candidate
-    // there (all writers store the same value, so no atomic is needed)
-    if (D == 3 && act_map && __ballot(v == kPersistent) != 0 && lane_ == 0) {
-      const int z = row_ / n, y = row_ - z * n;
-      act_map[((long long)(z / kAmrTz) * n + y) * gridDim.x + blockIdx.x] = 1;
     }
   }
 }
@@ -773,9 +768,6 @@ __global__ void k_amr_zero(unsigned long long* __restrict__ p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-__global__ void k_amr_zero32(uint32_t* __restrict__ p, long long n) {
-  for (long long k = blockIdx.x * 256ll + threadIdx.x; k < n; k += (long long)gridDim.x * 256) p[k] = 0;
-}
 
 template <class F2, class F3, class... A>
 hipError_t amr_launch(int dim, F2 k2, F3 k3, dim3 g, hipStream_t s, A... a) {
@@ -792,8 +784,8 @@ struct AmrLevel {
   uint8_t* marks = nullptr;
   uint8_t* cells = nullptr;   // levels below the finest only
   long long ncells = 0;
-  uint8_t* act = nullptr;     // 3D: activity map of the criterion march
-  long long nact = 0;         // its size in 4-byte words
+  uint8_t* act = nullptr;     // 3D: activity map of the criterion march (written whole by the classification)
+  long long nact = 0;         // its bytes
   bool marked = false;
 };
 
@@ -836,8 +828,8 @@ struct mg_amr {
         hipLaunchKernelGGL(k_amr_classify3, amr_march_grid(v.n), dim3(256), 0, s, v.n, v.cls, par, v.act);
         MG_HIP(hipGetLastError());
       } else {
-        MG_HIP(amr_launch(dim, k_amr_classify<2>, k_amr_classify<3>, amr_grid(v.n, dim), s, v.n, v.cls, par,
-                          (uint8_t*)nullptr));
+        hipLaunchKernelGGL(k_amr_classify<2>, amr_grid(v.n, dim), dim3(256), 0, s, v.n, v.cls, par);
+        MG_HIP(hipGetLastError());
       }
     }
     return MG_OK;
@@ -879,8 +871,8 @@ int mg_amr_setup(int dim, int level_min, int level_keep, int level_max, void* hi
       // one byte per (x block of 64, row, chunk of planes), as the classification and the march enumerate them
       const dim3 gc = amr_grid(v.n, dim);
       const long long items = (long long)gc.x * v.n * ((v.n + kAmrTz - 1) / kAmrTz);
-      v.nact = (items + 3) / 4;
-      rc = a->alloc((void**)&v.act, v.nact * sizeof(uint32_t));
+      v.nact = items;
+      rc = a->alloc((void**)&v.act, (size_t)v.nact);
     }
     if (rc == MG_OK && v.ncells) {
       const hipError_t e = hipMemsetAsync(v.cells, l < level_keep ? 1 : 0, v.ncells, a->s);
@@ -1022,9 +1014,9 @@ int mg_amr_interpolate(mg_amr* a, int level, const mg_c128* u_coarse, mg_c128* u
                        (const uint8_t*)v.cls, (const cpx<double>*)u_coarse, (cpx<double>*)u);
     MG_HIP(hipGetLastError());
   } else {
-    MG_HIP(amr_launch(a->dim, k_amr_interp<2>, k_amr_interp<3>, amr_grid(v.n, a->dim), a->s, v.n,
-                      (const uint8_t*)v.cls_old, (const uint8_t*)v.cls, (const cpx<double>*)u_coarse,
-                      (cpx<double>*)u));
+    hipLaunchKernelGGL(k_amr_interp<2>, amr_grid(v.n, a->dim), dim3(256), 0, a->s, v.n, (const uint8_t*)v.cls_old,
+                       (const uint8_t*)v.cls, (const cpx<double>*)u_coarse, (cpx<double>*)u);
+    MG_HIP(hipGetLastError());
   }
   return MG_OK;
 }
