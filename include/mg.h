@@ -498,7 +498,8 @@ int mg_amr_interpolate(mg_amr* amr, int level, const mg_c128* u_coarse, mg_c128*
 
 /* Copies state to DEVICE memory: what 0 = vertex classes, 1 = classes before
  * the last step (n^d bytes each), 2 = refined-cell flags ((n-1)^d bytes, not
- * on level_max), 3 = the level's last marks (n^d bytes). */
+ * on level_max), 3 = the level's last marks at its candidates, MG_AMR_KEEP
+ * elsewhere (n^d bytes). */
 int mg_amr_get(mg_amr* amr, int level, int what, unsigned char* out);
 
 /* Replaces the refined-cell flags of one level (level_min <= level <

@@ -470,6 +470,67 @@ __device__ inline void amr_choose(const unsigned long long* hist, int nb, long l
   }
 }
 
+// The decision pass on a 3D level: the criterion march's walk and activity
+// map, so that chunks without a candidate are skipped (their mark bytes are
+// left as they are: only the candidates' marks are defined, and every reader
+// takes them there only).
+__global__ __launch_bounds__(256) void k_amr_decide3(int n, uint8_t* __restrict__ marks,
+                                                     const uint8_t* __restrict__ cls,
+                                                     const uint8_t* __restrict__ act_map,
+                                                     const double* __restrict__ stats, int nb, int can_refine,
+                                                     int can_erase, unsigned long long* __restrict__ counters) {
+  __shared__ double sr[4], se_[4];
+  const uint32_t top = (uint32_t)(nb - (int)stats[4]), bot = (uint32_t)(int)stats[5];
+  const int lane = threadIdx.x & 63;
+  const int nzc = (n + kAmrTz - 1) / kAmrTz, gx = (n + 63) / 64;
+  const long long plane = (long long)n * n;
+  const int items = gx * n * nzc;
+  double nr = 0, ne = 0;
+  for (AmrWalk w = amr_walk(gx);; w.q += w.step) {
+    const int it = w.item();
+    if (it >= items) break;
+    if (!act_map[it]) continue;   // no candidate in the chunk
+    const int bx = it % gx, t = it / gx;
+    const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
+    const int x = bx * 64 + lane;
+    if (x >= n) continue;
+    for (int z = zs; z < ze; ++z) {
+      const long long i = (long long)z * plane + (long long)y * n + x;
+      const uint32_t m = marks[i];
+      uint32_t d = kKeep;
+      if (cls[i] == kPersistent && !(m & (kNotCand | kVetoBit))) {
+        const uint32_t b = m & kBinMask;
+        if (can_refine && b >= top) d = kRefine;
+        else if (can_erase && b < bot) d = kErase;
+      }
+      nr += d == kRefine ? 1 : 0;
+      ne += d == kErase ? 1 : 0;
+      marks[i] = (uint8_t)d;
+    }
+  }
+  nr = wave_sum(nr);
+  ne = wave_sum(ne);
+  const int wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    sr[wv] = nr;
+    se_[wv] = ne;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double a = (sr[0] + sr[1]) + (sr[2] + sr[3]), b = (se_[0] + se_[1]) + (se_[2] + se_[3]);
+    if (a > 0) atomicAdd(&counters[0], (unsigned long long)a);
+    if (b > 0) atomicAdd(&counters[1], (unsigned long long)b);
+  }
+}
+
+// Marks of a level as the caller sees them: the mark at the candidates, KEEP
+// elsewhere.
+__global__ __launch_bounds__(256) void k_amr_mask_marks(long long N, const uint8_t* __restrict__ marks,
+                                                        const uint8_t* __restrict__ cls, uint8_t* __restrict__ out) {
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (long long)gridDim.x * 256)
+    out[i] = cls[i] == kPersistent ? marks[i] : (uint8_t)kKeep;
+}
+
 // One thread: the numbers of top and bottom bins into stats[4], stats[5].
 __global__ void k_amr_choose(const unsigned long long* __restrict__ hist, double* __restrict__ stats, int nb,
                              int rpct, int epct) {
@@ -529,12 +590,14 @@ __global__ __launch_bounds__(256) void k_amr_decide(long long nwords, uint32_t* 
 
 // Refined-cell update of one level (ncell cells per axis).  parent: the
 // coarser level's flags before this step (NULL on the coarsest level); marks:
-// this level's vertex marks (NULL: none); child: the finer level's flags after
-// this step (NULL on the last level of cells).
+// this level's vertex marks (NULL: none), read at its candidates (vcls, the
+// level's classes); child: the finer level's flags after this step (NULL on
+// the last level of cells).
 template <int D>
 __global__ __launch_bounds__(256) void k_amr_cells(int ncell, uint8_t* __restrict__ cells,
                                                    const uint8_t* __restrict__ parent,
                                                    const uint8_t* __restrict__ marks,
+                                                   const uint8_t* __restrict__ vcls,
                                                    const uint8_t* __restrict__ child) {
   MG_ROWS(D, ncell) {
     int c[3];
@@ -553,7 +616,8 @@ __global__ __launch_bounds__(256) void k_amr_cells(int ncell, uint8_t* __restric
       for (int k = 0; k < (1 << D); ++k) {
         long long vi = (c[0] + (k & 1)) + nv * (c[1] + ((k >> 1) & 1));
         if (D == 3) vi += nv * nv * (c[2] + ((k >> 2) & 1));
-        const uint8_t m = marks[vi];
+        // only the candidates' marks are defined (the 3D decision pass skips chunks without one)
+        const uint8_t m = vcls[vi] == kPersistent ? marks[vi] : (uint8_t)kKeep;
         any_r |= m == kRefine;
         any_e |= m == kErase;
       }
@@ -903,6 +967,10 @@ int mg_amr_setup(int dim, int level_min, int level_keep, int level_max, void* hi
     rc = a->alloc((void**)&v.cls, v.N);
     if (rc == MG_OK) rc = a->alloc((void**)&v.cls_old, v.N);
     if (rc == MG_OK) rc = a->alloc((void**)&v.marks, v.N);
+    if (rc == MG_OK) {
+      const hipError_t e = hipMemsetAsync(v.marks, 0, v.N, a->s);
+      if (e != hipSuccess) rc = fail(MG_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    }
     if (rc == MG_OK && v.ncells) rc = a->alloc((void**)&v.cells, v.ncells);
     if (rc == MG_OK && dim == 3) {
       // one byte per (x block of 64, row, chunk of planes), as the classification and the march enumerate them
@@ -985,9 +1053,14 @@ int mg_amr_mark(mg_amr* a, int level, const mg_c128* u, const mg_c128* r, mg_c12
   hipLaunchKernelGGL(k_amr_choose, dim3(1), dim3(64), 0, a->s, (const unsigned long long*)a->hist, a->stats, nbins,
                      refine_pct, erase_pct);
   MG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_amr_decide, dim3(gd), dim3(256), 0, a->s, nwords, (uint32_t*)v.marks, (const uint32_t*)v.cls,
-                     (const unsigned long long*)a->hist, a->stats, nbins, refine_pct, erase_pct,
-                     level < a->lmax ? 1 : 0, level >= a->lkeep ? 1 : 0, counters);
+  if (march)
+    hipLaunchKernelGGL(k_amr_decide3, gm, dim3(256), 0, a->s, v.n, v.marks, (const uint8_t*)v.cls,
+                       (const uint8_t*)v.act, (const double*)a->stats, nbins, level < a->lmax ? 1 : 0,
+                       level >= a->lkeep ? 1 : 0, counters);
+  else
+    hipLaunchKernelGGL(k_amr_decide, dim3(gd), dim3(256), 0, a->s, nwords, (uint32_t*)v.marks,
+                       (const uint32_t*)v.cls, (const unsigned long long*)a->hist, a->stats, nbins, refine_pct,
+                       erase_pct, level < a->lmax ? 1 : 0, level >= a->lkeep ? 1 : 0, counters);
   MG_HIP(hipGetLastError());
   v.marked = true;
   if (counts || s_range) {
@@ -1019,7 +1092,7 @@ int mg_amr_adapt(mg_amr* a, long long* class_counts) {
     const int nc = v.n - 1;
     MG_HIP(amr_launch(a->dim, k_amr_cells<2>, k_amr_cells<3>, amr_grid(nc, a->dim), a->s, nc, v.cells,
                       (const uint8_t*)(l > a->lmin ? a->at(l - 1).cells : nullptr),
-                      (const uint8_t*)(v.marked ? v.marks : nullptr),
+                      (const uint8_t*)(v.marked ? v.marks : nullptr), (const uint8_t*)v.cls,
                       (const uint8_t*)(l + 1 < a->lmax ? a->at(l + 1).cells : nullptr)));
   }
   for (int l = a->lmin; l <= a->lmax; ++l) a->at(l).marked = false;
@@ -1072,7 +1145,13 @@ int mg_amr_get(mg_amr* a, int level, int what, unsigned char* out) {
       src = v.cells;
       bytes = (size_t)v.ncells;
       break;
-    case 3: src = v.marks; break;
+    case 3: {
+      const unsigned g = (unsigned)std::min<long long>((v.N + 255) / 256, 8192);
+      hipLaunchKernelGGL(k_amr_mask_marks, dim3(g), dim3(256), 0, a->s, v.N, (const uint8_t*)v.marks,
+                         (const uint8_t*)v.cls, out);
+      MG_HIP(hipGetLastError());
+      return MG_OK;
+    }
     default: return fail(MG_EINVAL, "what must be 0..3");
   }
   MG_HIP(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, a->s));
