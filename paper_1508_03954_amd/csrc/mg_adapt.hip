@@ -681,10 +681,13 @@ __global__ __launch_bounds__(256) void k_amr_classify(int n, uint8_t* __restrict
 // cells x-1 and x, y-1 and y, and z-1 and z for every plane of the chunk lie
 // under at most 2 x 2 x 4 parent cells -- are read once per chunk into a bit
 // mask, and the activity byte of the chunk is written once (0 or 1), so the
-// map needs no clearing.
+// map needs no clearing.  absent_map holds, per chunk, whether the target
+// buffer is known to hold only absent classes there (it travels with the
+// buffer): a chunk that stays absent costs its parent flags and no store.
 __global__ __launch_bounds__(256) void k_amr_classify3(int n, uint8_t* __restrict__ cls,
                                                        const uint8_t* __restrict__ parent,
-                                                       uint8_t* __restrict__ act_map) {
+                                                       uint8_t* __restrict__ act_map,
+                                                       uint8_t* __restrict__ absent_map) {
   const int lane = threadIdx.x & 63;
   const int nzc = (n + kAmrTz - 1) / kAmrTz, gx = (n + 63) / 64;
   const long long plane = (long long)n * n;
@@ -718,6 +721,13 @@ __global__ __launch_bounds__(256) void k_amr_classify3(int n, uint8_t* __restric
             if (parent[((long long)pz * pc + py[b]) * pc + px[a]]) ex |= 1u << (4 * q + 2 * b + a);
       }
     }
+    // no parent refined around any lane: every vertex of the chunk is absent;
+    // when the target buffer already holds zeros there, nothing is written
+    const bool present = __ballot(xin && ex != 0u) != 0;
+    if (!present && absent_map[it]) {
+      if (act_map && lane == 0) act_map[it] = 0;
+      continue;
+    }
     bool any = false;
     for (int z = zs; z < ze; ++z) {
       const bool vz[2] = {z >= 1, z <= n - 2};
@@ -738,7 +748,10 @@ __global__ __launch_bounds__(256) void k_amr_classify3(int n, uint8_t* __restric
       any = any || (xin && v == kPersistent);
     }
     const bool act = __ballot(any) != 0;
-    if (act_map && lane == 0) act_map[it] = act ? 1 : 0;
+    if (lane == 0) {
+      if (act_map) act_map[it] = act ? 1 : 0;
+      absent_map[it] = present ? 0 : 1;
+    }
   }
 }
 
@@ -761,9 +774,10 @@ __global__ __launch_bounds__(256) void k_amr_interp(int n, const uint8_t* __rest
   }
 }
 
-// The same on a 3D level as a march along z.  The class bytes of a chunk of
-// kAmrTz planes are read first; a chunk in which no lane has a vertex to
-// write costs nothing more.  Where some lane takes P u_c: P is separable, so a
+// The same on a 3D level as a march along z.  A chunk known to be absent
+// before and after the step (the classification's absent maps) is skipped;
+// otherwise the class bytes of its kAmrTz planes are read first, and a chunk
+// in which no lane has a vertex to write costs nothing more.  Where some lane takes P u_c: P is separable, so a
 // lane interpolates its coarse corners in x and y once per coarse plane and
 // keeps the two coarse planes that bracket its z in registers.  Corners are
 // clamped so that every lane (boundary ones included) computes a bracket
@@ -778,6 +792,8 @@ __device__ inline cpx<double> amr_xy(const cpx<double>* __restrict__ v, long lon
 
 __global__ __launch_bounds__(256) void k_amr_interp3(int n, const uint8_t* __restrict__ cls_old,
                                                      const uint8_t* __restrict__ cls_new,
+                                                     const uint8_t* __restrict__ absent_old,
+                                                     const uint8_t* __restrict__ absent_new,
                                                      const cpx<double>* __restrict__ uc,
                                                      cpx<double>* __restrict__ u) {
   const int nc = (n - 1) / 3 + 1;
@@ -789,6 +805,7 @@ __global__ __launch_bounds__(256) void k_amr_interp3(int n, const uint8_t* __res
   for (AmrWalk w = amr_walk(gx);; w.q += w.step) {
     const int it = w.item();
     if (it >= items) break;
+    if (absent_old[it] && absent_new[it]) continue;   // absent before and after: nothing to write
     const int bx = it % gx, t = it / gx;
     const int y = t % n, zs = (t / n) * kAmrTz, ze = min(zs + kAmrTz, n);
     const int x = bx * 64 + lane;
@@ -887,6 +904,8 @@ struct AmrLevel {
   long long ncells = 0;
   uint8_t* act = nullptr;     // 3D: activity map of the criterion march (written whole by the classification)
   long long nact = 0;         // its bytes
+  uint8_t* amap = nullptr;    // 3D: chunks of cls known to hold only absent classes
+  uint8_t* amap_old = nullptr;   // the same for cls_old
   bool marked = false;
 };
 
@@ -924,9 +943,10 @@ struct mg_amr {
     for (int l = lmin; l <= lmax; ++l) {
       AmrLevel& v = at(l);
       std::swap(v.cls, v.cls_old);
+      std::swap(v.amap, v.amap_old);
       const uint8_t* par = l > lmin ? at(l - 1).cells : nullptr;
       if (dim == 3) {
-        hipLaunchKernelGGL(k_amr_classify3, amr_march_grid(v.n), dim3(256), 0, s, v.n, v.cls, par, v.act);
+        hipLaunchKernelGGL(k_amr_classify3, amr_march_grid(v.n), dim3(256), 0, s, v.n, v.cls, par, v.act, v.amap);
         MG_HIP(hipGetLastError());
       } else {
         hipLaunchKernelGGL(k_amr_classify<2>, amr_grid(v.n, dim), dim3(256), 0, s, v.n, v.cls, par);
@@ -937,8 +957,11 @@ struct mg_amr {
   }
 
   int sync_old() {
-    for (int l = lmin; l <= lmax; ++l)
+    for (int l = lmin; l <= lmax; ++l) {
       MG_HIP(hipMemcpyAsync(at(l).cls_old, at(l).cls, at(l).N, hipMemcpyDeviceToDevice, s));
+      if (at(l).amap)
+        MG_HIP(hipMemcpyAsync(at(l).amap_old, at(l).amap, (size_t)at(l).nact, hipMemcpyDeviceToDevice, s));
+    }
     return MG_OK;
   }
 };
@@ -978,6 +1001,14 @@ int mg_amr_setup(int dim, int level_min, int level_keep, int level_max, void* hi
       const long long items = (long long)gc.x * v.n * ((v.n + kAmrTz - 1) / kAmrTz);
       v.nact = items;
       rc = a->alloc((void**)&v.act, (size_t)v.nact);
+      // nothing is known of the fresh class buffers: every chunk is written the first time
+      if (rc == MG_OK) rc = a->alloc((void**)&v.amap, (size_t)v.nact);
+      if (rc == MG_OK) rc = a->alloc((void**)&v.amap_old, (size_t)v.nact);
+      for (uint8_t* m : {v.amap, v.amap_old})
+        if (rc == MG_OK) {
+          const hipError_t e = hipMemsetAsync(m, 0, (size_t)v.nact, a->s);
+          if (e != hipSuccess) rc = fail(MG_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+        }
     }
     if (rc == MG_OK && v.ncells) {
       const hipError_t e = hipMemsetAsync(v.cells, l < level_keep ? 1 : 0, v.ncells, a->s);
@@ -1121,7 +1152,8 @@ int mg_amr_interpolate(mg_amr* a, int level, const mg_c128* u_coarse, mg_c128* u
   AmrLevel& v = a->at(level);
   if (a->dim == 3) {
     hipLaunchKernelGGL(k_amr_interp3, amr_march_grid(v.n), dim3(256), 0, a->s, v.n, (const uint8_t*)v.cls_old,
-                       (const uint8_t*)v.cls, (const cpx<double>*)u_coarse, (cpx<double>*)u);
+                       (const uint8_t*)v.cls, (const uint8_t*)v.amap_old, (const uint8_t*)v.amap,
+                       (const cpx<double>*)u_coarse, (cpx<double>*)u);
     MG_HIP(hipGetLastError());
   } else {
     hipLaunchKernelGGL(k_amr_interp<2>, amr_grid(v.n, a->dim), dim3(256), 0, a->s, v.n, (const uint8_t*)v.cls_old,
